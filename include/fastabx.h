@@ -1,0 +1,287 @@
+/*
+ * fastabx-hip: ABX discriminability on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the hot path.  The calls follow the paper's pipeline (Poli, Chemla,
+ * Dupoux, "fastabx: A library for efficient computation of ABX
+ * discriminability", library-overview section and its pipeline figure):
+ *
+ *   dataset  -- labels plus a way to reach each item's features (Dataset)
+ *   task     -- every cell for given ON / BY / ACROSS conditions (Task)
+ *   score    -- d(x,a), d(x,b) for every triple of every cell, D_C per cell (Score)
+ *   collapse -- cell-size weighted average, or averaging level by level (collapse)
+ *
+ * Conventions
+ * -----------
+ *  - Every call that can fail returns an int status: FABX_OK (0) or a negative
+ *    FABX_E* code.  fabx_last_error() then returns a message for the calling
+ *    thread.  No C++ exception crosses this boundary.
+ *  - Pointers documented "device" are HIP device pointers on the context's
+ *    device; every other pointer is host memory.
+ *  - Objects returned through an out-parameter are owned by the library and
+ *    released with the matching *_destroy / *_free call.  A task keeps its
+ *    dataset alive, a result keeps its task alive; releasing the parent first
+ *    is allowed (the child holds a reference).
+ *  - Work runs on the context's HIP stream.  fabx_score blocks until the
+ *    per-cell results are on the host.
+ *  - Objects are not thread-safe: one thread per context at a time (the
+ *    server object is the exception and documents its own rules).
+ */
+#ifndef FASTABX_H
+#define FASTABX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define FABX_OK 0
+#define FABX_EINVAL (-1)     /* bad argument or task specification */
+#define FABX_ENOMEM (-2)     /* device or host allocation failed, or over budget */
+#define FABX_EDOMAIN (-3)    /* a frame (or pooled mean) has zero norm: its angle is undefined */
+#define FABX_EAGAIN (-4)     /* server: job accepted but not finished / not yet admitted */
+#define FABX_EHIP (-5)       /* a HIP runtime call failed */
+#define FABX_ECANCELED (-6)  /* server: job was cancelled */
+#define FABX_ENOTFOUND (-7)  /* server: unknown job id */
+
+/* ------------------------------------------------------------------ enums */
+#define FABX_DTYPE_F32 0
+#define FABX_DTYPE_BF16 1
+
+#define FABX_DISTANCE_ANGULAR 0      /* theta(u, v) / pi, in [0, 1] */
+
+#define FABX_MODE_DTW 0              /* align frames with DTW */
+#define FABX_MODE_POOLED 1           /* mean over time, one vector per item */
+
+#define FABX_PREC_FP32 0             /* plain form: FP32 distances, FP32 DTW */
+#define FABX_PREC_BF16_RECHECK 1     /* BF16 MFMA distances, FP32 DTW, FP64 recheck of near ties */
+
+#define FABX_NORM_PATH 0             /* DTW cost divided by the optimal path's length */
+#define FABX_NORM_NONE 1             /* raw DTW cost */
+
+/* Longest item (in frames) the DTW kernels accept. */
+#define FABX_MAX_ITEM_FRAMES 64
+
+typedef struct fabx_ctx fabx_ctx;
+typedef struct fabx_dataset fabx_dataset;
+typedef struct fabx_task fabx_task;
+typedef struct fabx_result fabx_result;
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char *fabx_last_error(void);
+
+/* Library version string. */
+const char *fabx_version(void);
+
+/* --------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t on
+ * that device (borrowed, must outlive the context) or NULL, in which case the
+ * context creates and owns a stream.  Errors: EINVAL (bad device), EHIP. */
+int fabx_create(fabx_ctx **out, int device, void *hip_stream);
+void fabx_destroy(fabx_ctx *ctx);
+
+/* --------------------------------------------------------------- dataset */
+
+/* A dataset: ragged feature sequences plus an integer attribute table
+ * (the Dataset class: "labels and a way to access the representations").
+ *
+ *  features  device pointer, [n_frames][dim] row-major, dtype F32 or BF16.
+ *            BORROWED: it must stay valid and unchanged while the dataset
+ *            (or any task / result made from it) is alive.
+ *  offsets   host int64 [n_items + 1]; item i owns frames offsets[i] ..
+ *            offsets[i+1]-1.  offsets[0] = 0, offsets[n_items] = n_frames,
+ *            strictly increasing (every item has at least one frame) and,
+ *            for FABX_MODE_DTW, no item longer than FABX_MAX_ITEM_FRAMES.
+ *            Copied.
+ *  attrs     host int32 [n_items][n_attr], label-encoded attribute columns
+ *            (any int32 values).  Copied.
+ * Errors: EINVAL for a null pointer, n_items < 1, dim < 1, n_attr < 1, an
+ * unknown dtype, or offsets that break the rules above.  Zero-norm frames are
+ * reported by fabx_score (EDOMAIN). */
+typedef struct fabx_dataset_desc {
+    const void *features;
+    int32_t dtype;
+    int64_t n_frames;
+    int32_t dim;
+    const int64_t *offsets;
+    int64_t n_items;
+    const int32_t *attrs;
+    int32_t n_attr;
+} fabx_dataset_desc;
+
+int fabx_dataset_create(fabx_ctx *ctx, const fabx_dataset_desc *desc, fabx_dataset **out);
+void fabx_dataset_destroy(fabx_dataset *ds);
+
+/* ------------------------------------------------------------------ task */
+
+/* Build every cell for ON attribute `on`, BY attributes `by[n_by]` and ACROSS
+ * attributes `across[n_across]` (attribute = column of the attrs table).
+ *
+ * Triple predicate (Background section, ABX figure caption and Table 1):
+ * a and x share the ON value, b does not; a, b, x share every BY value; a and
+ * b share every ACROSS value and x differs from them in every ACROSS
+ * attribute.  Without ACROSS the X set is A itself and a == x is excluded
+ * (x is compared with *another* a), so |C| = |A|(|A|-1)|B|; with ACROSS
+ * |C| = |A||B||X|.  Cells are ordered pairs (on_ax, on_b); cells with no
+ * triple are not built.  Cells are numbered in ascending order of
+ * (by..., on_ax, on_b, across_ab..., across_x...).
+ *
+ * This is host work only (integer sort and grouping); device tables are
+ * uploaded on the first fabx_score.  Zero cells is valid (num_cells = 0).
+ * Errors: EINVAL for a column out of range, a repeated column among on / by /
+ * across, or n_by / n_across < 0. */
+int fabx_task_create(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_by,
+                     const int32_t *across, int32_t n_across, fabx_task **out);
+void fabx_task_destroy(fabx_task *task);
+
+int64_t fabx_task_num_cells(const fabx_task *task);
+/* Number of int32 columns of a cell key: 2 + n_by + 2 * n_across. */
+int32_t fabx_task_key_width(const fabx_task *task);
+/* Cell keys into host int32 out[num_cells][key_width]:
+ * (on_ax, on_b, by..., across_ab..., across_x...), attribute values as given. */
+int fabx_task_cell_keys(const fabx_task *task, int32_t *out);
+/* Cell sizes into host int64 out[num_cells] (|C|), and the item counts
+ * |A|, |B|, |X| into host int32 abx[num_cells][3] (either may be NULL). */
+int fabx_task_cell_sizes(const fabx_task *task, int64_t *n_triplets, int32_t *abx);
+
+/* ----------------------------------------------------------------- score */
+
+typedef struct fabx_score_opts {
+    int32_t distance;    /* FABX_DISTANCE_ANGULAR */
+    int32_t mode;        /* FABX_MODE_DTW | FABX_MODE_POOLED */
+    int32_t precision;   /* FABX_PREC_FP32 | FABX_PREC_BF16_RECHECK */
+    int32_t dtw_norm;    /* FABX_NORM_PATH | FABX_NORM_NONE */
+    double margin;       /* BF16_RECHECK: a comparison with |d(x,a) - d(x,b)| <= margin
+                            is re-decided on FP64 distances; < 0 selects the default
+                            2e-2 / sqrt(dim) */
+    double delta;        /* BF16_RECHECK + PATH: cumulative-cost window within which
+                            alternative DTW predecessors must agree on the path length,
+                            else the pair is recomputed in FP64; < 0 selects the default
+                            4e-2 / sqrt(dim) */
+    int32_t keep_pairs;  /* nonzero: keep the per-pair distances for fabx_result_pairs */
+} fabx_score_opts;
+
+/* Defaults: ANGULAR, DTW, BF16_RECHECK, PATH, margin/delta = -1 (library
+ * defaults), keep_pairs = 0. */
+int fabx_score_opts_default(fabx_score_opts *opts);
+
+/* Score every cell: for each cell C and each triple (a, b, x) in it, compare
+ * d(x, a) with d(x, b) and accumulate W_C = sum 2[d(x,a) < d(x,b)] +
+ * [d(x,a) = d(x,b)] in int64 "half units", so that D_C = W_C / (2 |C|)
+ * (the cell discriminability formula of the Background section).
+ *
+ * d is the angular distance between frames (theta / pi), aligned with DTW
+ * (c[0][0] = d00, cumulative first row and column, c[i][j] = d[i][j] +
+ * min(c[i-1][j-1], c[i][j-1], c[i-1][j]), "Dynamic Time Warping on GPU"
+ * section) and divided by the optimal path length for FABX_NORM_PATH, or the
+ * angular distance between time-averaged frames for FABX_MODE_POOLED.
+ *
+ * Synchronous on the context stream.  Errors: EINVAL (bad opts), EDOMAIN
+ * (zero-norm frame / mean), ENOMEM (device workspace), EHIP. */
+int fabx_score(fabx_task *task, const fabx_score_opts *opts, fabx_result **out);
+void fabx_result_free(fabx_result *res);
+
+/* Number of cells of the scored task, and its cell keys (same layout as
+ * fabx_task_cell_keys); useful for results returned by the server. */
+int64_t fabx_result_num_cells(const fabx_result *res);
+int32_t fabx_result_key_width(const fabx_result *res);
+int fabx_result_cell_keys(const fabx_result *res, int32_t *out);
+
+/* Per-cell results into caller-owned host buffers of length num_cells (any
+ * may be NULL): W_C (half units), |C|, and D_C = W_C / (2|C|). */
+int fabx_result_cells(const fabx_result *res, int64_t *half_units, int64_t *n_triplets,
+                      double *score);
+
+/* Distances of item pairs (x = row item, y = column item, original item ids,
+ * both in the same BY group of the task and both used by some cell) from a
+ * result scored with keep_pairs != 0.  out_f32[n]: the GPU distance;
+ * flags[n] (may be NULL): bit 0 = the pair's DTW path length was not robust,
+ * bit 1 = the pair was recomputed in FP64; out_f64[n] (may be NULL): the FP64
+ * recomputed distance where bit 1 is set, else the FP32 value widened.
+ * Errors: EINVAL (keep_pairs was 0, or a pair outside the task). */
+int fabx_result_pairs(const fabx_result *res, int64_t n, const int64_t *x_items,
+                      const int64_t *y_items, float *out_f32, uint8_t *flags, double *out_f64);
+
+typedef struct fabx_stats {
+    int64_t n_cells;
+    int64_t n_triplets;         /* sum of |C| */
+    int64_t n_items;            /* items that take part in some cell */
+    int64_t n_frames;           /* their frames */
+    int64_t n_pairs;            /* item pairs scored (x, y), both orientations */
+    int64_t dtw_cells;          /* sum over the unique pairs the cells need of len(x) * len(y) */
+    int64_t computed_dtw_cells; /* DTW cells the kernels actually evaluated */
+    int64_t n_nonrobust_pairs;  /* pairs whose DTW path length was not robust */
+    int64_t n_recheck_pairs;    /* pairs recomputed in FP64 */
+    int64_t n_recount_rows;     /* (cell, x) rows re-counted with FP64 distances */
+    int64_t workspace_bytes;    /* device workspace held by the task */
+    double ms_total;            /* first kernel to per-cell results on the host */
+    double ms_normalize;
+    double ms_distance;         /* frame distances + DTW (or pooled distances) */
+    double ms_triplets;
+    double ms_recheck;          /* FP64 recheck + recount */
+    double margin;              /* near-tie margin used (BF16 form; 0 for FP32) */
+    double delta;               /* path-length window used (BF16 form, DTW; else 0) */
+} fabx_stats;
+
+int fabx_result_stats(const fabx_result *res, fabx_stats *stats);
+
+/* -------------------------------------------------------------- collapse */
+
+/* ABX error rate 1 - D (Score.collapse).  n_levels = 0: D is the cell-size
+ * weighted mean, sum W / (2 sum |C|).  Otherwise level k names
+ * level_len[k] attributes, listed one after another in level_attr; for each
+ * level in order, the key columns of its attributes (both the _ab and _x
+ * columns of an ACROSS attribute) are removed and D_C is averaged, unweighted,
+ * over the rows sharing the remaining key; D is the unweighted mean of what is
+ * left.  Errors: EINVAL if a level names the ON attribute or an attribute that
+ * is not a BY / ACROSS attribute of the task, or the task has no cell. */
+int fabx_collapse(const fabx_result *res, const int32_t *level_attr, const int32_t *level_len,
+                  int32_t n_levels, double *error_rate);
+
+/* ---------------------------------------------------------------- server */
+
+/* Continuous-batching job server on one context.  Jobs (dataset + task spec
+ * + options) are queued by fabx_server_submit and admitted, in arrival order,
+ * when their device-memory footprint fits in `hbm_budget_bytes` next to the
+ * jobs already running; admitted jobs run concurrently on `n_streams` HIP
+ * streams of the context's device.  A job's result is identical to what
+ * fabx_score returns for it alone.
+ *
+ * Thread rules: submit / poll / wait / cancel may be called from any thread.
+ * A dataset passed to submit must stay alive until the job completes or is
+ * cancelled (the job holds a reference to it). */
+typedef struct fabx_server fabx_server;
+
+int fabx_server_create(fabx_ctx *ctx, int64_t hbm_budget_bytes, int32_t n_streams,
+                       fabx_server **out);
+/* Stops accepting jobs, cancels queued ones, waits for running ones. */
+void fabx_server_destroy(fabx_server *srv);
+
+/* Queue a job.  Errors: EINVAL (bad spec), ENOMEM (the job's footprint
+ * exceeds the whole budget, so it could never run). */
+int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int32_t *by,
+                       int32_t n_by, const int32_t *across, int32_t n_across,
+                       const fabx_score_opts *opts, uint64_t *job_id);
+/* FABX_OK and *out set when finished (caller frees the result); EAGAIN while
+ * queued or running; ECANCELED; ENOTFOUND; or the job's own error code. */
+int fabx_server_poll(fabx_server *srv, uint64_t job_id, fabx_result **out);
+/* Like poll, but blocks until the job is no longer queued or running. */
+int fabx_server_wait(fabx_server *srv, uint64_t job_id, fabx_result **out);
+/* Cancel a queued job (running jobs finish).  Errors: ENOTFOUND, EAGAIN if
+ * already running or finished. */
+int fabx_server_cancel(fabx_server *srv, uint64_t job_id);
+
+typedef struct fabx_server_stats {
+    int64_t submitted, completed, cancelled, failed, queued, running;
+    int64_t hbm_in_use, hbm_high_water;
+    double p50_ms, p99_ms;        /* completion - submission, over completed jobs */
+} fabx_server_stats;
+
+int fabx_server_stats_get(fabx_server *srv, fabx_server_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTABX_H */

@@ -1,0 +1,363 @@
+"""fastabx-hip: ABX discriminability on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI declared in include/fastabx.h.  The
+functions named ``fabx_*`` mirror the C calls one to one (argument
+marshalling only: every step runs in the native library's HIP kernels);
+``Context`` / ``Dataset`` / ``Task`` / ``Result`` / ``Server`` wrap them with
+ownership.  PyTorch is used only for device memory and the current stream.
+
+    ctx = Context(0)
+    ds = Dataset(ctx, features, offsets, attrs)       # features: cuda tensor
+    task = Task(ds, on=0, by=[1, 2, 3])
+    res = task.score(mode="dtw", precision="bf16")
+    err = res.collapse(levels=[[1, 2], [3]])
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (FABX_DTYPE_BF16, FABX_DTYPE_F32, FABX_MODE_DTW, FABX_MODE_POOLED, FABX_NORM_NONE,
+                   FABX_NORM_PATH, FABX_PREC_BF16_RECHECK, FABX_PREC_FP32, fabx_dataset_desc,
+                   fabx_score_opts, fabx_server_stats, fabx_stats)
+
+__all__ = ["FabxError", "Context", "Dataset", "Task", "Result", "Server", "make_opts", "lib"]
+
+
+class FabxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{L.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    return L.load()
+
+
+def _check(code: int) -> None:
+    if code != 0:
+        raise FabxError(code, lib().fabx_last_error().decode())
+
+
+def _i32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if a is not None else None
+
+
+def _i64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if a is not None else None
+
+
+# --------------------------------------------------------- same-name calls --
+
+def fabx_create(device: int = 0, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().fabx_create(ctypes.byref(h), int(device), stream))
+    return h
+
+
+def fabx_destroy(ctx) -> None:
+    lib().fabx_destroy(ctx)
+
+
+def fabx_dataset_create(ctx, features_ptr: int, dtype: int, n_frames: int, dim: int,
+                        offsets: np.ndarray, attrs: np.ndarray) -> ctypes.c_void_p:
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    attrs = np.ascontiguousarray(attrs, dtype=np.int32)
+    if attrs.ndim == 1:
+        attrs = attrs[:, None]
+    d = fabx_dataset_desc(features_ptr, dtype, int(n_frames), int(dim), _i64p(offsets),
+                          int(attrs.shape[0]), _i32p(attrs), int(attrs.shape[1]))
+    h = ctypes.c_void_p()
+    _check(lib().fabx_dataset_create(ctx, ctypes.byref(d), ctypes.byref(h)))
+    return h
+
+
+def fabx_dataset_destroy(ds) -> None:
+    lib().fabx_dataset_destroy(ds)
+
+
+def fabx_task_create(ds, on: int, by: Sequence[int], across: Sequence[int]) -> ctypes.c_void_p:
+    b = np.ascontiguousarray(list(by), dtype=np.int32)
+    a = np.ascontiguousarray(list(across), dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().fabx_task_create(ds, int(on), _i32p(b), len(b), _i32p(a), len(a), ctypes.byref(h)))
+    return h
+
+
+def fabx_task_destroy(t) -> None:
+    lib().fabx_task_destroy(t)
+
+
+def fabx_task_num_cells(t) -> int:
+    return int(lib().fabx_task_num_cells(t))
+
+
+def fabx_task_key_width(t) -> int:
+    return int(lib().fabx_task_key_width(t))
+
+
+def fabx_task_cell_keys(t) -> np.ndarray:
+    n, k = fabx_task_num_cells(t), fabx_task_key_width(t)
+    out = np.zeros((n, k), np.int32)
+    _check(lib().fabx_task_cell_keys(t, _i32p(out)))
+    return out
+
+
+def fabx_task_cell_sizes(t):
+    n = fabx_task_num_cells(t)
+    nt = np.zeros(n, np.int64)
+    abx = np.zeros((n, 3), np.int32)
+    _check(lib().fabx_task_cell_sizes(t, _i64p(nt), _i32p(abx)))
+    return nt, abx
+
+
+def fabx_score_opts_default() -> fabx_score_opts:
+    o = fabx_score_opts()
+    _check(lib().fabx_score_opts_default(ctypes.byref(o)))
+    return o
+
+
+def fabx_score(t, opts: fabx_score_opts) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().fabx_score(t, ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def fabx_result_free(r) -> None:
+    lib().fabx_result_free(r)
+
+
+def fabx_result_num_cells(r) -> int:
+    return int(lib().fabx_result_num_cells(r))
+
+
+def fabx_result_cell_keys(r) -> np.ndarray:
+    n, k = fabx_result_num_cells(r), int(lib().fabx_result_key_width(r))
+    out = np.zeros((n, k), np.int32)
+    _check(lib().fabx_result_cell_keys(r, _i32p(out)))
+    return out
+
+
+def fabx_result_cells(r, n_cells: Optional[int] = None):
+    n_cells = fabx_result_num_cells(r) if n_cells is None else n_cells
+    w = np.zeros(n_cells, np.int64)
+    n = np.zeros(n_cells, np.int64)
+    s = np.zeros(n_cells, np.float64)
+    _check(lib().fabx_result_cells(r, _i64p(w), _i64p(n), s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return w, n, s
+
+
+def fabx_result_pairs(r, xs, ys):
+    xs = np.ascontiguousarray(xs, np.int64)
+    ys = np.ascontiguousarray(ys, np.int64)
+    f32 = np.zeros(len(xs), np.float32)
+    fl = np.zeros(len(xs), np.uint8)
+    f64 = np.zeros(len(xs), np.float64)
+    _check(lib().fabx_result_pairs(r, len(xs), _i64p(xs), _i64p(ys),
+                                   f32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   f64.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return f32, fl, f64
+
+
+def fabx_result_stats(r) -> dict:
+    st = fabx_stats()
+    _check(lib().fabx_result_stats(r, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def fabx_collapse(r, levels: Optional[Sequence[Sequence[int]]] = None) -> float:
+    levels = [list(l) for l in (levels or [])]
+    flat = np.ascontiguousarray([a for l in levels for a in l] or [0], np.int32)
+    lens = np.ascontiguousarray([len(l) for l in levels] or [0], np.int32)
+    out = ctypes.c_double()
+    _check(lib().fabx_collapse(r, _i32p(flat), _i32p(lens), len(levels), ctypes.byref(out)))
+    return out.value
+
+
+def fabx_server_create(ctx, hbm_budget_bytes: int, n_streams: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().fabx_server_create(ctx, int(hbm_budget_bytes), int(n_streams), ctypes.byref(h)))
+    return h
+
+
+def fabx_server_destroy(srv) -> None:
+    lib().fabx_server_destroy(srv)
+
+
+def fabx_server_submit(srv, ds, on, by, across, opts: fabx_score_opts) -> int:
+    b = np.ascontiguousarray(list(by), dtype=np.int32)
+    a = np.ascontiguousarray(list(across), dtype=np.int32)
+    jid = ctypes.c_uint64()
+    _check(lib().fabx_server_submit(srv, ds, int(on), _i32p(b), len(b), _i32p(a), len(a),
+                                    ctypes.byref(opts), ctypes.byref(jid)))
+    return int(jid.value)
+
+
+def fabx_server_poll(srv, job_id: int):
+    """(status, result handle or None); status FABX_OK, FABX_EAGAIN or an error code."""
+    h = ctypes.c_void_p()
+    rc = lib().fabx_server_poll(srv, ctypes.c_uint64(job_id), ctypes.byref(h))
+    return rc, (h if rc == 0 else None)
+
+
+def fabx_server_wait(srv, job_id: int):
+    h = ctypes.c_void_p()
+    rc = lib().fabx_server_wait(srv, ctypes.c_uint64(job_id), ctypes.byref(h))
+    return rc, (h if rc == 0 else None)
+
+
+def fabx_server_cancel(srv, job_id: int) -> int:
+    return int(lib().fabx_server_cancel(srv, ctypes.c_uint64(job_id)))
+
+
+def fabx_server_stats_get(srv) -> dict:
+    st = fabx_server_stats()
+    _check(lib().fabx_server_stats_get(srv, ctypes.byref(st)))
+    return st.as_dict()
+
+
+# ----------------------------------------------------------- convenience --
+
+def make_opts(mode: str = "dtw", precision: str = "bf16", norm: str = "path", margin: float = -1.0,
+              delta: float = -1.0, keep_pairs: bool = False) -> fabx_score_opts:
+    o = fabx_score_opts_default()
+    o.mode = {"dtw": FABX_MODE_DTW, "pooled": FABX_MODE_POOLED}[mode]
+    o.precision = {"fp32": FABX_PREC_FP32, "bf16": FABX_PREC_BF16_RECHECK}[precision]
+    o.dtw_norm = {"path": FABX_NORM_PATH, "none": FABX_NORM_NONE}[norm]
+    o.margin = float(margin)
+    o.delta = float(delta)
+    o.keep_pairs = 1 if keep_pairs else 0
+    return o
+
+
+def _current_stream_ptr(device: int):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A device (or, with device=-1, a host-only context that can build tasks but not score)."""
+
+    def __init__(self, device: int = 0, stream="torch"):
+        self.device = device
+        s = None
+        if device >= 0 and stream == "torch":
+            s = _current_stream_ptr(device)
+        elif stream not in (None, "torch"):
+            s = ctypes.c_void_p(int(stream))
+        self.h = fabx_create(device, s)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            fabx_destroy(self.h)
+            self.h = None
+
+
+class Dataset:
+    """Ragged features (device tensor [n_frames, dim], float32 or bfloat16) + attribute table."""
+
+    def __init__(self, ctx: Context, features, offsets, attrs):
+        self.ctx = ctx
+        self.features = features  # keep the borrowed tensor alive
+        offsets = np.ascontiguousarray(offsets, np.int64)
+        attrs = np.ascontiguousarray(attrs, np.int32)
+        if features is None:
+            ptr, dtype, nf, dim = None, FABX_DTYPE_F32, int(offsets[-1]), 1
+        else:
+            import torch
+            if not features.is_contiguous():
+                raise ValueError("features must be contiguous")
+            dtype = {torch.float32: FABX_DTYPE_F32, torch.bfloat16: FABX_DTYPE_BF16}[features.dtype]
+            ptr, nf, dim = features.data_ptr(), int(features.shape[0]), int(features.shape[1])
+        self.h = fabx_dataset_create(ctx.h, ptr, dtype, nf, dim, offsets, attrs)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            fabx_dataset_destroy(self.h)
+            self.h = None
+
+
+class Task:
+    def __init__(self, ds: Dataset, on: int, by: Sequence[int] = (), across: Sequence[int] = ()):
+        self.ds = ds
+        self.on, self.by, self.across = int(on), list(by), list(across)
+        self.h = fabx_task_create(ds.h, on, by, across)
+
+    def __len__(self):
+        return fabx_task_num_cells(self.h)
+
+    @property
+    def keys(self) -> np.ndarray:
+        return fabx_task_cell_keys(self.h)
+
+    @property
+    def sizes(self):
+        return fabx_task_cell_sizes(self.h)
+
+    def score(self, **kw) -> "Result":
+        return Result(self, fabx_score(self.h, make_opts(**kw)))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            fabx_task_destroy(self.h)
+            self.h = None
+
+
+class Result:
+    def __init__(self, task: Task, h):
+        self.task = task
+        self.h = h
+        self.half_units, self.n_triplets, self.scores = fabx_result_cells(h, len(task))
+
+    @property
+    def stats(self) -> dict:
+        return fabx_result_stats(self.h)
+
+    def pairs(self, xs, ys):
+        return fabx_result_pairs(self.h, xs, ys)
+
+    def collapse(self, levels=None) -> float:
+        return fabx_collapse(self.h, levels)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            fabx_result_free(self.h)
+            self.h = None
+
+
+class Server:
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, n_streams: int = 4):
+        self.ctx = ctx
+        self.h = fabx_server_create(ctx.h, hbm_budget_bytes, n_streams)
+        self._tasks = {}
+
+    def submit(self, ds: Dataset, on, by=(), across=(), **kw) -> int:
+        return fabx_server_submit(self.h, ds.h, on, by, across, make_opts(**kw))
+
+    def wait(self, job_id: int):
+        """Block until the job ends; returns (keys, W, |C|, D_C) and frees the native result."""
+        rc, h = fabx_server_wait(self.h, job_id)
+        if rc != 0:
+            raise FabxError(rc, lib().fabx_last_error().decode())
+        try:
+            keys = fabx_result_cell_keys(h)
+            w, n, s = fabx_result_cells(h)
+        finally:
+            fabx_result_free(h)
+        return keys, w, n, s
+
+    @property
+    def stats(self) -> dict:
+        return fabx_server_stats_get(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            fabx_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,123 @@
+"""ctypes declarations of the fastabx-hip C ABI (include/fastabx.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfastabx_hip.so")
+
+FABX_OK = 0
+FABX_EINVAL = -1
+FABX_ENOMEM = -2
+FABX_EDOMAIN = -3
+FABX_EAGAIN = -4
+FABX_EHIP = -5
+FABX_ECANCELED = -6
+FABX_ENOTFOUND = -7
+
+FABX_DTYPE_F32 = 0
+FABX_DTYPE_BF16 = 1
+FABX_DISTANCE_ANGULAR = 0
+FABX_MODE_DTW = 0
+FABX_MODE_POOLED = 1
+FABX_PREC_FP32 = 0
+FABX_PREC_BF16_RECHECK = 1
+FABX_NORM_PATH = 0
+FABX_NORM_NONE = 1
+FABX_MAX_ITEM_FRAMES = 64
+
+STATUS_NAMES = {0: "FABX_OK", -1: "FABX_EINVAL", -2: "FABX_ENOMEM", -3: "FABX_EDOMAIN",
+                -4: "FABX_EAGAIN", -5: "FABX_EHIP", -6: "FABX_ECANCELED", -7: "FABX_ENOTFOUND"}
+
+
+class fabx_dataset_desc(ctypes.Structure):
+    _fields_ = [("features", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("n_frames", ctypes.c_int64),
+                ("dim", ctypes.c_int32), ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("n_items", ctypes.c_int64), ("attrs", ctypes.POINTER(ctypes.c_int32)),
+                ("n_attr", ctypes.c_int32)]
+
+
+class fabx_score_opts(ctypes.Structure):
+    _fields_ = [("distance", ctypes.c_int32), ("mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("dtw_norm", ctypes.c_int32), ("margin", ctypes.c_double), ("delta", ctypes.c_double),
+                ("keep_pairs", ctypes.c_int32)]
+
+
+class fabx_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "n_cells", "n_triplets", "n_items", "n_frames", "n_pairs", "dtw_cells", "computed_dtw_cells",
+        "n_nonrobust_pairs", "n_recheck_pairs", "n_recount_rows", "workspace_bytes")] + \
+        [(n, ctypes.c_double) for n in ("ms_total", "ms_normalize", "ms_distance", "ms_triplets",
+                                         "ms_recheck", "margin", "delta")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class fabx_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "cancelled", "failed", "queued",
+                                              "running", "hbm_in_use", "hbm_high_water")] + \
+        [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "fabx_last_error": (ctypes.c_char_p, []),
+    "fabx_version": (ctypes.c_char_p, []),
+    "fabx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _vp]),
+    "fabx_destroy": (None, [_vp]),
+    "fabx_dataset_create": (ctypes.c_int, [_vp, _P(fabx_dataset_desc), _P(_vp)]),
+    "fabx_dataset_destroy": (None, [_vp]),
+    "fabx_task_create": (ctypes.c_int, [_vp, _i32, _P(_i32), _i32, _P(_i32), _i32, _P(_vp)]),
+    "fabx_task_destroy": (None, [_vp]),
+    "fabx_task_num_cells": (_i64, [_vp]),
+    "fabx_task_key_width": (_i32, [_vp]),
+    "fabx_task_cell_keys": (ctypes.c_int, [_vp, _P(_i32)]),
+    "fabx_task_cell_sizes": (ctypes.c_int, [_vp, _P(_i64), _P(_i32)]),
+    "fabx_score_opts_default": (ctypes.c_int, [_P(fabx_score_opts)]),
+    "fabx_score": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
+    "fabx_result_free": (None, [_vp]),
+    "fabx_result_num_cells": (_i64, [_vp]),
+    "fabx_result_key_width": (_i32, [_vp]),
+    "fabx_result_cell_keys": (ctypes.c_int, [_vp, _P(_i32)]),
+    "fabx_result_cells": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(ctypes.c_double)]),
+    "fabx_result_pairs": (ctypes.c_int, [_vp, _i64, _P(_i64), _P(_i64), _P(ctypes.c_float),
+                                         _P(ctypes.c_uint8), _P(ctypes.c_double)]),
+    "fabx_result_stats": (ctypes.c_int, [_vp, _P(fabx_stats)]),
+    "fabx_collapse": (ctypes.c_int, [_vp, _P(_i32), _P(_i32), _i32, _P(ctypes.c_double)]),
+    "fabx_server_create": (ctypes.c_int, [_vp, _i64, _i32, _P(_vp)]),
+    "fabx_server_destroy": (None, [_vp]),
+    "fabx_server_submit": (ctypes.c_int, [_vp, _vp, _i32, _P(_i32), _i32, _P(_i32), _i32,
+                                          _P(fabx_score_opts), _P(ctypes.c_uint64)]),
+    "fabx_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(_vp)]),
+    "fabx_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(_vp)]),
+    "fabx_server_cancel": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "fabx_server_stats_get": (ctypes.c_int, [_vp, _P(fabx_server_stats)]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library; fail loudly when it is missing (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"fastabx-hip native library not found at {LIB_PATH}; build it with "
+                "`python -m paper_2505_02692_amd.build` (hipcc, gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

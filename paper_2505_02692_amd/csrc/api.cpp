@@ -1,0 +1,264 @@
+// C ABI of fastabx-hip: argument checks, handle management, error codes.
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace fabx {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void DevBuf::ensure(size_t n) {
+    if (n <= bytes && ptr) return;
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        fail(FABX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+}
+
+CtxImpl::~CtxImpl() {
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// Runs `f`, converting internal errors into status codes.
+template <typename F>
+int guarded(F &&f) {
+    try {
+        f();
+        set_last_error("");
+        return FABX_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return FABX_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return FABX_EINVAL;
+    } catch (...) {
+        set_last_error("unknown internal error");
+        return FABX_EINVAL;
+    }
+}
+
+}  // namespace fabx
+
+using namespace fabx;
+
+extern "C" {
+
+const char *fabx_last_error(void) { return last_error_cstr(); }
+
+const char *fabx_version(void) { return "fastabx-hip 0.1.0 (gfx950)"; }
+
+int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
+    return guarded([&] {
+        if (!out) fail(FABX_EINVAL, "out is NULL");
+        *out = nullptr;
+        auto c = std::make_shared<CtxImpl>();
+        c->device = device;
+        if (device >= 0) {
+            int n = 0;
+            if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+                (void)hipGetLastError();
+                fail(FABX_EINVAL, "no HIP device " + std::to_string(device));
+            }
+            FABX_HIP(hipSetDevice(device));
+            hipDeviceProp_t prop;
+            FABX_HIP(hipGetDeviceProperties(&prop, device));
+            c->n_cu = prop.multiProcessorCount;
+            if (hip_stream) {
+                c->stream = static_cast<hipStream_t>(hip_stream);
+            } else {
+                FABX_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+                c->own_stream = true;
+            }
+        } else if (device != -1) {
+            fail(FABX_EINVAL, "device must be >= 0 (or -1 for a host-only context)");
+        }
+        *out = new fabx_ctx{c};
+    });
+}
+
+void fabx_destroy(fabx_ctx *ctx) { delete ctx; }
+
+int fabx_dataset_create(fabx_ctx *ctx, const fabx_dataset_desc *d, fabx_dataset **out) {
+    return guarded([&] {
+        if (!ctx || !d || !out) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        if (d->n_items < 1) fail(FABX_EINVAL, "n_items must be >= 1");
+        if (d->dim < 1) fail(FABX_EINVAL, "dim must be >= 1");
+        if (d->n_attr < 1) fail(FABX_EINVAL, "n_attr must be >= 1");
+        if (d->dtype != FABX_DTYPE_F32 && d->dtype != FABX_DTYPE_BF16) fail(FABX_EINVAL, "unknown dtype");
+        if (!d->offsets || !d->attrs) fail(FABX_EINVAL, "offsets / attrs is NULL");
+        if (!d->features && ctx->p->device >= 0) fail(FABX_EINVAL, "features is NULL");
+        if (d->offsets[0] != 0) fail(FABX_EINVAL, "offsets[0] must be 0");
+        auto ds = std::make_shared<DatasetImpl>();
+        ds->ctx = ctx->p;
+        ds->features = d->features;
+        ds->dtype = d->dtype;
+        ds->n_frames = d->n_frames;
+        ds->dim = d->dim;
+        ds->n_items = d->n_items;
+        ds->n_attr = d->n_attr;
+        ds->offsets.assign(d->offsets, d->offsets + d->n_items + 1);
+        for (int64_t i = 0; i < d->n_items; ++i) {
+            const int64_t L = ds->offsets[i + 1] - ds->offsets[i];
+            if (L < 1) fail(FABX_EINVAL, "item " + std::to_string(i) + " has no frame");
+            if (L > ds->max_len) ds->max_len = int(L);
+        }
+        if (ds->offsets[d->n_items] != d->n_frames) fail(FABX_EINVAL, "offsets[n_items] != n_frames");
+        ds->attrs.assign(d->attrs, d->attrs + d->n_items * int64_t(d->n_attr));
+        *out = new fabx_dataset{ds};
+    });
+}
+
+void fabx_dataset_destroy(fabx_dataset *ds) { delete ds; }
+
+int fabx_task_create(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_by,
+                     const int32_t *across, int32_t n_across, fabx_task **out) {
+    return guarded([&] {
+        if (!ds || !out) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        auto t = build_task(ds->p, on, by, n_by, across, n_across);
+        *out = new fabx_task{t};
+    });
+}
+
+void fabx_task_destroy(fabx_task *t) { delete t; }
+
+int64_t fabx_task_num_cells(const fabx_task *t) { return t ? int64_t(t->p->cells.size()) : -1; }
+
+int32_t fabx_task_key_width(const fabx_task *t) { return t ? t->p->key_width : -1; }
+
+int fabx_task_cell_keys(const fabx_task *t, int32_t *out) {
+    return guarded([&] {
+        if (!t || !out) fail(FABX_EINVAL, "null argument");
+        if (!t->p->keys.empty()) std::memcpy(out, t->p->keys.data(), t->p->keys.size() * sizeof(int32_t));
+    });
+}
+
+int fabx_task_cell_sizes(const fabx_task *t, int64_t *n_triplets, int32_t *abx) {
+    return guarded([&] {
+        if (!t) fail(FABX_EINVAL, "null task");
+        const auto &T = *t->p;
+        for (size_t c = 0; c < T.cells.size(); ++c) {
+            if (n_triplets) n_triplets[c] = T.n_triplets[c];
+            if (abx) {
+                abx[3 * c] = T.cells[c].na;
+                abx[3 * c + 1] = T.cells[c].nb;
+                abx[3 * c + 2] = T.cells[c].nx;
+            }
+        }
+    });
+}
+
+int fabx_score_opts_default(fabx_score_opts *o) {
+    if (!o) return FABX_EINVAL;
+    o->distance = FABX_DISTANCE_ANGULAR;
+    o->mode = FABX_MODE_DTW;
+    o->precision = FABX_PREC_BF16_RECHECK;
+    o->dtw_norm = FABX_NORM_PATH;
+    o->margin = -1.0;
+    o->delta = -1.0;
+    o->keep_pairs = 0;
+    return FABX_OK;
+}
+
+int fabx_score(fabx_task *t, const fabx_score_opts *opts, fabx_result **out) {
+    return guarded([&] {
+        if (!t || !out) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        ScoreParams p = resolve_opts(opts, *t->p->ds);
+        auto r = run_score(t->p, p, t->p->ds->ctx->stream);
+        *out = new fabx_result{r};
+    });
+}
+
+void fabx_result_free(fabx_result *r) { delete r; }
+
+int64_t fabx_result_num_cells(const fabx_result *r) { return r ? int64_t(r->p->half_units.size()) : -1; }
+
+int32_t fabx_result_key_width(const fabx_result *r) { return r ? r->p->task->key_width : -1; }
+
+int fabx_result_cell_keys(const fabx_result *r, int32_t *out) {
+    return guarded([&] {
+        if (!r || !out) fail(FABX_EINVAL, "null argument");
+        const auto &k = r->p->task->keys;
+        if (!k.empty()) std::memcpy(out, k.data(), k.size() * sizeof(int32_t));
+    });
+}
+
+int fabx_result_cells(const fabx_result *r, int64_t *half_units, int64_t *n_triplets, double *score) {
+    return guarded([&] {
+        if (!r) fail(FABX_EINVAL, "null result");
+        const auto &R = *r->p;
+        const auto &T = *R.task;
+        for (size_t c = 0; c < R.half_units.size(); ++c) {
+            if (half_units) half_units[c] = R.half_units[c];
+            if (n_triplets) n_triplets[c] = T.n_triplets[c];
+            if (score) score[c] = double(R.half_units[c]) / (2.0 * double(T.n_triplets[c]));
+        }
+    });
+}
+
+int fabx_result_pairs(const fabx_result *r, int64_t n, const int64_t *xs, const int64_t *ys,
+                      float *out_f32, uint8_t *flags, double *out_f64) {
+    return guarded([&] {
+        if (!r || (n > 0 && (!xs || !ys || !out_f32))) fail(FABX_EINVAL, "null argument");
+        const auto &R = *r->p;
+        if (!R.has_pairs) fail(FABX_EINVAL, "result was scored without keep_pairs");
+        const auto &T = *R.task;
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t x = xs[k], y = ys[k];
+            if (x < 0 || y < 0 || x >= T.ds->n_items || y >= T.ds->n_items)
+                fail(FABX_EINVAL, "item id out of range");
+            const int64_t px = T.item_pos_of[x], py = T.item_pos_of[y];
+            if (px < 0 || py < 0 || T.item_group[px] != T.item_group[py])
+                fail(FABX_EINVAL, "pair not in one BY group of the task");
+            const Group &g = T.groups[T.item_group[px]];
+            const int64_t slot = g.pair_base + (px - g.item0) * g.n_items + (py - g.item0);
+            out_f32[k] = R.p32[slot];
+            const uint8_t f = R.flags.empty() ? 0 : R.flags[slot];
+            if (flags) flags[k] = f;
+            if (out_f64) out_f64[k] = (f & 2) ? R.p64[slot] : double(R.p32[slot]);
+        }
+    });
+}
+
+int fabx_result_stats(const fabx_result *r, fabx_stats *st) {
+    return guarded([&] {
+        if (!r || !st) fail(FABX_EINVAL, "null argument");
+        *st = r->p->stats;
+    });
+}
+
+int fabx_collapse(const fabx_result *r, const int32_t *level_attr, const int32_t *level_len,
+                  int32_t n_levels, double *error_rate) {
+    return guarded([&] {
+        if (!r || !error_rate) fail(FABX_EINVAL, "null argument");
+        if (n_levels < 0 || (n_levels > 0 && (!level_attr || !level_len))) fail(FABX_EINVAL, "bad levels");
+        *error_rate = collapse(*r->p, level_attr, level_len, n_levels);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Internal types of the fastabx-hip runtime (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fastabx.h"
+
+namespace fabx {
+
+// Errors travel as exceptions inside the library and become status codes at
+// the C boundary (api.cpp); nothing throws across extern "C".
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define FABX_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            ::fabx::fail(FABX_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release();
+    // Ensure capacity >= n bytes (contents are not preserved on growth).
+    void ensure(size_t n);
+    template <typename T>
+    T *as() const { return static_cast<T *>(ptr); }
+};
+
+struct CtxImpl {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 0;
+    ~CtxImpl();
+};
+
+struct DatasetImpl {
+    std::shared_ptr<CtxImpl> ctx;
+    const void *features = nullptr;   // borrowed device pointer
+    int dtype = FABX_DTYPE_F32;
+    int64_t n_frames = 0;
+    int dim = 0;
+    int64_t n_items = 0;
+    int n_attr = 0;
+    int max_len = 0;
+    std::vector<int64_t> offsets;     // [n_items + 1]
+    std::vector<int32_t> attrs;       // [n_items * n_attr]
+};
+
+// One BY group that holds at least one cell.  Items of a group are
+// contiguous in task order, and so are their packed frames.
+struct Group {
+    int64_t item0;      // first task item
+    int64_t n_items;
+    int64_t frame0;     // first packed frame
+    int64_t n_frames;
+    int64_t pair_base;  // offset of the group's [n_items x n_items] pair matrix
+    int64_t dmat_base;  // offset of the group's [n_frames x n_frames] distance matrix (plain form)
+};
+
+// A cell on the device: item positions are local to the group.
+struct CellDev {
+    int32_t group;
+    int32_t a0, na;
+    int32_t b0, nb;
+    int32_t x0, nx;
+    int32_t exclude_self;  // X is A: skip a == x
+};
+static_assert(sizeof(CellDev) == 32, "CellDev layout");
+
+// Device copies of the task tables.
+struct TaskDevice {
+    DevBuf item_src, item_len, item_dst, item_group;
+    DevBuf g_item0, g_n, g_frame0, g_nframes, g_pair_base, g_dmat_base;
+    DevBuf cells, units, unit_count;
+    DevBuf tiles_prefix;         // plain Gram tile prefix per group
+    DevBuf rb, cb, unit_prefix;  // BF16 fused kernel: row/col blocks and work prefix
+    bool uploaded = false;
+};
+
+// Device workspace kept by a task between scores.
+struct Workspace {
+    DevBuf xn;          // packed normalised frames (F32 or BF16) [n_frames x dim_pad]
+    DevBuf rinv;        // F32 [n_frames]: 1 / ||bf16 frame|| (BF16 form)
+    DevBuf dmat;        // plain form: F32 frame distances per group
+    DevBuf p32;         // F32 [n_pair_slots]
+    DevBuf flags;       // uint8 [n_pair_slots]: bit0 non-robust, bit1 marked for FP64
+    DevBuf p64;         // F64 [n_pair_slots]
+    DevBuf half_units;  // uint64 [n_cells]
+    DevBuf counters;    // misc device counters
+    DevBuf recheck_list, recount_list;
+    size_t total() const;
+    void release();
+};
+
+struct TaskImpl {
+    std::shared_ptr<DatasetImpl> ds;
+    int32_t on = 0;
+    std::vector<int32_t> by, across;
+    std::vector<int32_t> key_attr;  // attribute behind each key column
+    int32_t key_width = 0;
+
+    // task items (those in groups with cells), in task order
+    std::vector<int64_t> items;     // original ids
+    std::vector<int32_t> item_len;
+    std::vector<int64_t> item_src;  // first source frame
+    std::vector<int64_t> item_dst;  // first packed frame
+    std::vector<int32_t> item_group;
+    std::vector<int64_t> item_pos_of;  // original id -> task position, -1 if absent
+
+    std::vector<Group> groups;
+    std::vector<CellDev> cells;
+    std::vector<int64_t> n_triplets;
+    std::vector<int32_t> keys;      // [n_cells * key_width]
+
+    int64_t n_frames = 0;
+    int64_t n_pair_slots = 0;       // sum over groups of n_items^2
+    int64_t n_dmat = 0;             // sum over groups of n_frames^2
+    int64_t n_pairs_needed = 0;     // unique ordered pairs some cell uses
+    int64_t dtw_cells_needed = 0;   // sum of len(x) * len(y) over those pairs
+    int64_t total_triplets = 0;
+    int max_len = 0;
+
+    TaskDevice dev;
+    Workspace ws;
+    std::mutex mu;                  // one score at a time per task
+};
+
+struct ResultImpl {
+    std::shared_ptr<TaskImpl> task;
+    std::vector<int64_t> half_units;
+    fabx_stats stats{};
+    bool has_pairs = false;
+    std::vector<float> p32;
+    std::vector<uint8_t> flags;
+    std::vector<double> p64;
+};
+
+// task.cpp
+std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,
+                                     const int32_t *by, int32_t n_by, const int32_t *across,
+                                     int32_t n_across);
+
+// score.cpp
+struct ScoreParams {
+    int mode, precision, dtw_norm;
+    double margin, delta;
+    bool keep_pairs;
+};
+ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds);
+std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &task, const ScoreParams &p,
+                                      hipStream_t stream);
+// Device bytes a score of this task would hold (admission control).
+int64_t footprint_bytes(const TaskImpl &task, const ScoreParams &p);
+
+// collapse.cpp
+double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t *level_len,
+                int32_t n_levels);
+
+}  // namespace fabx
+
+// Opaque handle types of the C ABI.
+struct fabx_ctx {
+    std::shared_ptr<fabx::CtxImpl> p;
+};
+struct fabx_dataset {
+    std::shared_ptr<fabx::DatasetImpl> p;
+};
+struct fabx_task {
+    std::shared_ptr<fabx::TaskImpl> p;
+};
+struct fabx_result {
+    std::shared_ptr<fabx::ResultImpl> p;
+};

@@ -1,0 +1,351 @@
+// BF16 form: frame distances on MFMA fused with the DTW wavefront.
+//
+// Work unit = (row block, column block) of one BY group.  A row block packs
+// whole items into at most 64 frames (one DTW lane per frame row); a column
+// block packs whole items into at most kCols frames.  For each unit:
+//
+//  1. Gram tile on MFMA: S = Xr (64 x D) * Xc^T (D x kCols), BF16 operands
+//     staged through LDS in K chunks of 64, FP32 accumulation
+//     (v_mfma_f32_32x32x16_bf16; wave w owns columns [32w, 32w + 32) of a
+//     128-column tile, two 32 x 32 accumulators for the 64 rows).
+//  2. Epilogue: cos = S * rinv_r * rinv_c, d = acos(cos) / pi (Abramowitz &
+//     Stegun 4.4.46), written to an LDS tile; it never reaches HBM.
+//  3. DTW wavefront (the recurrence of the "Dynamic Time Warping on GPU"
+//     section), laid out for wave64 instead of one pair per block: lane r
+//     owns frame row r of the row block, whatever item it belongs to, and
+//     each wave streams the columns of its share of the column items past
+//     all 64 rows.  Lane r works on column t - i_r at step t (i_r = row
+//     index inside its own item), so the value above comes from lane r - 1
+//     one step earlier (DPP wave_shr:1) and the diagonal one from two steps
+//     earlier; a column that starts a new item resets the left neighbour.
+//     Every step all lanes do useful work except the fill and drain of the
+//     longest row item.
+//
+// Path length (FABX_NORM_PATH): with BF16 distances the predecessor chosen in
+// FP32 can differ from the FP64 one when their cumulative costs are within
+// the error bound, and then the length (the divisor) changes.  Each cell
+// therefore carries the interval [Lmin, Lmax] of lengths over all
+// predecessors within `delta` of the minimum (packed as two u16 halves,
+// high = Lmax, low = 0xFFFF - Lmin, so one packed max merges both ends).
+// If delta is at least twice the cumulative-cost error, the FP64 length lies
+// in the interval; a pair whose interval is not a single value is flagged
+// non-robust (flag bit 0) and recomputed in FP64.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fabx {
+namespace kern {
+namespace {
+
+using dev::kInf;
+using dev::kWave;
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kRows = 64;             // row block frames = DTW lanes
+constexpr int kCols = 128;            // column block frames
+constexpr int kKc = 64;               // K chunk (bf16 elements) staged in LDS
+constexpr int kLdsRow = kKc + 8;      // padded LDS row of a K chunk (bf16)
+constexpr int kDStride = kCols + 2;   // LDS distance tile stride (floats)
+constexpr int kStageBytes = (kRows + kCols) * kLdsRow * 2;
+constexpr int kTileBytes = kRows * kDStride * 4;
+constexpr int kSmemBytes = kStageBytes > kTileBytes ? kStageBytes : kTileBytes;
+
+__device__ __forceinline__ float shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(v), 0x138,
+                                                      0xf, 0xf, false));
+}
+__device__ __forceinline__ uint32_t shr1u(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+    u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
+}
+__device__ __forceinline__ uint32_t pk_step(uint32_t a) {
+    // Lmax + 1 (high half), (0xFFFF - Lmin) - 1 (low half), each half wrapping
+    u16x2 x = __builtin_bit_cast(u16x2, a);
+    u16x2 inc = {(unsigned short)0xFFFF, (unsigned short)1};
+    return __builtin_bit_cast(uint32_t, x + inc);
+}
+
+// Stage one K chunk of `nr` rows starting at packed row `row0` into LDS
+// (zero rows beyond nr).  Each 16-byte piece is one load.
+template <int kN>
+__device__ __forceinline__ void stage_rows(uint16_t *lds, const uint16_t *__restrict__ xn, int dim_pad,
+                                           int64_t row0, int nr, int k0) {
+    constexpr int kPieces = kN * (kKc / 8);
+    for (int p = threadIdx.x; p < kPieces; p += 256) {
+        const int r = p / (kKc / 8), q = p % (kKc / 8);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (r < nr) v = *reinterpret_cast<const uint4 *>(xn + (row0 + r) * dim_pad + k0 + q * 8);
+        *reinterpret_cast<uint4 *>(lds + r * kLdsRow + q * 8) = v;
+    }
+}
+
+// acc0 = rows 0..31, acc1 = rows 32..63 against columns [32w, 32w+32).
+__device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__restrict__ xn, int dim_pad,
+                                          int64_t r0, int nr, int64_t c0, int nc, f32x16 &acc0,
+                                          f32x16 &acc1) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    uint16_t *As = smem;
+    uint16_t *Bs = smem + kRows * kLdsRow;
+    for (int i = 0; i < 16; ++i) { acc0[i] = 0.0f; acc1[i] = 0.0f; }
+    for (int k0 = 0; k0 < dim_pad; k0 += kKc) {
+        stage_rows<kRows>(As, xn, dim_pad, r0, nr, k0);
+        stage_rows<kCols>(Bs, xn, dim_pad, c0, nc, k0);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKc / 16; ++ks) {
+            const int kk = ks * 16 + (lane / 32) * 8;
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + (lane % 32) * kLdsRow + kk);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(As + (32 + lane % 32) * kLdsRow + kk);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (32 * w + lane % 32) * kLdsRow + kk);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc1, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+}
+
+// Row (within the 32 x 32 tile) of accumulator element i of this lane.
+__device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i / 4) + 4 * (lane / 32) + (i % 4); }
+
+template <bool kPath>
+__global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ xn,
+                                                  const float *__restrict__ rinv, int dim_pad,
+                                                  const int64_t *__restrict__ g_item0,
+                                                  const int64_t *__restrict__ g_n,
+                                                  const int64_t *__restrict__ g_pair_base,
+                                                  const int32_t *__restrict__ item_len,
+                                                  const int64_t *__restrict__ item_dst,
+                                                  const int32_t *__restrict__ rb,
+                                                  const int32_t *__restrict__ cb,
+                                                  const int64_t *__restrict__ unit_prefix,
+                                                  const int32_t *__restrict__ g_rb0,
+                                                  const int32_t *__restrict__ g_cb0,
+                                                  const int32_t *__restrict__ g_ncb,
+                                                  int64_t n_groups, int64_t n_units, int64_t grid_q,
+                                                  float delta, float *__restrict__ p32,
+                                                  uint8_t *__restrict__ flags,
+                                                  unsigned int *__restrict__ nonrobust_n) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kSmemBytes];
+    __shared__ uint16_t colflag[4][kCols];
+    // XCD-aware order: the 8 XCDs take blocks round-robin, so give each XCD a
+    // contiguous run of units (units of one group share its frames in L2).
+    const int64_t b = blockIdx.x;
+    const int64_t unit = (b % 8) * grid_q + b / 8;
+    if (unit >= n_units) return;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+
+    const int64_t g = dev::find_segment(unit_prefix, n_groups, unit);
+    const int64_t local = unit - unit_prefix[g];
+    const int ncb = g_ncb[g];
+    const int rbi = g_rb0[g] + int(local / ncb), cbi = g_cb0[g] + int(local % ncb);
+    const int r_item0 = rb[4 * rbi + 1], r_nitems = rb[4 * rbi + 2], r_frames = rb[4 * rbi + 3];
+    const int c_item0 = cb[4 * cbi + 1], c_nitems = cb[4 * cbi + 2], c_frames = cb[4 * cbi + 3];
+    const int64_t r_frame0 = item_dst[r_item0], c_frame0 = item_dst[c_item0];
+
+    // 1. Gram tile
+    f32x16 acc0, acc1;
+    gram_tile(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
+              c_frames, acc0, acc1);
+
+    // 2. epilogue -> LDS distance tile (the staging buffers are dead now)
+    float *dt = reinterpret_cast<float *>(smem_raw);
+    {
+        const int col = 32 * w + lane % 32;
+        const float rc = col < c_frames ? rinv[c_frame0 + col] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r0 = acc_row(i, lane), r1 = 32 + r0;
+            const float rr0 = r0 < r_frames ? rinv[r_frame0 + r0] : 0.0f;
+            const float rr1 = r1 < r_frames ? rinv[r_frame0 + r1] : 0.0f;
+            dt[r0 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc0[i] * rr0 * rc, -1.0f), 1.0f));
+            dt[r1 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc1[i] * rr1 * rc, -1.0f), 1.0f));
+        }
+    }
+
+    // 3. DTW.  Column items of this block split over the 4 waves by start frame.
+    // Lane constants: the row item of lane `lane`.
+    int ir = 0, nx = 0, x_task = -1;
+    {
+        int start = 0;
+        for (int k = 0; k < r_nitems; ++k) {
+            const int L = item_len[r_item0 + k];
+            if (lane >= start && lane < start + L) { ir = lane - start; nx = L; x_task = r_item0 + k; }
+            start += L;
+        }
+    }
+    int max_n = 0;
+    for (int k = 0; k < r_nitems; ++k) max_n = max(max_n, item_len[r_item0 + k]);
+    // this wave's column items: those whose first frame falls in its quarter
+    int y_begin = 0, y_end = 0, s_begin = 0, s_end = 0;
+    {
+        int start = 0;
+        bool seen = false;
+        for (int k = 0; k < c_nitems; ++k) {
+            const int L = item_len[c_item0 + k];
+            const int owner = (4 * start) / max(c_frames, 1);
+            if (owner == w) {
+                if (!seen) { y_begin = k; s_begin = start; seen = true; }
+                y_end = k + 1;
+                s_end = start + L;
+            }
+            start += L;
+        }
+        if (seen) {
+            int start2 = s_begin;
+            for (int k = y_begin; k < y_end; ++k) {
+                const int L = item_len[c_item0 + k];
+                for (int j = lane; j < L; j += kWave)
+                    colflag[w][start2 - s_begin + j] =
+                        uint16_t((j == 0 ? 1 : 0) | (j == L - 1 ? 2 : 0) | (k << 2));
+                start2 += L;
+            }
+        }
+    }
+    __syncthreads();
+    const int S = s_end - s_begin;
+    if (S == 0) return;  // nothing for this wave (no barrier follows)
+
+    const int64_t pbase = g_pair_base[g];
+    const int64_t gn = g_n[g];
+    const int64_t gitem0 = g_item0[g];
+    const bool row_valid = x_task >= 0;
+    const bool top = ir == 0;
+    const int64_t x_row = row_valid ? (int64_t(x_task) - gitem0) * gn : 0;
+    const float *drow = dt + lane * kDStride + s_begin;
+
+    float c = kInf, up_prev = kInf;
+    uint32_t P = 0, Pup_prev = 0;
+    const int steps = S + max_n - 1;
+    for (int t = 0; t < steps; ++t) {
+        const int gcol = t - ir;
+        const bool act = row_valid && gcol >= 0 && gcol < S;
+        const int gc = min(max(gcol, 0), S - 1);
+        const uint32_t cf = colflag[w][gc];
+        const float dv = drow[gc];
+        const bool first = cf & 1;
+        float up = shr1(c);
+        uint32_t Pup = kPath ? shr1u(P) : 0u;
+        float diag = up_prev, left = c;
+        uint32_t Pd = Pup_prev, Pl = P;
+        up_prev = up;
+        Pup_prev = Pup;
+        if (top) {
+            up = kInf;
+            diag = first ? 0.0f : kInf;
+            Pd = 0x0000FFFFu;  // virtual start: Lmin = Lmax = 0
+        }
+        if (first) {
+            left = kInf;
+            if (!top) diag = kInf;
+        }
+        const float m = fminf(fminf(diag, left), up);
+        float cn = dv + m;
+        uint32_t Pn = 0;
+        if (kPath) {
+            const float thr = m + delta;
+            const uint32_t sd = diag <= thr ? Pd : 0u;
+            const uint32_t sl = left <= thr ? Pl : 0u;
+            const uint32_t su = up <= thr ? Pup : 0u;
+            Pn = pk_step(pk_max(pk_max(sd, sl), su));
+        }
+        if (act) {
+            c = cn;
+            P = Pn;
+            if ((cf & 2) && ir == nx - 1) {
+                const int64_t slot = pbase + x_row + (int64_t(c_item0) + (cf >> 2) - gitem0);
+                if (kPath) {
+                    const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
+                    p32[slot] = c / float(lmin);
+                    flags[slot] = lmin == lmax ? 0 : 1;
+                    if (lmin != lmax) atomicAdd(nonrobust_n, 1u);
+                } else {
+                    p32[slot] = c;
+                    flags[slot] = 0;
+                }
+            }
+        }
+    }
+}
+
+// Pooled mode: MFMA Gram tile of pooled unit vectors, angular distance straight
+// into the pair matrix (64 x 128 item tile per block).
+__global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__restrict__ xn,
+                                                              const float *__restrict__ rinv,
+                                                              int dim_pad,
+                                                              const int64_t *__restrict__ row0,
+                                                              const int64_t *__restrict__ nrows,
+                                                              const int64_t *__restrict__ base,
+                                                              const int64_t *__restrict__ tile_prefix,
+                                                              int64_t n_groups,
+                                                              float *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kStageBytes];
+    const int64_t tile = blockIdx.x;
+    const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
+    const int64_t n = nrows[g];
+    const int64_t ntc = (n + kCols - 1) / kCols;
+    const int64_t local = tile - tile_prefix[g];
+    const int64_t r0 = (local / ntc) * kRows, c0 = (local % ntc) * kCols;
+    const int nr = int(min<int64_t>(kRows, n - r0)), nc = int(min<int64_t>(kCols, n - c0));
+    f32x16 acc0, acc1;
+    gram_tile(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc,
+              acc0, acc1);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int col = 32 * w + lane % 32;
+    if (col >= nc) return;
+    const float rc = rinv[row0[g] + c0 + col];
+    float *o = out + base[g];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int ra = acc_row(i, lane), rb2 = 32 + ra;
+        if (ra < nr)
+            o[(r0 + ra) * n + c0 + col] =
+                dev::acos_over_pi(fminf(fmaxf(acc0[i] * rinv[row0[g] + r0 + ra] * rc, -1.0f), 1.0f));
+        if (rb2 < nr)
+            o[(r0 + rb2) * n + c0 + col] =
+                dev::acos_over_pi(fminf(fmaxf(acc1[i] * rinv[row0[g] + r0 + rb2] * rc, -1.0f), 1.0f));
+    }
+}
+
+}  // namespace
+
+void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
+                const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,
+                float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n) {
+    if (plan.n_units <= 0) return;
+    if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
+    const int64_t q = (plan.n_units + 7) / 8;
+    const int64_t blocks = 8 * q;
+    if (blocks > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many work units for one launch");
+    if (norm == FABX_NORM_PATH)
+        hipLaunchKernelGGL(k_fused<true>, dim3(unsigned(blocks)), dim3(256), 0, s, xn, rinv, dim_pad,
+                           g.item0, g.n_items, g.pair_base, it.len, it.dst, plan.rb, plan.cb,
+                           plan.unit_prefix, plan.g_rb0, plan.g_cb0, plan.g_ncb, g.n_groups,
+                           plan.n_units, q, delta, p32, flags, nonrobust_n);
+    else
+        hipLaunchKernelGGL(k_fused<false>, dim3(unsigned(blocks)), dim3(256), 0, s, xn, rinv, dim_pad,
+                           g.item0, g.n_items, g.pair_base, it.len, it.dst, plan.rb, plan.cb,
+                           plan.unit_prefix, plan.g_rb0, plan.g_cb0, plan.g_ncb, g.n_groups,
+                           plan.n_units, q, delta, p32, flags, nonrobust_n);
+    FABX_HIP(hipGetLastError());
+}
+
+void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
+                       const int64_t *row0, const int64_t *nrows, const int64_t *base,
+                       const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out) {
+    if (n_tiles <= 0) return;
+    if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
+    if (n_tiles > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many tiles for one launch");
+    hipLaunchKernelGGL(k_gram_angular_bf16, dim3(unsigned(n_tiles)), dim3(256), 0, s, xn, rinv,
+                       dim_pad, row0, nrows, base, tile_prefix, n_groups, out);
+    FABX_HIP(hipGetLastError());
+}
+
+}  // namespace kern
+}  // namespace fabx

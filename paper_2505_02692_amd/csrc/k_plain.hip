@@ -1,0 +1,161 @@
+// Plain FP32 form: the straightforward GPU pipeline the BF16 form is
+// measured against.
+//
+//  gram_angular_f32: per BY group, every pair of unit rows -> theta / pi in FP32
+//    (64 x 64 output tile per 256-thread block, 4 x 4 per thread, K staged
+//    through LDS in steps of 16), written to HBM.
+//  dtw_plain: one wave per ordered item pair; lane i owns row i of the DTW
+//    matrix and the wave sweeps the anti-diagonals t = i + j, reading the
+//    distance matrix from HBM: the paper's wavefront scheme (one pair per
+//    block, the cells of a diagonal in parallel), with the previous two
+//    diagonals held in registers of neighbouring lanes.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fabx {
+namespace kern {
+namespace {
+
+using dev::kInf;
+using dev::kWave;
+
+constexpr int kTile = 64;
+constexpr int kK = 16;
+
+__global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restrict__ xn, int dim_pad,
+                                                          const int64_t *__restrict__ row0,
+                                                          const int64_t *__restrict__ nrows,
+                                                          const int64_t *__restrict__ base,
+                                                          const int64_t *__restrict__ tile_prefix,
+                                                          int64_t n_groups, float *__restrict__ out) {
+    __shared__ float As[kK][kTile + 4];
+    __shared__ float Bs[kK][kTile + 4];
+    const int64_t tile = blockIdx.x;
+    const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
+    const int64_t n = nrows[g];
+    const int64_t nt = (n + kTile - 1) / kTile;
+    const int64_t local = tile - tile_prefix[g];
+    const int64_t r0 = (local / nt) * kTile, c0 = (local % nt) * kTile;
+    const float *rows = xn + row0[g] * int64_t(dim_pad);
+    const int tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    float acc[4][4] = {};
+    // staging: each thread loads 4 consecutive k of one row for A and for B
+    const int lr = tid / 4, lk = (tid % 4) * 4;
+    for (int k0 = 0; k0 < dim_pad; k0 += kK) {
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+        if (r0 + lr < n) a = *reinterpret_cast<const float4 *>(rows + (r0 + lr) * dim_pad + k0 + lk);
+        if (c0 + lr < n) b = *reinterpret_cast<const float4 *>(rows + (c0 + lr) * dim_pad + k0 + lk);
+        As[lk + 0][lr] = a.x; As[lk + 1][lr] = a.y; As[lk + 2][lr] = a.z; As[lk + 3][lr] = a.w;
+        Bs[lk + 0][lr] = b.x; Bs[lk + 1][lr] = b.y; Bs[lk + 2][lr] = b.z; Bs[lk + 3][lr] = b.w;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kK; ++k) {
+            float av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[k][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[k][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    float *o = out + base[g];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + ty * 4 + i;
+        if (r >= n) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t c = c0 + tx * 4 + j;
+            if (c >= n) continue;
+            const float cs = fminf(fmaxf(acc[i][j], -1.0f), 1.0f);
+            o[r * n + c] = acosf(cs) * dev::kInvPi;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dmat,
+                                                   const int64_t *__restrict__ g_item0,
+                                                   const int64_t *__restrict__ g_n,
+                                                   const int64_t *__restrict__ g_frame0,
+                                                   const int64_t *__restrict__ g_nframes,
+                                                   const int64_t *__restrict__ g_pair_base,
+                                                   const int64_t *__restrict__ g_dmat_base,
+                                                   int64_t n_groups, int64_t n_slots,
+                                                   const int32_t *__restrict__ item_len,
+                                                   const int64_t *__restrict__ item_dst, int norm,
+                                                   float *__restrict__ p32) {
+    const int64_t slot = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave;
+    const int i = threadIdx.x % kWave;
+    if (slot >= n_slots) return;  // whole wave leaves together
+    const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
+    const int64_t n = g_n[g];
+    const int64_t local = slot - g_pair_base[g];
+    const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
+    const int N = item_len[x], M = item_len[y];
+    const int64_t F = g_nframes[g];
+    const float *d = dmat + g_dmat_base[g] + (item_dst[x] - g_frame0[g]) * F + (item_dst[y] - g_frame0[g]);
+
+    float c = kInf;          // c[i][j-1] (own value of the previous step)
+    int len = 0;
+    float up_prev = kInf;    // c[i-1][j-1]
+    int lup_prev = 0;
+    for (int t = 0; t < N + M - 1; ++t) {
+        const int j = t - i;
+        float up = __shfl_up(c, 1, kWave);  // c[i-1][j]: lane i-1 at step t-1
+        int lup = __shfl_up(len, 1, kWave);
+        float diag = up_prev, left = c;
+        int ldiag = lup_prev, lleft = len;
+        if (i == 0) { up = kInf; diag = kInf; }
+        if (j == 0) { left = kInf; diag = kInf; }
+        up_prev = up;
+        lup_prev = lup;
+        if (i < N && j >= 0 && j < M) {
+            const float dv = d[int64_t(i) * F + j];
+            if (i == 0 && j == 0) {
+                c = dv;
+                len = 1;
+            } else {
+                float best;
+                int lb;
+                if (diag <= left && diag <= up) { best = diag; lb = ldiag; }
+                else if (left <= up) { best = left; lb = lleft; }
+                else { best = up; lb = lup; }
+                c = dv + best;
+                len = lb + 1;
+            }
+        }
+    }
+    if (i == N - 1) p32[slot] = norm == FABX_NORM_PATH ? c / float(len) : c;
+}
+
+}  // namespace
+
+void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t *row0,
+                      const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
+                      int64_t n_groups, int64_t n_tiles, float *out) {
+    if (n_tiles <= 0) return;
+    if (n_tiles > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many distance tiles for one launch");
+    if (dim_pad % kK) fail(FABX_EINVAL, "padded dim must be a multiple of 16");
+    hipLaunchKernelGGL(k_gram_angular_f32, dim3(unsigned(n_tiles)), dim3(256), 0, s, xn, dim_pad,
+                       row0, nrows, base, tile_prefix, n_groups, out);
+    FABX_HIP(hipGetLastError());
+}
+
+void dtw_plain(hipStream_t s, const float *dmat, const GroupTables &g, const ItemTables &it,
+               int norm, float *p32) {
+    if (g.n_pair_slots <= 0) return;
+    const int64_t blocks = (g.n_pair_slots + 3) / 4;
+    if (blocks > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many pairs for one launch");
+    hipLaunchKernelGGL(k_dtw_plain, dim3(unsigned(blocks)), dim3(256), 0, s, dmat, g.item0,
+                       g.n_items, g.frame0, g.n_frames, g.pair_base, g.dmat_base, g.n_groups,
+                       g.n_pair_slots, it.len, it.dst, norm, p32);
+    FABX_HIP(hipGetLastError());
+}
+
+}  // namespace kern
+}  // namespace fabx

@@ -1,0 +1,233 @@
+// Frame normalisation and time pooling.
+//
+// The angular distance only depends on directions, so every frame is scaled
+// to unit length once and packed in task order (frames of a BY group are
+// contiguous, row stride padded to a multiple of 64 with zeros) so that a
+// group's frame-distance matrix is one dense Gram product.
+//
+// HBM-bound: one read of each feature row, one write of the packed row.
+// One 256-thread block per task item, each wave takes every 4th frame.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fabx {
+namespace kern {
+namespace {
+
+using dev::kWave;
+
+template <typename Tin>
+__device__ __forceinline__ void load_row_chunk(const Tin *row, int k, int dim, float v[4]);
+
+template <>
+__device__ __forceinline__ void load_row_chunk<float>(const float *row, int k, int dim, float v[4]) {
+    if (k + 3 < dim && (dim & 3) == 0) {
+        float4 q = *reinterpret_cast<const float4 *>(row + k);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (k + e < dim) ? row[k + e] : 0.0f;
+    }
+}
+
+template <>
+__device__ __forceinline__ void load_row_chunk<uint16_t>(const uint16_t *row, int k, int dim, float v[4]) {
+    if (k + 3 < dim && (dim & 3) == 0) {
+        uint2 q = *reinterpret_cast<const uint2 *>(row + k);
+        v[0] = __uint_as_float(q.x << 16);
+        v[1] = __uint_as_float(q.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(q.y << 16);
+        v[3] = __uint_as_float(q.y & 0xFFFF0000u);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (k + e < dim) ? dev::bf16_to_f32(row[k + e]) : 0.0f;
+    }
+}
+
+// Scale one row held as 4-element chunks (k = 4 * (lane + 64 * c)) and store it.
+template <int kChunks>
+__device__ __forceinline__ void store_unit_row(float (&v)[kChunks][4], float ss, int lane, int dim_pad,
+                                               int64_t out_row, void *out, int out_bf16,
+                                               float *rinv) {
+    const float r = 1.0f / __builtin_sqrtf(ss);
+    if (!out_bf16) {
+        float *o = static_cast<float *>(out) + out_row * dim_pad;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            int k = 4 * (lane + kWave * c);
+            if (k < dim_pad)
+                *reinterpret_cast<float4 *>(o + k) =
+                    make_float4(v[c][0] * r, v[c][1] * r, v[c][2] * r, v[c][3] * r);
+        }
+    } else {
+        uint16_t *o = static_cast<uint16_t *>(out) + out_row * dim_pad;
+        float ss16 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            int k = 4 * (lane + kWave * c);
+            if (k < dim_pad) {
+                uint16_t h[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    h[e] = dev::f32_to_bf16(v[c][e] * r);
+                    float b = dev::bf16_to_f32(h[e]);
+                    ss16 = fmaf(b, b, ss16);
+                }
+                uint2 q;
+                q.x = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
+                q.y = uint32_t(h[2]) | (uint32_t(h[3]) << 16);
+                *reinterpret_cast<uint2 *>(o + k) = q;
+            }
+        }
+        ss16 = dev::wave_sum(ss16);
+        if (lane == 0) rinv[out_row] = 1.0f / __builtin_sqrtf(ss16);
+    }
+}
+
+// kChunks * 256 >= dim_pad: each lane keeps its 4 * kChunks elements in registers.
+template <typename Tin, int kChunks>
+__global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, int dim, int dim_pad,
+                                                   const int64_t *__restrict__ item_src,
+                                                   const int32_t *__restrict__ item_len,
+                                                   const int64_t *__restrict__ item_dst,
+                                                   void *out, int out_bf16, float *rinv, int *err,
+                                                   unsigned long long *err_item) {
+    const int64_t item = blockIdx.x;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int L = item_len[item];
+    const int64_t s0 = item_src[item], d0 = item_dst[item];
+    for (int t = wave; t < L; t += 4) {
+        const Tin *row = src + (s0 + t) * int64_t(dim);
+        float v[kChunks][4];
+        float ss = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            int k = 4 * (lane + kWave * c);
+            load_row_chunk<Tin>(row, k, dim, v[c]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ss = fmaf(v[c][e], v[c][e], ss);
+        }
+        ss = dev::wave_sum(ss);
+        if (!(ss > 0.0f)) {
+            if (lane == 0) {
+                atomicExch(err, 1);
+                atomicMin(err_item, (unsigned long long)item);
+            }
+            ss = 1.0f;
+        }
+        store_unit_row<kChunks>(v, ss, lane, dim_pad, d0 + t, out, out_bf16, rinv);
+    }
+}
+
+template <typename Tin, int kChunks>
+__global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ src, int dim, int dim_pad,
+                                                        const int64_t *__restrict__ item_src,
+                                                        const int32_t *__restrict__ item_len,
+                                                        int64_t n_items, void *out, int out_bf16,
+                                                        float *rinv, int *err,
+                                                        unsigned long long *err_item) {
+    // one wave per item
+    const int64_t item = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (item >= n_items) return;
+    const int L = item_len[item];
+    const int64_t s0 = item_src[item];
+    float v[kChunks][4];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[c][e] = 0.0f;
+    for (int t = 0; t < L; ++t) {
+        const Tin *row = src + (s0 + t) * int64_t(dim);
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            float w[4];
+            load_row_chunk<Tin>(row, 4 * (lane + kWave * c), dim, w);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[c][e] += w[e];
+        }
+    }
+    const float invL = 1.0f / float(L);
+    float ss = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v[c][e] *= invL;
+            ss = fmaf(v[c][e], v[c][e], ss);
+        }
+    ss = dev::wave_sum(ss);
+    if (!(ss > 0.0f)) {
+        if (lane == 0) {
+            atomicExch(err, 1);
+            atomicMin(err_item, (unsigned long long)item);
+        }
+        ss = 1.0f;
+    }
+    store_unit_row<kChunks>(v, ss, lane, dim_pad, item, out, out_bf16, rinv);
+}
+
+template <int kChunks>
+void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
+                 const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+                 unsigned long long *err_item, bool pooled) {
+    if (pooled) {
+        dim3 grid(unsigned((it.n_items + 3) / 4));
+        if (dtype == FABX_DTYPE_F32)
+            hipLaunchKernelGGL((k_pool_normalize<float, kChunks>), grid, dim3(256), 0, s,
+                               static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
+                               it.n_items, out, out_bf16, rinv, err, err_item);
+        else
+            hipLaunchKernelGGL((k_pool_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
+                               static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
+                               it.len, it.n_items, out, out_bf16, rinv, err, err_item);
+    } else {
+        dim3 grid(unsigned(it.n_items));
+        if (dtype == FABX_DTYPE_F32)
+            hipLaunchKernelGGL((k_normalize<float, kChunks>), grid, dim3(256), 0, s,
+                               static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
+                               it.dst, out, out_bf16, rinv, err, err_item);
+        else
+            hipLaunchKernelGGL((k_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
+                               static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
+                               it.len, it.dst, out, out_bf16, rinv, err, err_item);
+    }
+    FABX_HIP(hipGetLastError());
+}
+
+void dispatch(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
+              const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+              unsigned long long *err_item, bool pooled) {
+    if (it.n_items <= 0) return;
+    if (it.n_items > 0x7FFFFFFFLL * (pooled ? 4 : 1)) fail(FABX_EINVAL, "too many items for one launch");
+    // chunks of 256 elements per wave pass
+    const int chunks = (dim_pad + 255) / 256;
+    switch (chunks) {
+        case 1: launch_norm<1>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 2: launch_norm<2>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 3: launch_norm<3>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 4: launch_norm<4>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 5: launch_norm<5>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 6: launch_norm<6>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 7: launch_norm<7>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 8: launch_norm<8>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        default: fail(FABX_EINVAL, "feature dim above 2048 is not supported");
+    }
+}
+
+}  // namespace
+
+void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
+               const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+               unsigned long long *err_item) {
+    dispatch(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, false);
+}
+
+void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
+                    const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+                    unsigned long long *err_item) {
+    dispatch(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, true);
+}
+
+}  // namespace kern
+}  // namespace fabx

@@ -1,0 +1,104 @@
+// Host-side launchers of the HIP kernels.  Each launcher checks the launch
+// shape it relies on and enqueues on `stream`; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace fabx {
+namespace kern {
+
+// Per-item task tables on the device.
+struct ItemTables {
+    const int64_t *src;    // first source frame of each task item
+    const int32_t *len;    // frames per item
+    const int64_t *dst;    // first packed frame
+    int64_t n_items;
+};
+
+// Per-group tables on the device (n_groups entries; *_prefix arrays have n_groups + 1).
+struct GroupTables {
+    const int64_t *item0, *n_items, *frame0, *n_frames, *pair_base, *dmat_base;
+    int64_t n_groups;
+    int64_t n_pair_slots;
+};
+
+// --- k_prep.hip
+// Unit-normalise every frame of every task item into the packed buffer
+// (row stride dim_pad, zero padded).  out_bf16 = 0: F32 rows; 1: BF16 rows plus
+// rinv[f] = 1 / ||bf16 row|| (F32).  A zero-norm frame sets err[0] = 1 and
+// lowers err_item (unsigned long long) to its task item.
+void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
+               const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+               unsigned long long *err_item);
+
+// Time pooling: mean of each item's frames (F32 accumulation), then the same
+// normalisation; one packed row per task item.
+void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
+                    const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+                    unsigned long long *err_item);
+
+// --- k_plain.hip (plain FP32 form)
+// Per group: theta/pi of every pair of packed rows [row0, row0 + n) of the
+// group, into out[base + r * n + c].  rows/row0/base come from `frame0`,
+// `n_frames`, `dmat_base` (DTW mode) or item0 / n_items / pair_base (pooled mode).
+void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t *row0,
+                      const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
+                      int64_t n_groups, int64_t n_tiles, float *out);
+
+// One wave per ordered item pair of each group: anti-diagonal DTW over the
+// group's F32 distance matrix (lane = row), exact diagonal > left > up
+// predecessor order.  norm: FABX_NORM_PATH / FABX_NORM_NONE.
+void dtw_plain(hipStream_t s, const float *dmat, const GroupTables &g, const ItemTables &it,
+               int norm, float *p32);
+
+// --- k_fused.hip (BF16 form)
+struct FusedPlan {
+    const int32_t *rb;        // row blocks: [n_rb][4] = group, first item (task), n items, n frames
+    const int32_t *cb;        // col blocks: same layout
+    const int64_t *unit_prefix;  // per group: work units (rb x cb) prefix, n_groups + 1
+    const int32_t *g_rb0, *g_cb0;  // per group: first row / col block, and counts
+    const int32_t *g_nrb, *g_ncb;
+    int64_t n_units;
+};
+void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
+                const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,
+                float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n);
+
+// Pooled mode, BF16 MFMA: theta/pi between pooled item vectors of each group.
+void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
+                       const int64_t *row0, const int64_t *nrows, const int64_t *base,
+                       const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out);
+
+// --- k_triplets.hip
+// One wave per unit [cell, x_begin, x_end): W[cell] += sum over the unit's rows of
+// 2[d(x,a) < d(x,b)] + [d(x,a) == d(x,b)].  With flags != nullptr (BF16 form), a row
+// holding a comparison with |d(x,a) - d(x,b)| <= margin, or a non-robust pair, is
+// not counted: its pairs get flag bit 1 and (cell, x) is appended to recount.
+void triplets(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
+              const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
+              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap);
+
+// Pair slots whose flag bit 1 is set -> list (order unspecified).
+void collect_marked(hipStream_t s, const uint8_t *flags, int64_t n_slots, int64_t *list,
+                    unsigned int *count, int64_t cap);
+
+// Re-count rows (cell, x): a comparison of two recomputed pairs (flag bit 1 on both)
+// uses their FP64 values, any other comparison the FP32 ones.
+void recount(hipStream_t s, const CellDev *cells, const int32_t *rows, const unsigned int *n_rows,
+             int64_t max_rows, const GroupTables &g, const float *p32, const double *p64,
+             const uint8_t *flags, unsigned long long *W);
+
+// --- k_recheck.hip
+// FP64 distance of each listed pair slot from the raw features (unit vectors
+// by division by the sequential-sum norm, cosine as a sequential sum, acos or
+// the half-chord atan2 form near |cos| = 1, DTW with diagonal > left > up).
+void recheck_fp64(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
+                  const ItemTables &it, const int64_t *list, const unsigned int *count,
+                  int64_t max_count, int mode, int norm, double *p64);
+
+}  // namespace kern
+}  // namespace fabx

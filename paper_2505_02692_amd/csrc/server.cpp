@@ -1,0 +1,297 @@
+// Continuous-batching job server.
+//
+// Jobs are queued in arrival order.  A job is admitted when its device
+// footprint (workspace + tables of its task, as computed by footprint_bytes)
+// fits in the budget next to the jobs already running and a stream is free;
+// admitted jobs run concurrently, one per HIP stream, so the kernels of
+// several jobs overlap on the device.  Each job runs the same code path as
+// fabx_score with its own task and workspace, so its result does not depend
+// on what else is running.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+
+#include "internal.h"
+
+namespace fabx {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class JobState { Queued, Running, Done, Failed, Cancelled };
+
+struct Job {
+    std::shared_ptr<TaskImpl> task;
+    ScoreParams params{};
+    int64_t footprint = 0;
+    JobState state = JobState::Queued;
+    std::shared_ptr<ResultImpl> result;
+    int code = FABX_OK;
+    std::string msg;
+    Clock::time_point t_submit, t_done;
+};
+
+}  // namespace
+
+struct ServerImpl {
+    std::shared_ptr<CtxImpl> ctx;
+    int64_t budget = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, Job> jobs;
+    uint64_t next_id = 1;
+    int64_t in_use = 0, high_water = 0;
+    int64_t submitted = 0, completed = 0, cancelled = 0, failed = 0, running = 0;
+    std::vector<double> latencies_ms;
+    bool stop = false;
+
+    void worker(size_t k) {
+        (void)hipSetDevice(ctx->device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            cv.wait(lk, [&] {
+                if (stop) return true;
+                if (queue.empty()) return false;
+                return jobs[queue.front()].footprint <= budget - in_use;
+            });
+            if (stop && queue.empty()) return;
+            if (stop) {
+                // cancel what is still queued
+                for (uint64_t id : queue) {
+                    jobs[id].state = JobState::Cancelled;
+                    ++cancelled;
+                }
+                queue.clear();
+                cv.notify_all();
+                return;
+            }
+            const uint64_t id = queue.front();
+            queue.pop_front();
+            Job &job = jobs[id];
+            job.state = JobState::Running;
+            in_use += job.footprint;
+            high_water = std::max(high_water, in_use);
+            ++running;
+            auto task = job.task;
+            auto params = job.params;
+            lk.unlock();
+            std::shared_ptr<ResultImpl> res;
+            int code = FABX_OK;
+            std::string msg;
+            try {
+                res = run_score(task, params, streams[k]);
+            } catch (const Error &e) {
+                code = e.code;
+                msg = e.msg;
+            } catch (const std::exception &e) {
+                code = FABX_ENOMEM;
+                msg = e.what();
+            }
+            // the result keeps per-cell counts on the host; give the device memory back
+            {
+                std::lock_guard<std::mutex> g(task->mu);
+                task->ws.release();
+            }
+            lk.lock();
+            Job &j2 = jobs[id];
+            j2.t_done = Clock::now();
+            in_use -= j2.footprint;
+            --running;
+            if (code == FABX_OK) {
+                j2.state = JobState::Done;
+                j2.result = res;
+                ++completed;
+                latencies_ms.push_back(
+                    std::chrono::duration<double, std::milli>(j2.t_done - j2.t_submit).count());
+            } else {
+                j2.state = JobState::Failed;
+                j2.code = code;
+                j2.msg = msg;
+                ++failed;
+            }
+            cv.notify_all();
+        }
+    }
+};
+
+}  // namespace fabx
+
+struct fabx_server {
+    std::unique_ptr<fabx::ServerImpl> p;
+};
+
+using namespace fabx;
+
+namespace fabx {
+template <typename F>
+int guarded_server(F &&f) {
+    try {
+        f();
+        set_last_error("");
+        return FABX_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return FABX_ENOMEM;
+    }
+}
+}  // namespace fabx
+
+extern "C" {
+
+int fabx_server_create(fabx_ctx *ctx, int64_t budget, int32_t n_streams, fabx_server **out) {
+    return guarded_server([&] {
+        if (!ctx || !out) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        if (ctx->p->device < 0) fail(FABX_EINVAL, "server needs a device context");
+        if (budget <= 0 || n_streams < 1 || n_streams > 16) fail(FABX_EINVAL, "bad budget or n_streams");
+        auto s = std::make_unique<ServerImpl>();
+        s->ctx = ctx->p;
+        s->budget = budget;
+        FABX_HIP(hipSetDevice(ctx->p->device));
+        for (int i = 0; i < n_streams; ++i) {
+            hipStream_t st;
+            FABX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            s->streams.push_back(st);
+        }
+        ServerImpl *raw = s.get();
+        for (int i = 0; i < n_streams; ++i) raw->workers.emplace_back([raw, i] { raw->worker(size_t(i)); });
+        *out = new fabx_server{std::move(s)};
+    });
+}
+
+void fabx_server_destroy(fabx_server *srv) {
+    if (!srv) return;
+    ServerImpl &s = *srv->p;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        s.stop = true;
+    }
+    s.cv.notify_all();
+    for (auto &w : s.workers) w.join();
+    for (auto st : s.streams) (void)hipStreamDestroy(st);
+    delete srv;
+}
+
+int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_by,
+                       const int32_t *across, int32_t n_across, const fabx_score_opts *opts,
+                       uint64_t *job_id) {
+    return guarded_server([&] {
+        if (!srv || !ds || !job_id) fail(FABX_EINVAL, "null argument");
+        ServerImpl &s = *srv->p;
+        if (ds->p->ctx->device != s.ctx->device) fail(FABX_EINVAL, "dataset is on another device");
+        Job job;
+        job.params = resolve_opts(opts, *ds->p);
+        job.task = build_task(ds->p, on, by, n_by, across, n_across);
+        job.footprint = footprint_bytes(*job.task, job.params);
+        if (job.footprint > s.budget)
+            fail(FABX_ENOMEM, "job footprint " + std::to_string(job.footprint) +
+                                  " bytes exceeds the server budget");
+        job.t_submit = Clock::now();
+        std::lock_guard<std::mutex> lk(s.mu);
+        if (s.stop) fail(FABX_ECANCELED, "server is stopping");
+        const uint64_t id = s.next_id++;
+        s.jobs.emplace(id, std::move(job));
+        s.queue.push_back(id);
+        ++s.submitted;
+        *job_id = id;
+        s.cv.notify_all();
+    });
+}
+
+static int server_result(ServerImpl &s, uint64_t id, fabx_result **out, bool wait) {
+    std::unique_lock<std::mutex> lk(s.mu);
+    auto it = s.jobs.find(id);
+    if (it == s.jobs.end()) {
+        set_last_error("unknown job id");
+        return FABX_ENOTFOUND;
+    }
+    if (wait)
+        s.cv.wait(lk, [&] {
+            auto st = s.jobs[id].state;
+            return st != JobState::Queued && st != JobState::Running;
+        });
+    Job &j = s.jobs[id];
+    switch (j.state) {
+        case JobState::Queued:
+        case JobState::Running:
+            set_last_error("job not finished");
+            return FABX_EAGAIN;
+        case JobState::Cancelled:
+            set_last_error("job was cancelled");
+            return FABX_ECANCELED;
+        case JobState::Failed:
+            set_last_error(j.msg);
+            return j.code;
+        case JobState::Done:
+            if (out) *out = new fabx_result{j.result};
+            set_last_error("");
+            return FABX_OK;
+    }
+    return FABX_EINVAL;
+}
+
+int fabx_server_poll(fabx_server *srv, uint64_t job_id, fabx_result **out) {
+    if (!srv) return FABX_EINVAL;
+    return server_result(*srv->p, job_id, out, false);
+}
+
+int fabx_server_wait(fabx_server *srv, uint64_t job_id, fabx_result **out) {
+    if (!srv) return FABX_EINVAL;
+    return server_result(*srv->p, job_id, out, true);
+}
+
+int fabx_server_cancel(fabx_server *srv, uint64_t job_id) {
+    if (!srv) return FABX_EINVAL;
+    ServerImpl &s = *srv->p;
+    std::lock_guard<std::mutex> lk(s.mu);
+    auto it = s.jobs.find(job_id);
+    if (it == s.jobs.end()) {
+        set_last_error("unknown job id");
+        return FABX_ENOTFOUND;
+    }
+    if (it->second.state != JobState::Queued) {
+        set_last_error("job already running or finished");
+        return FABX_EAGAIN;
+    }
+    s.queue.erase(std::find(s.queue.begin(), s.queue.end(), job_id));
+    it->second.state = JobState::Cancelled;
+    ++s.cancelled;
+    s.cv.notify_all();
+    return FABX_OK;
+}
+
+int fabx_server_stats_get(fabx_server *srv, fabx_server_stats *st) {
+    if (!srv || !st) return FABX_EINVAL;
+    ServerImpl &s = *srv->p;
+    std::lock_guard<std::mutex> lk(s.mu);
+    st->submitted = s.submitted;
+    st->completed = s.completed;
+    st->cancelled = s.cancelled;
+    st->failed = s.failed;
+    st->queued = int64_t(s.queue.size());
+    st->running = s.running;
+    st->hbm_in_use = s.in_use;
+    st->hbm_high_water = s.high_water;
+    std::vector<double> l = s.latencies_ms;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+        if (l.empty()) return 0.0;
+        size_t i = size_t(std::min<double>(double(l.size() - 1), std::ceil(q * double(l.size())) - 1));
+        return l[i];
+    };
+    st->p50_ms = pct(0.50);
+    st->p99_ms = pct(0.99);
+    return FABX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+"""Host-side tests of the C-ABI library (no GPU needed).
+
+* the shared library loads and exports every function include/fastabx.h declares;
+* a host-only context (device -1) builds tasks: the cells (keys, |A|, |B|, |X|,
+  |C|) equal the oracle's, on random tables and on the workload shapes;
+* argument errors return the documented status codes and set the message.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_2505_02692_amd as fx
+from paper_2505_02692_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fastabx.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fabx_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fx.lib()
+    names = _declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+    assert set(names) == set(L.SIGNATURES)          # the binding declares exactly the ABI
+    assert lib.fabx_version().decode().startswith("fastabx-hip")
+
+
+def _host_task(attrs, on, by, across, lengths=None):
+    ctx = fx.Context(-1)
+    n = attrs.shape[0]
+    lengths = np.ones(n, np.int64) if lengths is None else lengths
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(lengths)
+    ds = fx.Dataset(ctx, None, off, attrs)
+    return fx.Task(ds, on, by, across)
+
+
+def _compare_cells(attrs, on, by, across):
+    t = _host_task(attrs, on, by, across)
+    want = oracle.cells(attrs, on, by, across)
+    assert len(t) == len(want)
+    keys = t.keys
+    nt, abx = t.sizes
+    for k, c in enumerate(want):
+        assert tuple(keys[k]) == tuple(int(v) for v in c.key)
+        assert nt[k] == c.n_triplets
+        assert tuple(abx[k]) == (len(c.A), len(c.B), len(c.X))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_task_cells_match_oracle_random(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 120))
+    card = rng.integers(1, 6, size=5)
+    attrs = np.stack([rng.integers(-3, -3 + k, size=n) for k in card], axis=1).astype(np.int32)
+    specs = [(0, [], []), (0, [1], []), (0, [1, 2], []), (0, [1], [2]), (0, [], [1]),
+             (0, [], [1, 2]), (3, [0], [1, 2]), (4, [3, 2, 1], [0])]
+    on, by, across = specs[seed % len(specs)]
+    _compare_cells(attrs, on, by, across)
+
+
+def test_task_cells_match_oracle_wide_values():
+    rng = np.random.default_rng(99)
+    n = 300
+    # many distinct values per column: the composite key needs > 64 bits
+    attrs = np.stack([rng.integers(0, 3, size=n)] +
+                     [rng.integers(-2**30, 2**30, size=n) // (2**27) for _ in range(6)], axis=1).astype(np.int32)
+    _compare_cells(attrs, 0, [1, 2, 3], [4])
+
+
+@pytest.mark.parametrize("make", [
+    lambda: workloads.plain_c1(),
+    lambda: workloads.within_c2(n_items=3000, dim=8),
+    lambda: workloads.across_c3(n_items=3000, dim=8),
+    lambda: workloads.batched_c4(n_groups=40, dim=8, size_hi=60),
+])
+def test_task_cells_match_oracle_workloads(make):
+    w = make()
+    _compare_cells(w.attrs, w.on, w.by, w.across)
+
+
+def test_empty_task_is_valid():
+    attrs = np.zeros((6, 2), np.int32)
+    t = _host_task(attrs, 0, [1], [])
+    assert len(t) == 0
+
+
+@pytest.mark.parametrize("on,by,across", [(0, [0], []), (0, [1], [1]), (0, [7], []), (-1, [], []),
+                                          (0, [1, 2], [2])])
+def test_task_spec_errors(on, by, across):
+    attrs = np.zeros((6, 3), np.int32)
+    with pytest.raises(fx.FabxError) as e:
+        _host_task(attrs, on, by, across)
+    assert e.value.code == L.FABX_EINVAL
+    assert fx.lib().fabx_last_error().decode() != ""
+
+
+def test_dataset_errors():
+    ctx = fx.Context(-1)
+    attrs = np.zeros((3, 1), np.int32)
+    for off in ([0, 1, 1, 2], [1, 2, 3, 4], [0, 2, 1, 3]):       # empty item, bad start, decreasing
+        with pytest.raises(fx.FabxError) as e:
+            fx.Dataset(ctx, None, np.array(off), attrs)
+        assert e.value.code == L.FABX_EINVAL
+    with pytest.raises(fx.FabxError):
+        fx.fabx_dataset_create(ctx.h, None, L.FABX_DTYPE_F32, 3, 0, np.array([0, 1, 2, 3]), attrs)
+    with pytest.raises(fx.FabxError):
+        fx.fabx_dataset_create(ctx.h, None, 7, 3, 4, np.array([0, 1, 2, 3]), attrs)
+
+
+def test_bad_device_and_host_only_score():
+    with pytest.raises(fx.FabxError) as e:
+        fx.fabx_create(-5, None)
+    assert e.value.code == L.FABX_EINVAL
+    t = _host_task(np.array([[0], [0], [1]], np.int32), 0, [], [])
+    with pytest.raises(fx.FabxError) as e:
+        t.score()
+    assert e.value.code == L.FABX_EINVAL
+
+
+def test_bad_score_options():
+    t = _host_task(np.array([[0], [0], [1]], np.int32), 0, [], [])
+    o = fx.make_opts()
+    o.mode = 9
+    with pytest.raises(fx.FabxError) as e:
+        fx.fabx_score(t.h, o)
+    assert e.value.code == L.FABX_EINVAL
+    o = fx.make_opts()
+    o.distance = 3
+    with pytest.raises(fx.FabxError):
+        fx.fabx_score(t.h, o)
+
+
+def test_long_items_rejected_in_dtw_mode():
+    attrs = np.array([[0], [0], [1]], np.int32)
+    t = _host_task(attrs, 0, [], [], lengths=np.array([3, 65, 2]))
+    with pytest.raises(fx.FabxError) as e:
+        t.score(mode="dtw")
+    assert e.value.code == L.FABX_EINVAL
+
+
+def test_null_handles():
+    lib = fx.lib()
+    assert lib.fabx_task_num_cells(None) == -1
+    assert lib.fabx_score(None, None, None) == L.FABX_EINVAL
+    assert lib.fabx_collapse(None, None, None, 0, None) == L.FABX_EINVAL
+    assert lib.fabx_server_poll(None, 1, None) == L.FABX_EINVAL
+    lib.fabx_destroy(None)
+    lib.fabx_result_free(None)

@@ -1,0 +1,298 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars ("Parity"):
+* BF16 + FP64-recheck form: per-cell half-unit counts W equal the oracle's
+  exactly (near ties are re-decided in FP64), hence identical ABX error.
+* plain FP32 form: ABX error within 1e-4 absolute of the oracle, per-cell
+  mismatches reported (rare near-tie flips are expected).
+* per-pair distances: FP32 within 2e-6, BF16 (robust pairs) within the
+  stated margin / 3, FP64-rechecked pairs within 1e-12 of the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_2505_02692_amd as fx
+from paper_2505_02692_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+_CTX = {}
+
+
+def ctx():
+    if "c" not in _CTX:
+        _CTX["c"] = fx.Context(0)
+    return _CTX["c"]
+
+
+def gpu_score(w, **kw):
+    feats = w.features.to("cuda").contiguous()
+    ds = fx.Dataset(ctx(), feats, w.offsets, w.attrs)
+    t = fx.Task(ds, w.on, w.by, w.across)
+    res = t.score(**kw)
+    torch.cuda.synchronize()
+    return t, res
+
+
+def oracle_score(w, mode="dtw", norm="path"):
+    return oracle.score(w.features_f32_host(), w.offsets, w.attrs, w.on, w.by, w.across, mode, norm)
+
+
+def all_oracle_pairs(orc):
+    xs, ys, vs = [], [], []
+    for items, M in orc.groups.values():
+        i, j = np.nonzero(~np.isnan(M))
+        xs.append(items[i])
+        ys.append(items[j])
+        vs.append(M[i, j])
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(vs)
+
+
+def check(w, mode="dtw", precision="bf16", norm="path", exact=None, pair_tol=None, levels=True):
+    _say(f"{w.name} n_items={w.n_items} dim={w.dim} mode={mode} precision={precision} norm={norm}")
+    t, res = gpu_score(w, mode=mode, precision=precision, norm=norm, keep_pairs=True)
+    orc = oracle_score(w, mode, norm)
+    assert np.array_equal(t.keys, orc.keys.astype(np.int32))
+    nt, _ = t.sizes
+    assert np.array_equal(nt, orc.n_triplets)
+    exact = (precision == "bf16") if exact is None else exact
+    mism = int(np.count_nonzero(res.half_units != orc.half_units))
+    e_gpu, e_orc = res.collapse(), oracle.error_rate(orc)
+    xs, ys, want = all_oracle_pairs(orc)
+    f32, fl, f64 = res.pairs(xs, ys)
+    err = np.abs(f32.astype(np.float64) - want)
+    robust = (fl & 1) == 0
+    st = res.stats
+    print(f"  cells={st['n_cells']} triplets={st['n_triplets']} pairs={len(want)} mism={mism} "
+          f"max_pair_err={err[robust].max():.3g} p99={np.quantile(err[robust], 0.99):.3g} "
+          f"margin={st['margin']:.3g} delta={st['delta']:.3g} "
+          f"nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']} "
+          f"recount={st['n_recount_rows']} err={e_gpu:.6f} oracle_err={e_orc:.6f}", flush=True)
+    if exact:
+        assert mism == 0, f"{mism} cells differ"
+    assert abs(e_gpu - e_orc) <= (1e-12 if exact else 1e-4)
+    if levels and w.levels:
+        lg, lo = res.collapse(w.levels), oracle.error_rate(orc, w.levels)
+        assert abs(lg - lo) <= (1e-12 if exact else 1e-4)
+    if pair_tol is None:
+        # BF16: the recheck argument needs every robust pair within margin / 2
+        pair_tol = 2e-6 if precision == "fp32" else st["margin"] / 2
+    assert err[robust].max() <= pair_tol, f"max pair error {err[robust].max()}"
+    rechecked = (fl & 2) != 0
+    if rechecked.any():
+        assert np.abs(f64[rechecked] - want[rechecked]).max() <= 1e-12
+    return t, res, orc
+
+
+# ------------------------------------------------------------------ C1 --
+
+def test_c1_plain_fp32():
+    check(workloads.plain_c1(), precision="fp32", exact=True)
+
+
+def test_c1_bf16():
+    check(workloads.plain_c1())
+
+
+def test_c1_hard_bf16_exact():
+    check(workloads.plain_c1(centroid_std=0.15))
+
+
+def test_c1_hard_fp32():
+    check(workloads.plain_c1(centroid_std=0.15), precision="fp32")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_c1_hard_raw_cost(precision):
+    check(workloads.plain_c1(centroid_std=0.15, seed=5), precision=precision, norm="none",
+          pair_tol=(2e-5 if precision == "fp32" else 3e-3))
+
+
+# ------------------------------------------- C2 / C3 / C4 shaped, reduced --
+
+def test_within_c2_shape_bf16():
+    check(workloads.within_c2(n_items=4000, centroid_std=0.1))
+
+
+def test_within_c2_shape_fp32():
+    check(workloads.within_c2(n_items=4000, centroid_std=0.1), precision="fp32")
+
+
+def test_across_c3_shape_bf16():
+    check(workloads.across_c3(n_items=4000, centroid_std=0.1))
+
+
+def test_across_c3_shape_fp32():
+    check(workloads.across_c3(n_items=3000, centroid_std=0.1), precision="fp32")
+
+
+def test_batched_c4_shape_bf16():
+    # groups up to 150 items x up to 60 frames: many row / column blocks per group
+    check(workloads.batched_c4(n_groups=24, size_hi=150, centroid_std=0.3, seed=11))
+
+
+def test_batched_c4_shape_fp32():
+    check(workloads.batched_c4(n_groups=12, size_hi=90, centroid_std=0.3, seed=12), precision="fp32")
+
+
+# ---------------------------------------------------------------- pooled --
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_pooled_within(precision):
+    check(workloads.within_c2(n_items=4000, dim=512, centroid_std=0.05), mode="pooled",
+          precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_pooled_c4_shape(precision):
+    check(workloads.batched_c4(n_groups=30, size_hi=400, centroid_std=0.2, seed=13), mode="pooled",
+          precision=precision)
+
+
+# ------------------------------------------------------------ edge cases --
+
+@pytest.mark.parametrize("dim", [2, 33, 100, 130])
+def test_odd_dims(dim):
+    check(workloads.plain_c1(dim=dim, centroid_std=0.3, seed=dim))
+
+
+def test_single_frame_items_and_long_items():
+    w = workloads.batched_c4(n_groups=10, size_hi=70, len_lo=1, len_hi=64, dim=64, centroid_std=0.3,
+                             seed=21)
+    check(w)
+    w1 = workloads.batched_c4(n_groups=10, size_hi=70, len_lo=1, len_hi=1, dim=64, centroid_std=0.3,
+                              seed=22)
+    check(w1)
+    check(w1, precision="fp32")
+
+
+def test_exact_copies_tie_at_one_half():
+    _say("exact copies")
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((7, 40)).astype(np.float32)
+    xs = [rng.standard_normal((int(rng.integers(2, 9)), 40)).astype(np.float32) for _ in range(4)]
+    frames = [a, a.copy()] + xs
+    feats = torch.tensor(np.concatenate(frames))
+    off = np.zeros(len(frames) + 1, np.int64)
+    off[1:] = np.cumsum([len(f) for f in frames])
+    attrs = np.array([[0, 0], [1, 0], [0, 1], [0, 1], [0, 1], [0, 1]], np.int32)
+    w = workloads.Workload("copies", feats, off, attrs, ["label", "spk"], 0, [], [1])
+    for precision in ("fp32", "bf16"):
+        t, res = gpu_score(w, precision=precision)
+        k = [tuple(r) for r in t.keys].index((0, 1, 0, 1))
+        assert res.half_units[k] == res.n_triplets[k] == 4
+
+
+def test_zero_norm_frame_is_edomain():
+    _say("zero-norm frame / mean")
+    w = workloads.plain_c1(dim=16)
+    feats = w.features.clone()
+    feats[int(w.offsets[5]) + 1] = 0.0                       # one zero frame: DTW mode fails
+    w.features = feats
+    for precision in ("fp32", "bf16"):
+        with pytest.raises(fx.FabxError) as e:
+            gpu_score(w, mode="dtw", precision=precision)
+        assert e.value.code == L.FABX_EDOMAIN
+    feats = w.features.clone()
+    feats[int(w.offsets[7]):int(w.offsets[8])] = 0.0         # a whole item zero: its mean is zero
+    w.features = feats
+    with pytest.raises(fx.FabxError) as e:
+        gpu_score(w, mode="pooled", precision="bf16")
+    assert e.value.code == L.FABX_EDOMAIN
+
+
+def test_empty_task_scores():
+    _say("empty task")
+    w = workloads.plain_c1(dim=8)
+    w.attrs = np.zeros_like(w.attrs)        # one ON value: no cell
+    t, res = gpu_score(w)
+    assert len(t) == 0 and res.half_units.size == 0
+    with pytest.raises(fx.FabxError):
+        res.collapse()
+
+
+def test_collapse_level_errors():
+    _say("collapse levels")
+    w = workloads.within_c2(n_items=1500, dim=64, centroid_std=0.1)
+    t, res = gpu_score(w, precision="fp32")
+    with pytest.raises(fx.FabxError):
+        res.collapse([[0]])                  # the ON attribute
+    with pytest.raises(fx.FabxError):
+        res.collapse([[9]])
+
+
+def test_repeat_is_bitwise_deterministic():
+    _say("determinism")
+    w = workloads.within_c2(n_items=3000, dim=256, centroid_std=0.08, seed=31)
+    feats = w.features.to("cuda")
+    ds = fx.Dataset(ctx(), feats, w.offsets, w.attrs)
+    t = fx.Task(ds, w.on, w.by, w.across)
+    r1 = t.score(keep_pairs=True)
+    r2 = t.score(keep_pairs=True)
+    r3 = fx.Task(ds, w.on, w.by, w.across).score(keep_pairs=True)
+    assert np.array_equal(r1.half_units, r2.half_units) and np.array_equal(r1.half_units, r3.half_units)
+    # pair distances of the first group, bitwise
+    keys = t.keys
+    g = tuple(keys[0][2:])
+    items = np.nonzero(np.all(w.attrs[:, w.by] == np.array(g), axis=1))[0]
+    xs, ys = np.repeat(items, len(items)), np.tile(items, len(items))
+    a, b, c = r1.pairs(xs, ys), r2.pairs(xs, ys), r3.pairs(xs, ys)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b)) and all(np.array_equal(u, v) for u, v in zip(a, c))
+    assert r1.stats["ms_total"] > 0
+
+
+# ---------------------------------------------------------------- server --
+
+def test_server_alone_equals_mix():
+    _say("server alone vs mix")
+    jobs = [workloads.serving_job(j, n_items=int(n), dim=d, across=a, centroid_std=0.1)
+            for j, (n, d, a) in enumerate([(1200, 256, False), (2500, 512, True), (800, 1280, False),
+                                           (3000, 768, True), (1500, 1024, False)])]
+    dsets = []
+    alone = []
+    for w in jobs:
+        feats = w.features.to("cuda")
+        ds = fx.Dataset(ctx(), feats, w.offsets, w.attrs)
+        dsets.append((ds, w))
+        t = fx.Task(ds, w.on, w.by, w.across)
+        r = t.score()
+        alone.append((t.keys.copy(), r.half_units.copy()))
+    srv = fx.Server(ctx(), hbm_budget_bytes=8 << 30, n_streams=3)
+    ids = [srv.submit(ds, w.on, w.by, w.across) for ds, w in dsets]
+    for (keys, W), jid in zip(alone, ids):
+        k2, w2, n2, s2 = srv.wait(jid)
+        assert np.array_equal(keys, k2) and np.array_equal(W, w2)
+    st = srv.stats
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    assert st["hbm_high_water"] <= 8 << 30
+    srv.close()
+
+
+def test_server_rejects_oversized_job():
+    _say("server admission")
+    w = workloads.serving_job(0, n_items=2000, dim=256, across=False)
+    ds = fx.Dataset(ctx(), w.features.to("cuda"), w.offsets, w.attrs)
+    srv = fx.Server(ctx(), hbm_budget_bytes=1 << 20, n_streams=1)
+    with pytest.raises(fx.FabxError) as e:
+        srv.submit(ds, w.on, w.by, w.across)
+    assert e.value.code == -2
+    srv.close()
+
+
+# ----------------------------------------------- full-size bench workload --
+
+def test_within_c2_full_size_bf16():
+    """The bench workload at full size (100k items, dim 768): every cell exact."""
+    w = workloads.within_c2(device="cuda")
+    check(w, levels=True)
