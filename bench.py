@@ -1,0 +1,252 @@
+"""Benchmark of the ABX hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload: the within-speaker triphone-like task at full size (100k items,
+40 labels, BY prev / next / speaker, lengths 5-25 frames, dim 768, FP32
+features resident in HBM).  One step = the whole hot path on it: build the
+task (cells), score every cell (normalise -> frame distances -> DTW ->
+triplet comparison -> FP64 recheck -> per-cell counts on the host) and
+collapse to the ABX error rate.  `value` is triplets per second of the
+BF16-MFMA + FP64-recheck form; the plain FP32 form is timed beside it on the
+same data.  A short serving stream (jobs of 1k-50k items, dims 256-1280,
+within / across, Poisson arrivals) reports p50 / p99 job latency.
+
+Prints one JSON line ("Measurement").
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _stage_means(results):
+    keys = ["ms_total", "ms_normalize", "ms_distance", "ms_triplets", "ms_recheck"]
+    return {k: float(np.mean([r[k] for r in results])) for k in keys}
+
+
+def run_steps(fx, ds, w, precision, n, sync):
+    stats, errs = [], []
+    t0 = time.perf_counter()
+    for _ in range(n):
+        task = fx.Task(ds, w.on, w.by, w.across)
+        res = task.score(mode="dtw", precision=precision)
+        errs.append(res.collapse(w.levels))
+        stats.append(res.stats)
+    sync()
+    return time.perf_counter() - t0, stats, errs
+
+
+def serving_stream(fx, ctx, torch, workloads, n_jobs, seed=4):
+    """Poisson arrivals at 0.7 x the alone service rate; p50 / p99 of completion - arrival."""
+    jobs = []
+    for j in range(n_jobs):
+        w = workloads.serving_job(j, seed=seed, device="cuda")
+        ds = fx.Dataset(ctx, w.features, w.offsets, w.attrs)
+        jobs.append((w, ds))
+    log(f"serving: {n_jobs} jobs generated")
+    # alone service time of each job (also its reference result)
+    alone_ms, ref = [], []
+    for w, ds in jobs:
+        t0 = time.perf_counter()
+        r = fx.Task(ds, w.on, w.by, w.across).score()
+        alone_ms.append((time.perf_counter() - t0) * 1e3)
+        ref.append(r.half_units.copy())
+        st = r.stats
+        log(f"serving: alone {w.name} n={w.n_items} dim={w.dim} cells={len(r.half_units)} "
+            f"{alone_ms[-1]:.1f} ms  gpu {st['ms_total']:.1f} ms (dist {st['ms_distance']:.1f}, "
+            f"trip {st['ms_triplets']:.1f}, recheck {st['ms_recheck']:.1f}) nonrobust={st['n_nonrobust_pairs']} "
+            f"recheck_pairs={st['n_recheck_pairs']} recount_rows={st['n_recount_rows']} pairs={st['n_pairs']}")
+    mean_s = float(np.mean(alone_ms)) / 1e3
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(mean_s / 0.7, size=n_jobs)
+    srv = fx.Server(ctx, hbm_budget_bytes=96 << 30, n_streams=4)
+    start = time.perf_counter()
+    ids = []
+    t_next = start
+    for (w, ds), g in zip(jobs, gaps):
+        t_next += g
+        while time.perf_counter() < t_next:
+            time.sleep(0.0002)
+        ids.append(srv.submit(ds, w.on, w.by, w.across))
+    triplets = 0
+    same = True
+    log("serving: all jobs submitted")
+    for jid, rw in zip(ids, ref):
+        keys, W, n, s = srv.wait(jid)
+        triplets += int(n.sum())
+        same = same and np.array_equal(W, rw)
+    wall = time.perf_counter() - start
+    st = srv.stats
+    srv.close()
+    return {"jobs": n_jobs, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "triplets_per_s": triplets / wall, "hbm_high_water_bytes": st["hbm_high_water"],
+            "alone_mean_ms": float(np.mean(alone_ms)), "arrival_rate_per_s": 0.7 / mean_s,
+            "results_equal_alone": bool(same)}
+
+
+def cpu_baseline(oracle, w, max_seconds=30.0):
+    """The FP64 oracle on the host cores: whole BY groups of the same workload, in
+    group order, until about `max_seconds` of oracle work have been sampled."""
+    feats = w.features_f32_host()
+    cells = oracle.cells(w.attrs, w.on, w.by, w.across)
+    # estimated oracle cost per group ~ sum of frame pairs; take groups until the budget
+    groups = []
+    seen = set()
+    for c in cells:
+        if c.by_key not in seen:
+            seen.add(c.by_key)
+            groups.append(c.by_key)
+    log(f"cpu baseline: {len(cells)} cells in {len(groups)} groups")
+    # calibrate on a small prefix, then size the sample
+    probe = set(groups[: max(1, len(groups) // 50)])
+    t0 = time.perf_counter()
+    r = oracle.score(feats, w.offsets, w.attrs, w.on, w.by, w.across,
+                     cell_filter=lambda c: c.by_key in probe)
+    t_probe = time.perf_counter() - t0
+    log(f"cpu baseline: probe of {len(probe)} groups took {t_probe:.1f} s")
+    frac = min(1.0, (len(probe) / len(groups)) * max_seconds / max(t_probe, 1e-3))
+    take = set(groups[: max(1, int(len(groups) * frac))])
+    t0 = time.perf_counter()
+    r = oracle.score(feats, w.offsets, w.attrs, w.on, w.by, w.across,
+                     cell_filter=lambda c: c.by_key in take)
+    dt = time.perf_counter() - t0
+    n_trip = int(r.n_triplets.sum())
+    return {"value": n_trip / dt, "unit": "triplets/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(take)} of {len(groups)} BY groups ({len(r.cells)} cells, {n_trip} triplets) "
+                      f"of the same workload, FP64 DTW + scoring, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--serve-jobs", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the ABX hot path here is "
+              "single-GPU; see DESIGN.md for how it would shard across GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_2505_02692_amd as fx
+
+    fx.lib()  # fail loudly if the native library is missing
+    torch.cuda.set_device(0)
+    sync = torch.cuda.synchronize
+    if args.serving_only:
+        print(json.dumps({"serving": serving_stream(fx, fx.Context(0), torch, workloads, args.serve_jobs)}))
+        return
+    w = workloads.within_c2(device="cuda")
+    ctx = fx.Context(0)
+    ds = fx.Dataset(ctx, w.features, w.offsets, w.attrs)
+    log(f"workload ready: {w.n_items} items, {w.n_frames} frames, dim {w.dim}")
+
+    run_steps(fx, ds, w, "bf16", args.warmup, sync)
+    sync()
+    log("warmup done")
+    dt, stats, errs = run_steps(fx, ds, w, "bf16", args.steps, sync)
+    log(f"bf16 form: {dt / args.steps * 1e3:.2f} ms/step, stages {_stage_means(stats)}")
+    st0 = stats[-1]
+    ms_step = dt / args.steps * 1e3
+    n_trip = st0["n_triplets"]
+    value = n_trip / (ms_step / 1e3)
+    stages = _stage_means(stats)
+    t_build = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fx.Task(ds, w.on, w.by, w.across)
+        t_build.append((time.perf_counter() - t0) * 1e3)
+
+    plain = None
+    if not args.no_plain:
+        run_steps(fx, ds, w, "fp32", 1, sync)
+        pdt, pstats, perrs = run_steps(fx, ds, w, "fp32", args.steps, sync)
+        pms = pdt / args.steps * 1e3
+        pst = _stage_means(pstats)
+        log(f"fp32 form: {pms:.2f} ms/step, stages {pst}")
+        plain = {"triplets_per_s": n_trip / (pms / 1e3), "ms_per_step": pms,
+                 "gcups": pstats[-1]["dtw_cells"] / (pms / 1e3) / 1e9,
+                 "gpu_ms": pst["ms_total"], "gpu_triplets_per_s": n_trip / (pst["ms_total"] / 1e3),
+                 "abx_error": perrs[-1], "stages_ms": pst}
+
+    # roofline of the dominant kernel, from the live HIP-event stage times
+    dim, dim_pad = w.dim, (w.dim + 63) // 64 * 64
+    nf = st0["n_frames"]
+    norm_bytes = nf * dim * 4 + nf * dim_pad * 2 + nf * 4
+    dist_flops = 2.0 * dim * st0["dtw_cells"]
+    if stages["ms_normalize"] >= stages["ms_distance"]:
+        ach = norm_bytes / (stages["ms_normalize"] / 1e3) / 1e9
+        roof = {"kernel": "k_normalize", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes_per_launch": norm_bytes}
+    else:
+        ach = dist_flops / (stages["ms_distance"] / 1e3) / 1e12
+        roof = {"kernel": "k_fused", "bound": "mfma", "achieved": ach, "peak": MFMA_BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": dist_flops}
+
+    serving = None
+    if args.serve_jobs > 0:
+        serving = serving_stream(fx, ctx, torch, workloads, args.serve_jobs)
+        log(f"serving: {serving}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cpu = cpu_baseline(oracle, w)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "ABX triplets/s (BF16 MFMA + FP64 recheck form)",
+        "value": value,
+        "unit": "triplets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded Gaussian SSL-like features, see DESIGN.md)",
+        "config": {"workload": "within-speaker triphone task: 100k items, 40 labels, BY prev/next/speaker, "
+                               "lengths 5-25 (median 9), dim 768 fp32, DTW, path-normalised angular",
+                   "cells": st0["n_cells"], "triplets": n_trip, "dtw_cells": st0["dtw_cells"],
+                   "parallelism": "single GPU"},
+        "gcups": st0["dtw_cells"] / (ms_step / 1e3) / 1e9,
+        "gpu_ms": stages["ms_total"],
+        "gpu_triplets_per_s": n_trip / (stages["ms_total"] / 1e3),
+        "task_build_ms": float(np.median(t_build)),
+        "stages_ms": stages,
+        "abx_error": errs[-1],
+        "recheck_pairs": st0["n_recheck_pairs"], "nonrobust_pairs": st0["n_nonrobust_pairs"],
+        "plain_fp32": plain,
+        "roofline": roof,
+        "serving": serving,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -252,7 +252,7 @@ class Context:
         self.h = fabx_create(device, s)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
             fabx_destroy(self.h)
             self.h = None
 
@@ -276,7 +276,7 @@ class Dataset:
         self.h = fabx_dataset_create(ctx.h, ptr, dtype, nf, dim, offsets, attrs)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
             fabx_dataset_destroy(self.h)
             self.h = None
 
@@ -302,7 +302,7 @@ class Task:
         return Result(self, fabx_score(self.h, make_opts(**kw)))
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
             fabx_task_destroy(self.h)
             self.h = None
 
@@ -324,7 +324,7 @@ class Result:
         return fabx_collapse(self.h, levels)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
             fabx_result_free(self.h)
             self.h = None
 

@@ -15,8 +15,66 @@ const char *last_error_cstr() { return g_last_error.c_str(); }
 
 [[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
+static void *raw_alloc(size_t n) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void *Pool::alloc(size_t n, size_t *got) {
+    n = (n + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);  // 2 MiB granules
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        // best fit among free blocks no larger than twice the request
+        size_t best = free_blocks.size();
+        for (size_t i = 0; i < free_blocks.size(); ++i)
+            if (free_blocks[i].first >= n && free_blocks[i].first <= 2 * n &&
+                (best == free_blocks.size() || free_blocks[i].first < free_blocks[best].first))
+                best = i;
+        if (best != free_blocks.size()) {
+            auto b = free_blocks[best];
+            free_blocks.erase(free_blocks.begin() + long(best));
+            *got = b.first;
+            return b.second;
+        }
+    }
+    void *p = raw_alloc(n);
+    if (!p) {
+        trim();  // give cached blocks back and try once more
+        p = raw_alloc(n);
+    }
+    if (!p) fail(FABX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+    std::lock_guard<std::mutex> lk(mu);
+    held += n;
+    *got = n;
+    return p;
+}
+
+void Pool::free(void *p, size_t n) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_blocks.push_back({n, p});
+}
+
+void Pool::trim() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &b : free_blocks) {
+        (void)hipFree(b.second);
+        held -= b.first;
+    }
+    free_blocks.clear();
+}
+
+Pool::~Pool() { trim(); }
+
 void DevBuf::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        if (pool) pool->free(ptr, bytes);
+        else (void)hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
 }
@@ -25,17 +83,18 @@ void DevBuf::ensure(size_t n) {
     if (n <= bytes && ptr) return;
     release();
     if (n == 0) n = 16;
-    hipError_t e = hipMalloc(&ptr, n);
-    if (e != hipSuccess) {
-        ptr = nullptr;
-        (void)hipGetLastError();
-        fail(FABX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+    if (pool) {
+        ptr = pool->alloc(n, &bytes);
+        return;
     }
+    ptr = raw_alloc(n);
+    if (!ptr) fail(FABX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
     bytes = n;
 }
 
 CtxImpl::~CtxImpl() {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+    pool.trim();
 }
 
 // Runs `f`, converting internal errors into status codes.

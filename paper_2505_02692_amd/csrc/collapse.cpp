@@ -2,8 +2,11 @@
 // overall discriminability D is a weighted average over cells; the phoneme
 // task averages over contexts, then speakers, then phonemes; Score.collapse
 // offers cell-size weighting or averaging level by level).  FP64 on the host.
+//
+// Level by level: the rows (key tuple, score) are sorted by the key columns
+// that remain after removing the level's attributes, equal runs are averaged
+// (unweighted), and the averaged rows carry on to the next level.
 #include <algorithm>
-#include <map>
 #include <numeric>
 
 #include "internal.h"
@@ -41,38 +44,55 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
         levels.push_back(lv);
     }
     const int K = t.key_width;
-    // rows: remaining key columns -> mean score
+    // current rows: keys [m x width] (width = cols.size()), scores [m]
     std::vector<int> cols(static_cast<size_t>(K));
     std::iota(cols.begin(), cols.end(), 0);
-    std::map<std::vector<int32_t>, double> rows;
-    for (size_t i = 0; i < n; ++i) {
-        std::vector<int32_t> k(t.keys.begin() + int64_t(i) * K, t.keys.begin() + int64_t(i + 1) * K);
-        rows[k] = double(res.half_units[i]) / (2.0 * double(t.n_triplets[i]));
-    }
+    std::vector<int32_t> keys = t.keys;
+    std::vector<double> score(n);
+    for (size_t i = 0; i < n; ++i) score[i] = double(res.half_units[i]) / (2.0 * double(t.n_triplets[i]));
+    size_t width = size_t(K);
     for (const auto &lv : levels) {
-        std::vector<int> keep_pos;  // positions (in the current key) of kept columns
-        std::vector<int> kept;
+        std::vector<size_t> keep;  // positions (in the current key) of the kept columns
+        std::vector<int> kept_cols;
         for (size_t p = 0; p < cols.size(); ++p)
             if (std::find(lv.begin(), lv.end(), t.key_attr[size_t(cols[p])]) == lv.end()) {
-                keep_pos.push_back(int(p));
-                kept.push_back(cols[p]);
+                keep.push_back(p);
+                kept_cols.push_back(cols[p]);
             }
-        std::map<std::vector<int32_t>, std::pair<double, int64_t>> acc;
-        for (const auto &kv : rows) {
-            std::vector<int32_t> k;
-            k.reserve(keep_pos.size());
-            for (int p : keep_pos) k.push_back(kv.first[size_t(p)]);
-            auto &a = acc[k];
-            a.first += kv.second;
-            a.second += 1;
+        const size_t m = score.size();
+        std::vector<size_t> idx(m);
+        std::iota(idx.begin(), idx.end(), size_t(0));
+        auto less = [&](size_t a, size_t b) {
+            for (size_t p : keep) {
+                const int32_t x = keys[a * width + p], y = keys[b * width + p];
+                if (x != y) return x < y;
+            }
+            return a < b;
+        };
+        auto same = [&](size_t a, size_t b) {
+            for (size_t p : keep)
+                if (keys[a * width + p] != keys[b * width + p]) return false;
+            return true;
+        };
+        std::sort(idx.begin(), idx.end(), less);
+        std::vector<int32_t> nkeys;
+        std::vector<double> nscore;
+        for (size_t i = 0; i < m;) {
+            size_t j = i;
+            double s = 0.0;
+            while (j < m && same(idx[i], idx[j])) s += score[idx[j++]];
+            for (size_t p : keep) nkeys.push_back(keys[idx[i] * width + p]);
+            nscore.push_back(s / double(j - i));
+            i = j;
         }
-        rows.clear();
-        for (auto &kv : acc) rows[kv.first] = kv.second.first / double(kv.second.second);
-        cols = kept;
+        keys.swap(nkeys);
+        score.swap(nscore);
+        cols = kept_cols;
+        width = keep.size();
     }
     double s = 0.0;
-    for (auto &kv : rows) s += kv.second;
-    return 1.0 - s / double(rows.size());
+    for (double v : score) s += v;
+    return 1.0 - s / double(score.size());
 }
 
 }  // namespace fabx

@@ -31,10 +31,24 @@ void set_last_error(const std::string &msg);
             ::fabx::fail(FABX_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
     } while (0)
 
-// Grow-only device buffer.
+// Caching device allocator of one context: freed blocks are kept and handed
+// out again to later requests of a similar size, so scoring a new task does
+// not go back to hipMalloc for its (multi-GB) workspace.  Thread-safe.
+struct Pool {
+    std::mutex mu;
+    std::vector<std::pair<size_t, void *>> free_blocks;  // (bytes, ptr)
+    size_t held = 0;                                     // bytes owned (free + in use)
+    void *alloc(size_t n, size_t *got);
+    void free(void *p, size_t n);
+    void trim();  // return every free block to the runtime
+    ~Pool();
+};
+
+// Grow-only device buffer (from a context pool when one is attached).
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    Pool *pool = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -51,6 +65,7 @@ struct CtxImpl {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int n_cu = 0;
+    Pool pool;
     ~CtxImpl();
 };
 

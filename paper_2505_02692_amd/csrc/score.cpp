@@ -202,6 +202,12 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
 
     // ---- device tables (items / groups / cells are fixed for the task)
     TaskDevice &dv = t.dev;
+    for (DevBuf *b : {&dv.item_src, &dv.item_len, &dv.item_dst, &dv.item_group, &dv.g_item0, &dv.g_n,
+                      &dv.g_frame0, &dv.g_nframes, &dv.g_pair_base, &dv.g_dmat_base, &dv.cells})
+        if (!b->ptr) b->pool = &ds.ctx->pool;
+    for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
+                      &t.ws.half_units, &t.ws.counters, &t.ws.recheck_list, &t.ws.recount_list})
+        if (!b->ptr) b->pool = &ds.ctx->pool;
     if (!dv.uploaded) {
         upload(dv.item_src, t.item_src, stream);
         upload(dv.item_len, t.item_len, stream);
@@ -229,6 +235,8 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
         dv.uploaded = true;
     }
     DevBuf units_d, tiles_d, rb_d, cb_d, up_d, grb_d, gcb_d, gncb_d;
+    Pool *pool = &ds.ctx->pool;
+    for (DevBuf *b : {&units_d, &tiles_d, &rb_d, &cb_d, &up_d, &grb_d, &gcb_d, &gncb_d}) b->pool = pool;
     upload(units_d, pl.units, stream);
     if (!pl.tiles_prefix.empty()) upload(tiles_d, pl.tiles_prefix, stream);
     if (!pl.unit_prefix.empty()) {
@@ -273,13 +281,15 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     FABX_HIP(hipMemsetAsync(ws.counters.ptr, 0, 64, stream));
     FABX_HIP(hipMemsetAsync(err_item, 0xFF, 8, stream));
     FABX_HIP(hipMemsetAsync(ws.half_units.ptr, 0, size_t(n_cells) * 8, stream));
+    if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(ws.flags.ptr, 0, size_t(t.n_pair_slots), stream));
+    tm.mark();  // 1
     if (dtw)
         kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, bf16 ? 1 : 0,
                         ws.rinv.as<float>(), err, err_item);
     else
         kern::pool_normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, bf16 ? 1 : 0,
                              ws.rinv.as<float>(), err, err_item);
-    tm.mark();  // 1
+    tm.mark();  // 2
     if (dtw && !bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.frame0, gt.n_frames, gt.dmat_base,
                                tiles_d.as<int64_t>(), G, pl.tiles_prefix.back(), ws.dmat.as<float>());
@@ -296,17 +306,16 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.item0, gt.n_items, gt.pair_base,
                                tiles_d.as<int64_t>(), G, pl.tiles_prefix.back(), ws.p32.as<float>());
     } else {
-        FABX_HIP(hipMemsetAsync(ws.flags.ptr, 0, size_t(t.n_pair_slots), stream));
         kern::gram_angular_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt.item0,
                                 gt.n_items, gt.pair_base, tiles_d.as<int64_t>(), G,
                                 pl.tiles_prefix.back(), ws.p32.as<float>());
     }
-    tm.mark();  // 2
+    tm.mark();  // 3
     kern::triplets(stream, dv.cells.as<CellDev>(), units_d.as<int32_t>(), n_units, gt,
                    ws.p32.as<float>(), ws.half_units.as<unsigned long long>(),
                    bf16 ? ws.flags.as<uint8_t>() : nullptr, float(p.margin),
                    bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, pl.sum_nx);
-    tm.mark();  // 3
+    tm.mark();  // 4
     if (bf16) {
         kern::collect_marked(stream, ws.flags.as<uint8_t>(), t.n_pair_slots, ws.recheck_list.as<int64_t>(),
                              marked_n, t.n_pair_slots);
@@ -316,12 +325,12 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
                       gt, ws.p32.as<float>(), ws.p64.as<double>(), ws.flags.as<uint8_t>(),
                       ws.half_units.as<unsigned long long>());
     }
-    tm.mark();  // 4
+    tm.mark();  // 5
     unsigned char counters[64];
     FABX_HIP(hipMemcpyAsync(res->half_units.data(), ws.half_units.ptr, size_t(n_cells) * 8,
                             hipMemcpyDeviceToHost, stream));
     FABX_HIP(hipMemcpyAsync(counters, ws.counters.ptr, 64, hipMemcpyDeviceToHost, stream));
-    tm.mark();  // 5
+    tm.mark();  // 6
     FABX_HIP(hipStreamSynchronize(stream));
     int err_h;
     unsigned long long err_item_h;
@@ -336,11 +345,11 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
         fail(FABX_EDOMAIN, "zero-norm " + std::string(dtw ? "frame" : "mean") + " in item " +
                                std::to_string(bad) + ": its angle is undefined");
     }
-    st.ms_normalize = tm.ms(0, 1);
-    st.ms_distance = tm.ms(1, 2);
-    st.ms_triplets = tm.ms(2, 3);
-    st.ms_recheck = tm.ms(3, 4);
-    st.ms_total = tm.ms(0, 5);
+    st.ms_normalize = tm.ms(1, 2);
+    st.ms_distance = tm.ms(2, 3);
+    st.ms_triplets = tm.ms(3, 4);
+    st.ms_recheck = tm.ms(4, 5);
+    st.ms_total = tm.ms(0, 6);
     st.n_recheck_pairs = marked_h;
     st.n_recount_rows = recount_h;
     st.n_nonrobust_pairs = nonrobust_h;

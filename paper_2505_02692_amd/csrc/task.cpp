@@ -6,8 +6,11 @@
 // (by..., on, across...) with an LSD radix sort, so every BY group and every
 // class is a contiguous run; a cell is then three runs (A, B, X).
 #include <algorithm>
+#include <climits>
 #include <cstring>
+#include <functional>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -23,32 +26,56 @@ struct RankedColumn {
 RankedColumn rank_column(const DatasetImpl &ds, int col) {
     RankedColumn rc;
     const int64_t n = ds.n_items;
-    rc.values.resize(n);
-    for (int64_t i = 0; i < n; ++i) rc.values[i] = ds.attrs[i * ds.n_attr + col];
-    std::vector<int32_t> raw = rc.values;
-    std::sort(rc.values.begin(), rc.values.end());
-    rc.values.erase(std::unique(rc.values.begin(), rc.values.end()), rc.values.end());
     rc.rank.resize(n);
-    for (int64_t i = 0; i < n; ++i)
-        rc.rank[i] = uint32_t(std::lower_bound(rc.values.begin(), rc.values.end(), raw[i]) -
-                              rc.values.begin());
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t v = ds.attrs[i * ds.n_attr + col];
+        mn = std::min(mn, v);
+        mx = std::max(mx, v);
+    }
+    const int64_t range = int64_t(mx) - int64_t(mn) + 1;
+    if (range <= std::max<int64_t>(4 * n, 1 << 16)) {
+        // dense value range: rank by a direct table
+        std::vector<int32_t> table(size_t(range), -1);
+        for (int64_t i = 0; i < n; ++i) table[size_t(ds.attrs[i * ds.n_attr + col] - int64_t(mn))] = 0;
+        int32_t r = 0;
+        for (int64_t v = 0; v < range; ++v)
+            if (table[size_t(v)] == 0) {
+                table[size_t(v)] = r++;
+                rc.values.push_back(int32_t(v + mn));
+            }
+        for (int64_t i = 0; i < n; ++i)
+            rc.rank[i] = uint32_t(table[size_t(ds.attrs[i * ds.n_attr + col] - int64_t(mn))]);
+    } else {
+        rc.values.resize(n);
+        for (int64_t i = 0; i < n; ++i) rc.values[i] = ds.attrs[i * ds.n_attr + col];
+        std::sort(rc.values.begin(), rc.values.end());
+        rc.values.erase(std::unique(rc.values.begin(), rc.values.end()), rc.values.end());
+        for (int64_t i = 0; i < n; ++i)
+            rc.rank[i] = uint32_t(std::lower_bound(rc.values.begin(), rc.values.end(),
+                                                   ds.attrs[i * ds.n_attr + col]) -
+                                  rc.values.begin());
+    }
     uint64_t u = rc.values.size();
     while ((uint64_t(1) << rc.bits) < u) ++rc.bits;
     return rc;
 }
 
-// Stable LSD radix sort of items by a 64-bit key (8-bit digits, only the
+// Stable LSD radix sort of items by a 64-bit key (12-bit digits, only the
 // digits the key uses).  Ties keep ascending item order.
 void radix_sort(std::vector<uint64_t> &key, std::vector<int64_t> &idx, int key_bits) {
+    constexpr int kDigit = 12;
+    constexpr size_t kBuckets = size_t(1) << kDigit;
     const size_t n = key.size();
     std::vector<uint64_t> k2(n);
     std::vector<int64_t> i2(n);
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        size_t count[257] = {0};
-        for (size_t i = 0; i < n; ++i) ++count[((key[i] >> shift) & 0xFF) + 1];
-        for (int b = 0; b < 256; ++b) count[b + 1] += count[b];
+    std::vector<size_t> count(kBuckets + 1);
+    for (int shift = 0; shift < key_bits; shift += kDigit) {
+        std::fill(count.begin(), count.end(), 0);
+        for (size_t i = 0; i < n; ++i) ++count[((key[i] >> shift) & (kBuckets - 1)) + 1];
+        for (size_t b = 0; b < kBuckets; ++b) count[b + 1] += count[b];
         for (size_t i = 0; i < n; ++i) {
-            size_t d = count[(key[i] >> shift) & 0xFF]++;
+            size_t d = count[(key[i] >> shift) & (kBuckets - 1)]++;
             k2[d] = key[i];
             i2[d] = idx[i];
         }
@@ -63,6 +90,185 @@ struct ClassRun {
     uint32_t on_rank;
     int64_t first;      // one item of the class (for its ACROSS ranks)
 };
+
+
+template <typename F>
+void parallel_for(int n, F &&f) {
+    if (n <= 1) {
+        if (n == 1) f(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(size_t(n - 1));
+    for (int k = 1; k < n; ++k) th.emplace_back([&f, k] { f(k); });
+    f(0);
+    for (auto &x : th) x.join();
+}
+
+// Output of one thread's share of the group walk (group ids and pair-slot
+// bases local to the share; stitched together afterwards).
+struct WalkOut {
+    std::vector<CellDev> cells;
+    std::vector<int64_t> ntrip;
+    std::vector<int32_t> keys;
+    std::vector<Group> groups;
+    std::vector<std::pair<int64_t, int64_t>> kept;  // sorted-order range of each kept group
+    int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, pair_slots = 0;
+    void swap(WalkOut &o) {
+        cells.swap(o.cells);
+        ntrip.swap(o.ntrip);
+        keys.swap(o.keys);
+        groups.swap(o.groups);
+        kept.swap(o.kept);
+    }
+};
+
+struct WalkCtx {
+    const DatasetImpl *ds;
+    const TaskImpl *t;
+    const std::vector<int64_t> *order;
+    const std::vector<uint64_t> *by_part, *cls_part;
+    const std::vector<uint32_t> *on_rank;
+    const std::vector<int64_t> *pf, *pq;
+    int32_t on;
+    int32_t n_across;
+    std::function<int(int64_t, int64_t)> across_cmp;
+    std::function<bool(int64_t, int64_t)> across_all_differ;
+};
+
+// Cells of the groups that start in sorted positions [s_begin, s_end).
+void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, WalkOut &out) {
+    const auto &order = *w.order;
+    const auto &by_part = *w.by_part;
+    const auto &cls_part = *w.cls_part;
+    const auto &pf = *w.pf;
+    const auto &pq = *w.pq;
+    const int32_t *A = w.ds->attrs.data();
+    const int NA = w.ds->n_attr;
+    const TaskImpl &t = *w.t;
+    std::vector<ClassRun> cls;
+    std::vector<uint8_t> need;
+    std::vector<std::pair<int64_t, int64_t>> need_list, runs;
+    int64_t g0 = s_begin;
+    while (g0 < s_end) {
+        int64_t g1 = g0 + 1;
+        while (g1 < s_end && by_part[g1] == by_part[g0]) ++g1;
+        cls.clear();
+        for (int64_t s = g0; s < g1;) {
+            int64_t e = s + 1;
+            while (e < g1 && cls_part[e] == cls_part[s]) ++e;
+            cls.push_back({s, e - s, (*w.on_rank)[order[s]], order[s]});
+            s = e;
+        }
+        const int64_t K = int64_t(cls.size());
+        const int32_t group_id = int32_t(out.groups.size());
+        const size_t cells_before = out.cells.size();
+        const bool use_need = w.n_across > 0 && K <= 8192;
+        if (use_need) need.assign(size_t(K * K), 0);
+        need_list.clear();
+        auto add_cell = [&](int64_t ia, int64_t ib, int64_t ix, bool excl) {
+            CellDev c;
+            c.group = group_id;
+            c.a0 = int32_t(cls[ia].start - g0);
+            c.na = int32_t(cls[ia].count);
+            c.b0 = int32_t(cls[ib].start - g0);
+            c.nb = int32_t(cls[ib].count);
+            c.x0 = int32_t(cls[ix].start - g0);
+            c.nx = int32_t(cls[ix].count);
+            c.exclude_self = excl ? 1 : 0;
+            out.cells.push_back(c);
+            const int64_t nt = excl ? c.na * int64_t(c.na - 1) * c.nb : int64_t(c.na) * c.nb * c.nx;
+            out.ntrip.push_back(nt);
+            out.total_triplets += nt;
+            const int32_t *ka = A + cls[ia].first * NA;
+            const int32_t *kb = A + cls[ib].first * NA;
+            const int32_t *kx = A + cls[ix].first * NA;
+            out.keys.push_back(ka[w.on]);
+            out.keys.push_back(kb[w.on]);
+            for (int32_t b : t.by) out.keys.push_back(ka[b]);
+            for (int32_t a : t.across) out.keys.push_back(ka[a]);
+            for (int32_t a : t.across) out.keys.push_back(kx[a]);
+            if (use_need) {
+                need[size_t(ix * K + ia)] = 1;
+                need[size_t(ix * K + ib)] = 1;
+            } else if (w.n_across > 0) {
+                need_list.push_back({ix, ia});
+                need_list.push_back({ix, ib});
+            }
+        };
+        if (w.n_across == 0) {
+            for (int64_t i = 0; i < K; ++i) {
+                if (cls[i].count < 2) continue;
+                for (int64_t j = 0; j < K; ++j)
+                    if (j != i) add_cell(i, j, i, true);
+            }
+        } else {
+            // classes are sorted by (on, across): runs of equal on
+            runs.clear();
+            for (int64_t i = 0; i < K;) {
+                int64_t e = i + 1;
+                while (e < K && cls[e].on_rank == cls[i].on_rank) ++e;
+                runs.push_back({i, e});
+                i = e;
+            }
+            for (auto &r1 : runs)
+                for (auto &r2 : runs) {
+                    if (r1.first == r2.first) continue;
+                    for (int64_t ia = r1.first; ia < r1.second; ++ia) {
+                        // B: same across value, other on value
+                        int64_t lo = r2.first, hi = r2.second;
+                        while (lo < hi) {
+                            int64_t mid = (lo + hi) / 2;
+                            if (w.across_cmp(cls[mid].first, cls[ia].first) < 0) lo = mid + 1; else hi = mid;
+                        }
+                        if (lo == r2.second || w.across_cmp(cls[lo].first, cls[ia].first) != 0) continue;
+                        for (int64_t ix = r1.first; ix < r1.second; ++ix)
+                            if (w.across_all_differ(cls[ix].first, cls[ia].first))
+                                add_cell(ia, lo, ix, false);
+                    }
+                }
+        }
+        if (out.cells.size() > cells_before) {
+            Group g{};
+            g.n_items = g1 - g0;
+            g.pair_base = out.pair_slots;
+            out.pair_slots += g.n_items * g.n_items;
+            // unique needed pairs and their DTW cells, from prefix sums over sorted positions
+            auto cnt = [&](int64_t i) { return cls[i].count; };
+            auto frames = [&](int64_t i) { return pf[cls[i].start + cls[i].count] - pf[cls[i].start]; };
+            auto sq = [&](int64_t i) { return pq[cls[i].start + cls[i].count] - pq[cls[i].start]; };
+            auto count_pair = [&](int64_t ix, int64_t iy) {
+                if (ix == iy) {   // X x A with a != x
+                    out.pairs_needed += cnt(ix) * (cnt(ix) - 1);
+                    out.dtw_needed += frames(ix) * frames(ix) - sq(ix);
+                } else {
+                    out.pairs_needed += cnt(ix) * cnt(iy);
+                    out.dtw_needed += frames(ix) * frames(iy);
+                }
+            };
+            if (w.n_across == 0) {
+                // every item of a class with >= 2 items is an x; it needs every other item
+                const int64_t all_items = g1 - g0, all_frames = pf[g1] - pf[g0];
+                for (int64_t ix = 0; ix < K; ++ix) {
+                    if (cnt(ix) < 2) continue;
+                    out.pairs_needed += cnt(ix) * (all_items - 1);
+                    out.dtw_needed += frames(ix) * all_frames - sq(ix);
+                }
+            } else if (use_need) {
+                for (int64_t ix = 0; ix < K; ++ix)
+                    for (int64_t iy = 0; iy < K; ++iy)
+                        if (need[size_t(ix * K + iy)]) count_pair(ix, iy);
+            } else {
+                std::sort(need_list.begin(), need_list.end());
+                need_list.erase(std::unique(need_list.begin(), need_list.end()), need_list.end());
+                for (auto &pr : need_list) count_pair(pr.first, pr.second);
+            }
+            out.kept.push_back({g0, g1});
+            out.groups.push_back(g);
+        }
+        g0 = g1;
+    }
+}
 
 }  // namespace
 
@@ -97,10 +303,16 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
 
     const int64_t n = ds->n_items;
     // ---- composite key: by fields (high), on, across fields (low)
-    std::vector<RankedColumn> rby, racr;
-    for (int32_t c : t->by) rby.push_back(rank_column(*ds, c));
-    RankedColumn ron = rank_column(*ds, on);
-    for (int32_t c : t->across) racr.push_back(rank_column(*ds, c));
+    std::vector<RankedColumn> rby(t->by.size()), racr(t->across.size());
+    RankedColumn ron;
+    {
+        std::vector<int32_t> all_cols = cols;   // on, by..., across...
+        std::vector<RankedColumn> ranked(all_cols.size());
+        parallel_for(int(all_cols.size()), [&](int k) { ranked[size_t(k)] = rank_column(*ds, all_cols[size_t(k)]); });
+        ron = std::move(ranked[0]);
+        for (size_t i = 0; i < rby.size(); ++i) rby[i] = std::move(ranked[1 + i]);
+        for (size_t i = 0; i < racr.size(); ++i) racr[i] = std::move(ranked[1 + rby.size() + i]);
+    }
     int acr_bits = 0;
     std::vector<int> acr_shift(n_across);
     for (int k = n_across - 1; k >= 0; --k) {
@@ -155,179 +367,130 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         }
     }
     // ACROSS tuples of two items: lexicographic order (the sort order) and "differ in every one"
-    auto across_cmp = [&](int64_t a, int64_t b) {
+    std::function<int(int64_t, int64_t)> across_cmp = [&](int64_t a, int64_t b) {
         for (int j = 0; j < n_across; ++j)
             if (racr[j].rank[a] != racr[j].rank[b]) return racr[j].rank[a] < racr[j].rank[b] ? -1 : 1;
         return 0;
     };
-    auto across_all_differ = [&](int64_t a, int64_t b) {
+    std::function<bool(int64_t, int64_t)> across_all_differ = [&](int64_t a, int64_t b) {
         for (int j = 0; j < n_across; ++j)
             if (racr[j].rank[a] == racr[j].rank[b]) return false;
         return true;
     };
 
-    // ---- walk groups and classes
-    std::vector<int64_t> kept_pos;   // sorted positions of items kept, in task order
-    kept_pos.reserve(n);
-    std::vector<ClassRun> cls;
-    std::vector<uint8_t> need;       // class-pair need matrix of the current group
-    int64_t g0 = 0;
-    while (g0 < n) {
-        int64_t g1 = g0 + 1;
-        while (g1 < n && by_part[g1] == by_part[g0]) ++g1;
-        cls.clear();
-        for (int64_t s = g0; s < g1;) {
-            int64_t e = s + 1;
-            while (e < g1 && cls_part[e] == cls_part[s]) ++e;
-            cls.push_back({s, e - s, ron.rank[order[s]], order[s]});
-            s = e;
-        }
-        const int64_t K = int64_t(cls.size());
-        const int32_t group_id = int32_t(t->groups.size());
-        const int64_t cells_before = int64_t(t->cells.size());
-        // class-pair need matrix (ACROSS tasks only; within tasks use a closed form)
-        const bool use_need = n_across > 0 && K <= 8192;
-        if (use_need) need.assign(size_t(K * K), 0);
-        std::vector<std::pair<int64_t, int64_t>> need_list;
-        auto add_cell = [&](int64_t ia, int64_t ib, int64_t ix, bool excl) {
-            CellDev c;
-            c.group = group_id;
-            c.a0 = int32_t(cls[ia].start - g0);
-            c.na = int32_t(cls[ia].count);
-            c.b0 = int32_t(cls[ib].start - g0);
-            c.nb = int32_t(cls[ib].count);
-            c.x0 = int32_t(cls[ix].start - g0);
-            c.nx = int32_t(cls[ix].count);
-            c.exclude_self = excl ? 1 : 0;
-            t->cells.push_back(c);
-            int64_t nt = excl ? c.na * int64_t(c.na - 1) * c.nb : int64_t(c.na) * c.nb * c.nx;
-            t->n_triplets.push_back(nt);
-            t->total_triplets += nt;
-            const int64_t ia0 = order[cls[ia].start], ib0 = order[cls[ib].start],
-                          ix0 = order[cls[ix].start];
-            t->keys.push_back(ds->attrs[ia0 * ds->n_attr + on]);
-            t->keys.push_back(ds->attrs[ib0 * ds->n_attr + on]);
-            for (int32_t b : t->by) t->keys.push_back(ds->attrs[ia0 * ds->n_attr + b]);
-            for (int32_t a : t->across) t->keys.push_back(ds->attrs[ia0 * ds->n_attr + a]);
-            for (int32_t a : t->across) t->keys.push_back(ds->attrs[ix0 * ds->n_attr + a]);
-            if (use_need) {
-                need[size_t(ix * K + ia)] = 1;
-                need[size_t(ix * K + ib)] = 1;
-            } else if (n_across > 0) {
-                need_list.push_back({ix, ia});
-                need_list.push_back({ix, ib});
-            }
-        };
-        if (n_across == 0) {
-            for (int64_t i = 0; i < K; ++i) {
-                if (cls[i].count < 2) continue;
-                for (int64_t j = 0; j < K; ++j)
-                    if (j != i) add_cell(i, j, i, true);
-            }
-        } else {
-            // classes are sorted by (on, across): runs of equal on
-            std::vector<std::pair<int64_t, int64_t>> runs;
-            for (int64_t i = 0; i < K;) {
-                int64_t e = i + 1;
-                while (e < K && cls[e].on_rank == cls[i].on_rank) ++e;
-                runs.push_back({i, e});
-                i = e;
-            }
-            for (auto &r1 : runs)
-                for (auto &r2 : runs) {
-                    if (r1.first == r2.first) continue;
-                    for (int64_t ia = r1.first; ia < r1.second; ++ia) {
-                        // B: same across value, other on value
-                        int64_t lo = r2.first, hi = r2.second;
-                        while (lo < hi) {
-                            int64_t mid = (lo + hi) / 2;
-                            if (across_cmp(cls[mid].first, cls[ia].first) < 0) lo = mid + 1; else hi = mid;
-                        }
-                        if (lo == r2.second || across_cmp(cls[lo].first, cls[ia].first) != 0) continue;
-                        for (int64_t ix = r1.first; ix < r1.second; ++ix)
-                            if (across_all_differ(cls[ix].first, cls[ia].first))
-                                add_cell(ia, lo, ix, false);
-                    }
-                }
-        }
-        if (int64_t(t->cells.size()) > cells_before) {
-            Group g;
-            g.item0 = int64_t(kept_pos.size());
-            g.n_items = g1 - g0;
-            g.frame0 = 0;
-            g.n_frames = 0;
-            g.pair_base = t->n_pair_slots;
-            g.dmat_base = 0;
-            t->n_pair_slots += g.n_items * g.n_items;
-            // unique needed pairs and their DTW cells
-            std::vector<int64_t> cframes(size_t(K), 0);
-            for (int64_t i = 0; i < K; ++i)
-                for (int64_t s = cls[i].start; s < cls[i].start + cls[i].count; ++s) {
-                    int64_t it = order[s];
-                    cframes[size_t(i)] += ds->offsets[it + 1] - ds->offsets[it];
-                }
-            auto count_pair = [&](int64_t ix, int64_t iy) {
-                if (ix == iy) {   // X x A with a != x
-                    t->n_pairs_needed += cls[ix].count * (cls[ix].count - 1);
-                    int64_t sq = 0;
-                    for (int64_t s = cls[ix].start; s < cls[ix].start + cls[ix].count; ++s) {
-                        int64_t L = ds->offsets[order[s] + 1] - ds->offsets[order[s]];
-                        sq += L * L;
-                    }
-                    t->dtw_cells_needed += cframes[size_t(ix)] * cframes[size_t(ix)] - sq;
-                } else {
-                    t->n_pairs_needed += cls[ix].count * cls[iy].count;
-                    t->dtw_cells_needed += cframes[size_t(ix)] * cframes[size_t(iy)];
-                }
-            };
-            if (n_across == 0) {
-                // every item of a class with >= 2 items is an x; it needs every other item
-                for (int64_t ix = 0; ix < K; ++ix) {
-                    if (cls[ix].count < 2) continue;
-                    for (int64_t iy = 0; iy < K; ++iy) count_pair(ix, iy);
-                }
-            } else if (use_need) {
-                for (int64_t ix = 0; ix < K; ++ix)
-                    for (int64_t iy = 0; iy < K; ++iy)
-                        if (need[size_t(ix * K + iy)]) count_pair(ix, iy);
-            } else {
-                std::sort(need_list.begin(), need_list.end());
-                need_list.erase(std::unique(need_list.begin(), need_list.end()), need_list.end());
-                for (auto &pr : need_list) count_pair(pr.first, pr.second);
-            }
-            for (int64_t s = g0; s < g1; ++s) kept_pos.push_back(s);
-            t->groups.push_back(g);
-        }
-        g0 = g1;
+    // ---- per sorted position: length, and prefix sums of frames and squared lengths
+    std::vector<int32_t> len_s(static_cast<size_t>(n));
+    std::vector<int64_t> pf(static_cast<size_t>(n) + 1, 0), pq(static_cast<size_t>(n) + 1, 0);
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t L = ds->offsets[order[s] + 1] - ds->offsets[order[s]];
+        len_s[s] = int32_t(L);
+        pf[s + 1] = pf[s] + L;
+        pq[s + 1] = pq[s] + L * L;
     }
 
+    // ---- walk the groups: chunks of whole groups in parallel, then stitch
+    const int n_threads = int(std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()),
+                                                std::max<int64_t>(1, n / 4096)));
+    std::vector<int64_t> cut(size_t(n_threads) + 1, n);
+    cut[0] = 0;
+    for (int k = 1; k < n_threads; ++k) {
+        int64_t c = std::max(cut[k - 1], n * k / n_threads);
+        while (c > 0 && c < n && by_part[c] == by_part[c - 1]) ++c;   // move to a group start
+        cut[k] = c;
+    }
+    std::vector<WalkOut> parts(static_cast<size_t>(n_threads));
+    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, &ron.rank, &pf, &pq, on, n_across,
+               across_cmp, across_all_differ};
+    parallel_for(n_threads, [&](int k) { walk_groups(wc, cut[k], cut[k + 1], parts[size_t(k)]); });
+
+    size_t n_cells = 0, n_groups = 0;
+    for (auto &p : parts) {
+        n_cells += p.cells.size();
+        n_groups += p.groups.size();
+    }
+    t->cells.resize(n_cells);
+    t->n_triplets.resize(n_cells);
+    t->keys.resize(n_cells * size_t(t->key_width));
+    t->groups.resize(n_groups);
+    std::vector<std::pair<int64_t, int64_t>> kept(n_groups);
+    std::vector<size_t> cell_off(parts.size()), group_off(parts.size());
+    std::vector<int64_t> slot_off(parts.size());
+    {
+        size_t co = 0, go = 0;
+        int64_t so = 0;
+        for (size_t k = 0; k < parts.size(); ++k) {
+            cell_off[k] = co;
+            group_off[k] = go;
+            slot_off[k] = so;
+            co += parts[k].cells.size();
+            go += parts[k].groups.size();
+            so += parts[k].pair_slots;
+            t->total_triplets += parts[k].total_triplets;
+            t->n_pairs_needed += parts[k].pairs_needed;
+            t->dtw_cells_needed += parts[k].dtw_needed;
+        }
+        t->n_pair_slots = so;
+    }
+    parallel_for(int(parts.size()), [&](int k) {
+        WalkOut &p = parts[size_t(k)];
+        for (size_t c = 0; c < p.cells.size(); ++c) {
+            CellDev cd = p.cells[c];
+            cd.group += int32_t(group_off[size_t(k)]);
+            t->cells[cell_off[size_t(k)] + c] = cd;
+        }
+        std::copy(p.ntrip.begin(), p.ntrip.end(), t->n_triplets.begin() + long(cell_off[size_t(k)]));
+        std::copy(p.keys.begin(), p.keys.end(), t->keys.begin() + long(cell_off[size_t(k)] * size_t(t->key_width)));
+        for (size_t g = 0; g < p.groups.size(); ++g) {
+            Group gg = p.groups[g];
+            gg.pair_base += slot_off[size_t(k)];
+            t->groups[group_off[size_t(k)] + g] = gg;
+            kept[group_off[size_t(k)] + g] = p.kept[g];
+        }
+        WalkOut().swap(p);
+    });
+
     // ---- task items in task order, packed frame offsets
-    const int64_t nt = int64_t(kept_pos.size());
-    t->items.resize(nt);
-    t->item_len.resize(nt);
-    t->item_src.resize(nt);
-    t->item_dst.resize(nt);
-    t->item_group.resize(nt);
-    t->item_pos_of.assign(size_t(n), -1);
-    int64_t frame = 0;
+    int64_t nt = 0, frame_total = 0;
     for (size_t gi = 0; gi < t->groups.size(); ++gi) {
         Group &g = t->groups[gi];
-        g.frame0 = frame;
-        for (int64_t k = g.item0; k < g.item0 + g.n_items; ++k) {
-            int64_t it = order[kept_pos[k]];
-            t->items[k] = it;
-            t->item_pos_of[it] = k;
-            t->item_src[k] = ds->offsets[it];
-            t->item_len[k] = int32_t(ds->offsets[it + 1] - ds->offsets[it]);
-            t->item_dst[k] = frame;
-            t->item_group[k] = int32_t(gi);
-            t->max_len = std::max(t->max_len, t->item_len[k]);
-            frame += t->item_len[k];
-        }
-        g.n_frames = frame - g.frame0;
+        g.item0 = nt;
+        g.n_items = kept[gi].second - kept[gi].first;
+        g.frame0 = frame_total;
+        g.n_frames = pf[kept[gi].second] - pf[kept[gi].first];
         g.dmat_base = t->n_dmat;
         t->n_dmat += g.n_frames * g.n_frames;
+        nt += g.n_items;
+        frame_total += g.n_frames;
     }
+    t->items.resize(size_t(nt));
+    t->item_len.resize(size_t(nt));
+    t->item_src.resize(size_t(nt));
+    t->item_dst.resize(size_t(nt));
+    t->item_group.resize(size_t(nt));
+    t->item_pos_of.assign(size_t(n), -1);
+    std::vector<int> max_len_part(static_cast<size_t>(n_threads), 0);
+    const int64_t G = int64_t(t->groups.size());
+    parallel_for(n_threads, [&](int k) {
+        int ml = 0;
+        for (int64_t gi = G * k / n_threads; gi < G * (k + 1) / n_threads; ++gi) {
+            const Group &g = t->groups[size_t(gi)];
+            int64_t frame = g.frame0, q = g.item0;
+            for (int64_t s = kept[size_t(gi)].first; s < kept[size_t(gi)].second; ++s, ++q) {
+                const int64_t it = order[s];
+                t->items[q] = it;
+                t->item_pos_of[it] = q;
+                t->item_src[q] = ds->offsets[it];
+                t->item_len[q] = len_s[s];
+                t->item_dst[q] = frame;
+                t->item_group[q] = int32_t(gi);
+                ml = std::max(ml, len_s[s]);
+                frame += len_s[s];
+            }
+        }
+        max_len_part[size_t(k)] = ml;
+    });
+    for (int ml : max_len_part) t->max_len = std::max(t->max_len, ml);
+    const int64_t frame = frame_total;
     t->n_frames = frame;
     return t;
 }

@@ -279,6 +279,54 @@ def test_server_alone_equals_mix():
     srv.close()
 
 
+def test_server_mix_of_bench_jobs():
+    """The serving stream's job mix (items capped at 6k): alone twice, then served on
+    4 streams; every job's per-cell counts must agree bitwise, and disagreeing
+    groups are checked against the oracle."""
+    _say("server: bench job mix")
+    jobs = []
+    for j in range(12):
+        w = workloads.serving_job(j, device="cuda", n_hi=6000)
+        jobs.append((w, fx.Dataset(ctx(), w.features, w.offsets, w.attrs)))
+    runs = []
+    for rep in range(2):
+        out = []
+        for w, ds in jobs:
+            r = fx.Task(ds, w.on, w.by, w.across).score()
+            st = r.stats
+            if rep == 0:
+                print(f"  {w.name} n={w.n_items} dim={w.dim} cells={st['n_cells']} gpu={st['ms_total']:.1f}ms "
+                      f"nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']} "
+                      f"recount={st['n_recount_rows']}", flush=True)
+            out.append(r.half_units.copy())
+        runs.append(out)
+    srv = fx.Server(ctx(), hbm_budget_bytes=64 << 30, n_streams=4)
+    ids = [srv.submit(ds, w.on, w.by, w.across) for w, ds in jobs]
+    served = [srv.wait(i)[1] for i in ids]
+    srv.close()
+    bad = []
+    for k, (w, ds) in enumerate(jobs):
+        d_rep = int(np.count_nonzero(runs[0][k] != runs[1][k]))
+        d_srv = int(np.count_nonzero(runs[0][k] != served[k]))
+        if d_rep or d_srv:
+            print(f"  MISMATCH {w.name}: alone-vs-alone {d_rep} cells, alone-vs-served {d_srv} cells", flush=True)
+            bad.append(k)
+    for k in bad[:2]:
+        w, ds = jobs[k]
+        t = fx.Task(ds, w.on, w.by, w.across)
+        keys = t.keys
+        diff = np.nonzero((runs[0][k] != served[k]) | (runs[0][k] != runs[1][k]))[0][:5]
+        gkeys = {tuple(int(v) for v in keys[c][2:2 + len(w.by)]) for c in diff}
+        orc = oracle.score(w.features_f32_host(), w.offsets, w.attrs, w.on, w.by, w.across,
+                           cell_filter=lambda c: c.by_key in gkeys)
+        okeys = {tuple(int(v) for v in c.key): int(h) for c, h in zip(orc.cells, orc.half_units)}
+        for c in diff:
+            kk = tuple(int(v) for v in keys[c])
+            print(f"  cell {kk}: alone {runs[0][k][c]} {runs[1][k][c]} served {served[k][c]} "
+                  f"oracle {okeys.get(kk)}", flush=True)
+    assert not bad
+
+
 def test_server_rejects_oversized_job():
     _say("server admission")
     w = workloads.serving_job(0, n_items=2000, dim=256, across=False)
