@@ -9,6 +9,11 @@ namespace fabx {
 namespace dev {
 
 constexpr int kWave = 64;
+
+// Launches use at most this many blocks and loop over their work: an AQL
+// dispatch holds the grid as a 32-bit count of work-items, so a grid sized by
+// the work (pairs, tiles, units) could silently wrap.
+constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 constexpr float kInf = __builtin_huge_valf();
 constexpr float kInvPi = 0.318309886183790671537767526745f;
 

@@ -134,12 +134,15 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
                                                   unsigned int *__restrict__ nonrobust_n) {
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kSmemBytes];
     __shared__ uint16_t colflag[4][kCols];
-    // XCD-aware order: the 8 XCDs take blocks round-robin, so give each XCD a
-    // contiguous run of units (units of one group share its frames in L2).
-    const int64_t b = blockIdx.x;
-    const int64_t unit = (b % 8) * grid_q + b / 8;
-    if (unit >= n_units) return;
+    // Persistent blocks, XCD-aware order: the 8 XCDs take blocks round-robin,
+    // so XCD x works through the contiguous unit range [x * grid_q, (x+1) * grid_q)
+    // (units of one group share its frames in that XCD's L2).  gridDim.x is a
+    // multiple of 8.
+    const int64_t xcd = blockIdx.x % 8, m = blockIdx.x / 8, n_m = gridDim.x / 8;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    for (int64_t j = m; j < grid_q; j += n_m) {
+    const int64_t unit = xcd * grid_q + j;
+    if (unit >= n_units) continue;  // uniform across the block
 
     const int64_t g = dev::find_segment(unit_prefix, n_groups, unit);
     const int64_t local = unit - unit_prefix[g];
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     }
     __syncthreads();
     const int S = s_end - s_begin;
-    if (S == 0) return;  // nothing for this wave (no barrier follows)
+    if (S > 0) {  // this wave has column items
 
     const int64_t pbase = g_pair_base[g];
     const int64_t gn = g_n[g];
@@ -272,6 +275,9 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
             }
         }
     }
+    }  // S > 0
+    __syncthreads();  // the next unit overwrites the LDS tile and column flags
+    }
 }
 
 // Pooled mode: MFMA Gram tile of pooled unit vectors, angular distance straight
@@ -283,10 +289,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
                                                               const int64_t *__restrict__ nrows,
                                                               const int64_t *__restrict__ base,
                                                               const int64_t *__restrict__ tile_prefix,
-                                                              int64_t n_groups,
+                                                              int64_t n_groups, int64_t n_tiles,
                                                               float *__restrict__ out) {
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kStageBytes];
-    const int64_t tile = blockIdx.x;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
     const int64_t n = nrows[g];
     const int64_t ntc = (n + kCols - 1) / kCols;
@@ -298,18 +304,20 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
               acc0, acc1);
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int col = 32 * w + lane % 32;
-    if (col >= nc) return;
-    const float rc = rinv[row0[g] + c0 + col];
-    float *o = out + base[g];
+    if (col < nc) {
+        const float rc = rinv[row0[g] + c0 + col];
+        float *o = out + base[g];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int ra = acc_row(i, lane), rb2 = 32 + ra;
-        if (ra < nr)
-            o[(r0 + ra) * n + c0 + col] =
-                dev::acos_over_pi(fminf(fmaxf(acc0[i] * rinv[row0[g] + r0 + ra] * rc, -1.0f), 1.0f));
-        if (rb2 < nr)
-            o[(r0 + rb2) * n + c0 + col] =
-                dev::acos_over_pi(fminf(fmaxf(acc1[i] * rinv[row0[g] + r0 + rb2] * rc, -1.0f), 1.0f));
+        for (int i = 0; i < 16; ++i) {
+            const int ra = acc_row(i, lane), rb2 = 32 + ra;
+            if (ra < nr)
+                o[(r0 + ra) * n + c0 + col] =
+                    dev::acos_over_pi(fminf(fmaxf(acc0[i] * rinv[row0[g] + r0 + ra] * rc, -1.0f), 1.0f));
+            if (rb2 < nr)
+                o[(r0 + rb2) * n + c0 + col] =
+                    dev::acos_over_pi(fminf(fmaxf(acc1[i] * rinv[row0[g] + r0 + rb2] * rc, -1.0f), 1.0f));
+        }
+    }
     }
 }
 
@@ -321,8 +329,7 @@ void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pa
     if (plan.n_units <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
     const int64_t q = (plan.n_units + 7) / 8;
-    const int64_t blocks = 8 * q;
-    if (blocks > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many work units for one launch");
+    const int64_t blocks = 8 * std::min<int64_t>(q, dev::kMaxBlocks / 8);
     if (norm == FABX_NORM_PATH)
         hipLaunchKernelGGL(k_fused<true>, dim3(unsigned(blocks)), dim3(256), 0, s, xn, rinv, dim_pad,
                            g.item0, g.n_items, g.pair_base, it.len, it.dst, plan.rb, plan.cb,
@@ -341,9 +348,8 @@ void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int
                        const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out) {
     if (n_tiles <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
-    if (n_tiles > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many tiles for one launch");
-    hipLaunchKernelGGL(k_gram_angular_bf16, dim3(unsigned(n_tiles)), dim3(256), 0, s, xn, rinv,
-                       dim_pad, row0, nrows, base, tile_prefix, n_groups, out);
+    hipLaunchKernelGGL(k_gram_angular_bf16, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn, rinv,
+                       dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
     FABX_HIP(hipGetLastError());
 }
 

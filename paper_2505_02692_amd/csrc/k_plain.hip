@@ -27,10 +27,11 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
                                                           const int64_t *__restrict__ nrows,
                                                           const int64_t *__restrict__ base,
                                                           const int64_t *__restrict__ tile_prefix,
-                                                          int64_t n_groups, float *__restrict__ out) {
+                                                          int64_t n_groups, int64_t n_tiles,
+                                                          float *__restrict__ out) {
     __shared__ float As[kK][kTile + 4];
     __shared__ float Bs[kK][kTile + 4];
-    const int64_t tile = blockIdx.x;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
     const int64_t n = nrows[g];
     const int64_t nt = (n + kTile - 1) / kTile;
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
             o[r * n + c] = acosf(cs) * dev::kInvPi;
         }
     }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dmat,
@@ -89,9 +91,10 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst, int norm,
                                                    float *__restrict__ p32) {
-    const int64_t slot = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave;
     const int i = threadIdx.x % kWave;
-    if (slot >= n_slots) return;  // whole wave leaves together
+    // one wave per slot; the loop bound is uniform across the wave
+    for (int64_t slot = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; slot < n_slots;
+         slot += int64_t(gridDim.x) * 4) {
     const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
     const int64_t n = g_n[g];
     const int64_t local = slot - g_pair_base[g];
@@ -131,6 +134,7 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
         }
     }
     if (i == N - 1) p32[slot] = norm == FABX_NORM_PATH ? c / float(len) : c;
+    }
 }
 
 }  // namespace
@@ -139,19 +143,16 @@ void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t
                       const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
                       int64_t n_groups, int64_t n_tiles, float *out) {
     if (n_tiles <= 0) return;
-    if (n_tiles > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many distance tiles for one launch");
     if (dim_pad % kK) fail(FABX_EINVAL, "padded dim must be a multiple of 16");
-    hipLaunchKernelGGL(k_gram_angular_f32, dim3(unsigned(n_tiles)), dim3(256), 0, s, xn, dim_pad,
-                       row0, nrows, base, tile_prefix, n_groups, out);
+    hipLaunchKernelGGL(k_gram_angular_f32, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn, dim_pad,
+                       row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
     FABX_HIP(hipGetLastError());
 }
 
 void dtw_plain(hipStream_t s, const float *dmat, const GroupTables &g, const ItemTables &it,
                int norm, float *p32) {
     if (g.n_pair_slots <= 0) return;
-    const int64_t blocks = (g.n_pair_slots + 3) / 4;
-    if (blocks > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many pairs for one launch");
-    hipLaunchKernelGGL(k_dtw_plain, dim3(unsigned(blocks)), dim3(256), 0, s, dmat, g.item0,
+    hipLaunchKernelGGL(k_dtw_plain, dim3(grid_for(g.n_pair_slots, 4)), dim3(256), 0, s, dmat, g.item0,
                        g.n_items, g.frame0, g.n_frames, g.pair_base, g.dmat_base, g.n_groups,
                        g.n_pair_slots, it.len, it.dst, norm, p32);
     FABX_HIP(hipGetLastError());

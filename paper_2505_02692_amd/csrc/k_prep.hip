@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst,
                                                    void *out, int out_bf16, float *rinv, int *err,
-                                                   unsigned long long *err_item) {
-    const int64_t item = blockIdx.x;
+                                                   int64_t n_items, unsigned long long *err_item) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int L = item_len[item];
     const int64_t s0 = item_src[item], d0 = item_dst[item];
     for (int t = wave; t < L; t += 4) {
@@ -117,6 +117,7 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
         }
         store_unit_row<kChunks>(v, ss, lane, dim_pad, d0 + t, out, out_bf16, rinv);
     }
+    }
 }
 
 template <typename Tin, int kChunks>
@@ -127,9 +128,9 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
                                                         float *rinv, int *err,
                                                         unsigned long long *err_item) {
     // one wave per item
-    const int64_t item = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    if (item >= n_items) return;
+    for (int64_t item = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; item < n_items;
+         item += int64_t(gridDim.x) * 4) {
     const int L = item_len[item];
     const int64_t s0 = item_src[item];
     float v[kChunks][4];
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
         ss = 1.0f;
     }
     store_unit_row<kChunks>(v, ss, lane, dim_pad, item, out, out_bf16, rinv);
+    }
 }
 
 template <int kChunks>
@@ -172,7 +174,7 @@ void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int di
                  const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
                  unsigned long long *err_item, bool pooled) {
     if (pooled) {
-        dim3 grid(unsigned((it.n_items + 3) / 4));
+        dim3 grid(grid_for(it.n_items, 4));
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL((k_pool_normalize<float, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
@@ -182,15 +184,15 @@ void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int di
                                static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
                                it.len, it.n_items, out, out_bf16, rinv, err, err_item);
     } else {
-        dim3 grid(unsigned(it.n_items));
+        dim3 grid(grid_for(it.n_items, 1));
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL((k_normalize<float, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
-                               it.dst, out, out_bf16, rinv, err, err_item);
+                               it.dst, out, out_bf16, rinv, err, it.n_items, err_item);
         else
             hipLaunchKernelGGL((k_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
-                               it.len, it.dst, out, out_bf16, rinv, err, err_item);
+                               it.len, it.dst, out, out_bf16, rinv, err, it.n_items, err_item);
     }
     FABX_HIP(hipGetLastError());
 }
@@ -199,7 +201,6 @@ void dispatch(hipStream_t s, const void *features, int dtype, int dim, int dim_p
               const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
               unsigned long long *err_item, bool pooled) {
     if (it.n_items <= 0) return;
-    if (it.n_items > 0x7FFFFFFFLL * (pooled ? 4 : 1)) fail(FABX_EINVAL, "too many items for one launch");
     // chunks of 256 elements per wave pass
     const int chunks = (dim_pad + 255) / 256;
     switch (chunks) {

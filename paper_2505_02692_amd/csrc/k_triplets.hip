@@ -30,9 +30,10 @@ __global__ __launch_bounds__(256) void k_triplets(const CellDev *__restrict__ ce
                                                   int32_t *__restrict__ recount,
                                                   unsigned int *__restrict__ recount_n,
                                                   int64_t recount_cap) {
-    const int64_t unit = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    if (unit >= n_units) return;
+    // one wave per unit; the loop bound is uniform across the wave
+    for (int64_t unit = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; unit < n_units;
+         unit += int64_t(gridDim.x) * 4) {
     const int32_t cell_id = units[3 * unit];
     const int32_t xb = units[3 * unit + 1], xe = units[3 * unit + 2];
     const CellDev c = cells[cell_id];
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(256) void k_triplets(const CellDev *__restrict__ ce
         acc += row_total;
     }
     if (lane == 0 && acc) atomicAdd(&W[cell_id], acc);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_collect_marked(const uint8_t *__restrict__ flags, int64_t n_slots,
@@ -150,9 +152,7 @@ void triplets(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t
               const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
               float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap) {
     if (n_units <= 0) return;
-    const int64_t blocks = (n_units + 3) / 4;
-    if (blocks > 0x7FFFFFFFLL) fail(FABX_ENOMEM, "too many triplet units for one launch");
-    hipLaunchKernelGGL(k_triplets, dim3(unsigned(blocks)), dim3(256), 0, s, cells, units, n_units,
+    hipLaunchKernelGGL(k_triplets, dim3(grid_for(n_units, 4)), dim3(256), 0, s, cells, units, n_units,
                        g.pair_base, g.n_items, p32, W, flags, margin, recount, recount_n,
                        recount_cap);
     FABX_HIP(hipGetLastError());

@@ -11,6 +11,15 @@
 namespace fabx {
 namespace kern {
 
+// Blocks for `work` items handled `per_block` at a time, capped (the kernels
+// loop); threads * blocks always fits the 32-bit dispatch grid.
+inline unsigned grid_for(int64_t work, int64_t per_block, int64_t cap = int64_t(1) << 20) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return unsigned(b);
+}
+
 // Per-item task tables on the device.
 struct ItemTables {
     const int64_t *src;    // first source frame of each task item

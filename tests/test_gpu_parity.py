@@ -338,6 +338,44 @@ def test_server_rejects_oversized_job():
     srv.close()
 
 
+# ------------------------------------------ large groups, sampled pairs --
+
+@pytest.mark.parametrize("n_items", [12000, 24000, None])
+def test_large_groups_sampled_pairs(n_items):
+    """Serving-shaped across job with groups of thousands of items: sampled pair
+    distances against the oracle, and no spurious near ties.  n_items=None is the
+    serving stream's job 1 as drawn (32,660 items, a 9,616-item group: over 2^32
+    work-items if one block per unit were launched)."""
+    if n_items is None:
+        w = workloads.serving_job(1, device="cuda")
+    else:
+        w = workloads.serving_job(1, device="cuda", n_items=n_items, dim=1024, across=True)
+    _say(f"large groups n_items={n_items}")
+    t, res = gpu_score(w, keep_pairs=True)
+    st = res.stats
+    print(f"  cells={st['n_cells']} pairs={st['n_pairs']} recheck={st['n_recheck_pairs']} "
+          f"recount={st['n_recount_rows']} nonrobust={st['n_nonrobust_pairs']} gpu={st['ms_total']:.1f}ms",
+          flush=True)
+    # sample pairs (x, y) inside the largest BY group, spread over its row / column blocks
+    g = np.bincount(w.attrs[:, 1]).argmax()
+    items = np.nonzero(w.attrs[:, 1] == g)[0]
+    rng = np.random.default_rng(0)
+    xs = rng.choice(items, 400)
+    ys = rng.choice(items, 400)
+    f32, fl, f64 = res.pairs(xs, ys)
+    loc = {int(v): k for k, v in enumerate(items)}
+    want = oracle.pair_distances(w.features_f32_host(), w.offsets, [items],
+                                 [(np.array([loc[int(x)] for x in xs], np.int32),
+                                   np.array([loc[int(y)] for y in ys], np.int32))])[0]
+    err = np.abs(f32.astype(np.float64) - want)
+    worst = np.argsort(err)[-5:]
+    for k in worst:
+        print(f"  pair ({xs[k]},{ys[k]}) pos ({loc[int(xs[k])]},{loc[int(ys[k])]}) gpu {f32[k]:.6f} "
+              f"oracle {want[k]:.6f} flags {fl[k]}", flush=True)
+    assert err[(fl & 1) == 0].max() <= st["margin"] / 2
+    assert st["n_recheck_pairs"] < 0.01 * st["n_pairs"]
+
+
 # ----------------------------------------------- full-size bench workload --
 
 def test_within_c2_full_size_bf16():
