@@ -35,7 +35,8 @@ def log(msg):
 
 
 def _stage_means(results):
-    keys = ["ms_total", "ms_normalize", "ms_distance", "ms_triplets", "ms_recheck"]
+    keys = ["ms_total", "ms_normalize", "ms_distance", "ms_triplets", "ms_recheck", "ms_host_setup",
+            "ms_host_finish", "ms_task_build", "ms_score_call", "ms_collapse"]
     return {k: float(np.mean([r[k] for r in results])) for k in keys}
 
 
@@ -43,10 +44,16 @@ def run_steps(fx, ds, w, precision, n, sync):
     stats, errs = [], []
     t0 = time.perf_counter()
     for _ in range(n):
+        ta = time.perf_counter()
         task = fx.Task(ds, w.on, w.by, w.across)
+        tb = time.perf_counter()
         res = task.score(mode="dtw", precision=precision)
+        tc = time.perf_counter()
         errs.append(res.collapse(w.levels))
-        stats.append(res.stats)
+        td = time.perf_counter()
+        st = res.stats
+        st.update(ms_task_build=(tb - ta) * 1e3, ms_score_call=(tc - tb) * 1e3, ms_collapse=(td - tc) * 1e3)
+        stats.append(st)
     sync()
     return time.perf_counter() - t0, stats, errs
 
@@ -140,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run 3 plain device copies of this many MiB (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the ABX hot path here is "
@@ -156,6 +165,15 @@ def main():
     if args.serving_only:
         print(json.dumps({"serving": serving_stream(fx, fx.Context(0), torch, workloads, args.serve_jobs)}))
         return
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 18   # float32 elements
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        sync()
+        log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB (read + write each)")
+        del src, dst
     w = workloads.within_c2(device="cuda")
     ctx = fx.Context(0)
     ds = fx.Dataset(ctx, w.features, w.offsets, w.attrs)

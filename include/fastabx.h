@@ -77,8 +77,13 @@ const char *fabx_version(void);
 /* --------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t on
- * that device (borrowed, must outlive the context) or NULL, in which case the
- * context creates and owns a stream.  Errors: EINVAL (bad device), EHIP. */
+ * that device (borrowed, must outlive the context) or NULL for the device's
+ * null stream.  Every device operation of the context (uploads, kernels,
+ * copies) is enqueued on that stream, after whatever the caller enqueued there
+ * before the call: features written by earlier work on the same stream are
+ * read in order, with no host synchronisation needed.  fabx_score waits for
+ * its own work on the stream before it returns.  Errors: EINVAL (bad device),
+ * EHIP. */
 int fabx_create(fabx_ctx **out, int device, void *hip_stream);
 void fabx_destroy(fabx_ctx *ctx);
 
@@ -221,6 +226,8 @@ typedef struct fabx_stats {
     double ms_distance;         /* frame distances + DTW (or pooled distances) */
     double ms_triplets;
     double ms_recheck;          /* FP64 recheck + recount */
+    double ms_host_setup;       /* host: work plans, table uploads, workspace (before the first kernel) */
+    double ms_host_finish;      /* host: after the results reached the host, until fabx_score returns */
     double margin;              /* near-tie margin used (BF16 form; 0 for FP32) */
     double delta;               /* path-length window used (BF16 form, DTW; else 0) */
 } fabx_stats;
@@ -259,8 +266,11 @@ int fabx_server_create(fabx_ctx *ctx, int64_t hbm_budget_bytes, int32_t n_stream
 /* Stops accepting jobs, cancels queued ones, waits for running ones. */
 void fabx_server_destroy(fabx_server *srv);
 
-/* Queue a job.  Errors: EINVAL (bad spec), ENOMEM (the job's footprint
- * exceeds the whole budget, so it could never run). */
+/* Queue a job.  The job's kernels run on the server's own streams, after all
+ * work enqueued on the context's stream before this call (an event recorded
+ * there at submit), so features produced on that stream are read in order.
+ * Errors: EINVAL (bad spec), ENOMEM (the job's footprint exceeds the whole
+ * budget, so it could never run), EHIP. */
 int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int32_t *by,
                        int32_t n_by, const int32_t *across, int32_t n_across,
                        const fabx_score_opts *opts, uint64_t *job_id);

@@ -240,7 +240,12 @@ def _current_stream_ptr(device: int):
 
 
 class Context:
-    """A device (or, with device=-1, a host-only context that can build tasks but not score)."""
+    """A device (or, with device=-1, a host-only context that can build tasks but not score).
+
+    All device work of the context goes on one HIP stream, in order after what
+    was enqueued there before: by default torch's current stream at creation
+    (so features made by torch on it need no synchronisation), ``None`` for the
+    null stream, or a raw ``hipStream_t`` value."""
 
     def __init__(self, device: int = 0, stream="torch"):
         self.device = device

@@ -48,7 +48,7 @@ class fabx_stats(ctypes.Structure):
         "n_cells", "n_triplets", "n_items", "n_frames", "n_pairs", "dtw_cells", "computed_dtw_cells",
         "n_nonrobust_pairs", "n_recheck_pairs", "n_recount_rows", "workspace_bytes")] + \
         [(n, ctypes.c_double) for n in ("ms_total", "ms_normalize", "ms_distance", "ms_triplets",
-                                         "ms_recheck", "margin", "delta")]
+                                         "ms_recheck", "ms_host_setup", "ms_host_finish", "margin", "delta")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -1,4 +1,5 @@
 // C ABI of fastabx-hip: argument checks, handle management, error codes.
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -92,8 +93,50 @@ void DevBuf::ensure(size_t n) {
     bytes = n;
 }
 
+hipEvent_t EventPool::get() {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e;
+    FABX_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void EventPool::put(hipEvent_t e) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_events.push_back(e);
+}
+
+EventPool::~EventPool() {
+    for (auto e : free_events) (void)hipEventDestroy(e);
+}
+
+void Staging::reserve(size_t n) {
+    if (!done) FABX_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    if (n <= cap) return;
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    cap = 0;
+    const size_t want = std::max(n, size_t(8) << 20);
+    if (hipHostMalloc(&host, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        host = nullptr;
+        fail(FABX_ENOMEM, "pinned staging allocation of " + std::to_string(want) + " bytes failed");
+    }
+    cap = want;
+}
+
+Staging::~Staging() {
+    if (host) (void)hipHostFree(host);
+    if (done) (void)hipEventDestroy(done);
+}
+
 CtxImpl::~CtxImpl() {
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
     pool.trim();
 }
 
@@ -145,12 +188,9 @@ int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
             hipDeviceProp_t prop;
             FABX_HIP(hipGetDeviceProperties(&prop, device));
             c->n_cu = prop.multiProcessorCount;
-            if (hip_stream) {
-                c->stream = static_cast<hipStream_t>(hip_stream);
-            } else {
-                FABX_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-                c->own_stream = true;
-            }
+            // NULL is the device's null stream, as everywhere in HIP: the context's
+            // work is then ordered after what the caller enqueued there
+            c->stream = static_cast<hipStream_t>(hip_stream);
         } else if (device != -1) {
             fail(FABX_EINVAL, "device must be >= 0 (or -1 for a host-only context)");
         }

@@ -3,12 +3,18 @@
 // task averages over contexts, then speakers, then phonemes; Score.collapse
 // offers cell-size weighting or averaging level by level).  FP64 on the host.
 //
-// Level by level: the rows (key tuple, score) are sorted by the key columns
-// that remain after removing the level's attributes, equal runs are averaged
-// (unweighted), and the averaged rows carry on to the next level.
+// Level by level: every key value is replaced by its dense rank (computed by
+// the task builder); for a level, the ranks of the columns that remain are
+// packed into one key.  Rows with equal keys are averaged (unweighted, summed
+// in row order): when the key space is small, through a direct table indexed
+// by the key (one pass, no sort), otherwise after a stable radix sort.  The
+// averaged rows, in key order, carry on to the next level; the last rows are
+// averaged flat.
 #include <algorithm>
 #include <numeric>
 
+#include "host_pool.h"
+#include "host_sort.h"
 #include "internal.h"
 
 namespace fabx {
@@ -43,52 +49,88 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
         }
         levels.push_back(lv);
     }
-    const int K = t.key_width;
-    // current rows: keys [m x width] (width = cols.size()), scores [m]
-    std::vector<int> cols(static_cast<size_t>(K));
-    std::iota(cols.begin(), cols.end(), 0);
-    std::vector<int32_t> keys = t.keys;
+    Trace tr("collapse");
+    const size_t K = size_t(t.key_width);
+    // rows: dense ranks of the key values (from the task builder), row-major [m x K]
+    const uint32_t *rows = t.rkeys.data();
+    std::vector<uint32_t> own;  // rows after the first level
+    std::vector<size_t> cols(K);  // key columns still present
+    std::iota(cols.begin(), cols.end(), size_t(0));
     std::vector<double> score(n);
     for (size_t i = 0; i < n; ++i) score[i] = double(res.half_units[i]) / (2.0 * double(t.n_triplets[i]));
-    size_t width = size_t(K);
     for (const auto &lv : levels) {
-        std::vector<size_t> keep;  // positions (in the current key) of the kept columns
-        std::vector<int> kept_cols;
-        for (size_t p = 0; p < cols.size(); ++p)
-            if (std::find(lv.begin(), lv.end(), t.key_attr[size_t(cols[p])]) == lv.end()) {
-                keep.push_back(p);
-                kept_cols.push_back(cols[p]);
-            }
+        std::vector<size_t> kept;
+        for (size_t c : cols)
+            if (std::find(lv.begin(), lv.end(), t.key_attr[c]) == lv.end()) kept.push_back(c);
+        int total_bits = 0;
+        for (size_t c : kept) total_bits += t.key_bits[c];
         const size_t m = score.size();
-        std::vector<size_t> idx(m);
-        std::iota(idx.begin(), idx.end(), size_t(0));
-        auto less = [&](size_t a, size_t b) {
-            for (size_t p : keep) {
-                const int32_t x = keys[a * width + p], y = keys[b * width + p];
-                if (x != y) return x < y;
-            }
-            return a < b;
-        };
-        auto same = [&](size_t a, size_t b) {
-            for (size_t p : keep)
-                if (keys[a * width + p] != keys[b * width + p]) return false;
-            return true;
-        };
-        std::sort(idx.begin(), idx.end(), less);
-        std::vector<int32_t> nkeys;
         std::vector<double> nscore;
-        for (size_t i = 0; i < m;) {
-            size_t j = i;
-            double s = 0.0;
-            while (j < m && same(idx[i], idx[j])) s += score[idx[j++]];
-            for (size_t p : keep) nkeys.push_back(keys[idx[i] * width + p]);
-            nscore.push_back(s / double(j - i));
-            i = j;
+        std::vector<uint32_t> nrows;
+        auto pack = [&](size_t i) {
+            uint64_t k = 0;
+            for (size_t c : kept)
+                if (t.key_bits[c]) k = (k << t.key_bits[c]) | rows[i * K + c];
+            return k;
+        };
+        if (total_bits <= 22 && (uint64_t(1) << total_bits) <= 8 * uint64_t(m) + 4096) {
+            // direct table: sum and count per key, first row of each key for its ranks
+            const size_t nk = size_t(1) << total_bits;
+            std::vector<double> sum(nk, 0.0);
+            std::vector<uint32_t> cnt(nk, 0), first(nk, 0);
+            for (size_t i = 0; i < m; ++i) {
+                const uint64_t k = pack(i);
+                if (cnt[k]++ == 0) first[k] = uint32_t(i);
+                sum[k] += score[i];
+            }
+            nscore.reserve(m);
+            nrows.reserve(m * K);
+            for (size_t k = 0; k < nk; ++k)
+                if (cnt[k]) {
+                    nscore.push_back(sum[k] / double(cnt[k]));
+                    nrows.insert(nrows.end(), rows + size_t(first[k]) * K, rows + size_t(first[k]) * K + K);
+                }
+        } else {
+            std::vector<uint32_t> order(m);
+            std::iota(order.begin(), order.end(), 0u);
+            std::vector<uint64_t> key(m, 0);
+            if (total_bits <= 64) {
+                for (size_t i = 0; i < m; ++i) key[i] = pack(i);
+                radix_sort_pairs(key, order, total_bits);
+            } else {
+                std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+                    for (size_t c : kept)
+                        if (rows[a * K + c] != rows[b * K + c]) return rows[a * K + c] < rows[b * K + c];
+                    return false;
+                });
+                uint64_t id = 0;  // run ids as keys
+                for (size_t i = 0; i < m; ++i) {
+                    if (i > 0)
+                        for (size_t c : kept)
+                            if (rows[size_t(order[i]) * K + c] != rows[size_t(order[i - 1]) * K + c]) {
+                                ++id;
+                                break;
+                            }
+                    key[i] = id;
+                }
+            }
+            // average each run of equal keys; the new rows keep the ranks of the kept columns
+            nscore.reserve(m);
+            nrows.reserve(m * K);
+            for (size_t i = 0; i < m;) {
+                size_t j = i;
+                double sacc = 0.0;
+                while (j < m && key[j] == key[i]) sacc += score[order[j++]];
+                nscore.push_back(sacc / double(j - i));
+                nrows.insert(nrows.end(), rows + size_t(order[i]) * K, rows + size_t(order[i]) * K + K);
+                i = j;
+            }
         }
-        keys.swap(nkeys);
         score.swap(nscore);
-        cols = kept_cols;
-        width = keep.size();
+        own.swap(nrows);
+        rows = own.data();
+        cols = kept;
+        tr.mark("level");
     }
     double s = 0.0;
     for (double v : score) s += v;

@@ -60,12 +60,33 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Reusable HIP events of one context (stage timers of concurrent scores).
+struct EventPool {
+    std::mutex mu;
+    std::vector<hipEvent_t> free_events;
+    hipEvent_t get();
+    void put(hipEvent_t e);
+    ~EventPool();
+};
+
+// Pinned host buffer through which a score's tables reach the device with one
+// DMA copy.  One user at a time (the copy is waited for before release).
+struct Staging {
+    std::mutex mu;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    void reserve(size_t n);
+    ~Staging();
+};
+
 struct CtxImpl {
     int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr;  // borrowed; nullptr = the null stream
     int n_cu = 0;
     Pool pool;
+    EventPool events;
+    Staging staging;
     ~CtxImpl();
 };
 
@@ -81,6 +102,11 @@ struct DatasetImpl {
     std::vector<int64_t> offsets;     // [n_items + 1]
     std::vector<int32_t> attrs;       // [n_items * n_attr]
 };
+
+// Fused BF16 kernel tiling: frames per row block (one DTW lane per frame row)
+// and per column block.  Items are never split, so items are <= 64 frames.
+constexpr int kFusedRowFrames = 64;
+constexpr int kFusedColFrames = 128;
 
 // One BY group that holds at least one cell.  Items of a group are
 // contiguous in task order, and so are their packed frames.
@@ -103,13 +129,18 @@ struct CellDev {
 };
 static_assert(sizeof(CellDev) == 32, "CellDev layout");
 
-// Device copies of the task tables.
+// Device copy of the task tables: one buffer, uploaded with one copy on the
+// task's first score; the pointers below point into it.
 struct TaskDevice {
-    DevBuf item_src, item_len, item_dst, item_group;
-    DevBuf g_item0, g_n, g_frame0, g_nframes, g_pair_base, g_dmat_base;
-    DevBuf cells, units, unit_count;
-    DevBuf tiles_prefix;         // plain Gram tile prefix per group
-    DevBuf rb, cb, unit_prefix;  // BF16 fused kernel: row/col blocks and work prefix
+    DevBuf blob;
+    const int64_t *item_src = nullptr, *item_dst = nullptr;
+    const int32_t *item_len = nullptr, *item_group = nullptr;
+    const int64_t *g_item0 = nullptr, *g_n = nullptr, *g_frame0 = nullptr, *g_nframes = nullptr,
+                  *g_pair_base = nullptr, *g_dmat_base = nullptr;
+    const CellDev *cells = nullptr;
+    const int32_t *units = nullptr, *rb = nullptr, *cb = nullptr, *g_rb0 = nullptr, *g_cb0 = nullptr,
+                  *g_ncb = nullptr;
+    const int64_t *unit_prefix = nullptr;
     bool uploaded = false;
 };
 
@@ -147,6 +178,16 @@ struct TaskImpl {
     std::vector<CellDev> cells;
     std::vector<int64_t> n_triplets;
     std::vector<int32_t> keys;      // [n_cells * key_width]
+    std::vector<uint32_t> rkeys;    // dense ranks of the key values, same layout (for collapse)
+    std::vector<int> key_bits;      // bits of each key column's ranks
+
+    // work plans, fixed for the task
+    std::vector<int32_t> units;     // triplet units [n][3]: cell, x_begin, x_end
+    int64_t sum_nx = 0;             // sum over cells of |X|
+    std::vector<int32_t> rb, cb;    // fused kernel row / column blocks [n][4]
+    std::vector<int32_t> g_rb0, g_cb0, g_ncb;
+    std::vector<int64_t> unit_prefix;  // fused work units per group, prefix [n_groups + 1]
+    int64_t fused_cells = 0;        // frame pairs the fused kernel covers
 
     int64_t n_frames = 0;
     int64_t n_pair_slots = 0;       // sum over groups of n_items^2

@@ -72,21 +72,36 @@ __device__ __forceinline__ uint32_t pk_step(uint32_t a) {
     return __builtin_bit_cast(uint32_t, x + inc);
 }
 
-// Stage one K chunk of `nr` rows starting at packed row `row0` into LDS
-// (zero rows beyond nr).  Each 16-byte piece is one load.
+// A K chunk of the tile's rows, held in registers between its global load
+// and its store to LDS: each thread owns kN * kKc / 8 / 256 pieces of 16 bytes.
 template <int kN>
-__device__ __forceinline__ void stage_rows(uint16_t *lds, const uint16_t *__restrict__ xn, int dim_pad,
-                                           int64_t row0, int nr, int k0) {
-    constexpr int kPieces = kN * (kKc / 8);
-    for (int p = threadIdx.x; p < kPieces; p += 256) {
-        const int r = p / (kKc / 8), q = p % (kKc / 8);
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (r < nr) v = *reinterpret_cast<const uint4 *>(xn + (row0 + r) * dim_pad + k0 + q * 8);
-        *reinterpret_cast<uint4 *>(lds + r * kLdsRow + q * 8) = v;
+struct Chunk {
+    static constexpr int kPer = kN * (kKc / 8) / 256;
+    uint4 v[kPer];
+    // rows beyond nr read as zero
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ xn, int dim_pad, int64_t row0, int nr,
+                                         int k0) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            const int r = p / (kKc / 8), q = p % (kKc / 8);
+            v[i] = make_uint4(0, 0, 0, 0);
+            if (r < nr) v[i] = *reinterpret_cast<const uint4 *>(xn + (row0 + r) * dim_pad + k0 + q * 8);
+        }
     }
-}
+    __device__ __forceinline__ void store(uint16_t *lds) const {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            const int r = p / (kKc / 8), q = p % (kKc / 8);
+            *reinterpret_cast<uint4 *>(lds + r * kLdsRow + q * 8) = v[i];
+        }
+    }
+};
 
 // acc0 = rows 0..31, acc1 = rows 32..63 against columns [32w, 32w+32).
+// Software-pipelined: the next K chunk is loaded from memory into registers
+// while the MFMAs consume the current one from LDS.
 __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__restrict__ xn, int dim_pad,
                                           int64_t r0, int nr, int64_t c0, int nc, f32x16 &acc0,
                                           f32x16 &acc1) {
@@ -94,10 +109,18 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
     uint16_t *As = smem;
     uint16_t *Bs = smem + kRows * kLdsRow;
     for (int i = 0; i < 16; ++i) { acc0[i] = 0.0f; acc1[i] = 0.0f; }
+    Chunk<kRows> ca;
+    Chunk<kCols> cb;
+    ca.load(xn, dim_pad, r0, nr, 0);
+    cb.load(xn, dim_pad, c0, nc, 0);
     for (int k0 = 0; k0 < dim_pad; k0 += kKc) {
-        stage_rows<kRows>(As, xn, dim_pad, r0, nr, k0);
-        stage_rows<kCols>(Bs, xn, dim_pad, c0, nc, k0);
+        ca.store(As);
+        cb.store(Bs);
         __syncthreads();
+        if (k0 + kKc < dim_pad) {
+            ca.load(xn, dim_pad, r0, nr, k0 + kKc);
+            cb.load(xn, dim_pad, c0, nc, k0 + kKc);
+        }
 #pragma unroll
         for (int ks = 0; ks < kKc / 16; ++ks) {
             const int kk = ks * 16 + (lane / 32) * 8;
@@ -220,58 +243,52 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     const int64_t gitem0 = g_item0[g];
     const bool row_valid = x_task >= 0;
     const bool top = ir == 0;
+    const bool last_row = row_valid && ir == nx - 1;
+    // The lane below a row item's last row starts another item: share +inf with it
+    // instead of this lane's cost (its up and diagonal neighbours do not exist).
+    const bool send_inf = !row_valid || ir == nx - 1;
+    const float diag_first = top ? 0.0f : kInf;       // virtual c[-1][-1] = 0 at an item start
+    const uint32_t pd_first = top ? 0x0000FFFFu : 0u;  // its length interval: Lmin = Lmax = 0
     const int64_t x_row = row_valid ? (int64_t(x_task) - gitem0) * gn : 0;
     const float *drow = dt + lane * kDStride + s_begin;
 
+    // Cells outside a lane's column range are computed too (on clamped columns)
+    // but never read: the first column of every item resets left and diagonal.
     float c = kInf, up_prev = kInf;
     uint32_t P = 0, Pup_prev = 0;
     const int steps = S + max_n - 1;
     for (int t = 0; t < steps; ++t) {
         const int gcol = t - ir;
-        const bool act = row_valid && gcol >= 0 && gcol < S;
         const int gc = min(max(gcol, 0), S - 1);
         const uint32_t cf = colflag[w][gc];
         const float dv = drow[gc];
         const bool first = cf & 1;
-        float up = shr1(c);
-        uint32_t Pup = kPath ? shr1u(P) : 0u;
-        float diag = up_prev, left = c;
-        uint32_t Pd = Pup_prev, Pl = P;
-        up_prev = up;
-        Pup_prev = Pup;
-        if (top) {
-            up = kInf;
-            diag = first ? 0.0f : kInf;
-            Pd = 0x0000FFFFu;  // virtual start: Lmin = Lmax = 0
-        }
-        if (first) {
-            left = kInf;
-            if (!top) diag = kInf;
-        }
+        const float up = shr1(send_inf ? kInf : c);
+        const uint32_t Pup = kPath ? shr1u(P) : 0u;
+        const float diag = first ? diag_first : up_prev;
+        const float left = first ? kInf : c;
         const float m = fminf(fminf(diag, left), up);
-        float cn = dv + m;
-        uint32_t Pn = 0;
         if (kPath) {
+            const uint32_t Pd = first ? pd_first : Pup_prev;
             const float thr = m + delta;
             const uint32_t sd = diag <= thr ? Pd : 0u;
-            const uint32_t sl = left <= thr ? Pl : 0u;
+            const uint32_t sl = left <= thr ? P : 0u;
             const uint32_t su = up <= thr ? Pup : 0u;
-            Pn = pk_step(pk_max(pk_max(sd, sl), su));
+            P = pk_step(pk_max(pk_max(sd, sl), su));
         }
-        if (act) {
-            c = cn;
-            P = Pn;
-            if ((cf & 2) && ir == nx - 1) {
-                const int64_t slot = pbase + x_row + (int64_t(c_item0) + (cf >> 2) - gitem0);
-                if (kPath) {
-                    const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
-                    p32[slot] = c / float(lmin);
-                    flags[slot] = lmin == lmax ? 0 : 1;
-                    if (lmin != lmax) atomicAdd(nonrobust_n, 1u);
-                } else {
-                    p32[slot] = c;
-                    flags[slot] = 0;
-                }
+        c = dv + m;
+        up_prev = up;
+        Pup_prev = Pup;
+        if ((cf & 2) && last_row && gcol >= 0 && gcol < S) {
+            const int64_t slot = pbase + x_row + (int64_t(c_item0) + (cf >> 2) - gitem0);
+            if (kPath) {
+                const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
+                p32[slot] = c * __builtin_amdgcn_rcpf(float(lmin));
+                flags[slot] = lmin == lmax ? 0 : 1;
+                if (lmin != lmax) atomicAdd(nonrobust_n, 1u);
+            } else {
+                p32[slot] = c;
+                flags[slot] = 0;
             }
         }
     }

@@ -96,26 +96,38 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int L = item_len[item];
     const int64_t s0 = item_src[item], d0 = item_dst[item];
-    for (int t = wave; t < L; t += 4) {
-        const Tin *row = src + (s0 + t) * int64_t(dim);
-        float v[kChunks][4];
-        float ss = 0.0f;
+    // two frames per wave in flight (t and t + 4) to keep more loads outstanding
+    for (int t = wave; t < L; t += 8) {
+        const bool two = t + 4 < L;
+        const Tin *row0 = src + (s0 + t) * int64_t(dim);
+        const Tin *row1 = src + (s0 + (two ? t + 4 : t)) * int64_t(dim);
+        float v[kChunks][4], u[kChunks][4];
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            int k = 4 * (lane + kWave * c);
-            load_row_chunk<Tin>(row, k, dim, v[c]);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) ss = fmaf(v[c][e], v[c][e], ss);
+            const int k = 4 * (lane + kWave * c);
+            load_row_chunk<Tin>(row0, k, dim, v[c]);
+            load_row_chunk<Tin>(row1, k, dim, u[c]);
         }
+        float ss = 0.0f, su = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ss = fmaf(v[c][e], v[c][e], ss);
+                su = fmaf(u[c][e], u[c][e], su);
+            }
         ss = dev::wave_sum(ss);
-        if (!(ss > 0.0f)) {
+        su = dev::wave_sum(su);
+        if (!(ss > 0.0f) || !(su > 0.0f)) {
             if (lane == 0) {
                 atomicExch(err, 1);
                 atomicMin(err_item, (unsigned long long)item);
             }
-            ss = 1.0f;
+            ss = ss > 0.0f ? ss : 1.0f;
+            su = su > 0.0f ? su : 1.0f;
         }
         store_unit_row<kChunks>(v, ss, lane, dim_pad, d0 + t, out, out_bf16, rinv);
+        if (two) store_unit_row<kChunks>(u, su, lane, dim_pad, d0 + t + 4, out, out_bf16, rinv);
     }
     }
 }

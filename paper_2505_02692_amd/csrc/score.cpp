@@ -1,9 +1,12 @@
 // Score orchestration: device tables, workspace, work plans and the launch
 // sequence of one fabx_score call.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 
+#include "host_pool.h"
 #include "kernels.h"
 
 namespace fabx {
@@ -19,94 +22,77 @@ namespace {
 // wide safety factor over the errors measured by the parity tests.
 constexpr double kMarginK = 2e-2;
 constexpr double kDeltaK = 4e-2;
-constexpr int kRowBlock = 64;    // fused kernel: frames per row block
-constexpr int kColBlock = 128;   // fused kernel: frames per column block
-constexpr int64_t kUnitBudget = 8192;  // comparisons per triplet work unit (at least one x)
-
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-template <typename T>
-void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
-    b.ensure(std::max<size_t>(v.size() * sizeof(T), 16));
-    if (!v.empty())
-        FABX_HIP(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
-
-struct Plans {
-    std::vector<int32_t> units;                 // triplets: [n][3]
-    std::vector<int64_t> tiles_prefix;          // Gram tile prefix (plain / pooled)
-    std::vector<int32_t> rb, cb;                // fused: blocks [n][4]
-    std::vector<int32_t> g_rb0, g_cb0, g_nrb, g_ncb;
-    std::vector<int64_t> unit_prefix;
-    int64_t sum_nx = 0;
-    int64_t fused_cells = 0;                    // DTW cells the fused kernel evaluates
+// Collects host arrays (256-byte aligned pieces) and sends them to one device
+// buffer with a single DMA copy through the context's pinned staging buffer.
+struct Packer {
+    struct Piece {
+        const void *src;
+        size_t bytes, off;
+    };
+    std::vector<Piece> pieces;
+    size_t total = 0;
+    template <typename T>
+    size_t add(const T *p, size_t n) {
+        const size_t off = (total + 255) & ~size_t(255);
+        pieces.push_back({p, n * sizeof(T), off});
+        total = off + std::max<size_t>(n * sizeof(T), 16);
+        return off;
+    }
+    template <typename T>
+    size_t add(const std::vector<T> &v) { return add(v.data(), v.size()); }
+    void upload(DevBuf &dst, Staging &stg, hipStream_t s) {
+        dst.ensure(total);
+        std::lock_guard<std::mutex> lk(stg.mu);
+        stg.reserve(total);
+        char *h = static_cast<char *>(stg.host);
+        // host copy into the pinned buffer in 1 MiB slices on the host pool
+        constexpr size_t kSlice = size_t(1) << 20;
+        std::vector<std::pair<size_t, size_t>> slices;  // (piece, offset in piece)
+        for (size_t i = 0; i < pieces.size(); ++i)
+            for (size_t o = 0; o < pieces[i].bytes; o += kSlice) slices.push_back({i, o});
+        HostPool::get().parallel_for(int(slices.size()), [&](int k) {
+            const Piece &p = pieces[slices[size_t(k)].first];
+            const size_t o = slices[size_t(k)].second;
+            std::memcpy(h + p.off + o, static_cast<const char *>(p.src) + o, std::min(kSlice, p.bytes - o));
+        });
+        FABX_HIP(hipMemcpyAsync(dst.ptr, h, total, hipMemcpyHostToDevice, s));
+        FABX_HIP(hipEventRecord(stg.done, s));
+        FABX_HIP(hipEventSynchronize(stg.done));  // the staging buffer is free again
+    }
+    template <typename T>
+    static const T *at(const DevBuf &b, size_t off) {
+        return reinterpret_cast<const T *>(b.as<char>() + off);
+    }
 };
 
-void pack_blocks(const TaskImpl &t, const Group &g, int limit, std::vector<int32_t> &out) {
-    int64_t k = g.item0, end = g.item0 + g.n_items;
-    while (k < end) {
-        int32_t first = int32_t(k), frames = 0, n = 0;
-        while (k < end && frames + t.item_len[k] <= limit) {
-            frames += t.item_len[k];
-            ++n;
-            ++k;
-        }
-        out.insert(out.end(), {int32_t(&g - t.groups.data()), first, n, frames});
-    }
-}
-
-Plans make_plans(const TaskImpl &t, const ScoreParams &p) {
-    Plans pl;
-    // triplet units: split the X set of big cells so one unit does <= kUnitBudget comparisons
-    for (size_t c = 0; c < t.cells.size(); ++c) {
-        const CellDev &cd = t.cells[c];
-        const int64_t per_x = std::max<int64_t>(1, int64_t(cd.na) * cd.nb);
-        const int64_t chunk = std::max<int64_t>(1, kUnitBudget / per_x);
-        for (int64_t x = 0; x < cd.nx; x += chunk)
-            pl.units.insert(pl.units.end(),
-                            {int32_t(c), int32_t(x), int32_t(std::min<int64_t>(cd.nx, x + chunk))});
-        pl.sum_nx += cd.nx;
-    }
+// Gram tile prefix per group for the plain form (64 x 64 tiles of frames) or
+// the pooled mode (64 x 64 FP32 or 64 x 128 BF16 tiles of items).
+std::vector<int64_t> tile_prefix(const TaskImpl &t, const ScoreParams &p) {
     const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
     const int64_t G = int64_t(t.groups.size());
-    if (p.mode == FABX_MODE_DTW && bf16) {
-        pl.unit_prefix.assign(size_t(G + 1), 0);
-        for (int64_t gi = 0; gi < G; ++gi) {
-            const Group &g = t.groups[gi];
-            pl.g_rb0.push_back(int32_t(pl.rb.size() / 4));
-            pl.g_cb0.push_back(int32_t(pl.cb.size() / 4));
-            pack_blocks(t, g, kRowBlock, pl.rb);
-            pack_blocks(t, g, kColBlock, pl.cb);
-            const int32_t nrb = int32_t(pl.rb.size() / 4) - pl.g_rb0.back();
-            const int32_t ncb = int32_t(pl.cb.size() / 4) - pl.g_cb0.back();
-            pl.g_nrb.push_back(nrb);
-            pl.g_ncb.push_back(ncb);
-            pl.unit_prefix[gi + 1] = pl.unit_prefix[gi] + int64_t(nrb) * ncb;
-            pl.fused_cells += g.n_frames * g.n_frames;
-        }
-    } else {
-        // plain Gram tiles (64 x 64), or BF16 pooled tiles (64 x 128)
-        pl.tiles_prefix.assign(size_t(G + 1), 0);
-        for (int64_t gi = 0; gi < G; ++gi) {
-            const Group &g = t.groups[gi];
-            const int64_t n = p.mode == FABX_MODE_DTW ? g.n_frames : g.n_items;
-            const int64_t tr = (n + 63) / 64;
-            const int64_t tc = bf16 ? (n + 127) / 128 : tr;
-            pl.tiles_prefix[gi + 1] = pl.tiles_prefix[gi] + tr * tc;
-        }
+    std::vector<int64_t> pre(size_t(G) + 1, 0);
+    for (int64_t gi = 0; gi < G; ++gi) {
+        const Group &g = t.groups[size_t(gi)];
+        const int64_t n = p.mode == FABX_MODE_DTW ? g.n_frames : g.n_items;
+        const int64_t tr = (n + 63) / 64;
+        const int64_t tc = bf16 ? (n + 127) / 128 : tr;
+        pre[size_t(gi) + 1] = pre[size_t(gi)] + tr * tc;
     }
-    return pl;
+    return pre;
 }
 
 struct Timer {
     hipEvent_t ev[8];
     int n = 0;
     hipStream_t s;
-    explicit Timer(hipStream_t st) : s(st) {
-        for (auto &e : ev) FABX_HIP(hipEventCreate(&e));
+    EventPool &pool;
+    Timer(hipStream_t st, EventPool &p) : s(st), pool(p) {
+        for (auto &e : ev) e = pool.get();
     }
     ~Timer() {
-        for (auto &e : ev) (void)hipEventDestroy(e);
+        for (auto &e : ev) pool.put(e);
     }
     void mark() { FABX_HIP(hipEventRecord(ev[n++], s)); }
     double ms(int a, int b) {
@@ -149,9 +135,8 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
     if (p.mode == FABX_MODE_DTW && !bf16) b += t.n_dmat * 4;
     b += t.n_pair_slots * 4;
     if (bf16) b += t.n_pair_slots * (1 + 8 + 8);
-    int64_t sum_nx = 0;
-    for (auto &c : t.cells) sum_nx += c.nx;
-    b += int64_t(t.cells.size()) * (8 + 32 + 12) + sum_nx * 8 + int64_t(t.items.size()) * 24;
+    b += int64_t(t.cells.size()) * (8 + 32) + int64_t(t.units.size()) * 4 + t.sum_nx * 8 +
+         int64_t(t.items.size()) * 24;
     return b + (1 << 20);
 }
 
@@ -171,6 +156,8 @@ void Workspace::release() {
 
 std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,
                                       hipStream_t stream) {
+    using clock = std::chrono::steady_clock;
+    const auto t_enter = clock::now();
     TaskImpl &t = *tp;
     std::lock_guard<std::mutex> lock(t.mu);
     const DatasetImpl &ds = *t.ds;
@@ -197,22 +184,21 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     const int dim_pad = int(round_up(dim, 64));
     const int64_t n_items = int64_t(t.items.size());
     const int64_t G = int64_t(t.groups.size());
-    Plans pl = make_plans(t, p);
-    const int64_t n_units = int64_t(pl.units.size() / 3);
+    Trace tr("score");
+    const int64_t n_units = int64_t(t.units.size() / 3);
+    const bool plain_tiles = !(dtw && bf16);
+    const std::vector<int64_t> tiles = plain_tiles ? tile_prefix(t, p) : std::vector<int64_t>();
+    tr.mark("plans");
 
-    // ---- device tables (items / groups / cells are fixed for the task)
+    // ---- device tables (items / groups / cells are fixed for the task): one copy
     TaskDevice &dv = t.dev;
-    for (DevBuf *b : {&dv.item_src, &dv.item_len, &dv.item_dst, &dv.item_group, &dv.g_item0, &dv.g_n,
-                      &dv.g_frame0, &dv.g_nframes, &dv.g_pair_base, &dv.g_dmat_base, &dv.cells})
-        if (!b->ptr) b->pool = &ds.ctx->pool;
+    Pool *pool = &ds.ctx->pool;
+    if (!dv.blob.ptr) dv.blob.pool = pool;
     for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
                       &t.ws.half_units, &t.ws.counters, &t.ws.recheck_list, &t.ws.recount_list})
-        if (!b->ptr) b->pool = &ds.ctx->pool;
+        if (!b->ptr) b->pool = pool;
+    Packer pk;
     if (!dv.uploaded) {
-        upload(dv.item_src, t.item_src, stream);
-        upload(dv.item_len, t.item_len, stream);
-        upload(dv.item_dst, t.item_dst, stream);
-        upload(dv.item_group, t.item_group, stream);
         const size_t ng = static_cast<size_t>(G);
         std::vector<int64_t> a(ng), b(ng + 1), c(ng), d(ng), e(ng), f(ng + 1);
         for (int64_t i = 0; i < G; ++i) {
@@ -225,28 +211,52 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
         }
         b[G] = 0;
         f[G] = t.n_pair_slots;
-        upload(dv.g_item0, a, stream);
-        upload(dv.g_n, b, stream);
-        upload(dv.g_frame0, c, stream);
-        upload(dv.g_nframes, d, stream);
-        upload(dv.g_dmat_base, e, stream);
-        upload(dv.g_pair_base, f, stream);
-        upload(dv.cells, t.cells, stream);
+        const size_t o_src = pk.add(t.item_src), o_len = pk.add(t.item_len), o_dst = pk.add(t.item_dst),
+                     o_grp = pk.add(t.item_group), o_a = pk.add(a), o_b = pk.add(b), o_c = pk.add(c),
+                     o_d = pk.add(d), o_e = pk.add(e), o_f = pk.add(f), o_cells = pk.add(t.cells),
+                     o_units = pk.add(t.units), o_rb = pk.add(t.rb), o_cb = pk.add(t.cb),
+                     o_up = pk.add(t.unit_prefix), o_grb = pk.add(t.g_rb0), o_gcb = pk.add(t.g_cb0),
+                     o_gncb = pk.add(t.g_ncb);
+        pk.upload(dv.blob, ds.ctx->staging, stream);
+        dv.item_src = Packer::at<int64_t>(dv.blob, o_src);
+        dv.item_len = Packer::at<int32_t>(dv.blob, o_len);
+        dv.item_dst = Packer::at<int64_t>(dv.blob, o_dst);
+        dv.item_group = Packer::at<int32_t>(dv.blob, o_grp);
+        dv.g_item0 = Packer::at<int64_t>(dv.blob, o_a);
+        dv.g_n = Packer::at<int64_t>(dv.blob, o_b);
+        dv.g_frame0 = Packer::at<int64_t>(dv.blob, o_c);
+        dv.g_nframes = Packer::at<int64_t>(dv.blob, o_d);
+        dv.g_dmat_base = Packer::at<int64_t>(dv.blob, o_e);
+        dv.g_pair_base = Packer::at<int64_t>(dv.blob, o_f);
+        dv.cells = Packer::at<CellDev>(dv.blob, o_cells);
+        dv.units = Packer::at<int32_t>(dv.blob, o_units);
+        dv.rb = Packer::at<int32_t>(dv.blob, o_rb);
+        dv.cb = Packer::at<int32_t>(dv.blob, o_cb);
+        dv.unit_prefix = Packer::at<int64_t>(dv.blob, o_up);
+        dv.g_rb0 = Packer::at<int32_t>(dv.blob, o_grb);
+        dv.g_cb0 = Packer::at<int32_t>(dv.blob, o_gcb);
+        dv.g_ncb = Packer::at<int32_t>(dv.blob, o_gncb);
         dv.uploaded = true;
     }
-    DevBuf units_d, tiles_d, rb_d, cb_d, up_d, grb_d, gcb_d, gncb_d;
-    Pool *pool = &ds.ctx->pool;
-    for (DevBuf *b : {&units_d, &tiles_d, &rb_d, &cb_d, &up_d, &grb_d, &gcb_d, &gncb_d}) b->pool = pool;
-    upload(units_d, pl.units, stream);
-    if (!pl.tiles_prefix.empty()) upload(tiles_d, pl.tiles_prefix, stream);
-    if (!pl.unit_prefix.empty()) {
-        upload(rb_d, pl.rb, stream);
-        upload(cb_d, pl.cb, stream);
-        upload(up_d, pl.unit_prefix, stream);
-        upload(grb_d, pl.g_rb0, stream);
-        upload(gcb_d, pl.g_cb0, stream);
-        upload(gncb_d, pl.g_ncb, stream);
+    // Gram tile prefix of this score (plain form / pooled mode only)
+    DevBuf plan_d;
+    plan_d.pool = pool;
+    // on an error after launches, drain the stream before plan_d goes back to the pool
+    struct DrainOnError {
+        hipStream_t s;
+        ~DrainOnError() {
+            if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s);
+        }
+    } drain{stream};
+    const int64_t *tiles_p = nullptr;
+    if (plain_tiles) {
+        Packer pp;
+        const size_t o_tiles = pp.add(tiles);
+        pp.upload(plan_d, ds.ctx->staging, stream);
+        tiles_p = Packer::at<int64_t>(plan_d, o_tiles);
     }
+    tr.mark("upload");
+    const int32_t *units_p = dv.units;
 
     // ---- workspace
     Workspace &ws = t.ws;
@@ -259,7 +269,7 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
         ws.flags.ensure(size_t(t.n_pair_slots));
         ws.p64.ensure(size_t(t.n_pair_slots) * 8);
         ws.recheck_list.ensure(size_t(t.n_pair_slots) * 8);
-        ws.recount_list.ensure(size_t(pl.sum_nx) * 8);
+        ws.recount_list.ensure(size_t(std::max<int64_t>(t.sum_nx, 1)) * 8);
     }
     ws.half_units.ensure(size_t(n_cells) * 8);
     ws.counters.ensure(64);
@@ -270,13 +280,13 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 24);
     st.workspace_bytes = int64_t(ws.total());
 
-    kern::ItemTables it{dv.item_src.as<int64_t>(), dv.item_len.as<int32_t>(), dv.item_dst.as<int64_t>(),
-                        n_items};
-    kern::GroupTables gt{dv.g_item0.as<int64_t>(), dv.g_n.as<int64_t>(), dv.g_frame0.as<int64_t>(),
-                         dv.g_nframes.as<int64_t>(), dv.g_pair_base.as<int64_t>(),
-                         dv.g_dmat_base.as<int64_t>(), G, t.n_pair_slots};
+    kern::ItemTables it{dv.item_src, dv.item_len, dv.item_dst, n_items};
+    kern::GroupTables gt{dv.g_item0, dv.g_n, dv.g_frame0, dv.g_nframes, dv.g_pair_base, dv.g_dmat_base,
+                         G, t.n_pair_slots};
 
-    Timer tm(stream);
+    Timer tm(stream, ds.ctx->events);
+    tr.mark("workspace");
+    const auto t_launch = clock::now();
     tm.mark();  // 0
     FABX_HIP(hipMemsetAsync(ws.counters.ptr, 0, 64, stream));
     FABX_HIP(hipMemsetAsync(err_item, 0xFF, 8, stream));
@@ -292,36 +302,36 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     tm.mark();  // 2
     if (dtw && !bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.frame0, gt.n_frames, gt.dmat_base,
-                               tiles_d.as<int64_t>(), G, pl.tiles_prefix.back(), ws.dmat.as<float>());
+                               tiles_p, G, tiles.back(), ws.dmat.as<float>());
         kern::dtw_plain(stream, ws.dmat.as<float>(), gt, it, p.dtw_norm, ws.p32.as<float>());
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw) {
-        kern::FusedPlan fp{rb_d.as<int32_t>(), cb_d.as<int32_t>(), up_d.as<int64_t>(), grb_d.as<int32_t>(),
-                           gcb_d.as<int32_t>(), nullptr, gncb_d.as<int32_t>(), pl.unit_prefix.back()};
+        kern::FusedPlan fp{dv.rb, dv.cb, dv.unit_prefix, dv.g_rb0, dv.g_cb0, nullptr, dv.g_ncb,
+                           t.unit_prefix.back()};
         kern::fused_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt, it, fp,
                          p.dtw_norm, float(p.delta), ws.p32.as<float>(), ws.flags.as<uint8_t>(),
                          nonrobust_n);
-        st.computed_dtw_cells = pl.fused_cells;
+        st.computed_dtw_cells = t.fused_cells;
     } else if (!bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.item0, gt.n_items, gt.pair_base,
-                               tiles_d.as<int64_t>(), G, pl.tiles_prefix.back(), ws.p32.as<float>());
+                               tiles_p, G, tiles.back(), ws.p32.as<float>());
     } else {
         kern::gram_angular_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt.item0,
-                                gt.n_items, gt.pair_base, tiles_d.as<int64_t>(), G,
-                                pl.tiles_prefix.back(), ws.p32.as<float>());
+                                gt.n_items, gt.pair_base, tiles_p, G,
+                                tiles.back(), ws.p32.as<float>());
     }
     tm.mark();  // 3
-    kern::triplets(stream, dv.cells.as<CellDev>(), units_d.as<int32_t>(), n_units, gt,
+    kern::triplets(stream, dv.cells, units_p, n_units, gt,
                    ws.p32.as<float>(), ws.half_units.as<unsigned long long>(),
                    bf16 ? ws.flags.as<uint8_t>() : nullptr, float(p.margin),
-                   bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, pl.sum_nx);
+                   bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, t.sum_nx);
     tm.mark();  // 4
     if (bf16) {
         kern::collect_marked(stream, ws.flags.as<uint8_t>(), t.n_pair_slots, ws.recheck_list.as<int64_t>(),
                              marked_n, t.n_pair_slots);
         kern::recheck_fp64(stream, ds.features, ds.dtype, dim, gt, it, ws.recheck_list.as<int64_t>(),
                            marked_n, t.n_pair_slots, p.mode, p.dtw_norm, ws.p64.as<double>());
-        kern::recount(stream, dv.cells.as<CellDev>(), ws.recount_list.as<int32_t>(), recount_n, pl.sum_nx,
+        kern::recount(stream, dv.cells, ws.recount_list.as<int32_t>(), recount_n, t.sum_nx,
                       gt, ws.p32.as<float>(), ws.p64.as<double>(), ws.flags.as<uint8_t>(),
                       ws.half_units.as<unsigned long long>());
     }
@@ -332,6 +342,8 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     FABX_HIP(hipMemcpyAsync(counters, ws.counters.ptr, 64, hipMemcpyDeviceToHost, stream));
     tm.mark();  // 6
     FABX_HIP(hipStreamSynchronize(stream));
+    const auto t_synced = clock::now();
+    tr.mark("gpu");
     int err_h;
     unsigned long long err_item_h;
     unsigned int recount_h, marked_h, nonrobust_h;
@@ -364,6 +376,8 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
             FABX_HIP(hipMemcpy(res->p64.data(), ws.p64.ptr, res->p64.size() * 8, hipMemcpyDeviceToHost));
         }
     }
+    st.ms_host_setup = std::chrono::duration<double, std::milli>(t_launch - t_enter).count();
+    st.ms_host_finish = std::chrono::duration<double, std::milli>(clock::now() - t_synced).count();
     return res;
 }
 

@@ -33,6 +33,9 @@ struct Job {
     int code = FABX_OK;
     std::string msg;
     Clock::time_point t_submit, t_done;
+    // recorded on the context's stream at submit: the job's stream waits for it,
+    // so the job reads features produced there before the submit call
+    hipEvent_t ready = nullptr;
 };
 
 }  // namespace
@@ -52,6 +55,11 @@ struct ServerImpl {
     std::vector<double> latencies_ms;
     bool stop = false;
 
+    void drop_event(Job &j) {
+        if (j.ready) ctx->events.put(j.ready);
+        j.ready = nullptr;
+    }
+
     void worker(size_t k) {
         (void)hipSetDevice(ctx->device);
         std::unique_lock<std::mutex> lk(mu);
@@ -66,6 +74,7 @@ struct ServerImpl {
                 // cancel what is still queued
                 for (uint64_t id : queue) {
                     jobs[id].state = JobState::Cancelled;
+                    drop_event(jobs[id]);
                     ++cancelled;
                 }
                 queue.clear();
@@ -81,11 +90,13 @@ struct ServerImpl {
             ++running;
             auto task = job.task;
             auto params = job.params;
+            const hipEvent_t ready = job.ready;
             lk.unlock();
             std::shared_ptr<ResultImpl> res;
             int code = FABX_OK;
             std::string msg;
             try {
+                FABX_HIP(hipStreamWaitEvent(streams[k], ready, 0));
                 res = run_score(task, params, streams[k]);
             } catch (const Error &e) {
                 code = e.code;
@@ -94,6 +105,9 @@ struct ServerImpl {
                 code = FABX_ENOMEM;
                 msg = e.what();
             }
+            // nothing of the job may still run on the stream (a failed call can leave
+            // launches behind) before its memory and its event are reused
+            (void)hipStreamSynchronize(streams[k]);
             // the result keeps per-cell counts on the host; give the device memory back
             {
                 std::lock_guard<std::mutex> g(task->mu);
@@ -101,6 +115,7 @@ struct ServerImpl {
             }
             lk.lock();
             Job &j2 = jobs[id];
+            drop_event(j2);
             j2.t_done = Clock::now();
             in_use -= j2.footprint;
             --running;
@@ -196,9 +211,19 @@ int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int
         if (job.footprint > s.budget)
             fail(FABX_ENOMEM, "job footprint " + std::to_string(job.footprint) +
                                   " bytes exceeds the server budget");
+        FABX_HIP(hipSetDevice(s.ctx->device));
+        job.ready = s.ctx->events.get();
+        if (hipEventRecord(job.ready, s.ctx->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            s.ctx->events.put(job.ready);
+            fail(FABX_EHIP, "recording the submit event on the context's stream failed");
+        }
         job.t_submit = Clock::now();
         std::lock_guard<std::mutex> lk(s.mu);
-        if (s.stop) fail(FABX_ECANCELED, "server is stopping");
+        if (s.stop) {
+            s.drop_event(job);
+            fail(FABX_ECANCELED, "server is stopping");
+        }
         const uint64_t id = s.next_id++;
         s.jobs.emplace(id, std::move(job));
         s.queue.push_back(id);
@@ -265,6 +290,7 @@ int fabx_server_cancel(fabx_server *srv, uint64_t job_id) {
     }
     s.queue.erase(std::find(s.queue.begin(), s.queue.end(), job_id));
     it->second.state = JobState::Cancelled;
+    s.drop_event(it->second);
     ++s.cancelled;
     s.cv.notify_all();
     return FABX_OK;

@@ -12,6 +12,7 @@
 #include <numeric>
 #include <thread>
 
+#include "host_pool.h"
 #include "internal.h"
 
 namespace fabx {
@@ -94,15 +95,8 @@ struct ClassRun {
 
 template <typename F>
 void parallel_for(int n, F &&f) {
-    if (n <= 1) {
-        if (n == 1) f(0);
-        return;
-    }
-    std::vector<std::thread> th;
-    th.reserve(size_t(n - 1));
-    for (int k = 1; k < n; ++k) th.emplace_back([&f, k] { f(k); });
-    f(0);
-    for (auto &x : th) x.join();
+    const std::function<void(int)> fn = f;
+    HostPool::get().parallel_for(n, fn);
 }
 
 // Output of one thread's share of the group walk (group ids and pair-slot
@@ -111,17 +105,23 @@ struct WalkOut {
     std::vector<CellDev> cells;
     std::vector<int64_t> ntrip;
     std::vector<int32_t> keys;
+    std::vector<uint32_t> rkeys;
+    std::vector<int32_t> units;                     // [n][3], cell ids local to this share
     std::vector<Group> groups;
     std::vector<std::pair<int64_t, int64_t>> kept;  // sorted-order range of each kept group
-    int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, pair_slots = 0;
+    int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, pair_slots = 0, sum_nx = 0;
     void swap(WalkOut &o) {
         cells.swap(o.cells);
         ntrip.swap(o.ntrip);
         keys.swap(o.keys);
+        rkeys.swap(o.rkeys);
+        units.swap(o.units);
         groups.swap(o.groups);
         kept.swap(o.kept);
     }
 };
+
+constexpr int64_t kUnitBudget = 8192;  // comparisons per triplet work unit (at least one x)
 
 struct WalkCtx {
     const DatasetImpl *ds;
@@ -129,6 +129,7 @@ struct WalkCtx {
     const std::vector<int64_t> *order;
     const std::vector<uint64_t> *by_part, *cls_part;
     const std::vector<uint32_t> *on_rank;
+    const std::vector<const std::vector<uint32_t> *> *by_rank, *across_rank;
     const std::vector<int64_t> *pf, *pq;
     int32_t on;
     int32_t n_across;
@@ -188,6 +189,22 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, WalkOut &out)
             for (int32_t b : t.by) out.keys.push_back(ka[b]);
             for (int32_t a : t.across) out.keys.push_back(ka[a]);
             for (int32_t a : t.across) out.keys.push_back(kx[a]);
+            const int64_t ia0 = cls[ia].first, ib0 = cls[ib].first, ix0 = cls[ix].first;
+            out.rkeys.push_back((*w.on_rank)[ia0]);
+            out.rkeys.push_back((*w.on_rank)[ib0]);
+            for (auto *r : *w.by_rank) out.rkeys.push_back((*r)[ia0]);
+            for (auto *r : *w.across_rank) out.rkeys.push_back((*r)[ia0]);
+            for (auto *r : *w.across_rank) out.rkeys.push_back((*r)[ix0]);
+            // triplet work units: split X so one unit does <= kUnitBudget comparisons
+            const int64_t per_x = std::max<int64_t>(1, int64_t(c.na) * c.nb);
+            const int64_t chunk = std::max<int64_t>(1, kUnitBudget / per_x);
+            const int32_t cid = int32_t(out.cells.size() - 1);
+            for (int64_t x = 0; x < c.nx; x += chunk) {
+                out.units.push_back(cid);
+                out.units.push_back(int32_t(x));
+                out.units.push_back(int32_t(std::min<int64_t>(c.nx, x + chunk)));
+            }
+            out.sum_nx += c.nx;
             if (use_need) {
                 need[size_t(ix * K + ia)] = 1;
                 need[size_t(ix * K + ib)] = 1;
@@ -301,6 +318,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     for (int32_t c : t->across) t->key_attr.push_back(c);
     t->key_width = int32_t(t->key_attr.size());
 
+    Trace tr("task");
     const int64_t n = ds->n_items;
     // ---- composite key: by fields (high), on, across fields (low)
     std::vector<RankedColumn> rby(t->by.size()), racr(t->across.size());
@@ -323,6 +341,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     int total_bits = low_bits;
     for (auto &r : rby) total_bits += r.bits;
 
+    tr.mark("rank");
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), int64_t(0));
     std::vector<uint64_t> by_part(n, 0), cls_part(n, 0);   // BY tuple id / (on, across) class id
@@ -378,6 +397,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         return true;
     };
 
+    tr.mark("sort");
     // ---- per sorted position: length, and prefix sums of frames and squared lengths
     std::vector<int32_t> len_s(static_cast<size_t>(n));
     std::vector<int64_t> pf(static_cast<size_t>(n) + 1, 0), pq(static_cast<size_t>(n) + 1, 0);
@@ -389,28 +409,42 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     }
 
     // ---- walk the groups: chunks of whole groups in parallel, then stitch
-    const int n_threads = int(std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()),
-                                                std::max<int64_t>(1, n / 4096)));
-    std::vector<int64_t> cut(size_t(n_threads) + 1, n);
+    const int n_threads = int(std::min<int64_t>(HostPool::get().size(), std::max<int64_t>(1, n / 4096)));
+    // more shares than threads: the pool hands them out dynamically (group sizes vary)
+    const int n_shares = int(std::min<int64_t>(4 * int64_t(n_threads), std::max<int64_t>(1, n / 1024)));
+    std::vector<int64_t> cut(size_t(n_shares) + 1, n);
     cut[0] = 0;
-    for (int k = 1; k < n_threads; ++k) {
-        int64_t c = std::max(cut[k - 1], n * k / n_threads);
+    for (int k = 1; k < n_shares; ++k) {
+        int64_t c = std::max(cut[k - 1], n * k / n_shares);
         while (c > 0 && c < n && by_part[c] == by_part[c - 1]) ++c;   // move to a group start
         cut[k] = c;
     }
-    std::vector<WalkOut> parts(static_cast<size_t>(n_threads));
-    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, &ron.rank, &pf, &pq, on, n_across,
-               across_cmp, across_all_differ};
-    parallel_for(n_threads, [&](int k) { walk_groups(wc, cut[k], cut[k + 1], parts[size_t(k)]); });
+    std::vector<WalkOut> parts(static_cast<size_t>(n_shares));
+    std::vector<const std::vector<uint32_t> *> by_rank_p, across_rank_p;
+    for (auto &r : rby) by_rank_p.push_back(&r.rank);
+    for (auto &r : racr) across_rank_p.push_back(&r.rank);
+    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, &ron.rank, &by_rank_p, &across_rank_p,
+               &pf, &pq, on, n_across, across_cmp, across_all_differ};
+    t->key_bits = {ron.bits, ron.bits};
+    for (auto &r : rby) t->key_bits.push_back(r.bits);
+    for (auto &r : racr) t->key_bits.push_back(r.bits);
+    for (auto &r : racr) t->key_bits.push_back(r.bits);
+    parallel_for(n_shares, [&](int k) { walk_groups(wc, cut[k], cut[k + 1], parts[size_t(k)]); });
 
+    tr.mark("walk");
     size_t n_cells = 0, n_groups = 0;
     for (auto &p : parts) {
         n_cells += p.cells.size();
         n_groups += p.groups.size();
     }
+    size_t n_unit_ints = 0;
+    for (auto &p : parts) n_unit_ints += p.units.size();
     t->cells.resize(n_cells);
     t->n_triplets.resize(n_cells);
     t->keys.resize(n_cells * size_t(t->key_width));
+    t->rkeys.resize(n_cells * size_t(t->key_width));
+    t->units.resize(n_unit_ints);
+    std::vector<size_t> unit_off(parts.size());
     t->groups.resize(n_groups);
     std::vector<std::pair<int64_t, int64_t>> kept(n_groups);
     std::vector<size_t> cell_off(parts.size()), group_off(parts.size());
@@ -424,14 +458,20 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             slot_off[k] = so;
             co += parts[k].cells.size();
             go += parts[k].groups.size();
+            t->sum_nx += parts[k].sum_nx;
             so += parts[k].pair_slots;
             t->total_triplets += parts[k].total_triplets;
             t->n_pairs_needed += parts[k].pairs_needed;
             t->dtw_cells_needed += parts[k].dtw_needed;
         }
         t->n_pair_slots = so;
+        size_t uo = 0;
+        for (size_t k = 0; k < parts.size(); ++k) {
+            unit_off[k] = uo;
+            uo += parts[k].units.size();
+        }
     }
-    parallel_for(int(parts.size()), [&](int k) {
+    parallel_for(n_shares, [&](int k) {
         WalkOut &p = parts[size_t(k)];
         for (size_t c = 0; c < p.cells.size(); ++c) {
             CellDev cd = p.cells[c];
@@ -440,6 +480,12 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         }
         std::copy(p.ntrip.begin(), p.ntrip.end(), t->n_triplets.begin() + long(cell_off[size_t(k)]));
         std::copy(p.keys.begin(), p.keys.end(), t->keys.begin() + long(cell_off[size_t(k)] * size_t(t->key_width)));
+        std::copy(p.rkeys.begin(), p.rkeys.end(), t->rkeys.begin() + long(cell_off[size_t(k)] * size_t(t->key_width)));
+        for (size_t u = 0; u < p.units.size(); u += 3) {
+            t->units[unit_off[size_t(k)] + u] = p.units[u] + int32_t(cell_off[size_t(k)]);
+            t->units[unit_off[size_t(k)] + u + 1] = p.units[u + 1];
+            t->units[unit_off[size_t(k)] + u + 2] = p.units[u + 2];
+        }
         for (size_t g = 0; g < p.groups.size(); ++g) {
             Group gg = p.groups[g];
             gg.pair_base += slot_off[size_t(k)];
@@ -449,6 +495,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         WalkOut().swap(p);
     });
 
+    tr.mark("stitch");
     // ---- task items in task order, packed frame offsets
     int64_t nt = 0, frame_total = 0;
     for (size_t gi = 0; gi < t->groups.size(); ++gi) {
@@ -491,7 +538,40 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     });
     for (int ml : max_len_part) t->max_len = std::max(t->max_len, ml);
     const int64_t frame = frame_total;
+
+    // fused-kernel blocks: whole items packed into <= 64-frame row blocks and
+    // <= 128-frame column blocks per group; work units = row x column blocks
+    t->unit_prefix.assign(size_t(G) + 1, 0);
+    for (int64_t gi = 0; gi < G; ++gi) {
+        const Group &g = t->groups[size_t(gi)];
+        t->g_rb0.push_back(int32_t(t->rb.size() / 4));
+        t->g_cb0.push_back(int32_t(t->cb.size() / 4));
+        for (int pass = 0; pass < 2; ++pass) {
+            const int limit = pass == 0 ? kFusedRowFrames : kFusedColFrames;
+            std::vector<int32_t> &out = pass == 0 ? t->rb : t->cb;
+            int64_t k = g.item0;
+            const int64_t end = g.item0 + g.n_items;
+            while (k < end) {
+                const int32_t first = int32_t(k);
+                int32_t frames = 0, cnt = 0;
+                // at least one item per block (an item above the limit is only legal in
+                // pooled mode, which does not use these blocks)
+                while (k < end && (cnt == 0 || frames + t->item_len[size_t(k)] <= limit)) {
+                    frames += t->item_len[size_t(k)];
+                    ++cnt;
+                    ++k;
+                }
+                out.insert(out.end(), {int32_t(gi), first, cnt, frames});
+            }
+        }
+        const int32_t nrb = int32_t(t->rb.size() / 4) - t->g_rb0.back();
+        const int32_t ncb = int32_t(t->cb.size() / 4) - t->g_cb0.back();
+        t->g_ncb.push_back(ncb);
+        t->unit_prefix[size_t(gi) + 1] = t->unit_prefix[size_t(gi)] + int64_t(nrb) * ncb;
+        t->fused_cells += g.n_frames * g.n_frames;
+    }
     t->n_frames = frame;
+    tr.mark("items");
     return t;
 }
 

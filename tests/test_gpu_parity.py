@@ -338,6 +338,50 @@ def test_server_rejects_oversized_job():
     srv.close()
 
 
+# ------------------------------------------------------- stream ordering --
+
+def _slow_producer(dst, src):
+    """Enqueue on torch's current stream about 0.1 s of matrix products, then the
+    copy src -> dst, and return without waiting: whoever reads dst next must be
+    ordered after this work on the stream."""
+    a = torch.randn(8192, 8192, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(12):
+        torch.mm(a, a, out=c)
+    dst.copy_(src)
+
+
+def _ordering_case(seed):
+    w = workloads.within_c2(n_items=20000, dim=256, centroid_std=0.08, seed=seed, device="cuda")
+    ds_ref = fx.Dataset(ctx(), w.features, w.offsets, w.attrs)
+    want = fx.Task(ds_ref, w.on, w.by, w.across).score().half_units.copy()
+    # valid features of the wrong frames until the producer's copy lands
+    buf = torch.roll(w.features, 1, dims=0).contiguous()
+    torch.cuda.synchronize()
+    return w, want, buf
+
+
+def test_score_is_ordered_after_producer_on_stream():
+    _say("stream order: score")
+    w, want, buf = _ordering_case(41)
+    _slow_producer(buf, w.features)
+    ds = fx.Dataset(ctx(), buf, w.offsets, w.attrs)
+    got = fx.Task(ds, w.on, w.by, w.across).score().half_units
+    assert np.array_equal(got, want)
+
+
+def test_server_job_is_ordered_after_producer_on_stream():
+    _say("stream order: server")
+    w, want, buf = _ordering_case(42)
+    srv = fx.Server(ctx(), hbm_budget_bytes=8 << 30, n_streams=2)
+    _slow_producer(buf, w.features)
+    ds = fx.Dataset(ctx(), buf, w.offsets, w.attrs)
+    jid = srv.submit(ds, w.on, w.by, w.across)
+    _, got, _, _ = srv.wait(jid)
+    srv.close()
+    assert np.array_equal(got, want)
+
+
 # ------------------------------------------ large groups, sampled pairs --
 
 @pytest.mark.parametrize("n_items", [12000, 24000, None])
