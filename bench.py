@@ -40,14 +40,49 @@ def _stage_means(results):
     return {k: float(np.mean([r[k] for r in results])) for k in keys}
 
 
-def run_steps(fx, ds, w, precision, n, sync):
+# Workloads this bench can time.  The default, "c2", is the headline one; the
+# others exist to profile the kernels on large BY groups and the pooled mode.
+WORKLOADS = {
+    "c2": ("within_c2", "dtw", "within-speaker triphone task: 100k items, 40 labels, BY prev/next/speaker, "
+           "lengths 5-25 (median 9), dim 768 fp32, DTW, path-normalised angular"),
+    "c3": ("across_c3", "dtw", "across-speaker triphone task: 200k items, 40 labels, 100 speakers, BY prev/next "
+           "ACROSS speaker, lengths 3-40, dim 1024 fp32, DTW, path-normalised angular"),
+    "c4": ("batched_c4", "dtw", "batched uneven groups: 5000 BY groups of Zipf(1.1) sizes 2-2000 items, lengths "
+           "1-60, dim 512 bf16, DTW, path-normalised angular"),
+    "c4-pooled": ("batched_c4", "pooled", "batched uneven groups (as c4), mean-pooled mode: one vector per item"),
+}
+
+
+def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw"):
+    """n steps with host and device work overlapped across steps: while the
+    device scores step i (fabx_score_async), the host builds the task of step
+    i + 1 and collapses the result of step i - 1.  Every step still runs the
+    whole path on its own task."""
+    stats, errs = [], []
+    t0 = time.perf_counter()
+    prev = None
+    for _ in range(n):
+        task = fx.Task(ds, w.on, w.by, w.across)
+        res = task.score_async(mode=mode, precision=precision)
+        if prev is not None:
+            errs.append(prev.collapse(w.levels))
+            stats.append(prev.stats)
+        prev = res
+    if prev is not None:
+        errs.append(prev.collapse(w.levels))
+        stats.append(prev.stats)
+    sync()
+    return time.perf_counter() - t0, stats, errs
+
+
+def run_steps(fx, ds, w, precision, n, sync, mode="dtw"):
     stats, errs = [], []
     t0 = time.perf_counter()
     for _ in range(n):
         ta = time.perf_counter()
         task = fx.Task(ds, w.on, w.by, w.across)
         tb = time.perf_counter()
-        res = task.score(mode="dtw", precision=precision)
+        res = task.score(mode=mode, precision=precision)
         tc = time.perf_counter()
         errs.append(res.collapse(w.levels))
         td = time.perf_counter()
@@ -147,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
+                    help="c2 (default) is the headline workload; c3 / c4 / c4-pooled profile large groups")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run 3 plain device copies of this many MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -174,18 +211,25 @@ def main():
         sync()
         log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB (read + write each)")
         del src, dst
-    w = workloads.within_c2(device="cuda")
+    gen_name, mode, wl_desc = WORKLOADS[args.workload]
+    headline = args.workload == "c2"
+    w = getattr(workloads, gen_name)(device="cuda")
     ctx = fx.Context(0)
     ds = fx.Dataset(ctx, w.features, w.offsets, w.attrs)
-    log(f"workload ready: {w.n_items} items, {w.n_frames} frames, dim {w.dim}")
+    log(f"workload {args.workload} ready: {w.n_items} items, {w.n_frames} frames, dim {w.dim}")
 
-    run_steps(fx, ds, w, "bf16", args.warmup, sync)
+    run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode)
     sync()
     log("warmup done")
-    dt, stats, errs = run_steps(fx, ds, w, "bf16", args.steps, sync)
-    log(f"bf16 form: {dt / args.steps * 1e3:.2f} ms/step, stages {_stage_means(stats)}")
-    st0 = stats[-1]
+    dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode)
     ms_step = dt / args.steps * 1e3
+    log(f"bf16 form, pipelined: {ms_step:.2f} ms/step")
+    # the same steps one after another, for the per-stage breakdown
+    sdt, stats, serrs = run_steps(fx, ds, w, "bf16", args.steps, sync, mode)
+    ms_step_serial = sdt / args.steps * 1e3
+    log(f"bf16 form, serial: {ms_step_serial:.2f} ms/step, stages {_stage_means(stats)}")
+    assert errs[-1] == serrs[-1]
+    st0 = stats[-1]
     n_trip = st0["n_triplets"]
     value = n_trip / (ms_step / 1e3)
     stages = _stage_means(stats)
@@ -196,13 +240,15 @@ def main():
         t_build.append((time.perf_counter() - t0) * 1e3)
 
     plain = None
-    if not args.no_plain:
-        run_steps(fx, ds, w, "fp32", 1, sync)
-        pdt, pstats, perrs = run_steps(fx, ds, w, "fp32", args.steps, sync)
+    if not args.no_plain and headline:
+        run_pipelined(fx, ds, w, "fp32", 1, sync, mode)
+        pdt, _, perrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode)
         pms = pdt / args.steps * 1e3
+        psdt, pstats, _ = run_steps(fx, ds, w, "fp32", args.steps, sync, mode)
         pst = _stage_means(pstats)
-        log(f"fp32 form: {pms:.2f} ms/step, stages {pst}")
+        log(f"fp32 form: {pms:.2f} ms/step pipelined, {psdt / args.steps * 1e3:.2f} serial, stages {pst}")
         plain = {"triplets_per_s": n_trip / (pms / 1e3), "ms_per_step": pms,
+                 "ms_per_step_serial": psdt / args.steps * 1e3,
                  "gcups": pstats[-1]["dtw_cells"] / (pms / 1e3) / 1e9,
                  "gpu_ms": pst["ms_total"], "gpu_triplets_per_s": n_trip / (pst["ms_total"] / 1e3),
                  "abx_error": perrs[-1], "stages_ms": pst}
@@ -210,8 +256,10 @@ def main():
     # roofline of the dominant kernel, from the live HIP-event stage times
     dim, dim_pad = w.dim, (w.dim + 63) // 64 * 64
     nf = st0["n_frames"]
-    norm_bytes = nf * dim * 4 + nf * dim_pad * 2 + nf * 4
-    dist_flops = 2.0 * dim * st0["dtw_cells"]
+    in_bytes = w.features.element_size()
+    rows = nf if mode == "dtw" else st0["n_items"]
+    norm_bytes = (nf * dim * in_bytes) + rows * dim_pad * 2 + rows * 4
+    dist_flops = 2.0 * dim * (st0["dtw_cells"] if mode == "dtw" else st0["n_pairs"])
     if stages["ms_normalize"] >= stages["ms_distance"]:
         ach = norm_bytes / (stages["ms_normalize"] / 1e3) / 1e9
         roof = {"kernel": "k_normalize", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
@@ -219,17 +267,17 @@ def main():
                 "algorithmic_bytes_per_launch": norm_bytes}
     else:
         ach = dist_flops / (stages["ms_distance"] / 1e3) / 1e12
-        roof = {"kernel": "k_fused", "bound": "mfma", "achieved": ach, "peak": MFMA_BF16_PEAK_TFLOPS,
+        roof = {"kernel": "k_fused" if mode == "dtw" else "k_gram_angular_bf16", "bound": "mfma", "achieved": ach, "peak": MFMA_BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
                 "algorithmic_flops_per_launch": dist_flops}
 
     serving = None
-    if args.serve_jobs > 0:
+    if args.serve_jobs > 0 and headline:
         serving = serving_stream(fx, ctx, torch, workloads, args.serve_jobs)
         log(f"serving: {serving}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and headline:
         import oracle
         cpu = cpu_baseline(oracle, w)
         log(f"cpu baseline: {cpu}")
@@ -242,13 +290,15 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_serial": ms_step_serial,
+        "triplets_per_s_serial": n_trip / (ms_step_serial / 1e3),
+        "pipelined": "host work of neighbouring steps overlaps device work (fabx_score_async)",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic (seeded Gaussian SSL-like features, see DESIGN.md)",
-        "config": {"workload": "within-speaker triphone task: 100k items, 40 labels, BY prev/next/speaker, "
-                               "lengths 5-25 (median 9), dim 768 fp32, DTW, path-normalised angular",
+        "config": {"workload": wl_desc,
                    "cells": st0["n_cells"], "triplets": n_trip, "dtw_cells": st0["dtw_cells"],
                    "parallelism": "single GPU"},
         "gcups": st0["dtw_cells"] / (ms_step / 1e3) / 1e9,

@@ -186,6 +186,23 @@ int fabx_score_opts_default(fabx_score_opts *opts);
  * Synchronous on the context stream.  Errors: EINVAL (bad opts), EDOMAIN
  * (zero-norm frame / mean), ENOMEM (device workspace), EHIP. */
 int fabx_score(fabx_task *task, const fabx_score_opts *opts, fabx_result **out);
+
+/* The same score, returned as soon as its work is enqueued on the context
+ * stream (task tables are uploaded first if the task has not been scored
+ * before).  The result completes in fabx_result_wait, or implicitly in the
+ * first fabx_result_cells / _pairs / _stats / fabx_collapse call; num_cells,
+ * key_width and cell_keys do not wait.  Errors found on completion (EDOMAIN,
+ * EHIP) are returned there, every time it is asked.  A later score of the
+ * same task first waits for this one (the task's device workspace is reused).
+ * Freeing a pending result waits for its work.  Lets a caller build the next
+ * task or collapse the previous result while the device works.  Errors at
+ * launch: EINVAL, ENOMEM, EHIP. */
+int fabx_score_async(fabx_task *task, const fabx_score_opts *opts, fabx_result **out);
+
+/* Wait for a result and report its status (FABX_OK at once for a finished
+ * result).  Errors: EINVAL (NULL), EDOMAIN, EHIP. */
+int fabx_result_wait(fabx_result *res);
+
 void fabx_result_free(fabx_result *res);
 
 /* Number of cells of the scored task, and its cell keys (same layout as

@@ -126,6 +126,16 @@ def fabx_score(t, opts: fabx_score_opts) -> ctypes.c_void_p:
     return h
 
 
+def fabx_score_async(t, opts: fabx_score_opts) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().fabx_score_async(t, ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def fabx_result_wait(r) -> None:
+    _check(lib().fabx_result_wait(r))
+
+
 def fabx_result_free(r) -> None:
     lib().fabx_result_free(r)
 
@@ -306,6 +316,11 @@ class Task:
     def score(self, **kw) -> "Result":
         return Result(self, fabx_score(self.h, make_opts(**kw)))
 
+    def score_async(self, **kw) -> "Result":
+        """Enqueue the score and return at once; the result completes on wait()
+        or on first use."""
+        return Result(self, fabx_score_async(self.h, make_opts(**kw)))
+
     def __del__(self):
         if getattr(self, "h", None) and L is not None and L._lib is not None:
             fabx_task_destroy(self.h)
@@ -316,7 +331,24 @@ class Result:
     def __init__(self, task: Task, h):
         self.task = task
         self.h = h
-        self.half_units, self.n_triplets, self.scores = fabx_result_cells(h, len(task))
+        self._cells = None
+
+    def _get_cells(self):
+        if self._cells is None:
+            self._cells = fabx_result_cells(self.h, len(self.task))
+        return self._cells
+
+    @property
+    def half_units(self) -> np.ndarray:
+        return self._get_cells()[0]
+
+    @property
+    def n_triplets(self) -> np.ndarray:
+        return self._get_cells()[1]
+
+    @property
+    def scores(self) -> np.ndarray:
+        return self._get_cells()[2]
 
     @property
     def stats(self) -> dict:
@@ -327,6 +359,10 @@ class Result:
 
     def collapse(self, levels=None) -> float:
         return fabx_collapse(self.h, levels)
+
+    def wait(self) -> "Result":
+        fabx_result_wait(self.h)
+        return self
 
     def __del__(self):
         if getattr(self, "h", None) and L is not None and L._lib is not None:

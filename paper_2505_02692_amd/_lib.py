@@ -84,6 +84,8 @@ SIGNATURES = {
     "fabx_task_cell_sizes": (ctypes.c_int, [_vp, _P(_i64), _P(_i32)]),
     "fabx_score_opts_default": (ctypes.c_int, [_P(fabx_score_opts)]),
     "fabx_score": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
+    "fabx_score_async": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
+    "fabx_result_wait": (ctypes.c_int, [_vp]),
     "fabx_result_free": (None, [_vp]),
     "fabx_result_num_cells": (_i64, [_vp]),
     "fabx_result_key_width": (_i32, [_vp]),

@@ -131,6 +131,48 @@ void Staging::reserve(size_t n) {
     cap = want;
 }
 
+void *PinnedPool::get(size_t n, size_t *got) {
+    n = std::max<size_t>(n, 4096);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        size_t best = free_blocks.size();
+        for (size_t i = 0; i < free_blocks.size(); ++i)
+            if (free_blocks[i].first >= n && free_blocks[i].first <= 2 * n &&
+                (best == free_blocks.size() || free_blocks[i].first < free_blocks[best].first))
+                best = i;
+        if (best != free_blocks.size()) {
+            auto b = free_blocks[best];
+            free_blocks.erase(free_blocks.begin() + long(best));
+            cached -= b.first;
+            *got = b.first;
+            return b.second;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(FABX_ENOMEM, "pinned host allocation of " + std::to_string(n) + " bytes failed");
+    }
+    *got = n;
+    return p;
+}
+
+void PinnedPool::put(void *p, size_t n) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cached + n <= (size_t(256) << 20)) {
+            free_blocks.push_back({n, p});
+            cached += n;
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
+PinnedPool::~PinnedPool() {
+    for (auto &b : free_blocks) (void)hipHostFree(b.second);
+}
+
 Staging::~Staging() {
     if (host) (void)hipHostFree(host);
     if (done) (void)hipEventDestroy(done);
@@ -293,6 +335,23 @@ int fabx_score(fabx_task *t, const fabx_score_opts *opts, fabx_result **out) {
     });
 }
 
+int fabx_score_async(fabx_task *t, const fabx_score_opts *opts, fabx_result **out) {
+    return guarded([&] {
+        if (!t || !out) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        ScoreParams p = resolve_opts(opts, *t->p->ds);
+        auto r = launch_score(t->p, p, t->p->ds->ctx->stream);
+        *out = new fabx_result{r};
+    });
+}
+
+int fabx_result_wait(fabx_result *r) {
+    return guarded([&] {
+        if (!r) fail(FABX_EINVAL, "null result");
+        finish_score(*r->p);
+    });
+}
+
 void fabx_result_free(fabx_result *r) { delete r; }
 
 int64_t fabx_result_num_cells(const fabx_result *r) { return r ? int64_t(r->p->half_units.size()) : -1; }
@@ -310,6 +369,7 @@ int fabx_result_cell_keys(const fabx_result *r, int32_t *out) {
 int fabx_result_cells(const fabx_result *r, int64_t *half_units, int64_t *n_triplets, double *score) {
     return guarded([&] {
         if (!r) fail(FABX_EINVAL, "null result");
+        finish_score(*r->p);
         const auto &R = *r->p;
         const auto &T = *R.task;
         for (size_t c = 0; c < R.half_units.size(); ++c) {
@@ -324,6 +384,7 @@ int fabx_result_pairs(const fabx_result *r, int64_t n, const int64_t *xs, const 
                       float *out_f32, uint8_t *flags, double *out_f64) {
     return guarded([&] {
         if (!r || (n > 0 && (!xs || !ys || !out_f32))) fail(FABX_EINVAL, "null argument");
+        finish_score(*r->p);
         const auto &R = *r->p;
         if (!R.has_pairs) fail(FABX_EINVAL, "result was scored without keep_pairs");
         const auto &T = *R.task;
@@ -347,6 +408,7 @@ int fabx_result_pairs(const fabx_result *r, int64_t n, const int64_t *xs, const 
 int fabx_result_stats(const fabx_result *r, fabx_stats *st) {
     return guarded([&] {
         if (!r || !st) fail(FABX_EINVAL, "null argument");
+        finish_score(*r->p);
         *st = r->p->stats;
     });
 }
@@ -356,6 +418,7 @@ int fabx_collapse(const fabx_result *r, const int32_t *level_attr, const int32_t
     return guarded([&] {
         if (!r || !error_rate) fail(FABX_EINVAL, "null argument");
         if (n_levels < 0 || (n_levels > 0 && (!level_attr || !level_len))) fail(FABX_EINVAL, "bad levels");
+        finish_score(*r->p);
         *error_rate = collapse(*r->p, level_attr, level_len, n_levels);
     });
 }

@@ -4,12 +4,13 @@
 // offers cell-size weighting or averaging level by level).  FP64 on the host.
 //
 // Level by level: every key value is replaced by its dense rank (computed by
-// the task builder); for a level, the ranks of the columns that remain are
-// packed into one key.  Rows with equal keys are averaged (unweighted, summed
-// in row order): when the key space is small, through a direct table indexed
-// by the key (one pass, no sort), otherwise after a stable radix sort.  The
-// averaged rows, in key order, carry on to the next level; the last rows are
-// averaged flat.
+// the task builder); for a level, the ranks of the columns that remain form
+// one key.  Rows with equal keys are averaged (unweighted): when the key space
+// is small, through a direct table indexed by the mixed-radix key (one pass,
+// no sort; with many rows per key, fixed row ranges are accumulated in
+// parallel and merged in range order), otherwise after a stable radix sort of
+// the bit-packed key (summed in row order).  The averaged rows, in key order,
+// carry on to the next level; the last rows are averaged flat.
 #include <algorithm>
 #include <numeric>
 
@@ -51,12 +52,16 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
     }
     Trace tr("collapse");
     const size_t K = size_t(t.key_width);
-    // rows: dense ranks of the key values (from the task builder), row-major [m x K]
-    const uint32_t *rows = t.rkeys.data();
-    std::vector<uint32_t> own;  // rows after the first level
+    // Dense ranks of the key values (from the task builder), row-major [n x K].
+    // A row after a level stands for a run of cells that agree on every column
+    // still present, so it is represented by one of those cells (rep[i]) and
+    // its ranks are read from that cell's row.
+    const uint32_t *R = t.rkeys.data();
+    hvec<uint32_t> rep(n);
+    std::iota(rep.begin(), rep.end(), 0u);
     std::vector<size_t> cols(K);  // key columns still present
     std::iota(cols.begin(), cols.end(), size_t(0));
-    std::vector<double> score(n);
+    hvec<double> score(n);
     for (size_t i = 0; i < n; ++i) score[i] = double(res.half_units[i]) / (2.0 * double(t.n_triplets[i]));
     for (const auto &lv : levels) {
         std::vector<size_t> kept;
@@ -65,70 +70,98 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
         int total_bits = 0;
         for (size_t c : kept) total_bits += t.key_bits[c];
         const size_t m = score.size();
-        std::vector<double> nscore;
-        std::vector<uint32_t> nrows;
-        auto pack = [&](size_t i) {
-            uint64_t k = 0;
-            for (size_t c : kept)
-                if (t.key_bits[c]) k = (k << t.key_bits[c]) | rows[i * K + c];
-            return k;
-        };
-        if (total_bits <= 22 && (uint64_t(1) << total_bits) <= 8 * uint64_t(m) + 4096) {
-            // direct table: sum and count per key, first row of each key for its ranks
-            const size_t nk = size_t(1) << total_bits;
-            std::vector<double> sum(nk, 0.0);
-            std::vector<uint32_t> cnt(nk, 0), first(nk, 0);
-            for (size_t i = 0; i < m; ++i) {
-                const uint64_t k = pack(i);
-                if (cnt[k]++ == 0) first[k] = uint32_t(i);
-                sum[k] += score[i];
-            }
+        hvec<double> nscore;
+        hvec<uint32_t> nrep;
+        auto rank = [&](size_t i, size_t c) { return R[size_t(rep[i]) * K + c]; };
+        uint64_t space = 1;  // mixed-radix key space of the kept columns
+        for (size_t c : kept) space = std::min<uint64_t>(space * std::max<uint32_t>(t.key_card[c], 1), uint64_t(1) << 40);
+        if (space <= (uint64_t(1) << 24) && space <= 2 * uint64_t(m) + 4096) {
+            struct Acc {
+                double sum;
+                uint32_t cnt, first;
+            };
+            auto mixed = [&](size_t i) {
+                uint64_t k = 0;
+                for (size_t c : kept) k = k * t.key_card[c] + rank(i, c);
+                return k;
+            };
+            const size_t nk = size_t(space);
+            // Many rows per key: fixed row ranges (independent of the thread count)
+            // fill tables in parallel, merged in range order.
+            const size_t n_tab = m >= 16 * nk && m >= (size_t(1) << 18) ? 8 : 1;
+            std::vector<hvec<Acc>> tabs(n_tab);
+            auto fill = [&](size_t r) {
+                hvec<Acc> &tab = tabs[r];
+                tab.assign(nk, Acc{0.0, 0u, 0u});
+                const size_t i0 = m * r / n_tab, i1 = m * (r + 1) / n_tab;
+                for (size_t i = i0; i < i1; ++i) {
+                    Acc &a = tab[mixed(i)];
+                    if (a.cnt++ == 0) a.first = uint32_t(i);
+                    a.sum += score[i];
+                }
+            };
+            if (n_tab > 1) HostPool::get().parallel_for(int(n_tab), [&](int r) { fill(size_t(r)); });
+            else fill(0);
+            hvec<Acc> &tab = tabs[0];
+            for (size_t r = 1; r < n_tab; ++r)
+                for (size_t k = 0; k < nk; ++k) {
+                    const Acc &b = tabs[r][k];
+                    if (!b.cnt) continue;
+                    Acc &a = tab[k];
+                    if (!a.cnt) a.first = b.first;
+                    a.cnt += b.cnt;
+                    a.sum += b.sum;
+                }
             nscore.reserve(m);
-            nrows.reserve(m * K);
+            nrep.reserve(m);
             for (size_t k = 0; k < nk; ++k)
-                if (cnt[k]) {
-                    nscore.push_back(sum[k] / double(cnt[k]));
-                    nrows.insert(nrows.end(), rows + size_t(first[k]) * K, rows + size_t(first[k]) * K + K);
+                if (tab[k].cnt) {
+                    nscore.push_back(tab[k].sum / double(tab[k].cnt));
+                    nrep.push_back(rep[tab[k].first]);
                 }
         } else {
-            std::vector<uint32_t> order(m);
+            hvec<uint32_t> order(m);
             std::iota(order.begin(), order.end(), 0u);
-            std::vector<uint64_t> key(m, 0);
+            hvec<uint64_t> key(m);
             if (total_bits <= 64) {
-                for (size_t i = 0; i < m; ++i) key[i] = pack(i);
+                for (size_t i = 0; i < m; ++i) {
+                    uint64_t k = 0;
+                    for (size_t c : kept)
+                        if (t.key_bits[c]) k = (k << t.key_bits[c]) | rank(i, c);
+                    key[i] = k;
+                }
                 radix_sort_pairs(key, order, total_bits);
             } else {
                 std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
                     for (size_t c : kept)
-                        if (rows[a * K + c] != rows[b * K + c]) return rows[a * K + c] < rows[b * K + c];
+                        if (rank(a, c) != rank(b, c)) return rank(a, c) < rank(b, c);
                     return false;
                 });
                 uint64_t id = 0;  // run ids as keys
                 for (size_t i = 0; i < m; ++i) {
                     if (i > 0)
                         for (size_t c : kept)
-                            if (rows[size_t(order[i]) * K + c] != rows[size_t(order[i - 1]) * K + c]) {
+                            if (rank(order[i], c) != rank(order[i - 1], c)) {
                                 ++id;
                                 break;
                             }
                     key[i] = id;
                 }
             }
-            // average each run of equal keys; the new rows keep the ranks of the kept columns
+            // average each run of equal keys, summed in row order
             nscore.reserve(m);
-            nrows.reserve(m * K);
+            nrep.reserve(m);
             for (size_t i = 0; i < m;) {
                 size_t j = i;
                 double sacc = 0.0;
                 while (j < m && key[j] == key[i]) sacc += score[order[j++]];
                 nscore.push_back(sacc / double(j - i));
-                nrows.insert(nrows.end(), rows + size_t(order[i]) * K, rows + size_t(order[i]) * K + K);
+                nrep.push_back(rep[order[i]]);
                 i = j;
             }
         }
         score.swap(nscore);
-        own.swap(nrows);
-        rows = own.data();
+        rep.swap(nrep);
         cols = kept;
         tr.mark("level");
     }

@@ -9,14 +9,14 @@ namespace fabx {
 
 // Stable LSD radix sort of (key, idx) pairs by a key of `key_bits` bits
 // (12-bit digits, only the digits the key uses).  Ties keep their input order.
-template <typename Idx>
-void radix_sort_pairs(std::vector<uint64_t> &key, std::vector<Idx> &idx, int key_bits) {
+template <typename KeyVec, typename IdxVec>
+void radix_sort_pairs(KeyVec &key, IdxVec &idx, int key_bits) {
     constexpr int kDigit = 12;
     constexpr size_t kBuckets = size_t(1) << kDigit;
     const size_t n = key.size();
     if (key_bits <= 0 || n < 2) return;
-    std::vector<uint64_t> k2(n);
-    std::vector<Idx> i2(n);
+    KeyVec k2(n);
+    IdxVec i2(n);
     std::vector<size_t> count(kBuckets + 1);
     for (int shift = 0; shift < key_bits; shift += kDigit) {
         std::fill(count.begin(), count.end(), 0);

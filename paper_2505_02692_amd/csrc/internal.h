@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fastabx.h"
+#include "host_pool.h"
 
 namespace fabx {
 
@@ -80,6 +81,18 @@ struct Staging {
     ~Staging();
 };
 
+// Pinned host blocks for device-to-host result copies, cached by size class
+// (so a result can be copied back asynchronously without a hipHostMalloc per
+// score).
+struct PinnedPool {
+    std::mutex mu;
+    std::vector<std::pair<size_t, void *>> free_blocks;  // (bytes, ptr)
+    size_t cached = 0;
+    void *get(size_t n, size_t *got);
+    void put(void *p, size_t n);
+    ~PinnedPool();
+};
+
 struct CtxImpl {
     int device = 0;
     hipStream_t stream = nullptr;  // borrowed; nullptr = the null stream
@@ -87,6 +100,7 @@ struct CtxImpl {
     Pool pool;
     EventPool events;
     Staging staging;
+    PinnedPool pinned;
     ~CtxImpl();
 };
 
@@ -159,6 +173,8 @@ struct Workspace {
     void release();
 };
 
+struct ResultImpl;
+
 struct TaskImpl {
     std::shared_ptr<DatasetImpl> ds;
     int32_t on = 0;
@@ -167,26 +183,27 @@ struct TaskImpl {
     int32_t key_width = 0;
 
     // task items (those in groups with cells), in task order
-    std::vector<int64_t> items;     // original ids
-    std::vector<int32_t> item_len;
-    std::vector<int64_t> item_src;  // first source frame
-    std::vector<int64_t> item_dst;  // first packed frame
-    std::vector<int32_t> item_group;
-    std::vector<int64_t> item_pos_of;  // original id -> task position, -1 if absent
+    hvec<int64_t> items;     // original ids
+    hvec<int32_t> item_len;
+    hvec<int64_t> item_src;  // first source frame
+    hvec<int64_t> item_dst;  // first packed frame
+    hvec<int32_t> item_group;
+    hvec<int64_t> item_pos_of;  // original id -> task position, -1 if absent
 
-    std::vector<Group> groups;
-    std::vector<CellDev> cells;
-    std::vector<int64_t> n_triplets;
-    std::vector<int32_t> keys;      // [n_cells * key_width]
-    std::vector<uint32_t> rkeys;    // dense ranks of the key values, same layout (for collapse)
+    hvec<Group> groups;
+    hvec<CellDev> cells;
+    hvec<int64_t> n_triplets;
+    hvec<int32_t> keys;      // [n_cells * key_width]
+    hvec<uint32_t> rkeys;    // dense ranks of the key values, same layout (for collapse)
     std::vector<int> key_bits;      // bits of each key column's ranks
+    std::vector<uint32_t> key_card; // distinct values of each key column (ranks are 0 .. card - 1)
 
     // work plans, fixed for the task
-    std::vector<int32_t> units;     // triplet units [n][3]: cell, x_begin, x_end
+    hvec<int32_t> units;     // triplet units [n][3]: cell, x_begin, x_end
     int64_t sum_nx = 0;             // sum over cells of |X|
-    std::vector<int32_t> rb, cb;    // fused kernel row / column blocks [n][4]
+    hvec<int32_t> rb, cb;    // fused kernel row / column blocks [n][4]
     std::vector<int32_t> g_rb0, g_cb0, g_ncb;
-    std::vector<int64_t> unit_prefix;  // fused work units per group, prefix [n_groups + 1]
+    hvec<int64_t> unit_prefix;  // fused work units per group, prefix [n_groups + 1]
     int64_t fused_cells = 0;        // frame pairs the fused kernel covers
 
     int64_t n_frames = 0;
@@ -199,17 +216,28 @@ struct TaskImpl {
 
     TaskDevice dev;
     Workspace ws;
-    std::mutex mu;                  // one score at a time per task
+    std::mutex mu;                  // one score launch at a time per task
+    std::weak_ptr<ResultImpl> pending;  // the score whose kernels may still use ws
 };
+
+struct PendingScore;  // launched work of a score not finished yet (score.cpp)
 
 struct ResultImpl {
     std::shared_ptr<TaskImpl> task;
-    std::vector<int64_t> half_units;
+    hvec<int64_t> half_units;
     fabx_stats stats{};
     bool has_pairs = false;
-    std::vector<float> p32;
-    std::vector<uint8_t> flags;
-    std::vector<double> p64;
+    hvec<float> p32;
+    hvec<uint8_t> flags;
+    hvec<double> p64;
+    // Completion: a launched score stays pending until finish_score; its
+    // status (an error found on completion) is kept and reported again.
+    std::mutex mu;
+    std::unique_ptr<PendingScore> pending;
+    int status = FABX_OK;
+    std::string status_msg;
+    ResultImpl();
+    ~ResultImpl();
 };
 
 // task.cpp
@@ -224,6 +252,13 @@ struct ScoreParams {
     bool keep_pairs;
 };
 ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds);
+// launch_score enqueues the whole score on `stream` and returns a pending
+// result; finish_score waits for it and fills the result (idempotent, throws
+// the score's error every time it is called on a failed result).  run_score
+// is both.
+std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &task, const ScoreParams &p,
+                                         hipStream_t stream);
+void finish_score(ResultImpl &res);
 std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &task, const ScoreParams &p,
                                       hipStream_t stream);
 // Device bytes a score of this task would hold (admission control).

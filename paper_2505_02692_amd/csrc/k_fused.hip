@@ -50,15 +50,18 @@ constexpr int kKc = 64;               // K chunk (bf16 elements) staged in LDS
 constexpr int kLdsRow = kKc + 8;      // padded LDS row of a K chunk (bf16)
 constexpr int kDStride = kCols + 2;   // LDS distance tile stride (floats)
 constexpr int kStageBytes = (kRows + kCols) * kLdsRow * 2;
-constexpr int kTileBytes = kRows * kDStride * 4;
+// distance tile + a tail guard: the DTW loop reads up to 63 columns past a row's end
+constexpr int kTileBytes = (kRows * kDStride + kWave) * 4;
+constexpr int kFlagLen = kWave + kCols + kWave;  // column flags with a zero guard on each side
 constexpr int kSmemBytes = kStageBytes > kTileBytes ? kStageBytes : kTileBytes;
 
-__device__ __forceinline__ float shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(v), 0x138,
+// Value of lane - 1 (DPP wave_shr:1); lane 0, which has no source, keeps `old`.
+__device__ __forceinline__ float shr1(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138,
                                                       0xf, 0xf, false));
 }
-__device__ __forceinline__ uint32_t shr1u(uint32_t v) {
-    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xf, 0xf, false));
+__device__ __forceinline__ uint32_t shr1u(uint32_t old, uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(int(old), int(v), 0x138, 0xf, 0xf, false));
 }
 
 __device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
@@ -101,11 +104,15 @@ struct Chunk {
 
 // acc0 = rows 0..31, acc1 = rows 32..63 against columns [32w, 32w+32).
 // Software-pipelined: the next K chunk is loaded from memory into registers
-// while the MFMAs consume the current one from LDS.
+// while the MFMAs consume the current one from LDS.  A wave whose columns all
+// lie past nc skips its MFMAs, and so does the second row half when nr <= 32
+// (those accumulators are never read).
 __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__restrict__ xn, int dim_pad,
                                           int64_t r0, int nr, int64_t c0, int nc, f32x16 &acc0,
                                           f32x16 &acc1) {
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const bool do0 = 32 * w < nc, do1 = do0 && nr > 32;
     uint16_t *As = smem;
     uint16_t *Bs = smem + kRows * kLdsRow;
     for (int i = 0; i < 16; ++i) { acc0[i] = 0.0f; acc1[i] = 0.0f; }
@@ -121,14 +128,18 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
             ca.load(xn, dim_pad, r0, nr, k0 + kKc);
             cb.load(xn, dim_pad, c0, nc, k0 + kKc);
         }
+        if (do0) {
 #pragma unroll
-        for (int ks = 0; ks < kKc / 16; ++ks) {
-            const int kk = ks * 16 + (lane / 32) * 8;
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + (lane % 32) * kLdsRow + kk);
-            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(As + (32 + lane % 32) * kLdsRow + kk);
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (32 * w + lane % 32) * kLdsRow + kk);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc1, 0, 0, 0);
+            for (int ks = 0; ks < kKc / 16; ++ks) {
+                const int kk = ks * 16 + (lane / 32) * 8;
+                const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + (lane % 32) * kLdsRow + kk);
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (32 * w + lane % 32) * kLdsRow + kk);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc0, 0, 0, 0);
+                if (do1) {
+                    const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(As + (32 + lane % 32) * kLdsRow + kk);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc1, 0, 0, 0);
+                }
+            }
         }
         __syncthreads();
     }
@@ -156,13 +167,14 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
                                                   uint8_t *__restrict__ flags,
                                                   unsigned int *__restrict__ nonrobust_n) {
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kSmemBytes];
-    __shared__ uint16_t colflag[4][kCols];
+    __shared__ uint16_t colflag[4][kFlagLen];
     // Persistent blocks, XCD-aware order: the 8 XCDs take blocks round-robin,
     // so XCD x works through the contiguous unit range [x * grid_q, (x+1) * grid_q)
     // (units of one group share its frames in that XCD's L2).  gridDim.x is a
     // multiple of 8.
     const int64_t xcd = blockIdx.x % 8, m = blockIdx.x / 8, n_m = gridDim.x / 8;
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     for (int64_t j = m; j < grid_q; j += n_m) {
     const int64_t unit = xcd * grid_q + j;
     if (unit >= n_units) continue;  // uniform across the block
@@ -180,18 +192,26 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     gram_tile(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
               c_frames, acc0, acc1);
 
-    // 2. epilogue -> LDS distance tile (the staging buffers are dead now)
+    // 2. epilogue -> LDS distance tile (the staging buffers are dead now).  Only
+    // the rows and column waves that hold frames are written; the DTW reads the
+    // others only in lanes and steps whose results are discarded.
     float *dt = reinterpret_cast<float *>(smem_raw);
-    {
+    if (32 * w < c_frames) {
         const int col = 32 * w + lane % 32;
         const float rc = col < c_frames ? rinv[c_frame0 + col] : 0.0f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int r0 = acc_row(i, lane), r1 = 32 + r0;
+            const int r0 = acc_row(i, lane);
             const float rr0 = r0 < r_frames ? rinv[r_frame0 + r0] : 0.0f;
-            const float rr1 = r1 < r_frames ? rinv[r_frame0 + r1] : 0.0f;
             dt[r0 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc0[i] * rr0 * rc, -1.0f), 1.0f));
-            dt[r1 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc1[i] * rr1 * rc, -1.0f), 1.0f));
+        }
+        if (r_frames > 32) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r1 = 32 + acc_row(i, lane);
+                const float rr1 = r1 < r_frames ? rinv[r_frame0 + r1] : 0.0f;
+                dt[r1 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc1[i] * rr1 * rc, -1.0f), 1.0f));
+            }
         }
     }
 
@@ -223,12 +243,15 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
             }
             start += L;
         }
+        // column c of this wave's span is entry kWave + c; the guards read as 0
+        // (no item start, no output).  Same-wave LDS stores land in issue order.
+        for (int j = lane; j < kFlagLen; j += kWave) colflag[w][j] = 0;
         if (seen) {
             int start2 = s_begin;
             for (int k = y_begin; k < y_end; ++k) {
                 const int L = item_len[c_item0 + k];
                 for (int j = lane; j < L; j += kWave)
-                    colflag[w][start2 - s_begin + j] =
+                    colflag[w][kWave + start2 - s_begin + j] =
                         uint16_t((j == 0 ? 1 : 0) | (j == L - 1 ? 2 : 0) | (k << 2));
                 start2 += L;
             }
@@ -250,21 +273,24 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     const float diag_first = top ? 0.0f : kInf;       // virtual c[-1][-1] = 0 at an item start
     const uint32_t pd_first = top ? 0x0000FFFFu : 0u;  // its length interval: Lmin = Lmax = 0
     const int64_t x_row = row_valid ? (int64_t(x_task) - gitem0) * gn : 0;
-    const float *drow = dt + lane * kDStride + s_begin;
+    // at step t the lane is on column t - ir of the wave's span: distance
+    // dcol[t], flags fcol[t].  ir <= lane, so dcol[0] is inside the tile; the
+    // last step reads at most max_n - 2 columns past the span, within the guard.
+    const float *dcol = dt + lane * kDStride + s_begin - ir;
+    const uint16_t *fcol = &colflag[w][kWave - ir];
+    const uint32_t out_bit = last_row ? 2u : 0u;
 
-    // Cells outside a lane's column range are computed too (on clamped columns)
+    // Cells outside a lane's column range are computed too (on guard columns)
     // but never read: the first column of every item resets left and diagonal.
-    float c = kInf, up_prev = kInf;
-    uint32_t P = 0, Pup_prev = 0;
+    float c = kInf, up = kInf, up_prev = kInf;  // lane 0 keeps up = +inf (no row above)
+    uint32_t P = 0, Pup = 0, Pup_prev = 0;
     const int steps = S + max_n - 1;
     for (int t = 0; t < steps; ++t) {
-        const int gcol = t - ir;
-        const int gc = min(max(gcol, 0), S - 1);
-        const uint32_t cf = colflag[w][gc];
-        const float dv = drow[gc];
+        const uint32_t cf = fcol[t];
+        const float dv = dcol[t];
         const bool first = cf & 1;
-        const float up = shr1(send_inf ? kInf : c);
-        const uint32_t Pup = kPath ? shr1u(P) : 0u;
+        up = shr1(up, send_inf ? kInf : c);
+        if (kPath) Pup = shr1u(Pup, P);
         const float diag = first ? diag_first : up_prev;
         const float left = first ? kInf : c;
         const float m = fminf(fminf(diag, left), up);
@@ -279,7 +305,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
         c = dv + m;
         up_prev = up;
         Pup_prev = Pup;
-        if ((cf & 2) && last_row && gcol >= 0 && gcol < S) {
+        if (cf & out_bit) {
             const int64_t slot = pbase + x_row + (int64_t(c_item0) + (cf >> 2) - gitem0);
             if (kPath) {
                 const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);

@@ -40,8 +40,8 @@ struct Packer {
         total = off + std::max<size_t>(n * sizeof(T), 16);
         return off;
     }
-    template <typename T>
-    size_t add(const std::vector<T> &v) { return add(v.data(), v.size()); }
+    template <typename T, typename A>
+    size_t add(const std::vector<T, A> &v) { return add(v.data(), v.size()); }
     void upload(DevBuf &dst, Staging &stg, hipStream_t s) {
         dst.ensure(total);
         std::lock_guard<std::mutex> lk(stg.mu);
@@ -154,12 +154,46 @@ void Workspace::release() {
     for (auto *b : all) b->release();
 }
 
-std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,
-                                      hipStream_t stream) {
+// Launched work of a score, kept until finish_score.
+struct PendingScore {
+    std::shared_ptr<TaskImpl> task;
+    std::shared_ptr<CtxImpl> ctx;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<Timer> tm;
+    DevBuf plan_d;                 // Gram tile prefix read by the plain / pooled kernels
+    void *host = nullptr;          // pinned: half_units [n_cells] then 64 counter bytes
+    size_t host_bytes = 0;
+    bool bf16 = false, dtw = false, keep_pairs = false;
+    std::chrono::steady_clock::time_point t_enter, t_launch;
+    ~PendingScore() {
+        if (host) ctx->pinned.put(host, host_bytes);
+    }
+};
+
+ResultImpl::ResultImpl() = default;
+
+ResultImpl::~ResultImpl() {
+    // a result dropped while its kernels run must not let the memory go first
+    try {
+        finish_score(*this);
+    } catch (...) {
+    }
+}
+
+std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,
+                                         hipStream_t stream) {
     using clock = std::chrono::steady_clock;
     const auto t_enter = clock::now();
     TaskImpl &t = *tp;
     std::lock_guard<std::mutex> lock(t.mu);
+    // the workspace is reused: the task's previous score must have completed
+    if (auto prev = t.pending.lock()) {
+        try {
+            finish_score(*prev);
+        } catch (const Error &) {
+            // that score's error stays with its own result
+        }
+    }
     const DatasetImpl &ds = *t.ds;
     auto res = std::make_shared<ResultImpl>();
     res->task = tp;
@@ -178,8 +212,16 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     if (ds.ctx->device < 0) fail(FABX_EINVAL, "context has no device (host-only context)");
     FABX_HIP(hipSetDevice(ds.ctx->device));
 
+    auto pend = std::make_unique<PendingScore>();
+    pend->task = tp;
+    pend->ctx = ds.ctx;
+    pend->stream = stream;
+    pend->t_enter = t_enter;
     const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
     const bool dtw = p.mode == FABX_MODE_DTW;
+    pend->bf16 = bf16;
+    pend->dtw = dtw;
+    pend->keep_pairs = p.keep_pairs;
     const int dim = ds.dim;
     const int dim_pad = int(round_up(dim, 64));
     const int64_t n_items = int64_t(t.items.size());
@@ -197,8 +239,8 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
                       &t.ws.half_units, &t.ws.counters, &t.ws.recheck_list, &t.ws.recount_list})
         if (!b->ptr) b->pool = pool;
-    Packer pk;
     if (!dv.uploaded) {
+        Packer pk;
         const size_t ng = static_cast<size_t>(G);
         std::vector<int64_t> a(ng), b(ng + 1), c(ng), d(ng), e(ng), f(ng + 1);
         for (int64_t i = 0; i < G; ++i) {
@@ -239,15 +281,8 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
         dv.uploaded = true;
     }
     // Gram tile prefix of this score (plain form / pooled mode only)
-    DevBuf plan_d;
+    DevBuf &plan_d = pend->plan_d;
     plan_d.pool = pool;
-    // on an error after launches, drain the stream before plan_d goes back to the pool
-    struct DrainOnError {
-        hipStream_t s;
-        ~DrainOnError() {
-            if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s);
-        }
-    } drain{stream};
     const int64_t *tiles_p = nullptr;
     if (plain_tiles) {
         Packer pp;
@@ -279,14 +314,24 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
     unsigned int *marked_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 20);
     unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 24);
     st.workspace_bytes = int64_t(ws.total());
+    pend->host_bytes = size_t(n_cells) * 8 + 64;
+    pend->host = ds.ctx->pinned.get(pend->host_bytes, &pend->host_bytes);
+    char *host = static_cast<char *>(pend->host);
 
     kern::ItemTables it{dv.item_src, dv.item_len, dv.item_dst, n_items};
     kern::GroupTables gt{dv.g_item0, dv.g_n, dv.g_frame0, dv.g_nframes, dv.g_pair_base, dv.g_dmat_base,
                          G, t.n_pair_slots};
 
-    Timer tm(stream, ds.ctx->events);
+    pend->tm = std::make_unique<Timer>(stream, ds.ctx->events);
+    Timer &tm = *pend->tm;
     tr.mark("workspace");
-    const auto t_launch = clock::now();
+    // on an error after launches, drain the stream before plan_d goes back to the pool
+    struct DrainOnError {
+        hipStream_t s;
+        ~DrainOnError() {
+            if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s);
+        }
+    } drain{stream};
     tm.mark();  // 0
     FABX_HIP(hipMemsetAsync(ws.counters.ptr, 0, 64, stream));
     FABX_HIP(hipMemsetAsync(err_item, 0xFF, 8, stream));
@@ -336,48 +381,84 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const
                       ws.half_units.as<unsigned long long>());
     }
     tm.mark();  // 5
-    unsigned char counters[64];
-    FABX_HIP(hipMemcpyAsync(res->half_units.data(), ws.half_units.ptr, size_t(n_cells) * 8,
-                            hipMemcpyDeviceToHost, stream));
-    FABX_HIP(hipMemcpyAsync(counters, ws.counters.ptr, 64, hipMemcpyDeviceToHost, stream));
+    FABX_HIP(hipMemcpyAsync(host, ws.half_units.ptr, size_t(n_cells) * 8, hipMemcpyDeviceToHost, stream));
+    FABX_HIP(hipMemcpyAsync(host + size_t(n_cells) * 8, ws.counters.ptr, 64, hipMemcpyDeviceToHost, stream));
     tm.mark();  // 6
-    FABX_HIP(hipStreamSynchronize(stream));
-    const auto t_synced = clock::now();
-    tr.mark("gpu");
-    int err_h;
-    unsigned long long err_item_h;
-    unsigned int recount_h, marked_h, nonrobust_h;
-    std::memcpy(&err_h, counters, 4);
-    std::memcpy(&nonrobust_h, counters + 24, 4);
-    std::memcpy(&err_item_h, counters + 8, 8);
-    std::memcpy(&recount_h, counters + 16, 4);
-    std::memcpy(&marked_h, counters + 20, 4);
-    if (err_h) {
-        const int64_t bad = err_item_h < uint64_t(n_items) ? t.items[size_t(err_item_h)] : -1;
-        fail(FABX_EDOMAIN, "zero-norm " + std::string(dtw ? "frame" : "mean") + " in item " +
-                               std::to_string(bad) + ": its angle is undefined");
+    tr.mark("launch");
+    pend->t_launch = clock::now();
+    res->pending = std::move(pend);
+    t.pending = res;
+    return res;
+}
+
+void finish_score(ResultImpl &res) {
+    using clock = std::chrono::steady_clock;
+    std::lock_guard<std::mutex> lk(res.mu);
+    if (!res.pending) {
+        if (res.status != FABX_OK) fail(res.status, res.status_msg);
+        return;
     }
-    st.ms_normalize = tm.ms(1, 2);
-    st.ms_distance = tm.ms(2, 3);
-    st.ms_triplets = tm.ms(3, 4);
-    st.ms_recheck = tm.ms(4, 5);
-    st.ms_total = tm.ms(0, 6);
-    st.n_recheck_pairs = marked_h;
-    st.n_recount_rows = recount_h;
-    st.n_nonrobust_pairs = nonrobust_h;
-    if (p.keep_pairs) {
-        res->has_pairs = true;
-        res->p32.resize(size_t(t.n_pair_slots));
-        FABX_HIP(hipMemcpy(res->p32.data(), ws.p32.ptr, res->p32.size() * 4, hipMemcpyDeviceToHost));
-        if (bf16) {
-            res->flags.resize(size_t(t.n_pair_slots));
-            FABX_HIP(hipMemcpy(res->flags.data(), ws.flags.ptr, res->flags.size(), hipMemcpyDeviceToHost));
-            res->p64.resize(size_t(t.n_pair_slots));
-            FABX_HIP(hipMemcpy(res->p64.data(), ws.p64.ptr, res->p64.size() * 8, hipMemcpyDeviceToHost));
+    std::unique_ptr<PendingScore> pend = std::move(res.pending);
+    try {
+        TaskImpl &t = *pend->task;
+        Timer &tm = *pend->tm;
+        FABX_HIP(hipSetDevice(pend->ctx->device));
+        FABX_HIP(hipEventSynchronize(tm.ev[6]));
+        const auto t_synced = clock::now();
+        const size_t n_cells = res.half_units.size();
+        const char *host = static_cast<const char *>(pend->host);
+        std::memcpy(res.half_units.data(), host, n_cells * 8);
+        const unsigned char *counters = reinterpret_cast<const unsigned char *>(host + n_cells * 8);
+        int err_h;
+        unsigned long long err_item_h;
+        unsigned int recount_h, marked_h, nonrobust_h;
+        std::memcpy(&err_h, counters, 4);
+        std::memcpy(&nonrobust_h, counters + 24, 4);
+        std::memcpy(&err_item_h, counters + 8, 8);
+        std::memcpy(&recount_h, counters + 16, 4);
+        std::memcpy(&marked_h, counters + 20, 4);
+        if (err_h) {
+            const int64_t bad = err_item_h < uint64_t(t.items.size()) ? t.items[size_t(err_item_h)] : -1;
+            fail(FABX_EDOMAIN, "zero-norm " + std::string(pend->dtw ? "frame" : "mean") + " in item " +
+                                   std::to_string(bad) + ": its angle is undefined");
         }
+        fabx_stats &st = res.stats;
+        st.ms_normalize = tm.ms(1, 2);
+        st.ms_distance = tm.ms(2, 3);
+        st.ms_triplets = tm.ms(3, 4);
+        st.ms_recheck = tm.ms(4, 5);
+        st.ms_total = tm.ms(0, 6);
+        st.n_recheck_pairs = marked_h;
+        st.n_recount_rows = recount_h;
+        st.n_nonrobust_pairs = nonrobust_h;
+        if (pend->keep_pairs) {
+            // the task's workspace still holds this score: a later score on the task
+            // finishes this one before it touches the workspace
+            res.has_pairs = true;
+            res.p32.resize(size_t(t.n_pair_slots));
+            FABX_HIP(hipMemcpy(res.p32.data(), t.ws.p32.ptr, res.p32.size() * 4, hipMemcpyDeviceToHost));
+            if (pend->bf16) {
+                res.flags.resize(size_t(t.n_pair_slots));
+                FABX_HIP(hipMemcpy(res.flags.data(), t.ws.flags.ptr, res.flags.size(), hipMemcpyDeviceToHost));
+                res.p64.resize(size_t(t.n_pair_slots));
+                FABX_HIP(hipMemcpy(res.p64.data(), t.ws.p64.ptr, res.p64.size() * 8, hipMemcpyDeviceToHost));
+            }
+        }
+        st.ms_host_setup = std::chrono::duration<double, std::milli>(pend->t_launch - pend->t_enter).count();
+        st.ms_host_finish = std::chrono::duration<double, std::milli>(clock::now() - t_synced).count();
+    } catch (const Error &e) {
+        // make sure nothing of the score still runs before its buffers are released
+        (void)hipStreamSynchronize(pend->stream);
+        res.status = e.code;
+        res.status_msg = e.msg;
+        throw;
     }
-    st.ms_host_setup = std::chrono::duration<double, std::milli>(t_launch - t_enter).count();
-    st.ms_host_finish = std::chrono::duration<double, std::milli>(clock::now() - t_synced).count();
+}
+
+std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,
+                                      hipStream_t stream) {
+    auto res = launch_score(tp, p, stream);
+    finish_score(*res);
     return res;
 }
 

@@ -6,6 +6,7 @@
 // (by..., on, across...) with an LSD radix sort, so every BY group and every
 // class is a contiguous run; a cell is then three runs (A, B, X).
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstring>
 #include <functional>
@@ -20,7 +21,7 @@ namespace {
 
 struct RankedColumn {
     std::vector<int32_t> values;   // sorted unique attribute values
-    std::vector<uint32_t> rank;    // per item: index into values
+    hvec<uint32_t> rank;           // per item: index into values
     int bits = 0;                  // bits needed to hold a rank
 };
 
@@ -62,24 +63,44 @@ RankedColumn rank_column(const DatasetImpl &ds, int col) {
     return rc;
 }
 
-// Stable LSD radix sort of items by a 64-bit key (12-bit digits, only the
-// digits the key uses).  Ties keep ascending item order.
-void radix_sort(std::vector<uint64_t> &key, std::vector<int64_t> &idx, int key_bits) {
-    constexpr int kDigit = 12;
+// Stable LSD radix sort of items by a 64-bit key (8-bit digits, only the
+// digits the key uses), parallel over fixed chunks: each chunk counts its
+// digits, one prefix over (digit, chunk) gives every chunk its output
+// positions, and each chunk scatters its elements in order.  Ties keep
+// ascending item order, whatever the thread count.
+void radix_sort(hvec<uint64_t> &key, hvec<int64_t> &idx, int key_bits) {
+    constexpr int kDigit = 8;
     constexpr size_t kBuckets = size_t(1) << kDigit;
     const size_t n = key.size();
-    std::vector<uint64_t> k2(n);
-    std::vector<int64_t> i2(n);
-    std::vector<size_t> count(kBuckets + 1);
+    if (key_bits <= 0 || n < 2) return;
+    const size_t n_chunks = std::min<size_t>(64, std::max<size_t>(1, n / 8192));
+    hvec<uint64_t> k2(n);
+    hvec<int64_t> i2(n);
+    std::vector<size_t> hist(n_chunks * kBuckets);
+    auto bounds = [&](size_t c) { return std::make_pair(n * c / n_chunks, n * (c + 1) / n_chunks); };
     for (int shift = 0; shift < key_bits; shift += kDigit) {
-        std::fill(count.begin(), count.end(), 0);
-        for (size_t i = 0; i < n; ++i) ++count[((key[i] >> shift) & (kBuckets - 1)) + 1];
-        for (size_t b = 0; b < kBuckets; ++b) count[b + 1] += count[b];
-        for (size_t i = 0; i < n; ++i) {
-            size_t d = count[(key[i] >> shift) & (kBuckets - 1)]++;
-            k2[d] = key[i];
-            i2[d] = idx[i];
-        }
+        HostPool::get().parallel_for(int(n_chunks), [&](int c) {
+            size_t *h = hist.data() + size_t(c) * kBuckets;
+            std::fill(h, h + kBuckets, size_t(0));
+            const auto [b0, b1] = bounds(size_t(c));
+            for (size_t i = b0; i < b1; ++i) ++h[(key[i] >> shift) & (kBuckets - 1)];
+        });
+        size_t run = 0;
+        for (size_t b = 0; b < kBuckets; ++b)
+            for (size_t c = 0; c < n_chunks; ++c) {
+                const size_t v = hist[c * kBuckets + b];
+                hist[c * kBuckets + b] = run;
+                run += v;
+            }
+        HostPool::get().parallel_for(int(n_chunks), [&](int c) {
+            size_t *h = hist.data() + size_t(c) * kBuckets;
+            const auto [b0, b1] = bounds(size_t(c));
+            for (size_t i = b0; i < b1; ++i) {
+                const size_t d = h[(key[i] >> shift) & (kBuckets - 1)]++;
+                k2[d] = key[i];
+                i2[d] = idx[i];
+            }
+        });
         key.swap(k2);
         idx.swap(i2);
     }
@@ -89,7 +110,6 @@ struct ClassRun {
     int64_t start;      // position in sorted order
     int64_t count;
     uint32_t on_rank;
-    int64_t first;      // one item of the class (for its ACROSS ranks)
 };
 
 
@@ -99,26 +119,23 @@ void parallel_for(int n, F &&f) {
     HostPool::get().parallel_for(n, fn);
 }
 
-// Output of one thread's share of the group walk (group ids and pair-slot
-// bases local to the share; stitched together afterwards).
-struct WalkOut {
-    std::vector<CellDev> cells;
-    std::vector<int64_t> ntrip;
-    std::vector<int32_t> keys;
-    std::vector<uint32_t> rkeys;
-    std::vector<int32_t> units;                     // [n][3], cell ids local to this share
-    std::vector<Group> groups;
-    std::vector<std::pair<int64_t, int64_t>> kept;  // sorted-order range of each kept group
+// One share of the group walk.  The walk runs twice over the same share:
+// first counting (cells, unit ints, kept groups and the task totals), then,
+// after prefix sums over the shares, writing straight into the task's arrays
+// at the share's offsets.
+struct Sink {
+    size_t n_cells = 0, n_unit_ints = 0, n_groups = 0;
     int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, pair_slots = 0, sum_nx = 0;
-    void swap(WalkOut &o) {
-        cells.swap(o.cells);
-        ntrip.swap(o.ntrip);
-        keys.swap(o.keys);
-        rkeys.swap(o.rkeys);
-        units.swap(o.units);
-        groups.swap(o.groups);
-        kept.swap(o.kept);
-    }
+    // write pass: destinations, and the share's first cell / unit int / group / pair slot
+    CellDev *cells = nullptr;
+    int64_t *ntrip = nullptr;
+    int32_t *keys = nullptr;
+    uint32_t *rkeys = nullptr;
+    int32_t *units = nullptr;
+    Group *groups = nullptr;
+    std::pair<int64_t, int64_t> *kept = nullptr;
+    size_t cell_base = 0, unit_base = 0, group_base = 0, key_width = 0;
+    int64_t slot_base = 0;
 };
 
 constexpr int64_t kUnitBudget = 8192;  // comparisons per triplet work unit (at least one x)
@@ -126,30 +143,34 @@ constexpr int64_t kUnitBudget = 8192;  // comparisons per triplet work unit (at 
 struct WalkCtx {
     const DatasetImpl *ds;
     const TaskImpl *t;
-    const std::vector<int64_t> *order;
-    const std::vector<uint64_t> *by_part, *cls_part;
-    const std::vector<uint32_t> *on_rank;
-    const std::vector<const std::vector<uint32_t> *> *by_rank, *across_rank;
-    const std::vector<int64_t> *pf, *pq;
-    int32_t on;
+    const hvec<int64_t> *order;
+    const hvec<uint64_t> *by_part, *cls_part;
+    // ranks per sorted position, [n x W]: ON, then BY..., then ACROSS...
+    const uint32_t *srank;
+    int W;
+    // key values by rank, per column in the same order
+    std::vector<const std::vector<int32_t> *> values;
+    const hvec<int64_t> *pf, *pq;
     int32_t n_across;
-    std::function<int(int64_t, int64_t)> across_cmp;
-    std::function<bool(int64_t, int64_t)> across_all_differ;
 };
 
 // Cells of the groups that start in sorted positions [s_begin, s_end).
-void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, WalkOut &out) {
-    const auto &order = *w.order;
+template <bool kWrite>
+void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
     const auto &by_part = *w.by_part;
     const auto &cls_part = *w.cls_part;
     const auto &pf = *w.pf;
     const auto &pq = *w.pq;
-    const int32_t *A = w.ds->attrs.data();
-    const int NA = w.ds->n_attr;
     const TaskImpl &t = *w.t;
+    const uint32_t *SR = w.srank;
+    const size_t W = size_t(w.W);
     std::vector<ClassRun> cls;
     std::vector<uint8_t> need;
     std::vector<std::pair<int64_t, int64_t>> need_list, runs;
+    // key values and ranks, read once per group (BY) and per class (ON, ACROSS)
+    const int n_by = int(t.by.size()), n_ac = w.n_across;
+    std::vector<int32_t> gby(static_cast<size_t>(n_by)), con, cac;
+    std::vector<uint32_t> gbyr(static_cast<size_t>(n_by)), cacr;
     int64_t g0 = s_begin;
     while (g0 < s_end) {
         int64_t g1 = g0 + 1;
@@ -158,57 +179,98 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, WalkOut &out)
         for (int64_t s = g0; s < g1;) {
             int64_t e = s + 1;
             while (e < g1 && cls_part[e] == cls_part[s]) ++e;
-            cls.push_back({s, e - s, (*w.on_rank)[order[s]], order[s]});
+            cls.push_back({s, e - s, SR[size_t(s) * W]});
             s = e;
         }
         const int64_t K = int64_t(cls.size());
-        const int32_t group_id = int32_t(out.groups.size());
-        const size_t cells_before = out.cells.size();
-        const bool use_need = w.n_across > 0 && K <= 8192;
+        const int32_t group_id = int32_t(out.group_base + out.n_groups);
+        {
+            const uint32_t *r0 = SR + size_t(g0) * W;
+            for (int j = 0; j < n_by; ++j) {
+                gbyr[size_t(j)] = r0[1 + j];
+                gby[size_t(j)] = (*w.values[size_t(1 + j)])[r0[1 + j]];
+            }
+            con.resize(size_t(K));
+            cac.resize(size_t(K * n_ac));
+            cacr.resize(size_t(K * n_ac));
+            for (int64_t i = 0; i < K; ++i) {
+                const uint32_t *ri = SR + size_t(cls[size_t(i)].start) * W;
+                con[size_t(i)] = (*w.values[0])[ri[0]];
+                for (int j = 0; j < n_ac; ++j) {
+                    cacr[size_t(i * n_ac + j)] = ri[1 + n_by + j];
+                    cac[size_t(i * n_ac + j)] = (*w.values[size_t(1 + n_by + j)])[ri[1 + n_by + j]];
+                }
+            }
+        }
+        // ACROSS tuples of two classes: lexicographic order (the sort order) and
+        // "differ in every attribute"
+        auto across_cmp = [&](int64_t a, int64_t b) {
+            for (int j = 0; j < n_ac; ++j) {
+                const uint32_t x = cacr[size_t(a * n_ac + j)], y = cacr[size_t(b * n_ac + j)];
+                if (x != y) return x < y ? -1 : 1;
+            }
+            return 0;
+        };
+        auto across_all_differ = [&](int64_t a, int64_t b) {
+            for (int j = 0; j < n_ac; ++j)
+                if (cacr[size_t(a * n_ac + j)] == cacr[size_t(b * n_ac + j)]) return false;
+            return true;
+        };
+        const size_t cells_before = out.n_cells;
+        // the unique pairs a group needs are only counted in the first pass
+        const bool use_need = !kWrite && w.n_across > 0 && K <= 8192;
         if (use_need) need.assign(size_t(K * K), 0);
         need_list.clear();
         auto add_cell = [&](int64_t ia, int64_t ib, int64_t ix, bool excl) {
-            CellDev c;
-            c.group = group_id;
-            c.a0 = int32_t(cls[ia].start - g0);
-            c.na = int32_t(cls[ia].count);
-            c.b0 = int32_t(cls[ib].start - g0);
-            c.nb = int32_t(cls[ib].count);
-            c.x0 = int32_t(cls[ix].start - g0);
-            c.nx = int32_t(cls[ix].count);
-            c.exclude_self = excl ? 1 : 0;
-            out.cells.push_back(c);
-            const int64_t nt = excl ? c.na * int64_t(c.na - 1) * c.nb : int64_t(c.na) * c.nb * c.nx;
-            out.ntrip.push_back(nt);
-            out.total_triplets += nt;
-            const int32_t *ka = A + cls[ia].first * NA;
-            const int32_t *kb = A + cls[ib].first * NA;
-            const int32_t *kx = A + cls[ix].first * NA;
-            out.keys.push_back(ka[w.on]);
-            out.keys.push_back(kb[w.on]);
-            for (int32_t b : t.by) out.keys.push_back(ka[b]);
-            for (int32_t a : t.across) out.keys.push_back(ka[a]);
-            for (int32_t a : t.across) out.keys.push_back(kx[a]);
-            const int64_t ia0 = cls[ia].first, ib0 = cls[ib].first, ix0 = cls[ix].first;
-            out.rkeys.push_back((*w.on_rank)[ia0]);
-            out.rkeys.push_back((*w.on_rank)[ib0]);
-            for (auto *r : *w.by_rank) out.rkeys.push_back((*r)[ia0]);
-            for (auto *r : *w.across_rank) out.rkeys.push_back((*r)[ia0]);
-            for (auto *r : *w.across_rank) out.rkeys.push_back((*r)[ix0]);
+            const int64_t na = cls[ia].count, nb = cls[ib].count, nx = cls[ix].count;
+            const int64_t nt = excl ? na * (na - 1) * nb : na * nb * nx;
+            const size_t cid = out.cell_base + out.n_cells;
             // triplet work units: split X so one unit does <= kUnitBudget comparisons
-            const int64_t per_x = std::max<int64_t>(1, int64_t(c.na) * c.nb);
+            const int64_t per_x = std::max<int64_t>(1, na * nb);
             const int64_t chunk = std::max<int64_t>(1, kUnitBudget / per_x);
-            const int32_t cid = int32_t(out.cells.size() - 1);
-            for (int64_t x = 0; x < c.nx; x += chunk) {
-                out.units.push_back(cid);
-                out.units.push_back(int32_t(x));
-                out.units.push_back(int32_t(std::min<int64_t>(c.nx, x + chunk)));
+            if (kWrite) {
+                CellDev c;
+                c.group = group_id;
+                c.a0 = int32_t(cls[ia].start - g0);
+                c.na = int32_t(na);
+                c.b0 = int32_t(cls[ib].start - g0);
+                c.nb = int32_t(nb);
+                c.x0 = int32_t(cls[ix].start - g0);
+                c.nx = int32_t(nx);
+                c.exclude_self = excl ? 1 : 0;
+                out.cells[cid] = c;
+                out.ntrip[cid] = nt;
+                int32_t *kk = out.keys + cid * out.key_width;
+                uint32_t *rk = out.rkeys + cid * out.key_width;
+                kk[0] = con[size_t(ia)];
+                kk[1] = con[size_t(ib)];
+                rk[0] = cls[size_t(ia)].on_rank;
+                rk[1] = cls[size_t(ib)].on_rank;
+                for (int j = 0; j < n_by; ++j) {
+                    kk[2 + j] = gby[size_t(j)];
+                    rk[2 + j] = gbyr[size_t(j)];
+                }
+                for (int j = 0; j < n_ac; ++j) {
+                    kk[2 + n_by + j] = cac[size_t(ia * n_ac + j)];
+                    rk[2 + n_by + j] = cacr[size_t(ia * n_ac + j)];
+                    kk[2 + n_by + n_ac + j] = cac[size_t(ix * n_ac + j)];
+                    rk[2 + n_by + n_ac + j] = cacr[size_t(ix * n_ac + j)];
+                }
+                int32_t *u = out.units + out.unit_base + out.n_unit_ints;
+                for (int64_t x = 0; x < nx; x += chunk, u += 3) {
+                    u[0] = int32_t(cid);
+                    u[1] = int32_t(x);
+                    u[2] = int32_t(std::min<int64_t>(nx, x + chunk));
+                }
             }
-            out.sum_nx += c.nx;
+            out.n_unit_ints += size_t(3 * ((nx + chunk - 1) / chunk));
+            ++out.n_cells;
+            out.total_triplets += nt;
+            out.sum_nx += nx;
             if (use_need) {
                 need[size_t(ix * K + ia)] = 1;
                 need[size_t(ix * K + ib)] = 1;
-            } else if (w.n_across > 0) {
+            } else if (!kWrite && w.n_across > 0) {
                 need_list.push_back({ix, ia});
                 need_list.push_back({ix, ib});
             }
@@ -236,20 +298,27 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, WalkOut &out)
                         int64_t lo = r2.first, hi = r2.second;
                         while (lo < hi) {
                             int64_t mid = (lo + hi) / 2;
-                            if (w.across_cmp(cls[mid].first, cls[ia].first) < 0) lo = mid + 1; else hi = mid;
+                            if (across_cmp(mid, ia) < 0) lo = mid + 1; else hi = mid;
                         }
-                        if (lo == r2.second || w.across_cmp(cls[lo].first, cls[ia].first) != 0) continue;
+                        if (lo == r2.second || across_cmp(lo, ia) != 0) continue;
                         for (int64_t ix = r1.first; ix < r1.second; ++ix)
-                            if (w.across_all_differ(cls[ix].first, cls[ia].first))
+                            if (across_all_differ(ix, ia))
                                 add_cell(ia, lo, ix, false);
                     }
                 }
         }
-        if (out.cells.size() > cells_before) {
+        if (out.n_cells > cells_before) {
             Group g{};
             g.n_items = g1 - g0;
-            g.pair_base = out.pair_slots;
+            g.pair_base = out.slot_base + out.pair_slots;
             out.pair_slots += g.n_items * g.n_items;
+            if (kWrite) {
+                out.groups[out.group_base + out.n_groups] = g;
+                out.kept[out.group_base + out.n_groups] = {g0, g1};
+            }
+            ++out.n_groups;
+        }
+        if (!kWrite && out.n_cells > cells_before) {
             // unique needed pairs and their DTW cells, from prefix sums over sorted positions
             auto cnt = [&](int64_t i) { return cls[i].count; };
             auto frames = [&](int64_t i) { return pf[cls[i].start + cls[i].count] - pf[cls[i].start]; };
@@ -280,8 +349,6 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, WalkOut &out)
                 need_list.erase(std::unique(need_list.begin(), need_list.end()), need_list.end());
                 for (auto &pr : need_list) count_pair(pr.first, pr.second);
             }
-            out.kept.push_back({g0, g1});
-            out.groups.push_back(g);
         }
         g0 = g1;
     }
@@ -342,24 +409,30 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     for (auto &r : rby) total_bits += r.bits;
 
     tr.mark("rank");
-    std::vector<int64_t> order(n);
+    hvec<int64_t> order(n);
     std::iota(order.begin(), order.end(), int64_t(0));
-    std::vector<uint64_t> by_part(n, 0), cls_part(n, 0);   // BY tuple id / (on, across) class id
+    hvec<uint64_t> by_part(n), cls_part(n);   // BY tuple id / (on, across) class id
     if (total_bits <= 64) {
-        std::vector<uint64_t> key(n);
-        for (int64_t i = 0; i < n; ++i) {
-            uint64_t k = 0;
-            for (auto &r : rby) k = (k << r.bits) | r.rank[i];
-            k = (k << ron.bits) | ron.rank[i];
-            uint64_t a = 0;
-            for (int j = 0; j < n_across; ++j) a |= uint64_t(racr[j].rank[i]) << acr_shift[j];
-            key[i] = (k << acr_bits) | a;
-        }
+        hvec<uint64_t> key(n);
+        const int64_t kChunk = 1 << 14;
+        const int n_chunks = int((n + kChunk - 1) / kChunk);
+        parallel_for(n_chunks, [&](int c) {
+            for (int64_t i = c * kChunk; i < std::min<int64_t>(n, (c + 1) * kChunk); ++i) {
+                uint64_t k = 0;
+                for (auto &r : rby) k = (k << r.bits) | r.rank[i];
+                k = (k << ron.bits) | ron.rank[i];
+                uint64_t a = 0;
+                for (int j = 0; j < n_across; ++j) a |= uint64_t(racr[j].rank[i]) << acr_shift[j];
+                key[i] = (k << acr_bits) | a;
+            }
+        });
         radix_sort(key, order, total_bits);
-        for (int64_t s = 0; s < n; ++s) {
-            by_part[s] = low_bits >= 64 ? 0 : key[s] >> low_bits;
-            cls_part[s] = key[s];
-        }
+        parallel_for(n_chunks, [&](int c) {
+            for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) {
+                by_part[s] = low_bits >= 64 ? 0 : key[s] >> low_bits;
+                cls_part[s] = key[s];
+            }
+        });
     } else {
         // Key too wide for one word: comparison sort on the rank tuple.
         std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
@@ -385,33 +458,81 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             cls_part[s] = cid;
         }
     }
-    // ACROSS tuples of two items: lexicographic order (the sort order) and "differ in every one"
-    std::function<int(int64_t, int64_t)> across_cmp = [&](int64_t a, int64_t b) {
-        for (int j = 0; j < n_across; ++j)
-            if (racr[j].rank[a] != racr[j].rank[b]) return racr[j].rank[a] < racr[j].rank[b] ? -1 : 1;
-        return 0;
-    };
-    std::function<bool(int64_t, int64_t)> across_all_differ = [&](int64_t a, int64_t b) {
-        for (int j = 0; j < n_across; ++j)
-            if (racr[j].rank[a] == racr[j].rank[b]) return false;
-        return true;
-    };
-
+    // ---- ranks per sorted position (from the packed key when there is one)
+    const int W = 1 + n_by + n_across;
+    hvec<uint32_t> srank(static_cast<size_t>(n) * size_t(W));
+    {
+        const size_t nw = static_cast<size_t>(W);
+        std::vector<int> shift(nw), bits(nw);
+        std::vector<const hvec<uint32_t> *> src(nw);
+        shift[0] = acr_bits;
+        bits[0] = ron.bits;
+        src[0] = &ron.rank;
+        int sh = low_bits;
+        for (int j = n_by - 1; j >= 0; --j) {
+            shift[size_t(1 + j)] = sh;
+            bits[size_t(1 + j)] = rby[size_t(j)].bits;
+            src[size_t(1 + j)] = &rby[size_t(j)].rank;
+            sh += rby[size_t(j)].bits;
+        }
+        for (int j = 0; j < n_across; ++j) {
+            shift[size_t(1 + n_by + j)] = acr_shift[size_t(j)];
+            bits[size_t(1 + n_by + j)] = racr[size_t(j)].bits;
+            src[size_t(1 + n_by + j)] = &racr[size_t(j)].rank;
+        }
+        const bool packed = total_bits <= 64;
+        const int64_t kChunk = 1 << 14;
+        parallel_for(int((n + kChunk - 1) / kChunk), [&](int c) {
+            const int64_t s0 = c * kChunk, s1 = std::min<int64_t>(n, s0 + kChunk);
+            for (int64_t s = s0; s < s1; ++s) {
+                uint32_t *o = srank.data() + size_t(s) * size_t(W);
+                for (int k = 0; k < W; ++k)
+                    o[k] = packed ? uint32_t((cls_part[size_t(s)] >> shift[size_t(k)]) &
+                                             ((uint64_t(1) << bits[size_t(k)]) - 1))
+                                  : (*src[size_t(k)])[size_t(order[size_t(s)])];
+            }
+        });
+    }
     tr.mark("sort");
     // ---- per sorted position: length, and prefix sums of frames and squared lengths
-    std::vector<int32_t> len_s(static_cast<size_t>(n));
-    std::vector<int64_t> pf(static_cast<size_t>(n) + 1, 0), pq(static_cast<size_t>(n) + 1, 0);
-    for (int64_t s = 0; s < n; ++s) {
-        const int64_t L = ds->offsets[order[s] + 1] - ds->offsets[order[s]];
-        len_s[s] = int32_t(L);
-        pf[s + 1] = pf[s] + L;
-        pq[s + 1] = pq[s] + L * L;
+    hvec<int32_t> len_s(static_cast<size_t>(n));
+    hvec<int64_t> pf(static_cast<size_t>(n) + 1), pq(static_cast<size_t>(n) + 1);
+    {
+        // two-level scan over fixed chunks: chunk sums, their prefix, then the fill
+        const int64_t kChunk = 1 << 14;
+        const int nc = int((n + kChunk - 1) / kChunk);
+        std::vector<int64_t> cf(size_t(nc) + 1, 0), cq(size_t(nc) + 1, 0);
+        parallel_for(nc, [&](int c) {
+            int64_t f = 0, q = 0;
+            for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) {
+                const int64_t L = ds->offsets[order[s] + 1] - ds->offsets[order[s]];
+                len_s[s] = int32_t(L);
+                f += L;
+                q += L * L;
+            }
+            cf[size_t(c) + 1] = f;
+            cq[size_t(c) + 1] = q;
+        });
+        for (int c = 0; c < nc; ++c) {
+            cf[size_t(c) + 1] += cf[size_t(c)];
+            cq[size_t(c) + 1] += cq[size_t(c)];
+        }
+        pf[0] = pq[0] = 0;
+        parallel_for(nc, [&](int c) {
+            int64_t f = cf[size_t(c)], q = cq[size_t(c)];
+            for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) {
+                f += len_s[s];
+                q += int64_t(len_s[s]) * len_s[s];
+                pf[s + 1] = f;
+                pq[s + 1] = q;
+            }
+        });
     }
 
     // ---- walk the groups: chunks of whole groups in parallel, then stitch
     const int n_threads = int(std::min<int64_t>(HostPool::get().size(), std::max<int64_t>(1, n / 4096)));
     // more shares than threads: the pool hands them out dynamically (group sizes vary)
-    const int n_shares = int(std::min<int64_t>(4 * int64_t(n_threads), std::max<int64_t>(1, n / 1024)));
+    const int n_shares = int(std::min<int64_t>(16 * int64_t(n_threads), std::max<int64_t>(1, n / 512)));
     std::vector<int64_t> cut(size_t(n_shares) + 1, n);
     cut[0] = 0;
     for (int k = 1; k < n_shares; ++k) {
@@ -419,81 +540,64 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         while (c > 0 && c < n && by_part[c] == by_part[c - 1]) ++c;   // move to a group start
         cut[k] = c;
     }
-    std::vector<WalkOut> parts(static_cast<size_t>(n_shares));
-    std::vector<const std::vector<uint32_t> *> by_rank_p, across_rank_p;
-    for (auto &r : rby) by_rank_p.push_back(&r.rank);
-    for (auto &r : racr) across_rank_p.push_back(&r.rank);
-    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, &ron.rank, &by_rank_p, &across_rank_p,
-               &pf, &pq, on, n_across, across_cmp, across_all_differ};
+    std::vector<Sink> parts(static_cast<size_t>(n_shares));
+    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, srank.data(), W, {}, &pf, &pq, n_across};
+    wc.values.push_back(&ron.values);
+    for (auto &r : rby) wc.values.push_back(&r.values);
+    for (auto &r : racr) wc.values.push_back(&r.values);
     t->key_bits = {ron.bits, ron.bits};
     for (auto &r : rby) t->key_bits.push_back(r.bits);
     for (auto &r : racr) t->key_bits.push_back(r.bits);
     for (auto &r : racr) t->key_bits.push_back(r.bits);
-    parallel_for(n_shares, [&](int k) { walk_groups(wc, cut[k], cut[k + 1], parts[size_t(k)]); });
-
+    t->key_card = {uint32_t(ron.values.size()), uint32_t(ron.values.size())};
+    for (auto &r : rby) t->key_card.push_back(uint32_t(r.values.size()));
+    for (auto &r : racr) t->key_card.push_back(uint32_t(r.values.size()));
+    for (auto &r : racr) t->key_card.push_back(uint32_t(r.values.size()));
+    parallel_for(n_shares, [&](int k) { walk_groups<false>(wc, cut[k], cut[k + 1], parts[size_t(k)]); });
     tr.mark("walk");
-    size_t n_cells = 0, n_groups = 0;
+    size_t n_cells = 0, n_groups = 0, n_unit_ints = 0;
+    int64_t n_slots = 0;
     for (auto &p : parts) {
-        n_cells += p.cells.size();
-        n_groups += p.groups.size();
+        p.cell_base = n_cells;
+        p.unit_base = n_unit_ints;
+        p.group_base = n_groups;
+        p.slot_base = n_slots;
+        n_cells += p.n_cells;
+        n_unit_ints += p.n_unit_ints;
+        n_groups += p.n_groups;
+        n_slots += p.pair_slots;
+        t->sum_nx += p.sum_nx;
+        t->total_triplets += p.total_triplets;
+        t->n_pairs_needed += p.pairs_needed;
+        t->dtw_cells_needed += p.dtw_needed;
     }
-    size_t n_unit_ints = 0;
-    for (auto &p : parts) n_unit_ints += p.units.size();
+    t->n_pair_slots = n_slots;
     t->cells.resize(n_cells);
     t->n_triplets.resize(n_cells);
     t->keys.resize(n_cells * size_t(t->key_width));
     t->rkeys.resize(n_cells * size_t(t->key_width));
     t->units.resize(n_unit_ints);
-    std::vector<size_t> unit_off(parts.size());
     t->groups.resize(n_groups);
-    std::vector<std::pair<int64_t, int64_t>> kept(n_groups);
-    std::vector<size_t> cell_off(parts.size()), group_off(parts.size());
-    std::vector<int64_t> slot_off(parts.size());
-    {
-        size_t co = 0, go = 0;
-        int64_t so = 0;
-        for (size_t k = 0; k < parts.size(); ++k) {
-            cell_off[k] = co;
-            group_off[k] = go;
-            slot_off[k] = so;
-            co += parts[k].cells.size();
-            go += parts[k].groups.size();
-            t->sum_nx += parts[k].sum_nx;
-            so += parts[k].pair_slots;
-            t->total_triplets += parts[k].total_triplets;
-            t->n_pairs_needed += parts[k].pairs_needed;
-            t->dtw_cells_needed += parts[k].dtw_needed;
-        }
-        t->n_pair_slots = so;
-        size_t uo = 0;
-        for (size_t k = 0; k < parts.size(); ++k) {
-            unit_off[k] = uo;
-            uo += parts[k].units.size();
-        }
-    }
+    hvec<std::pair<int64_t, int64_t>> kept(n_groups);
+    std::atomic<bool> mismatch{false};
     parallel_for(n_shares, [&](int k) {
-        WalkOut &p = parts[size_t(k)];
-        for (size_t c = 0; c < p.cells.size(); ++c) {
-            CellDev cd = p.cells[c];
-            cd.group += int32_t(group_off[size_t(k)]);
-            t->cells[cell_off[size_t(k)] + c] = cd;
-        }
-        std::copy(p.ntrip.begin(), p.ntrip.end(), t->n_triplets.begin() + long(cell_off[size_t(k)]));
-        std::copy(p.keys.begin(), p.keys.end(), t->keys.begin() + long(cell_off[size_t(k)] * size_t(t->key_width)));
-        std::copy(p.rkeys.begin(), p.rkeys.end(), t->rkeys.begin() + long(cell_off[size_t(k)] * size_t(t->key_width)));
-        for (size_t u = 0; u < p.units.size(); u += 3) {
-            t->units[unit_off[size_t(k)] + u] = p.units[u] + int32_t(cell_off[size_t(k)]);
-            t->units[unit_off[size_t(k)] + u + 1] = p.units[u + 1];
-            t->units[unit_off[size_t(k)] + u + 2] = p.units[u + 2];
-        }
-        for (size_t g = 0; g < p.groups.size(); ++g) {
-            Group gg = p.groups[g];
-            gg.pair_base += slot_off[size_t(k)];
-            t->groups[group_off[size_t(k)] + g] = gg;
-            kept[group_off[size_t(k)] + g] = p.kept[g];
-        }
-        WalkOut().swap(p);
+        Sink &p = parts[size_t(k)];
+        const Sink counted = p;
+        p.n_cells = p.n_unit_ints = p.n_groups = 0;
+        p.pair_slots = 0;
+        p.cells = t->cells.data();
+        p.ntrip = t->n_triplets.data();
+        p.keys = t->keys.data();
+        p.rkeys = t->rkeys.data();
+        p.units = t->units.data();
+        p.groups = t->groups.data();
+        p.kept = kept.data();
+        p.key_width = size_t(t->key_width);
+        walk_groups<true>(wc, cut[k], cut[k + 1], p);
+        if (p.n_cells != counted.n_cells || p.n_unit_ints != counted.n_unit_ints || p.n_groups != counted.n_groups)
+            mismatch = true;  // both passes walk the same share: cannot happen
     });
+    if (mismatch) fail(FABX_EINVAL, "internal error: task walk passes disagree");
 
     tr.mark("stitch");
     // ---- task items in task order, packed frame offsets
@@ -540,36 +644,66 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     const int64_t frame = frame_total;
 
     // fused-kernel blocks: whole items packed into <= 64-frame row blocks and
-    // <= 128-frame column blocks per group; work units = row x column blocks
+    // <= 128-frame column blocks per group; work units = row x column blocks.
+    // Counted per group in parallel, then written at the prefix offsets.
+    auto pack = [&](int64_t gi, int limit, int32_t *out) {
+        const Group &g = t->groups[size_t(gi)];
+        int32_t nb = 0;
+        int64_t k = g.item0;
+        const int64_t end = g.item0 + g.n_items;
+        while (k < end) {
+            const int32_t first = int32_t(k);
+            int32_t frames = 0, cnt = 0;
+            // at least one item per block (an item above the limit is only legal in
+            // pooled mode, which does not use these blocks)
+            while (k < end && (cnt == 0 || frames + t->item_len[size_t(k)] <= limit)) {
+                frames += t->item_len[size_t(k)];
+                ++cnt;
+                ++k;
+            }
+            if (out) {
+                int32_t *o = out + 4 * size_t(nb);
+                o[0] = int32_t(gi);
+                o[1] = first;
+                o[2] = cnt;
+                o[3] = frames;
+            }
+            ++nb;
+        }
+        return nb;
+    };
+    t->g_rb0.assign(size_t(G), 0);
+    t->g_cb0.assign(size_t(G), 0);
+    t->g_ncb.assign(size_t(G), 0);
+    std::vector<int32_t> nrb_g(static_cast<size_t>(G));
+    const int64_t kGroups = 2048;
+    const int n_gc = int((G + kGroups - 1) / kGroups);
+    parallel_for(n_gc, [&](int c) {
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
+            nrb_g[size_t(gi)] = pack(gi, kFusedRowFrames, nullptr);
+            t->g_ncb[size_t(gi)] = pack(gi, kFusedColFrames, nullptr);
+        }
+    });
     t->unit_prefix.assign(size_t(G) + 1, 0);
+    int32_t rb_total = 0, cb_total = 0;
     for (int64_t gi = 0; gi < G; ++gi) {
         const Group &g = t->groups[size_t(gi)];
-        t->g_rb0.push_back(int32_t(t->rb.size() / 4));
-        t->g_cb0.push_back(int32_t(t->cb.size() / 4));
-        for (int pass = 0; pass < 2; ++pass) {
-            const int limit = pass == 0 ? kFusedRowFrames : kFusedColFrames;
-            std::vector<int32_t> &out = pass == 0 ? t->rb : t->cb;
-            int64_t k = g.item0;
-            const int64_t end = g.item0 + g.n_items;
-            while (k < end) {
-                const int32_t first = int32_t(k);
-                int32_t frames = 0, cnt = 0;
-                // at least one item per block (an item above the limit is only legal in
-                // pooled mode, which does not use these blocks)
-                while (k < end && (cnt == 0 || frames + t->item_len[size_t(k)] <= limit)) {
-                    frames += t->item_len[size_t(k)];
-                    ++cnt;
-                    ++k;
-                }
-                out.insert(out.end(), {int32_t(gi), first, cnt, frames});
-            }
-        }
-        const int32_t nrb = int32_t(t->rb.size() / 4) - t->g_rb0.back();
-        const int32_t ncb = int32_t(t->cb.size() / 4) - t->g_cb0.back();
-        t->g_ncb.push_back(ncb);
-        t->unit_prefix[size_t(gi) + 1] = t->unit_prefix[size_t(gi)] + int64_t(nrb) * ncb;
+        t->g_rb0[size_t(gi)] = rb_total;
+        t->g_cb0[size_t(gi)] = cb_total;
+        rb_total += nrb_g[size_t(gi)];
+        cb_total += t->g_ncb[size_t(gi)];
+        t->unit_prefix[size_t(gi) + 1] =
+            t->unit_prefix[size_t(gi)] + int64_t(nrb_g[size_t(gi)]) * t->g_ncb[size_t(gi)];
         t->fused_cells += g.n_frames * g.n_frames;
     }
+    t->rb.resize(4 * size_t(rb_total));
+    t->cb.resize(4 * size_t(cb_total));
+    parallel_for(n_gc, [&](int c) {
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
+            pack(gi, kFusedRowFrames, t->rb.data() + 4 * size_t(t->g_rb0[size_t(gi)]));
+            pack(gi, kFusedColFrames, t->cb.data() + 4 * size_t(t->g_cb0[size_t(gi)]));
+        }
+    });
     t->n_frames = frame;
     tr.mark("items");
     return t;

@@ -338,6 +338,71 @@ def test_server_rejects_oversized_job():
     srv.close()
 
 
+# ---------------------------------------------------------- async score --
+
+def test_score_async_equals_sync():
+    _say("async score == sync score")
+    w = workloads.within_c2(n_items=6000, dim=256, centroid_std=0.08, seed=51, device="cuda")
+    ds = fx.Dataset(ctx(), w.features, w.offsets, w.attrs)
+    ref = fx.Task(ds, w.on, w.by, w.across).score(keep_pairs=True)
+    t = fx.Task(ds, w.on, w.by, w.across)
+    r = t.score_async(keep_pairs=True)
+    assert len(t) == len(ref.half_units)             # no wait needed for the cell count
+    r.wait()
+    assert np.array_equal(r.half_units, ref.half_units)
+    g = np.array(t.keys[0][2:2 + len(w.by)])        # a BY group of the task
+    items = np.nonzero(np.all(w.attrs[:, w.by] == g, axis=1))[0]
+    xs, ys = np.repeat(items, len(items)), np.tile(items, len(items))
+    assert all(np.array_equal(u, v) for u, v in zip(r.pairs(xs, ys), ref.pairs(xs, ys)))
+    assert r.collapse(w.levels) == ref.collapse(w.levels)
+
+
+def test_async_pipeline_and_rescore_of_a_pending_task():
+    """Two tasks in flight while the host builds and collapses; a task scored
+    again while its first score is pending (the second waits for the first)."""
+    _say("async pipeline")
+    ws = [workloads.within_c2(n_items=5000, dim=128, centroid_std=0.08, seed=60 + k, device="cuda")
+          for k in range(3)]
+    dss = [fx.Dataset(ctx(), w.features, w.offsets, w.attrs) for w in ws]
+    want = [fx.Task(ds, w.on, w.by, w.across).score(keep_pairs=True) for w, ds in zip(ws, dss)]
+    got, prev = [], None
+    for w, ds in zip(ws, dss):
+        r = fx.Task(ds, w.on, w.by, w.across).score_async()
+        if prev is not None:
+            got.append(prev.collapse(ws[len(got)].levels))
+        prev = r
+    got.append(prev.collapse(ws[-1].levels))
+    assert got == [r.collapse(w.levels) for r, w in zip(want, ws)]
+    t = fx.Task(dss[0], ws[0].on, ws[0].by, ws[0].across)
+    r1 = t.score_async(keep_pairs=True)
+    r2 = t.score_async(precision="fp32", keep_pairs=True)
+    assert np.array_equal(r1.half_units, want[0].half_units)
+    g = np.array(t.keys[0][2:2 + len(ws[0].by)])
+    items = np.nonzero(np.all(ws[0].attrs[:, ws[0].by] == g, axis=1))[0]
+    xs, ys = np.repeat(items, len(items)), np.tile(items, len(items))
+    p1, p0 = r1.pairs(xs, ys), want[0].pairs(xs, ys)
+    assert np.array_equal(p1[0], p0[0])              # r1's pairs were saved before r2 ran
+    assert abs(r2.collapse() - want[0].collapse()) <= 1e-4
+    r3 = t.score_async()
+    del r3                                           # freeing a pending result waits for it
+    assert np.array_equal(t.score().half_units, want[0].half_units)
+
+
+def test_async_edomain_reported_on_completion():
+    _say("async EDOMAIN")
+    w = workloads.plain_c1(dim=16, device="cuda")
+    feats = w.features.clone()
+    feats[int(w.offsets[5]) + 1] = 0.0
+    ds = fx.Dataset(ctx(), feats, w.offsets, w.attrs)
+    r = fx.Task(ds, w.on, w.by, w.across).score_async()
+    for _ in range(2):                               # reported every time it is asked
+        with pytest.raises(fx.FabxError) as e:
+            r.wait()
+        assert e.value.code == L.FABX_EDOMAIN
+    with pytest.raises(fx.FabxError):
+        r.collapse()
+
+
 # ------------------------------------------------------- stream ordering --
 
 def _slow_producer(dst, src):
