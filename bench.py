@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default fused-kernel tiles")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
                     help="c2 (default) is the headline workload; c3 / c4 / c4-pooled profile large groups")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -221,6 +222,9 @@ def main():
     run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode)
     sync()
     log("warmup done")
+    # untimed: pick the fused kernel's tiles / grid for this task shape
+    tune = fx.Task(ds, w.on, w.by, w.across).autotune(mode=mode) if not args.no_autotune else None
+    log(f"autotune: {tune}")
     dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode)
     ms_step = dt / args.steps * 1e3
     log(f"bf16 form, pipelined: {ms_step:.2f} ms/step")
@@ -309,6 +313,8 @@ def main():
         "abx_error": errs[-1],
         "recheck_pairs": st0["n_recheck_pairs"], "nonrobust_pairs": st0["n_nonrobust_pairs"],
         "plain_fp32": plain,
+        "autotune": tune,
+        "fused_config": {"cols": st0["fused_cols"], "blocks_per_cu": st0["fused_blocks_per_cu"]},
         "roofline": roof,
         "serving": serving,
         "cpu_baseline": cpu,

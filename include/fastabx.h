@@ -247,9 +247,43 @@ typedef struct fabx_stats {
     double ms_host_finish;      /* host: after the results reached the host, until fabx_score returns */
     double margin;              /* near-tie margin used (BF16 form; 0 for FP32) */
     double delta;               /* path-length window used (BF16 form, DTW; else 0) */
+    int32_t fused_cols;         /* fused kernel column block width used (BF16 DTW; else 0) */
+    int32_t fused_blocks_per_cu;/* its grid: blocks per CU, 0 = one block per work unit */
 } fabx_stats;
 
 int fabx_result_stats(const fabx_result *res, fabx_stats *stats);
+
+/* ------------------------------------------------------------- autotune */
+
+/* Launch choices of the fused BF16 DTW kernel (batching of uneven cells in one
+ * persistent launch): the column block width in frames (128 or 256; wider
+ * blocks give each DTW wave a longer column stream, narrower ones keep more
+ * blocks resident) and the grid (blocks_per_cu > 0: a persistent grid of that
+ * many blocks per compute unit; 0: one block per work unit). */
+typedef struct fabx_tune_entry {
+    int32_t cols;
+    int32_t blocks_per_cu;
+    double ms_distance;   /* best of two runs, distance + DTW stage, device time */
+} fabx_tune_entry;
+
+typedef struct fabx_tune_report {
+    int32_t n_tried;      /* 0: nothing to tune for these options */
+    int32_t best;         /* index into tried, -1 if none */
+    int32_t key_dim_pad, key_max_len, key_frames_log2;  /* shape class the choice is kept for */
+    fabx_tune_entry tried[8];
+} fabx_tune_report;
+
+/* Score the task once per candidate configuration (twice, keeping the faster
+ * run), check that every candidate gives identical per-cell counts, and keep
+ * the fastest for the task's shape class (padded dim, longest item rounded up
+ * to 8 frames, log2 of mean frames per BY group, DTW normalisation) in the
+ * context's table; later scores of tasks in that class use it.  If the
+ * environment variable FABX_AUTOTUNE_CACHE names a file when the context is
+ * created, the table is read from it and rewritten after each new entry.
+ * Only the BF16 DTW form has choices; other options return FABX_OK with
+ * n_tried = 0.  keep_pairs is ignored.  Errors: as fabx_score; EINVAL if two
+ * candidates disagree (a defect). */
+int fabx_autotune(fabx_task *task, const fabx_score_opts *opts, fabx_tune_report *report);
 
 /* -------------------------------------------------------------- collapse */
 

@@ -136,6 +136,12 @@ def fabx_result_wait(r) -> None:
     _check(lib().fabx_result_wait(r))
 
 
+def fabx_autotune(t, opts: fabx_score_opts) -> dict:
+    rep = L.fabx_tune_report()
+    _check(lib().fabx_autotune(t, ctypes.byref(opts), ctypes.byref(rep)))
+    return rep.as_dict()
+
+
 def fabx_result_free(r) -> None:
     lib().fabx_result_free(r)
 
@@ -315,6 +321,11 @@ class Task:
 
     def score(self, **kw) -> "Result":
         return Result(self, fabx_score(self.h, make_opts(**kw)))
+
+    def autotune(self, **kw) -> dict:
+        """Time the fused kernel's launch configurations on this task and keep the
+        fastest for its shape class (see fabx_autotune)."""
+        return fabx_autotune(self.h, make_opts(**kw))
 
     def score_async(self, **kw) -> "Result":
         """Enqueue the score and return at once; the result completes on wait()

@@ -48,10 +48,28 @@ class fabx_stats(ctypes.Structure):
         "n_cells", "n_triplets", "n_items", "n_frames", "n_pairs", "dtw_cells", "computed_dtw_cells",
         "n_nonrobust_pairs", "n_recheck_pairs", "n_recount_rows", "workspace_bytes")] + \
         [(n, ctypes.c_double) for n in ("ms_total", "ms_normalize", "ms_distance", "ms_triplets",
-                                         "ms_recheck", "ms_host_setup", "ms_host_finish", "margin", "delta")]
+                                         "ms_recheck", "ms_host_setup", "ms_host_finish", "margin", "delta")] + \
+        [("fused_cols", ctypes.c_int32), ("fused_blocks_per_cu", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class fabx_tune_entry(ctypes.Structure):
+    _fields_ = [("cols", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("ms_distance", ctypes.c_double)]
+
+
+class fabx_tune_report(ctypes.Structure):
+    _fields_ = [("n_tried", ctypes.c_int32), ("best", ctypes.c_int32), ("key_dim_pad", ctypes.c_int32),
+                ("key_max_len", ctypes.c_int32), ("key_frames_log2", ctypes.c_int32),
+                ("tried", fabx_tune_entry * 8)]
+
+    def as_dict(self):
+        tried = [{"cols": e.cols, "blocks_per_cu": e.blocks_per_cu, "ms_distance": e.ms_distance}
+                 for e in self.tried[: self.n_tried]]
+        return {"tried": tried, "best": tried[self.best] if self.best >= 0 else None,
+                "key": {"dim_pad": self.key_dim_pad, "max_len": self.key_max_len,
+                        "frames_log2": self.key_frames_log2}}
 
 
 class fabx_server_stats(ctypes.Structure):
@@ -86,6 +104,7 @@ SIGNATURES = {
     "fabx_score": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
     "fabx_score_async": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
     "fabx_result_wait": (ctypes.c_int, [_vp]),
+    "fabx_autotune": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(fabx_tune_report)]),
     "fabx_result_free": (None, [_vp]),
     "fabx_result_num_cells": (_i64, [_vp]),
     "fabx_result_key_width": (_i32, [_vp]),

@@ -1,5 +1,6 @@
 // C ABI of fastabx-hip: argument checks, handle management, error codes.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -118,6 +119,10 @@ EventPool::~EventPool() {
 
 void Staging::reserve(size_t n) {
     if (!done) FABX_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    if (in_flight) {
+        FABX_HIP(hipEventSynchronize(done));
+        in_flight = false;
+    }
     if (n <= cap) return;
     if (host) (void)hipHostFree(host);
     host = nullptr;
@@ -174,6 +179,7 @@ PinnedPool::~PinnedPool() {
 }
 
 Staging::~Staging() {
+    if (in_flight) (void)hipEventSynchronize(done);
     if (host) (void)hipHostFree(host);
     if (done) (void)hipEventDestroy(done);
 }
@@ -230,6 +236,8 @@ int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
             hipDeviceProp_t prop;
             FABX_HIP(hipGetDeviceProperties(&prop, device));
             c->n_cu = prop.multiProcessorCount;
+            const char *tune_file = std::getenv("FABX_AUTOTUNE_CACHE");
+            if (tune_file && *tune_file) c->tuner.load(tune_file);
             // NULL is the device's null stream, as everywhere in HIP: the context's
             // work is then ordered after what the caller enqueued there
             c->stream = static_cast<hipStream_t>(hip_stream);
@@ -294,7 +302,7 @@ int32_t fabx_task_key_width(const fabx_task *t) { return t ? t->p->key_width : -
 int fabx_task_cell_keys(const fabx_task *t, int32_t *out) {
     return guarded([&] {
         if (!t || !out) fail(FABX_EINVAL, "null argument");
-        if (!t->p->keys.empty()) std::memcpy(out, t->p->keys.data(), t->p->keys.size() * sizeof(int32_t));
+        cell_keys(*t->p, out);
     });
 }
 
@@ -361,8 +369,7 @@ int32_t fabx_result_key_width(const fabx_result *r) { return r ? r->p->task->key
 int fabx_result_cell_keys(const fabx_result *r, int32_t *out) {
     return guarded([&] {
         if (!r || !out) fail(FABX_EINVAL, "null argument");
-        const auto &k = r->p->task->keys;
-        if (!k.empty()) std::memcpy(out, k.data(), k.size() * sizeof(int32_t));
+        cell_keys(*r->p->task, out);
     });
 }
 

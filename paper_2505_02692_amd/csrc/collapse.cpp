@@ -5,11 +5,10 @@
 //
 // Level by level: every key value is replaced by its dense rank (computed by
 // the task builder); for a level, the ranks of the columns that remain form
-// one key.  Rows with equal keys are averaged (unweighted): when the key space
-// is small, through a direct table indexed by the mixed-radix key (one pass,
-// no sort; with many rows per key, fixed row ranges are accumulated in
-// parallel and merged in range order), otherwise after a stable radix sort of
-// the bit-packed key (summed in row order).  The averaged rows, in key order,
+// one key.  Rows with equal keys are averaged (unweighted, summed in row
+// order): when the key space is small, through a direct table indexed by the
+// mixed-radix key (no sort; threads own key ranges of the table), otherwise
+// after a stable radix sort of the bit-packed key.  The averaged rows, in key order,
 // carry on to the next level; the last rows are averaged flat.
 #include <algorithm>
 #include <numeric>
@@ -86,39 +85,46 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
                 return k;
             };
             const size_t nk = size_t(space);
-            // Many rows per key: fixed row ranges (independent of the thread count)
-            // fill tables in parallel, merged in range order.
-            const size_t n_tab = m >= 16 * nk && m >= (size_t(1) << 18) ? 8 : 1;
-            std::vector<hvec<Acc>> tabs(n_tab);
-            auto fill = [&](size_t r) {
-                hvec<Acc> &tab = tabs[r];
-                tab.assign(nk, Acc{0.0, 0u, 0u});
-                const size_t i0 = m * r / n_tab, i1 = m * (r + 1) / n_tab;
-                for (size_t i = i0; i < i1; ++i) {
-                    Acc &a = tab[mixed(i)];
-                    if (a.cnt++ == 0) a.first = uint32_t(i);
-                    a.sum += score[i];
+            // Each part owns a contiguous key range of the table: it scans all
+            // keys in row order and accumulates its own, so every key's sum is
+            // formed in row order whatever the part count.
+            hvec<uint32_t> keyv(m);
+            const size_t kChunk = size_t(1) << 15;
+            HostPool &hp = HostPool::get();
+            hp.parallel_for(int((m + kChunk - 1) / kChunk), [&](int c) {
+                for (size_t i = size_t(c) * kChunk; i < std::min(m, size_t(c + 1) * kChunk); ++i)
+                    keyv[i] = uint32_t(mixed(i));
+            });
+            const size_t n_parts = m >= (size_t(1) << 15) ? size_t(std::max(1, hp.size())) : 1;
+            hvec<Acc> tab(nk);
+            std::vector<size_t> part_rows(n_parts + 1, 0);
+            hp.parallel_for(int(n_parts), [&](int r) {
+                const size_t k0 = nk * size_t(r) / n_parts, k1 = nk * size_t(r + 1) / n_parts;
+                for (size_t k = k0; k < k1; ++k) tab[k] = Acc{0.0, 0u, 0u};
+                for (size_t i = 0; i < m; ++i) {
+                    const size_t k = keyv[i];
+                    if (k < k0 || k >= k1) continue;
+                    Acc &acc = tab[k];
+                    if (acc.cnt++ == 0) acc.first = uint32_t(i);
+                    acc.sum += score[i];
                 }
-            };
-            if (n_tab > 1) HostPool::get().parallel_for(int(n_tab), [&](int r) { fill(size_t(r)); });
-            else fill(0);
-            hvec<Acc> &tab = tabs[0];
-            for (size_t r = 1; r < n_tab; ++r)
-                for (size_t k = 0; k < nk; ++k) {
-                    const Acc &b = tabs[r][k];
-                    if (!b.cnt) continue;
-                    Acc &a = tab[k];
-                    if (!a.cnt) a.first = b.first;
-                    a.cnt += b.cnt;
-                    a.sum += b.sum;
-                }
-            nscore.reserve(m);
-            nrep.reserve(m);
-            for (size_t k = 0; k < nk; ++k)
-                if (tab[k].cnt) {
-                    nscore.push_back(tab[k].sum / double(tab[k].cnt));
-                    nrep.push_back(rep[tab[k].first]);
-                }
+                size_t used = 0;
+                for (size_t k = k0; k < k1; ++k) used += tab[k].cnt != 0;
+                part_rows[size_t(r) + 1] = used;
+            });
+            for (size_t r = 0; r < n_parts; ++r) part_rows[r + 1] += part_rows[r];
+            nscore.resize(part_rows[n_parts]);
+            nrep.resize(part_rows[n_parts]);
+            hp.parallel_for(int(n_parts), [&](int r) {
+                const size_t k0 = nk * size_t(r) / n_parts, k1 = nk * size_t(r + 1) / n_parts;
+                size_t o = part_rows[size_t(r)];
+                for (size_t k = k0; k < k1; ++k)
+                    if (tab[k].cnt) {
+                        nscore[o] = tab[k].sum / double(tab[k].cnt);
+                        nrep[o] = rep[tab[k].first];
+                        ++o;
+                    }
+            });
         } else {
             hvec<uint32_t> order(m);
             std::iota(order.begin(), order.end(), 0u);

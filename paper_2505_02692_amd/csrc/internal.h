@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -72,12 +73,15 @@ struct EventPool {
 
 // Pinned host buffer through which a score's tables reach the device with one
 // DMA copy.  One user at a time (the copy is waited for before release).
+// Pinned host buffer that uploads go through.  An upload returns once its DMA
+// is enqueued; the next one waits for that DMA before writing the buffer.
 struct Staging {
     std::mutex mu;
     void *host = nullptr;
     size_t cap = 0;
     hipEvent_t done = nullptr;
-    void reserve(size_t n);
+    bool in_flight = false;   // a DMA out of `host` may still run (done not yet waited for)
+    void reserve(size_t n);   // caller holds mu; waits for an in-flight DMA first
     ~Staging();
 };
 
@@ -93,6 +97,42 @@ struct PinnedPool {
     ~PinnedPool();
 };
 
+// Launch choices of the fused kernel: column block width (128 or 256 frames)
+// and grid (blocks_per_cu > 0: a persistent grid of that many blocks per CU;
+// 0: one block per work unit).  Results do not depend on them.
+struct FusedConfig {
+    int cols = 0;           // 0: not set
+    int blocks_per_cu = 0;
+};
+
+// Shape class of a task for tuning the fused kernel.
+struct TuneKey {
+    int dim_pad = 0, max_len = 0, frames_log2 = 0, path = 0;
+    bool operator<(const TuneKey &o) const {
+        if (dim_pad != o.dim_pad) return dim_pad < o.dim_pad;
+        if (max_len != o.max_len) return max_len < o.max_len;
+        if (frames_log2 != o.frames_log2) return frames_log2 < o.frames_log2;
+        return path < o.path;
+    }
+};
+
+// Best fused-kernel configuration per shape class, filled by fabx_autotune and
+// kept in the file named by FABX_AUTOTUNE_CACHE (read at context creation,
+// rewritten on each new entry).  Untuned shapes get the default.
+class Tuner {
+public:
+    void load(const std::string &path);
+    FusedConfig lookup(const TuneKey &k);
+    void record(const TuneKey &k, const FusedConfig &c);
+    static FusedConfig default_config() { return FusedConfig{128, 0}; }
+
+private:
+    std::mutex mu_;
+    std::string path_;
+    std::map<TuneKey, FusedConfig> table_;
+    void save_locked();
+};
+
 struct CtxImpl {
     int device = 0;
     hipStream_t stream = nullptr;  // borrowed; nullptr = the null stream
@@ -101,6 +141,7 @@ struct CtxImpl {
     EventPool events;
     Staging staging;
     PinnedPool pinned;
+    Tuner tuner;
     ~CtxImpl();
 };
 
@@ -120,7 +161,7 @@ struct DatasetImpl {
 // Fused BF16 kernel tiling: frames per row block (one DTW lane per frame row)
 // and per column block.  Items are never split, so items are <= 64 frames.
 constexpr int kFusedRowFrames = 64;
-constexpr int kFusedColFrames = 128;
+constexpr int kFusedColFrames = 128;  // default column block width (the other is 256)
 
 // One BY group that holds at least one cell.  Items of a group are
 // contiguous in task order, and so are their packed frames.
@@ -152,9 +193,7 @@ struct TaskDevice {
     const int64_t *g_item0 = nullptr, *g_n = nullptr, *g_frame0 = nullptr, *g_nframes = nullptr,
                   *g_pair_base = nullptr, *g_dmat_base = nullptr;
     const CellDev *cells = nullptr;
-    const int32_t *units = nullptr, *rb = nullptr, *cb = nullptr, *g_rb0 = nullptr, *g_cb0 = nullptr,
-                  *g_ncb = nullptr;
-    const int64_t *unit_prefix = nullptr;
+    const int32_t *units = nullptr, *rb = nullptr, *g_rb0 = nullptr;
     bool uploaded = false;
 };
 
@@ -175,6 +214,19 @@ struct Workspace {
 
 struct ResultImpl;
 
+// Column blocks of the fused kernel for one column block width: whole items
+// packed into <= cols frames per group, and the work units (row block x
+// column block) they make with the task's row blocks.
+struct ColPlan {
+    int cols = 0;
+    hvec<int32_t> cb;                    // [n_cb][4] = group, first item (task), n items, n frames
+    std::vector<int32_t> g_cb0, g_ncb;   // per group: first column block, count
+    hvec<int64_t> unit_prefix;           // per group: work units prefix [n_groups + 1]
+    DevBuf dev;                          // device copy of the above, made on first use
+    const int32_t *d_cb = nullptr, *d_g_cb0 = nullptr, *d_g_ncb = nullptr;
+    const int64_t *d_unit_prefix = nullptr;
+};
+
 struct TaskImpl {
     std::shared_ptr<DatasetImpl> ds;
     int32_t on = 0;
@@ -193,17 +245,18 @@ struct TaskImpl {
     hvec<Group> groups;
     hvec<CellDev> cells;
     hvec<int64_t> n_triplets;
-    hvec<int32_t> keys;      // [n_cells * key_width]
-    hvec<uint32_t> rkeys;    // dense ranks of the key values, same layout (for collapse)
+    std::vector<std::vector<int32_t>> key_values;  // per key column: attribute value of each rank
+    hvec<uint32_t> rkeys;    // [n_cells * key_width]: dense ranks of the key values
+                             // (cell keys are key_values[c][rank]; collapse works on ranks)
     std::vector<int> key_bits;      // bits of each key column's ranks
     std::vector<uint32_t> key_card; // distinct values of each key column (ranks are 0 .. card - 1)
 
     // work plans, fixed for the task
     hvec<int32_t> units;     // triplet units [n][3]: cell, x_begin, x_end
     int64_t sum_nx = 0;             // sum over cells of |X|
-    hvec<int32_t> rb, cb;    // fused kernel row / column blocks [n][4]
-    std::vector<int32_t> g_rb0, g_cb0, g_ncb;
-    hvec<int64_t> unit_prefix;  // fused work units per group, prefix [n_groups + 1]
+    hvec<int32_t> rb;               // fused kernel row blocks [n][4] (<= 64 frames)
+    std::vector<int32_t> g_rb0, g_nrb;
+    std::vector<std::unique_ptr<ColPlan>> col_plans;  // by column block width, made on demand
     int64_t fused_cells = 0;        // frame pairs the fused kernel covers
 
     int64_t n_frames = 0;
@@ -230,6 +283,7 @@ struct ResultImpl {
     hvec<float> p32;
     hvec<uint8_t> flags;
     hvec<double> p64;
+    FusedConfig fused;  // fused kernel configuration used (BF16 DTW)
     // Completion: a launched score stays pending until finish_score; its
     // status (an error found on completion) is kept and reported again.
     std::mutex mu;
@@ -241,6 +295,11 @@ struct ResultImpl {
 };
 
 // task.cpp
+// Cell keys (attribute values) of cells [0, n) into out [n * key_width].
+void cell_keys(const TaskImpl &t, int32_t *out);
+// The task's column plan for `cols` (128 or 256), built on first use; the caller
+// holds the task's mutex.
+ColPlan &col_plan(TaskImpl &t, int cols);
 std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,
                                      const int32_t *by, int32_t n_by, const int32_t *across,
                                      int32_t n_across);
@@ -250,8 +309,10 @@ struct ScoreParams {
     int mode, precision, dtw_norm;
     double margin, delta;
     bool keep_pairs;
+    FusedConfig fused;  // cols > 0: use this instead of the tuning table
 };
 ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds);
+TuneKey tune_key(const TaskImpl &t, const ScoreParams &p);
 // launch_score enqueues the whole score on `stream` and returns a pending
 // result; finish_score waits for it and fills the result (idempotent, throws
 // the score's error every time it is called on a failed result).  run_score

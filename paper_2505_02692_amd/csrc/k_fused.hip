@@ -45,15 +45,24 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kRows = 64;             // row block frames = DTW lanes
-constexpr int kCols = 128;            // column block frames
 constexpr int kKc = 64;               // K chunk (bf16 elements) staged in LDS
 constexpr int kLdsRow = kKc + 8;      // padded LDS row of a K chunk (bf16)
-constexpr int kDStride = kCols + 2;   // LDS distance tile stride (floats)
-constexpr int kStageBytes = (kRows + kCols) * kLdsRow * 2;
-// distance tile + a tail guard: the DTW loop reads up to 63 columns past a row's end
-constexpr int kTileBytes = (kRows * kDStride + kWave) * 4;
-constexpr int kFlagLen = kWave + kCols + kWave;  // column flags with a zero guard on each side
-constexpr int kSmemBytes = kStageBytes > kTileBytes ? kStageBytes : kTileBytes;
+
+// Tile geometry for a column block of kC frames (128 or 256): wave w owns
+// columns [kWaveCols * w, kWaveCols * (w + 1)) of the Gram tile, kCT tiles of
+// 32 columns.
+template <int kC>
+struct Tile {
+    static constexpr int kCols = kC;
+    static constexpr int kWaveCols = kC / 4;
+    static constexpr int kCT = kWaveCols / 32;
+    static constexpr int kDStride = kC + 2;  // LDS distance tile stride (floats)
+    static constexpr int kStageBytes = (kRows + kC) * kLdsRow * 2;
+    // distance tile + a tail guard: the DTW loop reads up to 63 columns past a row's end
+    static constexpr int kTileBytes = (kRows * kDStride + kWave) * 4;
+    static constexpr int kFlagLen = kWave + kC + kWave;  // column flags, zero guard on each side
+    static constexpr int kSmemBytes = kStageBytes > kTileBytes ? kStageBytes : kTileBytes;
+};
 
 // Value of lane - 1 (DPP wave_shr:1); lane 0, which has no source, keeps `old`.
 __device__ __forceinline__ float shr1(float old, float v) {
@@ -102,22 +111,28 @@ struct Chunk {
     }
 };
 
-// acc0 = rows 0..31, acc1 = rows 32..63 against columns [32w, 32w+32).
+// acc[h][ct] = rows [32h, 32h + 32) against columns kWaveCols * w + 32 ct + [0, 32).
 // Software-pipelined: the next K chunk is loaded from memory into registers
-// while the MFMAs consume the current one from LDS.  A wave whose columns all
-// lie past nc skips its MFMAs, and so does the second row half when nr <= 32
-// (those accumulators are never read).
+// while the MFMAs consume the current one from LDS.  Column tiles that lie
+// past nc skip their MFMAs, and so does the second row half when nr <= 32
+// (those accumulators are never read).  Every product accumulates its K
+// range in the same order whatever the tile width, so results do not depend
+// on it.
+template <int kC>
 __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__restrict__ xn, int dim_pad,
-                                          int64_t r0, int nr, int64_t c0, int nc, f32x16 &acc0,
-                                          f32x16 &acc1) {
+                                          int64_t r0, int nr, int64_t c0, int nc,
+                                          f32x16 (&acc)[2][Tile<kC>::kCT]) {
+    using T = Tile<kC>;
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const bool do0 = 32 * w < nc, do1 = do0 && nr > 32;
+    const bool do1 = nr > 32;
     uint16_t *As = smem;
     uint16_t *Bs = smem + kRows * kLdsRow;
-    for (int i = 0; i < 16; ++i) { acc0[i] = 0.0f; acc1[i] = 0.0f; }
+#pragma unroll
+    for (int ct = 0; ct < T::kCT; ++ct)
+        for (int i = 0; i < 16; ++i) { acc[0][ct][i] = 0.0f; acc[1][ct][i] = 0.0f; }
     Chunk<kRows> ca;
-    Chunk<kCols> cb;
+    Chunk<kC> cb;
     ca.load(xn, dim_pad, r0, nr, 0);
     cb.load(xn, dim_pad, c0, nc, 0);
     for (int k0 = 0; k0 < dim_pad; k0 += kKc) {
@@ -128,16 +143,21 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
             ca.load(xn, dim_pad, r0, nr, k0 + kKc);
             cb.load(xn, dim_pad, c0, nc, k0 + kKc);
         }
-        if (do0) {
 #pragma unroll
-            for (int ks = 0; ks < kKc / 16; ++ks) {
-                const int kk = ks * 16 + (lane / 32) * 8;
-                const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + (lane % 32) * kLdsRow + kk);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (32 * w + lane % 32) * kLdsRow + kk);
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc0, 0, 0, 0);
-                if (do1) {
-                    const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(As + (32 + lane % 32) * kLdsRow + kk);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc1, 0, 0, 0);
+        for (int ct = 0; ct < T::kCT; ++ct) {
+            const int col0 = T::kWaveCols * w + 32 * ct;
+            if (col0 < nc) {
+#pragma unroll
+                for (int ks = 0; ks < kKc / 16; ++ks) {
+                    const int kk = ks * 16 + (lane / 32) * 8;
+                    const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + (lane % 32) * kLdsRow + kk);
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (col0 + lane % 32) * kLdsRow + kk);
+                    acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][ct], 0, 0, 0);
+                    if (do1) {
+                        const bf16x8 a1 =
+                            *reinterpret_cast<const bf16x8 *>(As + (32 + lane % 32) * kLdsRow + kk);
+                        acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][ct], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -148,7 +168,7 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
 // Row (within the 32 x 32 tile) of accumulator element i of this lane.
 __device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i / 4) + 4 * (lane / 32) + (i % 4); }
 
-template <bool kPath>
+template <int kC, bool kPath>
 __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ xn,
                                                   const float *__restrict__ rinv, int dim_pad,
                                                   const int64_t *__restrict__ g_item0,
@@ -166,7 +186,9 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
                                                   float delta, float *__restrict__ p32,
                                                   uint8_t *__restrict__ flags,
                                                   unsigned int *__restrict__ nonrobust_n) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kSmemBytes];
+    using T = Tile<kC>;
+    constexpr int kDStride = T::kDStride, kFlagLen = T::kFlagLen;
+    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kSmemBytes];
     __shared__ uint16_t colflag[4][kFlagLen];
     // Persistent blocks, XCD-aware order: the 8 XCDs take blocks round-robin,
     // so XCD x works through the contiguous unit range [x * grid_q, (x+1) * grid_q)
@@ -188,29 +210,33 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     const int64_t r_frame0 = item_dst[r_item0], c_frame0 = item_dst[c_item0];
 
     // 1. Gram tile
-    f32x16 acc0, acc1;
-    gram_tile(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
-              c_frames, acc0, acc1);
+    f32x16 acc[2][T::kCT];
+    gram_tile<kC>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
+                  c_frames, acc);
 
     // 2. epilogue -> LDS distance tile (the staging buffers are dead now).  Only
     // the rows and column waves that hold frames are written; the DTW reads the
     // others only in lanes and steps whose results are discarded.
     float *dt = reinterpret_cast<float *>(smem_raw);
-    if (32 * w < c_frames) {
-        const int col = 32 * w + lane % 32;
+#pragma unroll
+    for (int ct = 0; ct < T::kCT; ++ct) {
+        const int col0 = T::kWaveCols * w + 32 * ct;
+        if (col0 >= c_frames) continue;
+        const int col = col0 + lane % 32;
         const float rc = col < c_frames ? rinv[c_frame0 + col] : 0.0f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r0 = acc_row(i, lane);
             const float rr0 = r0 < r_frames ? rinv[r_frame0 + r0] : 0.0f;
-            dt[r0 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc0[i] * rr0 * rc, -1.0f), 1.0f));
+            dt[r0 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc[0][ct][i] * rr0 * rc, -1.0f), 1.0f));
         }
         if (r_frames > 32) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r1 = 32 + acc_row(i, lane);
                 const float rr1 = r1 < r_frames ? rinv[r_frame0 + r1] : 0.0f;
-                dt[r1 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc1[i] * rr1 * rc, -1.0f), 1.0f));
+                dt[r1 * kDStride + col] =
+                    dev::acos_over_pi(fminf(fmaxf(acc[1][ct][i] * rr1 * rc, -1.0f), 1.0f));
             }
         }
     }
@@ -334,7 +360,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
                                                               const int64_t *__restrict__ tile_prefix,
                                                               int64_t n_groups, int64_t n_tiles,
                                                               float *__restrict__ out) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[kStageBytes];
+    using T = Tile<128>;
+    constexpr int kCols = T::kCols;
+    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kStageBytes];
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
     const int64_t n = nrows[g];
@@ -342,9 +370,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     const int64_t local = tile - tile_prefix[g];
     const int64_t r0 = (local / ntc) * kRows, c0 = (local % ntc) * kCols;
     const int nr = int(min<int64_t>(kRows, n - r0)), nc = int(min<int64_t>(kCols, n - c0));
-    f32x16 acc0, acc1;
-    gram_tile(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc,
-              acc0, acc1);
+    f32x16 acc[2][1];
+    gram_tile<128>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc,
+                   acc);
+    const f32x16 &acc0 = acc[0][0], &acc1 = acc[1][0];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int col = 32 * w + lane % 32;
     if (col < nc) {
@@ -364,6 +393,29 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     }
 }
 
+template <int kC>
+void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad, const GroupTables &g,
+                  const ItemTables &it, const FusedPlan &plan, int norm, float delta, float *p32,
+                  uint8_t *flags, unsigned int *nonrobust_n) {
+    // units are split into 8 contiguous ranges, one per XCD; blocks of XCD x take
+    // the units of range x in turn
+    const int64_t q = (plan.n_units + 7) / 8;
+    int64_t per_xcd = std::min<int64_t>(q, dev::kMaxBlocks / 8);
+    if (plan.blocks_per_cu > 0)
+        per_xcd = std::min<int64_t>(per_xcd, std::max<int64_t>(1, int64_t(plan.blocks_per_cu) * plan.n_cu / 8));
+    const dim3 grid(unsigned(8 * per_xcd)), block(256);
+    if (norm == FABX_NORM_PATH)
+        hipLaunchKernelGGL((k_fused<kC, true>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
+                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.g_rb0,
+                           plan.g_cb0, plan.g_ncb, g.n_groups, plan.n_units, q, delta, p32, flags,
+                           nonrobust_n);
+    else
+        hipLaunchKernelGGL((k_fused<kC, false>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
+                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.g_rb0,
+                           plan.g_cb0, plan.g_ncb, g.n_groups, plan.n_units, q, delta, p32, flags,
+                           nonrobust_n);
+}
+
 }  // namespace
 
 void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
@@ -371,18 +423,12 @@ void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pa
                 float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n) {
     if (plan.n_units <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
-    const int64_t q = (plan.n_units + 7) / 8;
-    const int64_t blocks = 8 * std::min<int64_t>(q, dev::kMaxBlocks / 8);
-    if (norm == FABX_NORM_PATH)
-        hipLaunchKernelGGL(k_fused<true>, dim3(unsigned(blocks)), dim3(256), 0, s, xn, rinv, dim_pad,
-                           g.item0, g.n_items, g.pair_base, it.len, it.dst, plan.rb, plan.cb,
-                           plan.unit_prefix, plan.g_rb0, plan.g_cb0, plan.g_ncb, g.n_groups,
-                           plan.n_units, q, delta, p32, flags, nonrobust_n);
+    if (plan.cols == 128)
+        launch_fused<128>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n);
+    else if (plan.cols == 256)
+        launch_fused<256>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n);
     else
-        hipLaunchKernelGGL(k_fused<false>, dim3(unsigned(blocks)), dim3(256), 0, s, xn, rinv, dim_pad,
-                           g.item0, g.n_items, g.pair_base, it.len, it.dst, plan.rb, plan.cb,
-                           plan.unit_prefix, plan.g_rb0, plan.g_cb0, plan.g_ncb, g.n_groups,
-                           plan.n_units, q, delta, p32, flags, nonrobust_n);
+        fail(FABX_EINVAL, "fused kernel column block must be 128 or 256 frames");
     FABX_HIP(hipGetLastError());
 }
 

@@ -72,6 +72,9 @@ struct FusedPlan {
     const int32_t *g_rb0, *g_cb0;  // per group: first row / col block, and counts
     const int32_t *g_nrb, *g_ncb;
     int64_t n_units;
+    int cols;            // column block width the blocks were packed for: 128 or 256
+    int blocks_per_cu;   // persistent grid of blocks_per_cu * n_cu blocks; 0: one block per unit
+    int n_cu;
 };
 void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                 const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,

@@ -1,6 +1,7 @@
 // Score orchestration: device tables, workspace, work plans and the launch
 // sequence of one fabx_score call.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -59,7 +60,7 @@ struct Packer {
         });
         FABX_HIP(hipMemcpyAsync(dst.ptr, h, total, hipMemcpyHostToDevice, s));
         FABX_HIP(hipEventRecord(stg.done, s));
-        FABX_HIP(hipEventSynchronize(stg.done));  // the staging buffer is free again
+        stg.in_flight = true;  // the next upload waits for this DMA before reusing the buffer
     }
     template <typename T>
     static const T *at(const DevBuf &b, size_t off) {
@@ -239,7 +240,28 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
                       &t.ws.half_units, &t.ws.counters, &t.ws.recheck_list, &t.ws.recount_list})
         if (!b->ptr) b->pool = pool;
+    // fused kernel: tile width and grid from the tuning table (or the caller),
+    // and the task's column blocks for that width (uploaded on first use)
+    FusedConfig fcfg;
+    ColPlan *cplan = nullptr;
+    if (dtw && bf16) {
+        fcfg = p.fused.cols > 0 ? p.fused : ds.ctx->tuner.lookup(tune_key(t, p));
+        cplan = &col_plan(t, fcfg.cols);
+        res->fused = fcfg;
+        st.fused_cols = fcfg.cols;
+        st.fused_blocks_per_cu = fcfg.blocks_per_cu;
+    }
+    auto add_col_plan = [](Packer &pc, ColPlan &cp) {
+        return std::array<size_t, 4>{pc.add(cp.cb), pc.add(cp.unit_prefix), pc.add(cp.g_cb0), pc.add(cp.g_ncb)};
+    };
+    auto set_col_plan = [](ColPlan &cp, const DevBuf &buf, const std::array<size_t, 4> &o) {
+        cp.d_cb = Packer::at<int32_t>(buf, o[0]);
+        cp.d_unit_prefix = Packer::at<int64_t>(buf, o[1]);
+        cp.d_g_cb0 = Packer::at<int32_t>(buf, o[2]);
+        cp.d_g_ncb = Packer::at<int32_t>(buf, o[3]);
+    };
     if (!dv.uploaded) {
+        // one DMA for the task's tables (and the column plan this score uses)
         Packer pk;
         const size_t ng = static_cast<size_t>(G);
         std::vector<int64_t> a(ng), b(ng + 1), c(ng), d(ng), e(ng), f(ng + 1);
@@ -256,9 +278,10 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         const size_t o_src = pk.add(t.item_src), o_len = pk.add(t.item_len), o_dst = pk.add(t.item_dst),
                      o_grp = pk.add(t.item_group), o_a = pk.add(a), o_b = pk.add(b), o_c = pk.add(c),
                      o_d = pk.add(d), o_e = pk.add(e), o_f = pk.add(f), o_cells = pk.add(t.cells),
-                     o_units = pk.add(t.units), o_rb = pk.add(t.rb), o_cb = pk.add(t.cb),
-                     o_up = pk.add(t.unit_prefix), o_grb = pk.add(t.g_rb0), o_gcb = pk.add(t.g_cb0),
-                     o_gncb = pk.add(t.g_ncb);
+                     o_units = pk.add(t.units), o_rb = pk.add(t.rb), o_grb = pk.add(t.g_rb0);
+        const bool with_plan = cplan && !cplan->d_cb;
+        std::array<size_t, 4> o_plan{};
+        if (with_plan) o_plan = add_col_plan(pk, *cplan);
         pk.upload(dv.blob, ds.ctx->staging, stream);
         dv.item_src = Packer::at<int64_t>(dv.blob, o_src);
         dv.item_len = Packer::at<int32_t>(dv.blob, o_len);
@@ -273,12 +296,16 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         dv.cells = Packer::at<CellDev>(dv.blob, o_cells);
         dv.units = Packer::at<int32_t>(dv.blob, o_units);
         dv.rb = Packer::at<int32_t>(dv.blob, o_rb);
-        dv.cb = Packer::at<int32_t>(dv.blob, o_cb);
-        dv.unit_prefix = Packer::at<int64_t>(dv.blob, o_up);
         dv.g_rb0 = Packer::at<int32_t>(dv.blob, o_grb);
-        dv.g_cb0 = Packer::at<int32_t>(dv.blob, o_gcb);
-        dv.g_ncb = Packer::at<int32_t>(dv.blob, o_gncb);
+        if (with_plan) set_col_plan(*cplan, dv.blob, o_plan);
         dv.uploaded = true;
+    }
+    if (cplan && !cplan->d_cb) {  // another column width for an already uploaded task
+        Packer pc;
+        const auto o = add_col_plan(pc, *cplan);
+        cplan->dev.pool = pool;
+        pc.upload(cplan->dev, ds.ctx->staging, stream);
+        set_col_plan(*cplan, cplan->dev, o);
     }
     // Gram tile prefix of this score (plain form / pooled mode only)
     DevBuf &plan_d = pend->plan_d;
@@ -351,8 +378,9 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         kern::dtw_plain(stream, ws.dmat.as<float>(), gt, it, p.dtw_norm, ws.p32.as<float>());
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw) {
-        kern::FusedPlan fp{dv.rb, dv.cb, dv.unit_prefix, dv.g_rb0, dv.g_cb0, nullptr, dv.g_ncb,
-                           t.unit_prefix.back()};
+        kern::FusedPlan fp{dv.rb, cplan->d_cb, cplan->d_unit_prefix, dv.g_rb0, cplan->d_g_cb0, nullptr,
+                           cplan->d_g_ncb, cplan->unit_prefix.back(), fcfg.cols, fcfg.blocks_per_cu,
+                           ds.ctx->n_cu};
         kern::fused_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt, it, fp,
                          p.dtw_norm, float(p.delta), ws.p32.as<float>(), ws.flags.as<uint8_t>(),
                          nonrobust_n);

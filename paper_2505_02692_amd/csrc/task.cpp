@@ -129,7 +129,6 @@ struct Sink {
     // write pass: destinations, and the share's first cell / unit int / group / pair slot
     CellDev *cells = nullptr;
     int64_t *ntrip = nullptr;
-    int32_t *keys = nullptr;
     uint32_t *rkeys = nullptr;
     int32_t *units = nullptr;
     Group *groups = nullptr;
@@ -148,8 +147,6 @@ struct WalkCtx {
     // ranks per sorted position, [n x W]: ON, then BY..., then ACROSS...
     const uint32_t *srank;
     int W;
-    // key values by rank, per column in the same order
-    std::vector<const std::vector<int32_t> *> values;
     const hvec<int64_t> *pf, *pq;
     int32_t n_across;
 };
@@ -167,9 +164,8 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
     std::vector<ClassRun> cls;
     std::vector<uint8_t> need;
     std::vector<std::pair<int64_t, int64_t>> need_list, runs;
-    // key values and ranks, read once per group (BY) and per class (ON, ACROSS)
+    // key ranks, read once per group (BY) and per class (ACROSS)
     const int n_by = int(t.by.size()), n_ac = w.n_across;
-    std::vector<int32_t> gby(static_cast<size_t>(n_by)), con, cac;
     std::vector<uint32_t> gbyr(static_cast<size_t>(n_by)), cacr;
     int64_t g0 = s_begin;
     while (g0 < s_end) {
@@ -186,20 +182,11 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
         const int32_t group_id = int32_t(out.group_base + out.n_groups);
         {
             const uint32_t *r0 = SR + size_t(g0) * W;
-            for (int j = 0; j < n_by; ++j) {
-                gbyr[size_t(j)] = r0[1 + j];
-                gby[size_t(j)] = (*w.values[size_t(1 + j)])[r0[1 + j]];
-            }
-            con.resize(size_t(K));
-            cac.resize(size_t(K * n_ac));
+            for (int j = 0; j < n_by; ++j) gbyr[size_t(j)] = r0[1 + j];
             cacr.resize(size_t(K * n_ac));
             for (int64_t i = 0; i < K; ++i) {
                 const uint32_t *ri = SR + size_t(cls[size_t(i)].start) * W;
-                con[size_t(i)] = (*w.values[0])[ri[0]];
-                for (int j = 0; j < n_ac; ++j) {
-                    cacr[size_t(i * n_ac + j)] = ri[1 + n_by + j];
-                    cac[size_t(i * n_ac + j)] = (*w.values[size_t(1 + n_by + j)])[ri[1 + n_by + j]];
-                }
+                for (int j = 0; j < n_ac; ++j) cacr[size_t(i * n_ac + j)] = ri[1 + n_by + j];
             }
         }
         // ACROSS tuples of two classes: lexicographic order (the sort order) and
@@ -240,20 +227,12 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
                 c.exclude_self = excl ? 1 : 0;
                 out.cells[cid] = c;
                 out.ntrip[cid] = nt;
-                int32_t *kk = out.keys + cid * out.key_width;
                 uint32_t *rk = out.rkeys + cid * out.key_width;
-                kk[0] = con[size_t(ia)];
-                kk[1] = con[size_t(ib)];
                 rk[0] = cls[size_t(ia)].on_rank;
                 rk[1] = cls[size_t(ib)].on_rank;
-                for (int j = 0; j < n_by; ++j) {
-                    kk[2 + j] = gby[size_t(j)];
-                    rk[2 + j] = gbyr[size_t(j)];
-                }
+                for (int j = 0; j < n_by; ++j) rk[2 + j] = gbyr[size_t(j)];
                 for (int j = 0; j < n_ac; ++j) {
-                    kk[2 + n_by + j] = cac[size_t(ia * n_ac + j)];
                     rk[2 + n_by + j] = cacr[size_t(ia * n_ac + j)];
-                    kk[2 + n_by + n_ac + j] = cac[size_t(ix * n_ac + j)];
                     rk[2 + n_by + n_ac + j] = cacr[size_t(ix * n_ac + j)];
                 }
                 int32_t *u = out.units + out.unit_base + out.n_unit_ints;
@@ -354,7 +333,76 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
     }
 }
 
+// Whole items of group gi packed, in task order, into blocks of at most
+// `limit` frames (at least one item per block: an item above the limit is only
+// legal in pooled mode, which does not use these blocks).  Writes [n][4] =
+// group, first item, n items, n frames to `out` if given; returns the count.
+int32_t pack_blocks(const TaskImpl &t, int64_t gi, int limit, int32_t *out) {
+    const Group &g = t.groups[size_t(gi)];
+    int32_t nb = 0;
+    int64_t k = g.item0;
+    const int64_t end = g.item0 + g.n_items;
+    while (k < end) {
+        const int32_t first = int32_t(k);
+        int32_t frames = 0, cnt = 0;
+        while (k < end && (cnt == 0 || frames + t.item_len[size_t(k)] <= limit)) {
+            frames += t.item_len[size_t(k)];
+            ++cnt;
+            ++k;
+        }
+        if (out) {
+            int32_t *o = out + 4 * size_t(nb);
+            o[0] = int32_t(gi);
+            o[1] = first;
+            o[2] = cnt;
+            o[3] = frames;
+        }
+        ++nb;
+    }
+    return nb;
+}
+
 }  // namespace
+
+void cell_keys(const TaskImpl &t, int32_t *out) {
+    const size_t K = size_t(t.key_width), n = t.cells.size();
+    const size_t kChunk = size_t(1) << 15;
+    parallel_for(int((n + kChunk - 1) / kChunk), [&](int c) {
+        for (size_t i = size_t(c) * kChunk; i < std::min(n, size_t(c + 1) * kChunk); ++i)
+            for (size_t k = 0; k < K; ++k) out[i * K + k] = t.key_values[k][t.rkeys[i * K + k]];
+    });
+}
+
+ColPlan &col_plan(TaskImpl &t, int cols) {
+    for (auto &p : t.col_plans)
+        if (p->cols == cols) return *p;
+    auto cp = std::make_unique<ColPlan>();
+    cp->cols = cols;
+    const int64_t G = int64_t(t.groups.size());
+    cp->g_cb0.assign(size_t(G), 0);
+    cp->g_ncb.assign(size_t(G), 0);
+    const int64_t kGroups = 2048;
+    const int n_gc = int((G + kGroups - 1) / kGroups);
+    parallel_for(n_gc, [&](int c) {
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+            cp->g_ncb[size_t(gi)] = pack_blocks(t, gi, cols, nullptr);
+    });
+    cp->unit_prefix.assign(size_t(G) + 1, 0);
+    int32_t total = 0;
+    for (int64_t gi = 0; gi < G; ++gi) {
+        cp->g_cb0[size_t(gi)] = total;
+        total += cp->g_ncb[size_t(gi)];
+        cp->unit_prefix[size_t(gi) + 1] =
+            cp->unit_prefix[size_t(gi)] + int64_t(t.g_nrb[size_t(gi)]) * cp->g_ncb[size_t(gi)];
+    }
+    cp->cb.resize(4 * size_t(total));
+    parallel_for(n_gc, [&](int c) {
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+            pack_blocks(t, gi, cols, cp->cb.data() + 4 * size_t(cp->g_cb0[size_t(gi)]));
+    });
+    t.col_plans.push_back(std::move(cp));
+    return *t.col_plans.back();
+}
 
 std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,
                                      const int32_t *by, int32_t n_by, const int32_t *across,
@@ -541,10 +589,11 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         cut[k] = c;
     }
     std::vector<Sink> parts(static_cast<size_t>(n_shares));
-    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, srank.data(), W, {}, &pf, &pq, n_across};
-    wc.values.push_back(&ron.values);
-    for (auto &r : rby) wc.values.push_back(&r.values);
-    for (auto &r : racr) wc.values.push_back(&r.values);
+    WalkCtx wc{ds.get(), t.get(), &order, &by_part, &cls_part, srank.data(), W, &pf, &pq, n_across};
+    t->key_values = {ron.values, ron.values};
+    for (auto &r : rby) t->key_values.push_back(r.values);
+    for (auto &r : racr) t->key_values.push_back(r.values);
+    for (auto &r : racr) t->key_values.push_back(r.values);
     t->key_bits = {ron.bits, ron.bits};
     for (auto &r : rby) t->key_bits.push_back(r.bits);
     for (auto &r : racr) t->key_bits.push_back(r.bits);
@@ -574,7 +623,6 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     t->n_pair_slots = n_slots;
     t->cells.resize(n_cells);
     t->n_triplets.resize(n_cells);
-    t->keys.resize(n_cells * size_t(t->key_width));
     t->rkeys.resize(n_cells * size_t(t->key_width));
     t->units.resize(n_unit_ints);
     t->groups.resize(n_groups);
@@ -587,7 +635,6 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         p.pair_slots = 0;
         p.cells = t->cells.data();
         p.ntrip = t->n_triplets.data();
-        p.keys = t->keys.data();
         p.rkeys = t->rkeys.data();
         p.units = t->units.data();
         p.groups = t->groups.data();
@@ -643,67 +690,29 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     for (int ml : max_len_part) t->max_len = std::max(t->max_len, ml);
     const int64_t frame = frame_total;
 
-    // fused-kernel blocks: whole items packed into <= 64-frame row blocks and
-    // <= 128-frame column blocks per group; work units = row x column blocks.
-    // Counted per group in parallel, then written at the prefix offsets.
-    auto pack = [&](int64_t gi, int limit, int32_t *out) {
-        const Group &g = t->groups[size_t(gi)];
-        int32_t nb = 0;
-        int64_t k = g.item0;
-        const int64_t end = g.item0 + g.n_items;
-        while (k < end) {
-            const int32_t first = int32_t(k);
-            int32_t frames = 0, cnt = 0;
-            // at least one item per block (an item above the limit is only legal in
-            // pooled mode, which does not use these blocks)
-            while (k < end && (cnt == 0 || frames + t->item_len[size_t(k)] <= limit)) {
-                frames += t->item_len[size_t(k)];
-                ++cnt;
-                ++k;
-            }
-            if (out) {
-                int32_t *o = out + 4 * size_t(nb);
-                o[0] = int32_t(gi);
-                o[1] = first;
-                o[2] = cnt;
-                o[3] = frames;
-            }
-            ++nb;
-        }
-        return nb;
-    };
-    t->g_rb0.assign(size_t(G), 0);
-    t->g_cb0.assign(size_t(G), 0);
-    t->g_ncb.assign(size_t(G), 0);
-    std::vector<int32_t> nrb_g(static_cast<size_t>(G));
+    // fused-kernel row blocks: whole items packed into <= 64 frames per group
+    // (column blocks depend on the tile width and are made by col_plan)
+    std::vector<int32_t> nrb(static_cast<size_t>(G));
     const int64_t kGroups = 2048;
     const int n_gc = int((G + kGroups - 1) / kGroups);
     parallel_for(n_gc, [&](int c) {
-        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
-            nrb_g[size_t(gi)] = pack(gi, kFusedRowFrames, nullptr);
-            t->g_ncb[size_t(gi)] = pack(gi, kFusedColFrames, nullptr);
-        }
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+            nrb[size_t(gi)] = pack_blocks(*t, gi, kFusedRowFrames, nullptr);
     });
-    t->unit_prefix.assign(size_t(G) + 1, 0);
-    int32_t rb_total = 0, cb_total = 0;
+    t->g_rb0.assign(size_t(G), 0);
+    t->g_nrb.assign(nrb.begin(), nrb.end());
+    int32_t rb_total = 0;
     for (int64_t gi = 0; gi < G; ++gi) {
-        const Group &g = t->groups[size_t(gi)];
         t->g_rb0[size_t(gi)] = rb_total;
-        t->g_cb0[size_t(gi)] = cb_total;
-        rb_total += nrb_g[size_t(gi)];
-        cb_total += t->g_ncb[size_t(gi)];
-        t->unit_prefix[size_t(gi) + 1] =
-            t->unit_prefix[size_t(gi)] + int64_t(nrb_g[size_t(gi)]) * t->g_ncb[size_t(gi)];
-        t->fused_cells += g.n_frames * g.n_frames;
+        rb_total += nrb[size_t(gi)];
+        t->fused_cells += t->groups[size_t(gi)].n_frames * t->groups[size_t(gi)].n_frames;
     }
     t->rb.resize(4 * size_t(rb_total));
-    t->cb.resize(4 * size_t(cb_total));
     parallel_for(n_gc, [&](int c) {
-        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
-            pack(gi, kFusedRowFrames, t->rb.data() + 4 * size_t(t->g_rb0[size_t(gi)]));
-            pack(gi, kFusedColFrames, t->cb.data() + 4 * size_t(t->g_cb0[size_t(gi)]));
-        }
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+            pack_blocks(*t, gi, kFusedRowFrames, t->rb.data() + 4 * size_t(t->g_rb0[size_t(gi)]));
     });
+    col_plan(*t, kFusedColFrames);
     t->n_frames = frame;
     tr.mark("items");
     return t;

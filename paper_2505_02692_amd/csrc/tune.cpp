@@ -1,0 +1,128 @@
+// Autotuning of the fused BF16 kernel's launch configuration.
+//
+// The candidates differ only in how the same work is tiled and scheduled
+// (column block width 128 or 256 frames, one block per work unit or a
+// persistent grid), never in what is computed: every frame pair is formed
+// with the same K order and every DTW cell updated by the same recurrence, so
+// all candidates must give identical per-cell counts, and fabx_autotune checks
+// that they do.  The fastest one (distance stage time, best of two runs) is
+// recorded for the task's shape class in the context's table and, when
+// FABX_AUTOTUNE_CACHE names a file, written there for later processes.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+
+#include "internal.h"
+
+namespace fabx {
+
+TuneKey tune_key(const TaskImpl &t, const ScoreParams &p) {
+    TuneKey k;
+    k.dim_pad = (t.ds->dim + 63) / 64 * 64;
+    k.max_len = (t.max_len + 7) / 8 * 8;
+    const double fpg = t.groups.empty() ? 1.0 : double(t.n_frames) / double(t.groups.size());
+    k.frames_log2 = int(std::floor(std::log2(std::max(1.0, fpg))));
+    k.path = p.dtw_norm == FABX_NORM_PATH ? 1 : 0;
+    return k;
+}
+
+void Tuner::load(const std::string &path) {
+    std::lock_guard<std::mutex> lk(mu_);
+    path_ = path;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream ss(line);
+        std::string tag;
+        TuneKey k;
+        FusedConfig c;
+        if (!(ss >> tag) || tag != "fused") continue;
+        if (!(ss >> k.dim_pad >> k.max_len >> k.frames_log2 >> k.path >> c.cols >> c.blocks_per_cu)) continue;
+        if ((c.cols != 128 && c.cols != 256) || c.blocks_per_cu < 0 || c.blocks_per_cu > 64) continue;
+        table_[k] = c;
+    }
+}
+
+FusedConfig Tuner::lookup(const TuneKey &k) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = table_.find(k);
+    return it == table_.end() ? default_config() : it->second;
+}
+
+void Tuner::record(const TuneKey &k, const FusedConfig &c) {
+    std::lock_guard<std::mutex> lk(mu_);
+    table_[k] = c;
+    if (!path_.empty()) save_locked();
+}
+
+void Tuner::save_locked() {
+    const std::string tmp = path_ + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return;  // the table still holds the entry for this process
+        f << "# fastabx-hip fused kernel tuning: fused dim_pad max_len frames_log2 path cols blocks_per_cu\n";
+        for (const auto &e : table_)
+            f << "fused " << e.first.dim_pad << ' ' << e.first.max_len << ' ' << e.first.frames_log2 << ' '
+              << e.first.path << ' ' << e.second.cols << ' ' << e.second.blocks_per_cu << '\n';
+    }
+    std::rename(tmp.c_str(), path_.c_str());
+}
+
+}  // namespace fabx
+
+using namespace fabx;
+
+extern "C" int fabx_autotune(fabx_task *task, const fabx_score_opts *opts, fabx_tune_report *report) {
+    try {
+        if (!task || !report) fail(FABX_EINVAL, "null argument");
+        *report = fabx_tune_report{};
+        auto &t = task->p;
+        ScoreParams p = resolve_opts(opts, *t->ds);
+        p.keep_pairs = false;
+        if (t->ds->ctx->device < 0) fail(FABX_EINVAL, "context has no device (host-only context)");
+        const TuneKey key = tune_key(*t, p);
+        report->key_dim_pad = key.dim_pad;
+        report->key_max_len = key.max_len;
+        report->key_frames_log2 = key.frames_log2;
+        report->best = -1;
+        if (p.mode != FABX_MODE_DTW || p.precision != FABX_PREC_BF16_RECHECK || t->cells.empty()) {
+            set_last_error("");
+            return FABX_OK;  // only the fused kernel has choices
+        }
+        const FusedConfig cands[] = {{128, 0}, {128, 4}, {256, 0}, {256, 2}};
+        hvec<int64_t> ref;
+        double best_ms = 0.0;
+        for (const FusedConfig &c : cands) {
+            double ms = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                p.fused = c;
+                auto r = run_score(t, p, t->ds->ctx->stream);
+                ms = std::min(ms, r->stats.ms_distance);
+                if (ref.empty()) ref = r->half_units;
+                else if (r->half_units != ref)
+                    fail(FABX_EINVAL, "internal error: fused kernel configurations disagree on a cell count");
+            }
+            fabx_tune_entry &e = report->tried[report->n_tried];
+            e.cols = c.cols;
+            e.blocks_per_cu = c.blocks_per_cu;
+            e.ms_distance = ms;
+            if (report->best < 0 || ms < best_ms) {
+                report->best = report->n_tried;
+                best_ms = ms;
+            }
+            ++report->n_tried;
+        }
+        const fabx_tune_entry &b = report->tried[report->best];
+        t->ds->ctx->tuner.record(key, FusedConfig{b.cols, b.blocks_per_cu});
+        set_last_error("");
+        return FABX_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return FABX_ENOMEM;
+    }
+}

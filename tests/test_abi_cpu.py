@@ -126,6 +126,12 @@ def test_bad_device_and_host_only_score():
     with pytest.raises(fx.FabxError) as e:
         t.score()
     assert e.value.code == L.FABX_EINVAL
+    for call in (t.score_async, t.autotune):                 # no device: refused, nothing launched
+        with pytest.raises(fx.FabxError) as e:
+            call()
+        assert e.value.code == L.FABX_EINVAL
+    assert fx.lib().fabx_autotune(t.h, None, None) == L.FABX_EINVAL
+    assert fx.lib().fabx_result_wait(None) == L.FABX_EINVAL
 
 
 def test_bad_score_options():

@@ -403,6 +403,36 @@ def test_async_edomain_reported_on_completion():
         r.collapse()
 
 
+# ------------------------------------------------------------- autotune --
+
+def test_autotune_tiles_give_identical_counts_and_persist(tmp_path, monkeypatch):
+    """Every fused-kernel configuration gives the same per-cell counts (checked
+    inside fabx_autotune), the chosen one is exact against the oracle, and a new
+    context picks it up from the cache file."""
+    _say("autotune")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FABX_AUTOTUNE_CACHE", str(cache))
+    w = workloads.batched_c4(n_groups=24, size_hi=150, centroid_std=0.3, seed=11)
+    feats = w.features.to("cuda")
+    c1 = fx.Context(0)
+    t = fx.Task(fx.Dataset(c1, feats, w.offsets, w.attrs), w.on, w.by, w.across)
+    rep = t.autotune()
+    print(f"  tried {rep['tried']} best {rep['best']} key {rep['key']}", flush=True)
+    assert len(rep["tried"]) == 4 and rep["best"] is not None
+    assert "fused" in cache.read_text()
+    r = t.score()
+    assert (r.stats["fused_cols"], r.stats["fused_blocks_per_cu"]) == \
+        (rep["best"]["cols"], rep["best"]["blocks_per_cu"])
+    orc = oracle_score(w)
+    assert np.array_equal(r.half_units, orc.half_units)
+    c2 = fx.Context(0)                                   # reads the cache file
+    r2 = fx.Task(fx.Dataset(c2, feats, w.offsets, w.attrs), w.on, w.by, w.across).score()
+    assert r2.stats["fused_cols"] == rep["best"]["cols"]
+    assert np.array_equal(r2.half_units, r.half_units)
+    assert fx.Task(fx.Dataset(c2, feats, w.offsets, w.attrs), w.on, w.by, w.across).autotune(
+        mode="pooled")["tried"] == []                    # nothing to tune outside the fused kernel
+
+
 # ------------------------------------------------------- stream ordering --
 
 def _slow_producer(dst, src):
