@@ -89,13 +89,16 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
             // keys in row order and accumulates its own, so every key's sum is
             // formed in row order whatever the part count.
             hvec<uint32_t> keyv(m);
-            const size_t kChunk = size_t(1) << 15;
+            const size_t kChunk = size_t(1) << 16;
             HostPool &hp = HostPool::get();
             hp.parallel_for(int((m + kChunk - 1) / kChunk), [&](int c) {
                 for (size_t i = size_t(c) * kChunk; i < std::min(m, size_t(c + 1) * kChunk); ++i)
                     keyv[i] = uint32_t(mixed(i));
             });
-            const size_t n_parts = m >= (size_t(1) << 15) ? size_t(std::max(1, hp.size())) : 1;
+            // parts of at least 4096 keys, and only when there are many rows
+            const size_t n_parts = m >= (size_t(1) << 15)
+                                       ? std::max<size_t>(1, std::min<size_t>(size_t(hp.size()), nk / 4096))
+                                       : 1;
             hvec<Acc> tab(nk);
             std::vector<size_t> part_rows(n_parts + 1, 0);
             hp.parallel_for(int(n_parts), [&](int r) {
