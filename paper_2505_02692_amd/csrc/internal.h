@@ -161,6 +161,7 @@ struct DatasetImpl {
 // Fused BF16 kernel tiling: frames per row block (one DTW lane per frame row)
 // and per column block.  Items are never split, so items are <= 64 frames.
 constexpr int kFusedRowFrames = 64;
+constexpr int kSortedMaxB = 4096;      // largest |B| counted from sorted rows (sorted in LDS)
 constexpr int kFusedColFrames = 128;  // default column block width (the other is 256)
 
 // One BY group that holds at least one cell.  Items of a group are
@@ -252,7 +253,10 @@ struct TaskImpl {
     std::vector<uint32_t> key_card; // distinct values of each key column (ranks are 0 .. card - 1)
 
     // work plans, fixed for the task
-    hvec<int32_t> units;     // triplet units [n][3]: cell, x_begin, x_end
+    hvec<int32_t> units;     // triplet units [n][3]: cell, x_begin, x_end; the first
+                             // n_units_small are counted by brute force, the rest
+                             // (one x each, large cells) from sorted rows
+    int64_t n_units_small = 0;
     int64_t sum_nx = 0;             // sum over cells of |X|
     hvec<int32_t> rb;               // fused kernel row blocks [n][4] (<= 64 frames)
     std::vector<int32_t> g_rb0, g_nrb;

@@ -84,6 +84,138 @@ __global__ __launch_bounds__(256) void k_triplets(const CellDev *__restrict__ ce
     }
 }
 
+// Count of sorted values v[0..n) below `key` (strict: v < key) or at most `key`.
+__device__ __forceinline__ int count_below(const float *v, int n, float key, bool inclusive) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const bool left = inclusive ? v[mid] <= key : v[mid] < key;
+        if (left) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Large cells, one block per unit (cell, one x): the row's distances to B are
+// sorted in LDS (bitonic, with their B positions), then each a adds
+// 2|B| - #(d_xb < d_xa) - #(d_xb <= d_xa), which equals the sum over b of
+// 2[d_xa < d_xb] + [d_xa == d_xb].  Near ties and non-robust pairs are found as
+// in k_triplets (the b within margin of d_xa form one sorted range) and make
+// the row go to the FP64 recount with the involved pairs marked.
+__global__ __launch_bounds__(256) void k_triplets_sorted(const CellDev *__restrict__ cells,
+                                                         const int32_t *__restrict__ units, int64_t n_units,
+                                                         const int64_t *__restrict__ g_pair_base,
+                                                         const int64_t *__restrict__ g_n,
+                                                         const float *__restrict__ p32,
+                                                         unsigned long long *__restrict__ W,
+                                                         uint8_t *flags, float margin,
+                                                         int32_t *__restrict__ recount,
+                                                         unsigned int *__restrict__ recount_n,
+                                                         int64_t recount_cap) {
+    __shared__ float sv[kSortedMaxB];
+    __shared__ uint16_t si[kSortedMaxB];
+    __shared__ unsigned long long red[4];
+    __shared__ int bad[4];
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    for (int64_t unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const int32_t cell_id = units[3 * unit];
+        const int32_t xi = units[3 * unit + 1];
+        const CellDev c = cells[cell_id];
+        const int64_t base = g_pair_base[c.group];
+        const int64_t n = g_n[c.group];
+        const int nb = c.nb;
+        int nb2 = 2;
+        while (nb2 < nb) nb2 <<= 1;
+        const int xl = c.x0 + xi;
+        const float *row = p32 + base + int64_t(xl) * n;
+        uint8_t *frow = flags ? flags + base + int64_t(xl) * n : nullptr;
+        for (int j = tid; j < nb2; j += 256) {
+            sv[j] = j < nb ? row[c.b0 + j] : __builtin_inff();
+            si[j] = uint16_t(j);
+        }
+        __syncthreads();
+        for (int k = 2; k <= nb2; k <<= 1)
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < nb2; i += 256) {
+                    const int l = i ^ jj;
+                    if (l > i) {
+                        const bool up = (i & k) == 0;
+                        const float vi = sv[i], vl = sv[l];
+                        if ((vi > vl) == up) {
+                            sv[i] = vl;
+                            sv[l] = vi;
+                            const uint16_t t = si[i];
+                            si[i] = si[l];
+                            si[l] = t;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // count, near ties, non-robust pairs
+        unsigned long long cnt = 0;
+        int dirty = 0, all_b = 0, all_a = 0;
+        for (int a = tid; a < c.na; a += 256) {
+            const int al = c.a0 + a;
+            if (c.exclude_self && al == xl) continue;
+            const float da = row[al];
+            const int lb = count_below(sv, nb, da, false), ub = count_below(sv, nb, da, true);
+            cnt += unsigned(2 * nb - lb - ub);
+            if (frow) {
+                const uint8_t fa = frow[al];
+                if (fa & kNonRobust) {
+                    dirty = all_b = 1;
+                    frow[al] = fa | kMarked;
+                }
+                const int lo = count_below(sv, nb, da - margin, false);
+                const int hi = count_below(sv, nb, da + margin, true);
+                if (lo < hi) {
+                    dirty = 1;
+                    frow[al] = frow[al] | kMarked;
+                    for (int k = lo; k < hi; ++k) {
+                        const int bl = c.b0 + si[k];
+                        frow[bl] = frow[bl] | kMarked;
+                    }
+                }
+            }
+        }
+        if (frow)
+            for (int b = tid; b < nb; b += 256)
+                if (frow[c.b0 + b] & kNonRobust) {
+                    dirty = all_a = 1;
+                    frow[c.b0 + b] = frow[c.b0 + b] | kMarked;
+                }
+        const unsigned long long wsum = dev::wave_sum_u64(cnt);
+        const int wflags = (dev::wave_any(dirty) ? 1 : 0) | (dev::wave_any(all_b) ? 2 : 0) |
+                           (dev::wave_any(all_a) ? 4 : 0);
+        if (lane == 0) {
+            red[w] = wsum;
+            bad[w] = wflags;
+        }
+        __syncthreads();
+        const unsigned long long total = red[0] + red[1] + red[2] + red[3];
+        const int f = bad[0] | bad[1] | bad[2] | bad[3];
+        if (f & 2)  // a non-robust (x, a): every comparison it takes part in is a near tie
+            for (int b = tid; b < nb; b += 256) frow[c.b0 + b] = frow[c.b0 + b] | kMarked;
+        if (f & 4)  // a non-robust (x, b)
+            for (int a = tid; a < c.na; a += 256) {
+                const int al = c.a0 + a;
+                if (!(c.exclude_self && al == xl)) frow[al] = frow[al] | kMarked;
+            }
+        if (tid == 0) {
+            if (f & 1) {
+                const unsigned int k = atomicAdd(recount_n, 1u);
+                if (int64_t(k) < recount_cap) {
+                    recount[2 * int64_t(k)] = cell_id;
+                    recount[2 * int64_t(k) + 1] = xi;
+                }
+            } else if (total) {
+                atomicAdd(&W[cell_id], total);
+            }
+        }
+        __syncthreads();  // the next unit reuses the sort buffers and reductions
+    }
+}
+
 __global__ __launch_bounds__(256) void k_collect_marked(const uint8_t *__restrict__ flags, int64_t n_slots,
                                                         int64_t *__restrict__ list,
                                                         unsigned int *__restrict__ count, int64_t cap) {
@@ -155,6 +287,15 @@ void triplets(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t
     hipLaunchKernelGGL(k_triplets, dim3(grid_for(n_units, 4)), dim3(256), 0, s, cells, units, n_units,
                        g.pair_base, g.n_items, p32, W, flags, margin, recount, recount_n,
                        recount_cap);
+    FABX_HIP(hipGetLastError());
+}
+
+void triplets_sorted(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
+                     const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
+                     float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap) {
+    if (n_units <= 0) return;
+    hipLaunchKernelGGL(k_triplets_sorted, dim3(grid_for(n_units, 1)), dim3(256), 0, s, cells, units, n_units,
+                       g.pair_base, g.n_items, p32, W, flags, margin, recount, recount_n, recount_cap);
     FABX_HIP(hipGetLastError());
 }
 

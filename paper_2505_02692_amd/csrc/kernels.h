@@ -93,6 +93,11 @@ void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int
 void triplets(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
               const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
               float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap);
+// Large cells, one x per unit: the same counts and marks from the row's B
+// distances sorted in LDS (|B| <= kSortedMaxB).
+void triplets_sorted(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
+              const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
+              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap);
 
 // Pair slots whose flag bit 1 is set -> list (order unspecified).
 void collect_marked(hipStream_t s, const uint8_t *flags, int64_t n_slots, int64_t *list,

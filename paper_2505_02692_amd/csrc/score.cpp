@@ -394,10 +394,14 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
                                 tiles.back(), ws.p32.as<float>());
     }
     tm.mark();  // 3
-    kern::triplets(stream, dv.cells, units_p, n_units, gt,
+    kern::triplets(stream, dv.cells, units_p, t.n_units_small, gt,
                    ws.p32.as<float>(), ws.half_units.as<unsigned long long>(),
                    bf16 ? ws.flags.as<uint8_t>() : nullptr, float(p.margin),
                    bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, t.sum_nx);
+    kern::triplets_sorted(stream, dv.cells, units_p + 3 * t.n_units_small, n_units - t.n_units_small, gt,
+                          ws.p32.as<float>(), ws.half_units.as<unsigned long long>(),
+                          bf16 ? ws.flags.as<uint8_t>() : nullptr, float(p.margin),
+                          bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, t.sum_nx);
     tm.mark();  // 4
     if (bf16) {
         kern::collect_marked(stream, ws.flags.as<uint8_t>(), t.n_pair_slots, ws.recheck_list.as<int64_t>(),

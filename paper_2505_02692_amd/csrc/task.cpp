@@ -124,7 +124,7 @@ void parallel_for(int n, F &&f) {
 // after prefix sums over the shares, writing straight into the task's arrays
 // at the share's offsets.
 struct Sink {
-    size_t n_cells = 0, n_unit_ints = 0, n_groups = 0;
+    size_t n_cells = 0, n_unit_ints = 0, n_big_unit_ints = 0, n_groups = 0;
     int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, pair_slots = 0, sum_nx = 0;
     // write pass: destinations, and the share's first cell / unit int / group / pair slot
     CellDev *cells = nullptr;
@@ -133,11 +133,14 @@ struct Sink {
     int32_t *units = nullptr;
     Group *groups = nullptr;
     std::pair<int64_t, int64_t> *kept = nullptr;
-    size_t cell_base = 0, unit_base = 0, group_base = 0, key_width = 0;
+    size_t cell_base = 0, unit_base = 0, big_unit_base = 0, group_base = 0, key_width = 0;
     int64_t slot_base = 0;
 };
 
 constexpr int64_t kUnitBudget = 8192;  // comparisons per triplet work unit (at least one x)
+// Cells with at least this many comparisons per x, and |B| within the sort
+// capacity, are counted from sorted rows (one unit per x, after the others).
+constexpr int64_t kSortedMinPerX = 8192;
 
 struct WalkCtx {
     const DatasetImpl *ds;
@@ -212,9 +215,11 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
             const int64_t na = cls[ia].count, nb = cls[ib].count, nx = cls[ix].count;
             const int64_t nt = excl ? na * (na - 1) * nb : na * nb * nx;
             const size_t cid = out.cell_base + out.n_cells;
-            // triplet work units: split X so one unit does <= kUnitBudget comparisons
+            // triplet work units: split X so one unit does <= kUnitBudget comparisons;
+            // large cells get one unit per x, in the sorted-row region
             const int64_t per_x = std::max<int64_t>(1, na * nb);
-            const int64_t chunk = std::max<int64_t>(1, kUnitBudget / per_x);
+            const bool big = per_x >= kSortedMinPerX && nb <= kSortedMaxB;
+            const int64_t chunk = big ? 1 : std::max<int64_t>(1, kUnitBudget / per_x);
             if (kWrite) {
                 CellDev c;
                 c.group = group_id;
@@ -235,14 +240,15 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
                     rk[2 + n_by + j] = cacr[size_t(ia * n_ac + j)];
                     rk[2 + n_by + n_ac + j] = cacr[size_t(ix * n_ac + j)];
                 }
-                int32_t *u = out.units + out.unit_base + out.n_unit_ints;
+                int32_t *u = big ? out.units + out.big_unit_base + out.n_big_unit_ints
+                                 : out.units + out.unit_base + out.n_unit_ints;
                 for (int64_t x = 0; x < nx; x += chunk, u += 3) {
                     u[0] = int32_t(cid);
                     u[1] = int32_t(x);
                     u[2] = int32_t(std::min<int64_t>(nx, x + chunk));
                 }
             }
-            out.n_unit_ints += size_t(3 * ((nx + chunk - 1) / chunk));
+            (big ? out.n_big_unit_ints : out.n_unit_ints) += size_t(3 * ((nx + chunk - 1) / chunk));
             ++out.n_cells;
             out.total_triplets += nt;
             out.sum_nx += nx;
@@ -604,11 +610,16 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     for (auto &r : racr) t->key_card.push_back(uint32_t(r.values.size()));
     parallel_for(n_shares, [&](int k) { walk_groups<false>(wc, cut[k], cut[k + 1], parts[size_t(k)]); });
     tr.mark("walk");
-    size_t n_cells = 0, n_groups = 0, n_unit_ints = 0;
+    size_t n_cells = 0, n_groups = 0, n_unit_ints = 0, n_big_ints = 0;
     int64_t n_slots = 0;
+    for (auto &p : parts) n_unit_ints += p.n_unit_ints;   // small-cell units first
+    const size_t n_small_ints = n_unit_ints;
+    n_unit_ints = 0;
     for (auto &p : parts) {
         p.cell_base = n_cells;
         p.unit_base = n_unit_ints;
+        p.big_unit_base = n_small_ints + n_big_ints;
+        n_big_ints += p.n_big_unit_ints;
         p.group_base = n_groups;
         p.slot_base = n_slots;
         n_cells += p.n_cells;
@@ -624,14 +635,15 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     t->cells.resize(n_cells);
     t->n_triplets.resize(n_cells);
     t->rkeys.resize(n_cells * size_t(t->key_width));
-    t->units.resize(n_unit_ints);
+    t->units.resize(n_unit_ints + n_big_ints);
+    t->n_units_small = int64_t(n_unit_ints / 3);
     t->groups.resize(n_groups);
     hvec<std::pair<int64_t, int64_t>> kept(n_groups);
     std::atomic<bool> mismatch{false};
     parallel_for(n_shares, [&](int k) {
         Sink &p = parts[size_t(k)];
         const Sink counted = p;
-        p.n_cells = p.n_unit_ints = p.n_groups = 0;
+        p.n_cells = p.n_unit_ints = p.n_big_unit_ints = p.n_groups = 0;
         p.pair_slots = 0;
         p.cells = t->cells.data();
         p.ntrip = t->n_triplets.data();
@@ -641,7 +653,8 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         p.kept = kept.data();
         p.key_width = size_t(t->key_width);
         walk_groups<true>(wc, cut[k], cut[k + 1], p);
-        if (p.n_cells != counted.n_cells || p.n_unit_ints != counted.n_unit_ints || p.n_groups != counted.n_groups)
+        if (p.n_cells != counted.n_cells || p.n_unit_ints != counted.n_unit_ints ||
+            p.n_big_unit_ints != counted.n_big_unit_ints || p.n_groups != counted.n_groups)
             mismatch = true;  // both passes walk the same share: cannot happen
     });
     if (mismatch) fail(FABX_EINVAL, "internal error: task walk passes disagree");

@@ -338,6 +338,49 @@ def test_server_rejects_oversized_job():
     srv.close()
 
 
+# ------------------------------------------- large cells: sorted rows --
+
+def _big_cells(seed, centroid_std=0.3, dim=32):
+    # groups of 200-800 items, two labels each: |A| x |B| per x well above the
+    # brute-force budget, so every cell is counted from sorted rows
+    return workloads.batched_c4(n_groups=8, size_lo=200, size_hi=800, len_lo=1, len_hi=8, dim=dim,
+                                centroid_std=centroid_std, seed=seed)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_large_cells_sorted_rows(precision):
+    w = _big_cells(71, centroid_std=0.05)            # close labels: many near ties
+    t, res, orc = check(w, precision=precision)
+    assert min(len(c.A) * len(c.B) for c in orc.cells) >= 8192
+
+
+def test_large_cells_sorted_rows_pooled():
+    check(_big_cells(72, centroid_std=0.05), mode="pooled")
+
+
+def test_large_cells_many_exact_ties():
+    """Every item of a group repeats the first item's frames (cut or extended to
+    its own length): pairs of equal length are exact copies, so many
+    comparisons are exact ties, which the sorted rows send to the FP64 recount."""
+    _say("large cells, many exact ties")
+    w = _big_cells(73)
+    feats = w.features.clone()
+    for g in np.unique(w.attrs[:, 1]):
+        items = np.nonzero(w.attrs[:, 1] == g)[0]
+        first = items[0]
+        L0 = int(w.offsets[first + 1] - w.offsets[first])
+        src = feats[int(w.offsets[first]):int(w.offsets[first]) + L0].clone()
+        for i in items[1:]:
+            Li = int(w.offsets[i + 1] - w.offsets[i])
+            idx = torch.clamp(torch.arange(Li), max=L0 - 1)
+            feats[int(w.offsets[i]):int(w.offsets[i]) + Li] = src[idx]
+    w.features = feats
+    t, res = gpu_score(w)
+    assert res.stats["n_recount_rows"] > 0
+    orc = oracle_score(w)
+    assert np.array_equal(res.half_units, orc.half_units)
+
+
 # ---------------------------------------------------------- async score --
 
 def test_score_async_equals_sync():
