@@ -61,7 +61,13 @@ double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t 
     std::vector<size_t> cols(K);  // key columns still present
     std::iota(cols.begin(), cols.end(), size_t(0));
     hvec<double> score(n);
-    for (size_t i = 0; i < n; ++i) score[i] = double(res.half_units[i]) / (2.0 * double(t.n_triplets[i]));
+    {
+        const size_t kChunk = size_t(1) << 16;
+        HostPool::get().parallel_for(int((n + kChunk - 1) / kChunk), [&](int c) {
+            for (size_t i = size_t(c) * kChunk; i < std::min(n, size_t(c + 1) * kChunk); ++i)
+                score[i] = double(res.half_units[i]) / (2.0 * double(t.n_triplets[i]));
+        });
+    }
     for (const auto &lv : levels) {
         std::vector<size_t> kept;
         for (size_t c : cols)

@@ -125,11 +125,18 @@ public:
     int size() const { return int(workers_.size()) + 1; }
 
     void parallel_for(int n, const std::function<void(int)> &f) {
-        if (n <= 1 || workers_.empty()) {
+        // One parallel region at a time: other threads wait for the workers.  A
+        // region started from inside a worker (or from the thread running the
+        // current region) runs its items in place, as waiting would deadlock.
+        if (n <= 1 || workers_.empty() || in_region()) {
             for (int k = 0; k < n; ++k) f(k);
             return;
         }
-        std::lock_guard<std::mutex> call(call_mu_);  // one parallel region at a time
+        std::unique_lock<std::mutex> call(call_mu_);
+        in_region() = true;
+        struct Reset {
+            ~Reset() { in_region() = false; }
+        } reset;
         fn_ = &f;
         total_ = n;
         next_.store(0, std::memory_order_relaxed);
@@ -169,7 +176,12 @@ private:
             (*fn_)(k);
         }
     }
+    static bool &in_region() {
+        thread_local bool flag = false;
+        return flag;
+    }
     void worker() {
+        in_region() = true;
         uint64_t seen = 0;
         for (;;) {
             uint64_t g = generation_.load(std::memory_order_acquire);

@@ -678,7 +678,14 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     t->item_src.resize(size_t(nt));
     t->item_dst.resize(size_t(nt));
     t->item_group.resize(size_t(nt));
-    t->item_pos_of.assign(size_t(n), -1);
+    t->item_pos_of.resize(size_t(n));
+    {
+        const int64_t kChunk = 1 << 16;
+        parallel_for(int((n + kChunk - 1) / kChunk), [&](int c) {
+            std::fill(t->item_pos_of.begin() + c * kChunk,
+                      t->item_pos_of.begin() + std::min<int64_t>(n, (c + 1) * kChunk), int64_t(-1));
+        });
+    }
     std::vector<int> max_len_part(static_cast<size_t>(n_threads), 0);
     const int64_t G = int64_t(t->groups.size());
     parallel_for(n_threads, [&](int k) {
@@ -703,29 +710,43 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     for (int ml : max_len_part) t->max_len = std::max(t->max_len, ml);
     const int64_t frame = frame_total;
 
-    // fused-kernel row blocks: whole items packed into <= 64 frames per group
-    // (column blocks depend on the tile width and are made by col_plan)
+    // fused-kernel row blocks (whole items packed into <= 64 frames per group)
+    // and the default column plan, counted in one parallel pass and written in
+    // another (other column widths are made by col_plan on demand)
+    auto cp = std::make_unique<ColPlan>();
+    cp->cols = kFusedColFrames;
     std::vector<int32_t> nrb(static_cast<size_t>(G));
+    cp->g_ncb.assign(size_t(G), 0);
+    cp->g_cb0.assign(size_t(G), 0);
     const int64_t kGroups = 2048;
     const int n_gc = int((G + kGroups - 1) / kGroups);
     parallel_for(n_gc, [&](int c) {
-        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
             nrb[size_t(gi)] = pack_blocks(*t, gi, kFusedRowFrames, nullptr);
+            cp->g_ncb[size_t(gi)] = pack_blocks(*t, gi, kFusedColFrames, nullptr);
+        }
     });
     t->g_rb0.assign(size_t(G), 0);
     t->g_nrb.assign(nrb.begin(), nrb.end());
-    int32_t rb_total = 0;
+    cp->unit_prefix.assign(size_t(G) + 1, 0);
+    int32_t rb_total = 0, cb_total = 0;
     for (int64_t gi = 0; gi < G; ++gi) {
         t->g_rb0[size_t(gi)] = rb_total;
+        cp->g_cb0[size_t(gi)] = cb_total;
         rb_total += nrb[size_t(gi)];
+        cb_total += cp->g_ncb[size_t(gi)];
+        cp->unit_prefix[size_t(gi) + 1] = cp->unit_prefix[size_t(gi)] + int64_t(nrb[size_t(gi)]) * cp->g_ncb[size_t(gi)];
         t->fused_cells += t->groups[size_t(gi)].n_frames * t->groups[size_t(gi)].n_frames;
     }
     t->rb.resize(4 * size_t(rb_total));
+    cp->cb.resize(4 * size_t(cb_total));
     parallel_for(n_gc, [&](int c) {
-        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
             pack_blocks(*t, gi, kFusedRowFrames, t->rb.data() + 4 * size_t(t->g_rb0[size_t(gi)]));
+            pack_blocks(*t, gi, kFusedColFrames, cp->cb.data() + 4 * size_t(cp->g_cb0[size_t(gi)]));
+        }
     });
-    col_plan(*t, kFusedColFrames);
+    t->col_plans.push_back(std::move(cp));
     t->n_frames = frame;
     tr.mark("items");
     return t;

@@ -163,3 +163,21 @@ def test_null_handles():
     assert lib.fabx_server_poll(None, 1, None) == L.FABX_EINVAL
     lib.fabx_destroy(None)
     lib.fabx_result_free(None)
+
+
+def test_concurrent_task_builds_agree():
+    """Task builds from several threads at once (the host pool runs a region
+    inline when its workers are busy) give the same cells as one build."""
+    from concurrent.futures import ThreadPoolExecutor
+    import workloads
+    w = workloads.within_c2(n_items=20000, dim=8, seed=5)
+    ctx = fx.Context(-1)
+    ds = fx.Dataset(ctx, None, w.offsets, w.attrs)
+    ref = fx.Task(ds, w.on, w.by, w.across)
+    ref_keys, ref_sizes = ref.keys, ref.sizes[0]
+    def build(_):
+        t = fx.Task(ds, w.on, w.by, w.across)
+        return t.keys, t.sizes[0]
+    with ThreadPoolExecutor(4) as ex:
+        for keys, sizes in ex.map(build, range(12)):
+            assert np.array_equal(keys, ref_keys) and np.array_equal(sizes, ref_sizes)

@@ -446,6 +446,28 @@ def test_async_edomain_reported_on_completion():
         r.collapse()
 
 
+def test_threaded_pipeline_equals_serial():
+    """Build + async score on one thread while another thread waits for and
+    collapses the previous results: same per-cell counts as serial scores."""
+    from concurrent.futures import ThreadPoolExecutor
+    _say("threaded pipeline")
+    ws = [workloads.within_c2(n_items=8000, dim=128, centroid_std=0.08, seed=80 + k, device="cuda")
+          for k in range(4)]
+    dss = [fx.Dataset(ctx(), w.features, w.offsets, w.attrs) for w in ws]
+    want = [fx.Task(ds, w.on, w.by, w.across).score().half_units.copy() for w, ds in zip(ws, dss)]
+    def finish(r, w):
+        return r.half_units.copy(), r.collapse(w.levels)
+    with ThreadPoolExecutor(1) as helper:
+        futs = []
+        for rep in range(3):
+            for w, ds in zip(ws, dss):
+                r = fx.Task(ds, w.on, w.by, w.across).score_async()
+                futs.append(helper.submit(finish, r, w))
+        got = [f.result() for f in futs]
+    for k, (hu, e) in enumerate(got):
+        assert np.array_equal(hu, want[k % len(ws)])
+
+
 # ------------------------------------------------------------- autotune --
 
 def test_autotune_tiles_give_identical_counts_and_persist(tmp_path, monkeypatch):
