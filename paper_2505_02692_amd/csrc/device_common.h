@@ -42,6 +42,29 @@ __device__ __forceinline__ int64_t find_segment(const int64_t *__restrict__ pref
     return lo;
 }
 
+// The same search done by a whole wave: each step compares `id` with 64 pivots
+// spread over the remaining range, one per lane, and keeps the part between the
+// last pivot at or below `id` and the next pivot, so about log64(n) dependent
+// loads instead of log2(n) (three for up to 250,000 segments).  Every lane
+// must pass the same arguments and gets the result; prefix[0] <= id.
+__device__ __forceinline__ int64_t find_segment_wave(const int64_t *__restrict__ prefix, int64_t n,
+                                                     int64_t id) {
+    const int lane = threadIdx.x % kWave;
+    int64_t lo = 0, hi = n;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int64_t span = hi - lo;
+        const int64_t p = lo + (span * lane + 63) / 64;
+        const bool le = p < hi && prefix[p] <= id;
+        const unsigned long long ball = __ballot(le);  // bit 0 set: prefix[lo] <= id
+        const int kmax = 63 - __clzll(ball);
+        const int64_t nlo = lo + (span * kmax + 63) / 64;
+        const int64_t nhi = kmax == 63 ? hi : min(hi, lo + (span * (kmax + 1) + 63) / 64);
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
 // float -> bf16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     uint32_t u = __float_as_uint(f);

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     const int64_t unit = xcd * grid_q + j;
     if (unit >= n_units) continue;  // uniform across the block
 
-    const int64_t g = dev::find_segment(unit_prefix, n_groups, unit);
+    const int64_t g = dev::find_segment_wave(unit_prefix, n_groups, unit);
     const int64_t local = unit - unit_prefix[g];
     const int ncb = g_ncb[g];
     const int rbi = g_rb0[g] + int(local / ncb), cbi = g_cb0[g] + int(local % ncb);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     constexpr int kCols = T::kCols;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kStageBytes];
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
+    const int64_t g = dev::find_segment_wave(tile_prefix, n_groups, tile);
     const int64_t n = nrows[g];
     const int64_t ntc = (n + kCols - 1) / kCols;
     const int64_t local = tile - tile_prefix[g];
