@@ -60,14 +60,15 @@ struct Tile {
     static constexpr int kStageBytes = (kRows + kC) * kLdsRow * 2;
     // distance tile + a tail guard: the DTW loop reads up to 63 columns past a row's end
     static constexpr int kTileBytes = (kRows * kDStride + kWave) * 4;
-    static constexpr int kFlagLen = kWave + kC + kWave;  // column flags, zero guard on each side
+    // column flags: a zero guard of one wave before the span and one wave + 2 after
+    static constexpr int kFlagLen = kWave + kC + kWave + 2;
     static constexpr int kSmemBytes = kStageBytes > kTileBytes ? kStageBytes : kTileBytes;
 };
 
-// Value of lane - 1 (DPP wave_shr:1); lane 0, which has no source, keeps `old`.
-__device__ __forceinline__ float shr1(float old, float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138,
-                                                      0xf, 0xf, false));
+// Value of lane - 1 (DPP wave_shr:1 with bound_ctrl); lane 0 reads 0.  The add
+// that consumes it folds the move into one DPP instruction.
+__device__ __forceinline__ float shr1z(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ uint32_t shr1u(uint32_t old, uint32_t v) {
     return uint32_t(__builtin_amdgcn_update_dpp(int(old), int(v), 0x138, 0xf, 0xf, false));
@@ -117,11 +118,12 @@ struct Chunk {
 // past nc skip their MFMAs, and so does the second row half when nr <= 32
 // (those accumulators are never read).  Every product accumulates its K
 // range in the same order whatever the tile width, so results do not depend
-// on it.
-template <int kC>
+// on it.  `stash` runs once, after the first chunk is stored and before the
+// barrier that publishes it, so LDS it writes is visible to the epilogue.
+template <int kC, typename Stash>
 __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__restrict__ xn, int dim_pad,
                                           int64_t r0, int nr, int64_t c0, int nc,
-                                          f32x16 (&acc)[2][Tile<kC>::kCT]) {
+                                          f32x16 (&acc)[2][Tile<kC>::kCT], Stash &&stash) {
     using T = Tile<kC>;
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -138,6 +140,7 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
     for (int k0 = 0; k0 < dim_pad; k0 += kKc) {
         ca.store(As);
         cb.store(Bs);
+        if (k0 == 0) stash();
         __syncthreads();
         if (k0 + kKc < dim_pad) {
             ca.load(xn, dim_pad, r0, nr, k0 + kKc);
@@ -165,11 +168,42 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
     }
 }
 
+// Inverse norms of a unit's kRows row frames and kC column frames (zero past
+// nr / nc), loaded into registers before the Gram tile and written to LDS by
+// its stash hook, so the epilogue reads them from LDS instead of issuing one
+// dependent global load per element.
+template <int kC>
+struct NormStage {
+    static constexpr int kN = kRows + kC;
+    static constexpr int kPer = (kN + 255) / 256;
+    float v[kPer];
+    __device__ __forceinline__ void load(const float *__restrict__ rinv, int64_t r0, int nr, int64_t c0,
+                                         int nc) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int j = threadIdx.x + 256 * i;
+            v[i] = 0.0f;
+            if (j < kRows) {
+                if (j < nr) v[i] = rinv[r0 + j];
+            } else if (j < kN && j - kRows < nc) {
+                v[i] = rinv[c0 + j - kRows];
+            }
+        }
+    }
+    __device__ __forceinline__ void store(float *lds) const {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int j = threadIdx.x + 256 * i;
+            if (j < kN) lds[j] = v[i];
+        }
+    }
+};
+
 // Row (within the 32 x 32 tile) of accumulator element i of this lane.
 __device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i / 4) + 4 * (lane / 32) + (i % 4); }
 
 template <int kC, bool kPath>
-__global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ xn,
+__global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ xn,
                                                   const float *__restrict__ rinv, int dim_pad,
                                                   const int64_t *__restrict__ g_item0,
                                                   const int64_t *__restrict__ g_n,
@@ -190,6 +224,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     constexpr int kDStride = T::kDStride, kFlagLen = T::kFlagLen;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kSmemBytes];
     __shared__ uint16_t colflag[4][kFlagLen];
+    __shared__ __attribute__((aligned(16))) float norm_s[kRows + kC];  // row then column inverse norms
     // Persistent blocks, XCD-aware order: the 8 XCDs take blocks round-robin,
     // so XCD x works through the contiguous unit range [x * grid_q, (x+1) * grid_q)
     // (units of one group share its frames in that XCD's L2).  gridDim.x is a
@@ -210,9 +245,11 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     const int64_t r_frame0 = item_dst[r_item0], c_frame0 = item_dst[c_item0];
 
     // 1. Gram tile
+    NormStage<kC> ns;
+    ns.load(rinv, r_frame0, r_frames, c_frame0, c_frames);
     f32x16 acc[2][T::kCT];
     gram_tile<kC>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
-                  c_frames, acc);
+                  c_frames, acc, [&] { ns.store(norm_s); });
 
     // 2. epilogue -> LDS distance tile (the staging buffers are dead now).  Only
     // the rows and column waves that hold frames are written; the DTW reads the
@@ -223,20 +260,19 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
         const int col0 = T::kWaveCols * w + 32 * ct;
         if (col0 >= c_frames) continue;
         const int col = col0 + lane % 32;
-        const float rc = col < c_frames ? rinv[c_frame0 + col] : 0.0f;
+        const float rc = norm_s[kRows + col];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r0 = acc_row(i, lane);
-            const float rr0 = r0 < r_frames ? rinv[r_frame0 + r0] : 0.0f;
-            dt[r0 * kDStride + col] = dev::acos_over_pi(fminf(fmaxf(acc[0][ct][i] * rr0 * rc, -1.0f), 1.0f));
+            dt[r0 * kDStride + col] =
+                dev::acos_over_pi(fminf(fmaxf(acc[0][ct][i] * norm_s[r0] * rc, -1.0f), 1.0f));
         }
         if (r_frames > 32) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r1 = 32 + acc_row(i, lane);
-                const float rr1 = r1 < r_frames ? rinv[r_frame0 + r1] : 0.0f;
                 dt[r1 * kDStride + col] =
-                    dev::acos_over_pi(fminf(fmaxf(acc[1][ct][i] * rr1 * rc, -1.0f), 1.0f));
+                    dev::acos_over_pi(fminf(fmaxf(acc[1][ct][i] * norm_s[r1] * rc, -1.0f), 1.0f));
             }
         }
     }
@@ -269,8 +305,10 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
             }
             start += L;
         }
-        // column c of this wave's span is entry kWave + c; the guards read as 0
-        // (no item start, no output).  Same-wave LDS stores land in issue order.
+        // column c of this wave's span is entry kWave + c: bit 0 = first column
+        // of an item, bits 1..14 = the item's index in the column block, bit 15 =
+        // last column.  The guards read as 0 (no item start, no output).
+        // Same-wave LDS stores land in issue order.
         for (int j = lane; j < kFlagLen; j += kWave) colflag[w][j] = 0;
         if (seen) {
             int start2 = s_begin;
@@ -278,7 +316,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
                 const int L = item_len[c_item0 + k];
                 for (int j = lane; j < L; j += kWave)
                     colflag[w][kWave + start2 - s_begin + j] =
-                        uint16_t((j == 0 ? 1 : 0) | (j == L - 1 ? 2 : 0) | (k << 2));
+                        uint16_t((j == 0 ? 1 : 0) | (k << 1) | (j == L - 1 ? 0x8000 : 0));
                 start2 += L;
             }
         }
@@ -293,29 +331,30 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
     const bool row_valid = x_task >= 0;
     const bool top = ir == 0;
     const bool last_row = row_valid && ir == nx - 1;
-    // The lane below a row item's last row starts another item: share +inf with it
-    // instead of this lane's cost (its up and diagonal neighbours do not exist).
-    const bool send_inf = !row_valid || ir == nx - 1;
+    // The first row of an item has no row above: it adds +inf to the cost it
+    // receives from lane - 1 (a row of another item, or nothing for lane 0).
+    const float top_pen = top ? kInf : 0.0f;
     const float diag_first = top ? 0.0f : kInf;       // virtual c[-1][-1] = 0 at an item start
     const uint32_t pd_first = top ? 0x0000FFFFu : 0u;  // its length interval: Lmin = Lmax = 0
     const int64_t x_row = row_valid ? (int64_t(x_task) - gitem0) * gn : 0;
     // at step t the lane is on column t - ir of the wave's span: distance
-    // dcol[t], flags fcol[t].  ir <= lane, so dcol[0] is inside the tile; the
-    // last step reads at most max_n - 2 columns past the span, within the guard.
+    // dcol[t], flags fcol[t], read a pair of steps ahead.  ir <= lane, so dcol[0]
+    // is inside the tile; the last read-ahead is at most max_n <= 64 columns past
+    // the span: row 63 then ends 2 floats short of the tile's tail guard, and the
+    // flags' zero guard covers it.
     const float *dcol = dt + lane * kDStride + s_begin - ir;
     const uint16_t *fcol = &colflag[w][kWave - ir];
-    const uint32_t out_bit = last_row ? 2u : 0u;
+    // a cell is output on the item's last row and last column: flags >= 0x8000
+    const uint32_t out_min = last_row ? 0x8000u : 0x10000u;
 
     // Cells outside a lane's column range are computed too (on guard columns)
     // but never read: the first column of every item resets left and diagonal.
-    float c = kInf, up = kInf, up_prev = kInf;  // lane 0 keeps up = +inf (no row above)
+    float c = kInf, up = kInf, up_prev = kInf;
     uint32_t P = 0, Pup = 0, Pup_prev = 0;
     const int steps = S + max_n - 1;
-    for (int t = 0; t < steps; ++t) {
-        const uint32_t cf = fcol[t];
-        const float dv = dcol[t];
+    auto step = [&](const uint32_t cf, const float dv) {
         const bool first = cf & 1;
-        up = shr1(up, send_inf ? kInf : c);
+        up = shr1z(c) + top_pen;
         if (kPath) Pup = shr1u(Pup, P);
         const float diag = first ? diag_first : up_prev;
         const float left = first ? kInf : c;
@@ -331,8 +370,8 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
         c = dv + m;
         up_prev = up;
         Pup_prev = Pup;
-        if (cf & out_bit) {
-            const int64_t slot = pbase + x_row + (int64_t(c_item0) + (cf >> 2) - gitem0);
+        if (cf >= out_min) {
+            const int64_t slot = pbase + x_row + (int64_t(c_item0) + ((cf >> 1) & 0x3FFF) - gitem0);
             if (kPath) {
                 const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
                 p32[slot] = c * __builtin_amdgcn_rcpf(float(lmin));
@@ -343,7 +382,21 @@ __global__ __launch_bounds__(256, 2) void k_fused(const uint16_t *__restrict__ x
                 flags[slot] = 0;
             }
         }
+    };
+    uint32_t cf0 = fcol[0], cf1 = fcol[1];
+    float dv0 = dcol[0], dv1 = dcol[1];
+    int t = 0;
+    for (; t + 1 < steps; t += 2) {
+        const uint32_t ca = cf0, cb2 = cf1;
+        const float da = dv0, db = dv1;
+        cf0 = fcol[t + 2];
+        cf1 = fcol[t + 3];
+        dv0 = dcol[t + 2];
+        dv1 = dcol[t + 3];
+        step(ca, da);
+        step(cb2, db);
     }
+    if (t < steps) step(cf0, dv0);
     }  // S > 0
     __syncthreads();  // the next unit overwrites the LDS tile and column flags
     }
@@ -363,6 +416,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     using T = Tile<128>;
     constexpr int kCols = T::kCols;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kStageBytes];
+    __shared__ __attribute__((aligned(16))) float norm_s[kRows + kCols];
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t g = dev::find_segment_wave(tile_prefix, n_groups, tile);
     const int64_t n = nrows[g];
@@ -370,26 +424,29 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     const int64_t local = tile - tile_prefix[g];
     const int64_t r0 = (local / ntc) * kRows, c0 = (local % ntc) * kCols;
     const int nr = int(min<int64_t>(kRows, n - r0)), nc = int(min<int64_t>(kCols, n - c0));
+    NormStage<128> ns;
+    ns.load(rinv, row0[g] + r0, nr, row0[g] + c0, nc);
     f32x16 acc[2][1];
     gram_tile<128>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc,
-                   acc);
+                   acc, [&] { ns.store(norm_s); });
     const f32x16 &acc0 = acc[0][0], &acc1 = acc[1][0];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int col = 32 * w + lane % 32;
     if (col < nc) {
-        const float rc = rinv[row0[g] + c0 + col];
+        const float rc = norm_s[kRows + col];
         float *o = out + base[g];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int ra = acc_row(i, lane), rb2 = 32 + ra;
             if (ra < nr)
                 o[(r0 + ra) * n + c0 + col] =
-                    dev::acos_over_pi(fminf(fmaxf(acc0[i] * rinv[row0[g] + r0 + ra] * rc, -1.0f), 1.0f));
+                    dev::acos_over_pi(fminf(fmaxf(acc0[i] * norm_s[ra] * rc, -1.0f), 1.0f));
             if (rb2 < nr)
                 o[(r0 + rb2) * n + c0 + col] =
-                    dev::acos_over_pi(fminf(fmaxf(acc1[i] * rinv[row0[g] + r0 + rb2] * rc, -1.0f), 1.0f));
+                    dev::acos_over_pi(fminf(fmaxf(acc1[i] * norm_s[rb2] * rc, -1.0f), 1.0f));
         }
     }
+    __syncthreads();  // the next tile overwrites the inverse norms
     }
 }
 

@@ -673,6 +673,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         nt += g.n_items;
         frame_total += g.n_frames;
     }
+    tr.mark("groups");
     t->items.resize(size_t(nt));
     t->item_len.resize(size_t(nt));
     t->item_src.resize(size_t(nt));
@@ -709,6 +710,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     });
     for (int ml : max_len_part) t->max_len = std::max(t->max_len, ml);
     const int64_t frame = frame_total;
+    tr.mark("items");
 
     // fused-kernel row blocks (whole items packed into <= 64 frames per group)
     // and the default column plan, counted in one parallel pass and written in
@@ -726,6 +728,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             cp->g_ncb[size_t(gi)] = pack_blocks(*t, gi, kFusedColFrames, nullptr);
         }
     });
+    tr.mark("blocks.count");
     t->g_rb0.assign(size_t(G), 0);
     t->g_nrb.assign(nrb.begin(), nrb.end());
     cp->unit_prefix.assign(size_t(G) + 1, 0);
@@ -738,6 +741,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         cp->unit_prefix[size_t(gi) + 1] = cp->unit_prefix[size_t(gi)] + int64_t(nrb[size_t(gi)]) * cp->g_ncb[size_t(gi)];
         t->fused_cells += t->groups[size_t(gi)].n_frames * t->groups[size_t(gi)].n_frames;
     }
+    tr.mark("blocks.prefix");
     t->rb.resize(4 * size_t(rb_total));
     cp->cb.resize(4 * size_t(cb_total));
     parallel_for(n_gc, [&](int c) {
@@ -748,7 +752,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     });
     t->col_plans.push_back(std::move(cp));
     t->n_frames = frame;
-    tr.mark("items");
+    tr.mark("blocks.write");
     return t;
 }
 
