@@ -185,6 +185,10 @@ Staging::~Staging() {
 }
 
 CtxImpl::~CtxImpl() {
+    if (copy_stream) {
+        (void)hipStreamSynchronize(copy_stream);
+        (void)hipStreamDestroy(copy_stream);
+    }
     pool.trim();
 }
 
@@ -236,6 +240,7 @@ int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
             hipDeviceProp_t prop;
             FABX_HIP(hipGetDeviceProperties(&prop, device));
             c->n_cu = prop.multiProcessorCount;
+            FABX_HIP(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
             const char *tune_file = std::getenv("FABX_AUTOTUNE_CACHE");
             if (tune_file && *tune_file) c->tuner.load(tune_file);
             // NULL is the device's null stream, as everywhere in HIP: the context's

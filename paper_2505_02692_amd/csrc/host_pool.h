@@ -109,13 +109,23 @@ template <class T>
 using hvec = std::vector<T, CachedAlloc<T>>;
 
 // Fixed set of worker threads shared by the library; parallel_for(n, f) runs
-// f(0..n-1) on the calling thread plus the workers and returns when all are done.
-// Work items are handed out through an atomic counter.  Every worker checks in
-// once per region after its last item, and the region ends only when all have,
-// so no worker can still be drawing from one region's counter when the next
-// region resets it.  Idle workers spin for a short while before sleeping on a
-// condition variable, so back-to-back regions (a task build has several) do
-// not pay a wake-up each.
+// f(0..n-1) on the calling thread plus the workers and returns when all items
+// are done.  Items are handed out through one atomic ticket holding a
+// generation (high 32 bits) and the next item (low 32 bits).  Region r first
+// closes the ticket (generation 2r - 1: no item can be claimed), then sets its
+// function, item count and done counter, then opens it (generation 2r, item
+// 0).  A worker claims item k only by advancing an open ticket (2r, k) with
+// k below the count it read, so a worker that wakes late, or still holds a
+// ticket of an earlier region, claims nothing: its exchange fails.  A region
+// therefore waits only for its claimed items, never for idle workers.  Idle
+// workers spin for a short while before sleeping on a condition variable, so
+// back-to-back regions (a task build has several) do not pay a wake-up each.
+//
+// One region runs at a time.  A parallel_for issued while another thread's
+// region is running (say a collapse on one thread while a task is built on
+// another), or from inside a region, runs its items in place on the calling
+// thread.  The pool leaves one hardware thread to such callers: it uses at
+// most 16 threads and, on machines with 8 or more, one fewer than there are.
 class HostPool {
 public:
     static HostPool &get() {
@@ -123,40 +133,49 @@ public:
         return pool;
     }
     int size() const { return int(workers_.size()) + 1; }
+    // Whether a parallel_for issued now from this thread would run on the
+    // workers (a hint: another thread may start a region meanwhile, and then
+    // the call still completes, in place).
+    bool would_run_parallel() const { return !workers_.empty() && !in_region() && !busy_.load(); }
 
     void parallel_for(int n, const std::function<void(int)> &f) {
-        // One parallel region at a time: other threads wait for the workers.  A
-        // region started from inside a worker (or from the thread running the
-        // current region) runs its items in place, as waiting would deadlock.
         if (n <= 1 || workers_.empty() || in_region()) {
             for (int k = 0; k < n; ++k) f(k);
             return;
         }
-        std::unique_lock<std::mutex> call(call_mu_);
+        std::unique_lock<std::mutex> call(call_mu_, std::try_to_lock);
+        if (!call.owns_lock()) {  // another thread's region is running
+            for (int k = 0; k < n; ++k) f(k);
+            return;
+        }
         in_region() = true;
+        busy_.store(true);
         struct Reset {
-            ~Reset() { in_region() = false; }
-        } reset;
-        fn_ = &f;
-        total_ = n;
-        next_.store(0, std::memory_order_relaxed);
-        arrived_.store(0, std::memory_order_relaxed);
+            std::atomic<bool> &busy;
+            ~Reset() {
+                in_region() = false;
+                busy.store(false);
+            }
+        } reset{busy_};
+        const uint64_t open = (ticket_.load() >> 32) + 2;  // even
+        ticket_.store((open - 1) << 32);                   // closed
+        fn_.store(&f);
+        total_.store(uint32_t(n));
+        done_.store(0);
         {
             std::lock_guard<std::mutex> lk(mu_);
-            generation_.fetch_add(1, std::memory_order_release);
+            ticket_.store(open << 32);
         }
         cv_.notify_all();
-        run_tasks();
-        const int nw = int(workers_.size());
-        while (arrived_.load(std::memory_order_acquire) != nw) std::this_thread::yield();
-        fn_ = nullptr;
+        run_tasks(open);
+        while (done_.load() != uint32_t(n)) std::this_thread::yield();
     }
 
     ~HostPool() {
         {
             std::lock_guard<std::mutex> lk(mu_);
             stop_.store(true);
-            generation_.fetch_add(1, std::memory_order_release);
+            ticket_.store(((ticket_.load() >> 32) + 2) << 32);
         }
         cv_.notify_all();
         for (auto &t : workers_) t.join();
@@ -166,50 +185,64 @@ private:
     HostPool() {
         unsigned hw = std::thread::hardware_concurrency();
         int n = int(hw == 0 ? 1 : hw);
+        if (n >= 8) n -= 1;
         if (n > 16) n = 16;
         for (int i = 1; i < n; ++i) workers_.emplace_back([this] { worker(); });
     }
-    void run_tasks() {
+    // Claim and run items of open generation g until none is left or g is over.
+    // All accesses are sequentially consistent: a count read after the next
+    // region's close is ordered after that close, so the exchange that follows
+    // it fails.
+    void run_tasks(uint64_t g) {
         for (;;) {
-            const int k = next_.fetch_add(1, std::memory_order_relaxed);
-            if (k >= total_) return;
-            (*fn_)(k);
+            uint64_t t = ticket_.load();
+            if ((t >> 32) != g) return;
+            const uint32_t k = uint32_t(t);
+            if (k >= total_.load()) return;
+            if (!ticket_.compare_exchange_weak(t, t + 1)) continue;
+            // item k is claimed and not done, so this region is still running
+            (*fn_.load())(int(k));
+            done_.fetch_add(1);
         }
     }
     static bool &in_region() {
         thread_local bool flag = false;
         return flag;
     }
+    // generation of an open region other than `seen`, or 0
+    uint64_t next_open(uint64_t seen) const {
+        const uint64_t g = ticket_.load() >> 32;
+        return (g != seen && g % 2 == 0) ? g : 0;
+    }
     void worker() {
         in_region() = true;
         uint64_t seen = 0;
         for (;;) {
-            uint64_t g = generation_.load(std::memory_order_acquire);
-            if (g == seen) {
+            uint64_t g = next_open(seen);
+            if (g == 0 && !stop_.load()) {
                 const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(300);
-                while ((g = generation_.load(std::memory_order_acquire)) == seen &&
-                       std::chrono::steady_clock::now() < until)
+                while ((g = next_open(seen)) == 0 && !stop_.load() && std::chrono::steady_clock::now() < until)
                     std::this_thread::yield();
             }
-            if (g == seen) {
+            if (g == 0 && !stop_.load()) {
                 std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [&] { return generation_.load(std::memory_order_acquire) != seen; });
-                g = generation_.load(std::memory_order_acquire);
+                cv_.wait(lk, [&] { return next_open(seen) != 0 || stop_.load(); });
+                g = next_open(seen);
             }
             if (stop_.load()) return;
+            if (g == 0) continue;
             seen = g;
-            run_tasks();
-            arrived_.fetch_add(1, std::memory_order_release);
+            run_tasks(g);
         }
     }
     std::vector<std::thread> workers_;
     std::mutex mu_, call_mu_;
     std::condition_variable cv_;
-    const std::function<void(int)> *fn_ = nullptr;
-    int total_ = 0;
-    std::atomic<int> next_{0}, arrived_{0};
-    std::atomic<uint64_t> generation_{0};
+    std::atomic<const std::function<void(int)> *> fn_{nullptr};
+    std::atomic<uint32_t> total_{0}, done_{0};
+    std::atomic<uint64_t> ticket_{0};  // generation << 32 | next item; odd generation: closed
     std::atomic<bool> stop_{false};
+    std::atomic<bool> busy_{false};  // a region is running
 };
 
 // Phase tracing: FABX_TRACE=1 prints "[fabx] <what> <ms> <minor page faults>"

@@ -136,6 +136,9 @@ private:
 struct CtxImpl {
     int device = 0;
     hipStream_t stream = nullptr;  // borrowed; nullptr = the null stream
+    // owned, non-blocking: uploads of task tables, so that the next score's
+    // tables travel while the current score's kernels run; `stream` waits for them
+    hipStream_t copy_stream = nullptr;
     int n_cu = 0;
     Pool pool;
     EventPool events;

@@ -27,6 +27,9 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Collects host arrays (256-byte aligned pieces) and sends them to one device
 // buffer with a single DMA copy through the context's pinned staging buffer.
+// The copy runs on the context's copy stream; the compute stream waits for it.
+// The destination is a buffer of this task or score, so no earlier kernel
+// still on the compute stream can be reading it.
 struct Packer {
     struct Piece {
         const void *src;
@@ -43,7 +46,7 @@ struct Packer {
     }
     template <typename T, typename A>
     size_t add(const std::vector<T, A> &v) { return add(v.data(), v.size()); }
-    void upload(DevBuf &dst, Staging &stg, hipStream_t s) {
+    void upload(DevBuf &dst, Staging &stg, hipStream_t copy, hipStream_t compute) {
         dst.ensure(total);
         std::lock_guard<std::mutex> lk(stg.mu);
         stg.reserve(total);
@@ -58,9 +61,10 @@ struct Packer {
             const size_t o = slices[size_t(k)].second;
             std::memcpy(h + p.off + o, static_cast<const char *>(p.src) + o, std::min(kSlice, p.bytes - o));
         });
-        FABX_HIP(hipMemcpyAsync(dst.ptr, h, total, hipMemcpyHostToDevice, s));
-        FABX_HIP(hipEventRecord(stg.done, s));
+        FABX_HIP(hipMemcpyAsync(dst.ptr, h, total, hipMemcpyHostToDevice, copy));
+        FABX_HIP(hipEventRecord(stg.done, copy));
         stg.in_flight = true;  // the next upload waits for this DMA before reusing the buffer
+        FABX_HIP(hipStreamWaitEvent(compute, stg.done, 0));
     }
     template <typename T>
     static const T *at(const DevBuf &b, size_t off) {
@@ -282,7 +286,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         const bool with_plan = cplan && !cplan->d_cb;
         std::array<size_t, 4> o_plan{};
         if (with_plan) o_plan = add_col_plan(pk, *cplan);
-        pk.upload(dv.blob, ds.ctx->staging, stream);
+        pk.upload(dv.blob, ds.ctx->staging, ds.ctx->copy_stream, stream);
         dv.item_src = Packer::at<int64_t>(dv.blob, o_src);
         dv.item_len = Packer::at<int32_t>(dv.blob, o_len);
         dv.item_dst = Packer::at<int64_t>(dv.blob, o_dst);
@@ -304,7 +308,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         Packer pc;
         const auto o = add_col_plan(pc, *cplan);
         cplan->dev.pool = pool;
-        pc.upload(cplan->dev, ds.ctx->staging, stream);
+        pc.upload(cplan->dev, ds.ctx->staging, ds.ctx->copy_stream, stream);
         set_col_plan(*cplan, cplan->dev, o);
     }
     // Gram tile prefix of this score (plain form / pooled mode only)
@@ -314,7 +318,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     if (plain_tiles) {
         Packer pp;
         const size_t o_tiles = pp.add(tiles);
-        pp.upload(plan_d, ds.ctx->staging, stream);
+        pp.upload(plan_d, ds.ctx->staging, ds.ctx->copy_stream, stream);
         tiles_p = Packer::at<int64_t>(plan_d, o_tiles);
     }
     tr.mark("upload");

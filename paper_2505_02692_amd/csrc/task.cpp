@@ -13,6 +13,10 @@
 #include <numeric>
 #include <thread>
 
+#if defined(__x86_64__)
+#include <immintrin.h>
+#endif
+
 #include "host_pool.h"
 #include "internal.h"
 
@@ -25,78 +29,152 @@ struct RankedColumn {
     int bits = 0;                  // bits needed to hold a rank
 };
 
-RankedColumn rank_column(const DatasetImpl &ds, int col) {
-    RankedColumn rc;
-    const int64_t n = ds.n_items;
-    rc.rank.resize(n);
-    int32_t mn = INT32_MAX, mx = INT32_MIN;
-    for (int64_t i = 0; i < n; ++i) {
-        const int32_t v = ds.attrs[i * ds.n_attr + col];
-        mn = std::min(mn, v);
-        mx = std::max(mx, v);
-    }
-    const int64_t range = int64_t(mx) - int64_t(mn) + 1;
-    if (range <= std::max<int64_t>(4 * n, 1 << 16)) {
-        // dense value range: rank by a direct table
-        std::vector<int32_t> table(size_t(range), -1);
-        for (int64_t i = 0; i < n; ++i) table[size_t(ds.attrs[i * ds.n_attr + col] - int64_t(mn))] = 0;
-        int32_t r = 0;
-        for (int64_t v = 0; v < range; ++v)
-            if (table[size_t(v)] == 0) {
-                table[size_t(v)] = r++;
-                rc.values.push_back(int32_t(v + mn));
-            }
-        for (int64_t i = 0; i < n; ++i)
-            rc.rank[i] = uint32_t(table[size_t(ds.attrs[i * ds.n_attr + col] - int64_t(mn))]);
-    } else {
-        rc.values.resize(n);
-        for (int64_t i = 0; i < n; ++i) rc.values[i] = ds.attrs[i * ds.n_attr + col];
-        std::sort(rc.values.begin(), rc.values.end());
-        rc.values.erase(std::unique(rc.values.begin(), rc.values.end()), rc.values.end());
-        for (int64_t i = 0; i < n; ++i)
-            rc.rank[i] = uint32_t(std::lower_bound(rc.values.begin(), rc.values.end(),
-                                                   ds.attrs[i * ds.n_attr + col]) -
-                                  rc.values.begin());
-    }
-    uint64_t u = rc.values.size();
-    while ((uint64_t(1) << rc.bits) < u) ++rc.bits;
-    return rc;
+template <typename F>
+void parallel_for(int n, F &&f);
+
+// Items per chunk of a per-item parallel loop: up to four chunks per pool
+// thread, at least 1024 items each.  Loops chunked this way compute the same
+// per-item results whatever the chunk size.
+int64_t item_chunk(int64_t n) {
+    const int64_t parts = 4 * int64_t(HostPool::get().size());
+    return std::max<int64_t>(1024, (n + parts - 1) / parts);
 }
 
-// Stable LSD radix sort of items by a 64-bit key (8-bit digits, only the
-// digits the key uses), parallel over fixed chunks: each chunk counts its
-// digits, one prefix over (digit, chunk) gives every chunk its output
-// positions, and each chunk scatters its elements in order.  Ties keep
-// ascending item order, whatever the thread count.
-void radix_sort(hvec<uint64_t> &key, hvec<int64_t> &idx, int key_bits) {
-    constexpr int kDigit = 8;
-    constexpr size_t kBuckets = size_t(1) << kDigit;
+// Dense ranks of attribute columns `cols`, all columns per pass over the
+// item rows, each pass parallel over fixed row chunks: per-chunk minima and
+// maxima; then, for a column whose value range is small, the values present
+// (marked in a byte table) numbered in value order, else its sorted unique
+// values; then every item's rank.
+std::vector<RankedColumn> rank_columns(const DatasetImpl &ds, const std::vector<int32_t> &cols) {
+    const int64_t n = ds.n_items;
+    const size_t nc = cols.size(), na = size_t(ds.n_attr);
+    std::vector<RankedColumn> out(nc);
+    for (auto &rc : out) rc.rank.resize(size_t(n));
+    if (n == 0 || nc == 0) return out;
+    const int32_t *A = ds.attrs.data();
+    const int64_t kChunk = item_chunk(n);
+    const int n_chunks = int((n + kChunk - 1) / kChunk);
+    auto rows = [&](int c) { return std::make_pair(c * kChunk, std::min<int64_t>(n, (c + 1) * kChunk)); };
+    std::vector<int32_t> cmn(size_t(n_chunks) * nc, INT32_MAX), cmx(size_t(n_chunks) * nc, INT32_MIN);
+    parallel_for(n_chunks, [&](int c) {
+        // one column at a time in locals; chunks' results share cache lines
+        const auto [i0, i1] = rows(c);
+        for (size_t j = 0; j < nc; ++j) {
+            const size_t col = size_t(cols[j]);
+            int32_t mn = INT32_MAX, mx = INT32_MIN;
+            for (int64_t i = i0; i < i1; ++i) {
+                const int32_t v = A[size_t(i) * na + col];
+                mn = std::min(mn, v);
+                mx = std::max(mx, v);
+            }
+            cmn[size_t(c) * nc + j] = mn;
+            cmx[size_t(c) * nc + j] = mx;
+        }
+    });
+    std::vector<int32_t> lo(nc, INT32_MAX), hi(nc, INT32_MIN);
+    std::vector<char> dense(nc);
+    std::vector<std::vector<int32_t>> table(nc);  // dense: value - lo -> rank
+    std::vector<std::vector<uint8_t>> seen(nc);
+    for (size_t j = 0; j < nc; ++j) {
+        for (int c = 0; c < n_chunks; ++c) {
+            lo[j] = std::min(lo[j], cmn[size_t(c) * nc + j]);
+            hi[j] = std::max(hi[j], cmx[size_t(c) * nc + j]);
+        }
+        const int64_t range = int64_t(hi[j]) - int64_t(lo[j]) + 1;
+        dense[j] = range <= std::max<int64_t>(4 * n, 1 << 16);
+        if (dense[j]) seen[j].assign(size_t(range), 0);
+    }
+    parallel_for(n_chunks, [&](int c) {
+        const auto [i0, i1] = rows(c);
+        for (size_t j = 0; j < nc; ++j) {
+            if (!dense[j]) continue;
+            uint8_t *sj = seen[j].data();
+            const int64_t l = lo[j];
+            // store only when unset: the few values of a label column then stay
+            // in shared cache lines instead of bouncing between threads
+            for (int64_t i = i0; i < i1; ++i) {
+                uint8_t *e = sj + (A[size_t(i) * na + size_t(cols[j])] - l);
+                if (!__atomic_load_n(e, __ATOMIC_RELAXED)) __atomic_store_n(e, uint8_t(1), __ATOMIC_RELAXED);
+            }
+        }
+    });
+    parallel_for(int(nc), [&](int jj) {
+        const size_t j = size_t(jj);
+        RankedColumn &rc = out[j];
+        if (dense[j]) {
+            table[j].assign(seen[j].size(), 0);
+            int32_t r = 0;
+            for (size_t v = 0; v < seen[j].size(); ++v)
+                if (seen[j][v]) {
+                    table[j][v] = r++;
+                    rc.values.push_back(int32_t(int64_t(v) + lo[j]));
+                }
+        } else {
+            rc.values.resize(size_t(n));
+            for (int64_t i = 0; i < n; ++i) rc.values[size_t(i)] = A[size_t(i) * na + size_t(cols[j])];
+            std::sort(rc.values.begin(), rc.values.end());
+            rc.values.erase(std::unique(rc.values.begin(), rc.values.end()), rc.values.end());
+        }
+        uint64_t u = rc.values.size();
+        while ((uint64_t(1) << rc.bits) < u) ++rc.bits;
+    });
+    parallel_for(n_chunks, [&](int c) {
+        const auto [i0, i1] = rows(c);
+        for (size_t j = 0; j < nc; ++j) {
+            uint32_t *rk = out[j].rank.data();
+            const size_t col = size_t(cols[j]);
+            if (dense[j]) {
+                const int32_t *tb = table[j].data();
+                const int64_t l = lo[j];
+                for (int64_t i = i0; i < i1; ++i) rk[i] = uint32_t(tb[A[size_t(i) * na + col] - l]);
+            } else {
+                const auto &vals = out[j].values;
+                for (int64_t i = i0; i < i1; ++i)
+                    rk[i] = uint32_t(std::lower_bound(vals.begin(), vals.end(), A[size_t(i) * na + col]) -
+                                     vals.begin());
+            }
+        }
+    });
+    return out;
+}
+
+// Stable LSD radix sort of items by a key of key_bits bits (digits of at
+// most 11 bits, as few passes as that allows), parallel over fixed chunks:
+// each chunk counts its digits, one prefix over (digit, chunk) gives every
+// chunk its output positions, and each chunk scatters its elements in order.
+// Ties keep ascending item order, whatever the thread count.
+template <typename K, typename I>
+void radix_sort(hvec<K> &key, hvec<I> &idx, int key_bits) {
     const size_t n = key.size();
     if (key_bits <= 0 || n < 2) return;
+    const int passes = (key_bits + 10) / 11;
+    const int digit = (key_bits + passes - 1) / passes;
+    const size_t buckets = size_t(1) << digit;
     const size_t n_chunks = std::min<size_t>(64, std::max<size_t>(1, n / 8192));
-    hvec<uint64_t> k2(n);
-    hvec<int64_t> i2(n);
-    std::vector<size_t> hist(n_chunks * kBuckets);
+    hvec<K> k2(n);
+    hvec<I> i2(n);
+    std::vector<size_t> hist(n_chunks * buckets);
     auto bounds = [&](size_t c) { return std::make_pair(n * c / n_chunks, n * (c + 1) / n_chunks); };
-    for (int shift = 0; shift < key_bits; shift += kDigit) {
+    for (int shift = 0; shift < key_bits; shift += digit) {
+        const K mask = K(buckets - 1);
         HostPool::get().parallel_for(int(n_chunks), [&](int c) {
-            size_t *h = hist.data() + size_t(c) * kBuckets;
-            std::fill(h, h + kBuckets, size_t(0));
+            size_t *h = hist.data() + size_t(c) * buckets;
+            std::fill(h, h + buckets, size_t(0));
             const auto [b0, b1] = bounds(size_t(c));
-            for (size_t i = b0; i < b1; ++i) ++h[(key[i] >> shift) & (kBuckets - 1)];
+            for (size_t i = b0; i < b1; ++i) ++h[(key[i] >> shift) & mask];
         });
         size_t run = 0;
-        for (size_t b = 0; b < kBuckets; ++b)
+        for (size_t b = 0; b < buckets; ++b)
             for (size_t c = 0; c < n_chunks; ++c) {
-                const size_t v = hist[c * kBuckets + b];
-                hist[c * kBuckets + b] = run;
+                const size_t v = hist[c * buckets + b];
+                hist[c * buckets + b] = run;
                 run += v;
             }
         HostPool::get().parallel_for(int(n_chunks), [&](int c) {
-            size_t *h = hist.data() + size_t(c) * kBuckets;
+            size_t *h = hist.data() + size_t(c) * buckets;
             const auto [b0, b1] = bounds(size_t(c));
             for (size_t i = b0; i < b1; ++i) {
-                const size_t d = h[(key[i] >> shift) & (kBuckets - 1)]++;
+                const size_t d = h[(key[i] >> shift) & mask]++;
                 k2[d] = key[i];
                 i2[d] = idx[i];
             }
@@ -219,36 +297,43 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
             // large cells get one unit per x, in the sorted-row region
             const int64_t per_x = std::max<int64_t>(1, na * nb);
             const bool big = per_x >= kSortedMinPerX && nb <= kSortedMaxB;
-            const int64_t chunk = big ? 1 : std::max<int64_t>(1, kUnitBudget / per_x);
+            // nx * per_x <= budget (the usual case): one unit for the whole cell,
+            // which is what the division below gives, without dividing
+            const bool one = !big && nx >= 1 && nx * per_x <= kUnitBudget;
+            const int64_t chunk = one ? nx : big ? 1 : std::max<int64_t>(1, kUnitBudget / per_x);
+            const int64_t n_units_cell = one ? 1 : (nx + chunk - 1) / chunk;
             if (kWrite) {
-                CellDev c;
-                c.group = group_id;
-                c.a0 = int32_t(cls[ia].start - g0);
-                c.na = int32_t(na);
-                c.b0 = int32_t(cls[ib].start - g0);
-                c.nb = int32_t(nb);
-                c.x0 = int32_t(cls[ix].start - g0);
-                c.nx = int32_t(nx);
-                c.exclude_self = excl ? 1 : 0;
-                out.cells[cid] = c;
-                out.ntrip[cid] = nt;
+                // The task's per-cell arrays are far larger than the caches and
+                // are read back only later (upload, collapse): streaming stores
+                // write them without first reading their lines.
+                auto put = [](auto *dst, auto v) { __builtin_nontemporal_store(v, dst); };
+                int32_t *c = reinterpret_cast<int32_t *>(out.cells + cid);
+                put(c + 0, group_id);
+                put(c + 1, int32_t(cls[ia].start - g0));
+                put(c + 2, int32_t(na));
+                put(c + 3, int32_t(cls[ib].start - g0));
+                put(c + 4, int32_t(nb));
+                put(c + 5, int32_t(cls[ix].start - g0));
+                put(c + 6, int32_t(nx));
+                put(c + 7, int32_t(excl ? 1 : 0));
+                put(out.ntrip + cid, int64_t(nt));
                 uint32_t *rk = out.rkeys + cid * out.key_width;
-                rk[0] = cls[size_t(ia)].on_rank;
-                rk[1] = cls[size_t(ib)].on_rank;
-                for (int j = 0; j < n_by; ++j) rk[2 + j] = gbyr[size_t(j)];
+                put(rk + 0, cls[size_t(ia)].on_rank);
+                put(rk + 1, cls[size_t(ib)].on_rank);
+                for (int j = 0; j < n_by; ++j) put(rk + 2 + j, gbyr[size_t(j)]);
                 for (int j = 0; j < n_ac; ++j) {
-                    rk[2 + n_by + j] = cacr[size_t(ia * n_ac + j)];
-                    rk[2 + n_by + n_ac + j] = cacr[size_t(ix * n_ac + j)];
+                    put(rk + 2 + n_by + j, cacr[size_t(ia * n_ac + j)]);
+                    put(rk + 2 + n_by + n_ac + j, cacr[size_t(ix * n_ac + j)]);
                 }
                 int32_t *u = big ? out.units + out.big_unit_base + out.n_big_unit_ints
                                  : out.units + out.unit_base + out.n_unit_ints;
                 for (int64_t x = 0; x < nx; x += chunk, u += 3) {
-                    u[0] = int32_t(cid);
-                    u[1] = int32_t(x);
-                    u[2] = int32_t(std::min<int64_t>(nx, x + chunk));
+                    put(u + 0, int32_t(cid));
+                    put(u + 1, int32_t(x));
+                    put(u + 2, int32_t(std::min<int64_t>(nx, x + chunk)));
                 }
             }
-            (big ? out.n_big_unit_ints : out.n_unit_ints) += size_t(3 * ((nx + chunk - 1) / chunk));
+            (big ? out.n_big_unit_ints : out.n_unit_ints) += size_t(3 * n_units_cell);
             ++out.n_cells;
             out.total_triplets += nt;
             out.sum_nx += nx;
@@ -446,8 +531,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     RankedColumn ron;
     {
         std::vector<int32_t> all_cols = cols;   // on, by..., across...
-        std::vector<RankedColumn> ranked(all_cols.size());
-        parallel_for(int(all_cols.size()), [&](int k) { ranked[size_t(k)] = rank_column(*ds, all_cols[size_t(k)]); });
+        std::vector<RankedColumn> ranked = rank_columns(*ds, all_cols);
         ron = std::move(ranked[0]);
         for (size_t i = 0; i < rby.size(); ++i) rby[i] = std::move(ranked[1 + i]);
         for (size_t i = 0; i < racr.size(); ++i) racr[i] = std::move(ranked[1 + rby.size() + i]);
@@ -464,31 +548,70 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
 
     tr.mark("rank");
     hvec<int64_t> order(n);
-    std::iota(order.begin(), order.end(), int64_t(0));
     hvec<uint64_t> by_part(n), cls_part(n);   // BY tuple id / (on, across) class id
     if (total_bits <= 64) {
-        hvec<uint64_t> key(n);
-        const int64_t kChunk = 1 << 14;
+        // packed key: BY ranks (high), ON rank, ACROSS ranks (low); sorted as
+        // 32-bit keys and item ids when it fits, which halves the bytes moved
+        const int64_t kChunk = item_chunk(n);
         const int n_chunks = int((n + kChunk - 1) / kChunk);
-        parallel_for(n_chunks, [&](int c) {
-            for (int64_t i = c * kChunk; i < std::min<int64_t>(n, (c + 1) * kChunk); ++i) {
-                uint64_t k = 0;
-                for (auto &r : rby) k = (k << r.bits) | r.rank[i];
-                k = (k << ron.bits) | ron.rank[i];
-                uint64_t a = 0;
-                for (int j = 0; j < n_across; ++j) a |= uint64_t(racr[j].rank[i]) << acr_shift[j];
-                key[i] = (k << acr_bits) | a;
-            }
-        });
-        radix_sort(key, order, total_bits);
-        parallel_for(n_chunks, [&](int c) {
-            for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) {
-                by_part[s] = low_bits >= 64 ? 0 : key[s] >> low_bits;
-                cls_part[s] = key[s];
-            }
-        });
+        // rank arrays and shifts of the key's fields, most significant first
+        std::vector<const uint32_t *> fr;
+        std::vector<int> fs;
+        for (auto &r : rby) {
+            fr.push_back(r.rank.data());
+            fs.push_back(r.bits);
+        }
+        fr.push_back(ron.rank.data());
+        fs.push_back(ron.bits);
+        for (int j = 0; j < n_across; ++j) {
+            fr.push_back(racr[size_t(j)].rank.data());
+            fs.push_back(racr[size_t(j)].bits);
+        }
+        const size_t nf = fr.size();
+        auto packed = [&](int64_t i) {
+            uint64_t k = 0;
+            for (size_t f = 0; f < nf; ++f) k = (k << fs[f]) | fr[f][i];
+            return k;
+        };
+        auto split = [&](int64_t s, uint64_t k) {
+            by_part[s] = low_bits >= 64 ? 0 : k >> low_bits;
+            cls_part[s] = k;
+        };
+        if (total_bits <= 32 && n <= INT32_MAX) {
+            hvec<uint32_t> key(n), ord(n);
+            parallel_for(n_chunks, [&](int c) {
+                for (int64_t i = c * kChunk; i < std::min<int64_t>(n, (c + 1) * kChunk); ++i) {
+                    key[i] = uint32_t(packed(i));
+                    ord[i] = uint32_t(i);
+                }
+            });
+            tr.mark("keys");
+            radix_sort(key, ord, total_bits);
+            tr.mark("radix");
+            parallel_for(n_chunks, [&](int c) {
+                for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) {
+                    order[s] = ord[s];
+                    split(s, key[s]);
+                }
+            });
+        } else {
+            hvec<uint64_t> key(n);
+            parallel_for(n_chunks, [&](int c) {
+                for (int64_t i = c * kChunk; i < std::min<int64_t>(n, (c + 1) * kChunk); ++i) {
+                    key[i] = packed(i);
+                    order[i] = i;
+                }
+            });
+            tr.mark("keys");
+            radix_sort(key, order, total_bits);
+            tr.mark("radix");
+            parallel_for(n_chunks, [&](int c) {
+                for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) split(s, key[s]);
+            });
+        }
     } else {
         // Key too wide for one word: comparison sort on the rank tuple.
+        std::iota(order.begin(), order.end(), int64_t(0));
         std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
             for (auto &r : rby)
                 if (r.rank[x] != r.rank[y]) return r.rank[x] < r.rank[y];
@@ -512,6 +635,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             cls_part[s] = cid;
         }
     }
+    tr.mark("parts");
     // ---- ranks per sorted position (from the packed key when there is one)
     const int W = 1 + n_by + n_across;
     hvec<uint32_t> srank(static_cast<size_t>(n) * size_t(W));
@@ -535,7 +659,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             src[size_t(1 + n_by + j)] = &racr[size_t(j)].rank;
         }
         const bool packed = total_bits <= 64;
-        const int64_t kChunk = 1 << 14;
+        const int64_t kChunk = item_chunk(n);
         parallel_for(int((n + kChunk - 1) / kChunk), [&](int c) {
             const int64_t s0 = c * kChunk, s1 = std::min<int64_t>(n, s0 + kChunk);
             for (int64_t s = s0; s < s1; ++s) {
@@ -547,13 +671,13 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             }
         });
     }
-    tr.mark("sort");
+    tr.mark("srank");
     // ---- per sorted position: length, and prefix sums of frames and squared lengths
     hvec<int32_t> len_s(static_cast<size_t>(n));
     hvec<int64_t> pf(static_cast<size_t>(n) + 1), pq(static_cast<size_t>(n) + 1);
     {
         // two-level scan over fixed chunks: chunk sums, their prefix, then the fill
-        const int64_t kChunk = 1 << 14;
+        const int64_t kChunk = item_chunk(n);
         const int nc = int((n + kChunk - 1) / kChunk);
         std::vector<int64_t> cf(size_t(nc) + 1, 0), cq(size_t(nc) + 1, 0);
         parallel_for(nc, [&](int c) {
@@ -583,6 +707,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         });
     }
 
+    tr.mark("lengths");
     // ---- walk the groups: chunks of whole groups in parallel, then stitch
     const int n_threads = int(std::min<int64_t>(HostPool::get().size(), std::max<int64_t>(1, n / 4096)));
     // more shares than threads: the pool hands them out dynamically (group sizes vary)
@@ -653,6 +778,12 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         p.kept = kept.data();
         p.key_width = size_t(t->key_width);
         walk_groups<true>(wc, cut[k], cut[k + 1], p);
+        // the walk's streaming stores are weakly ordered: make them visible
+        // before the region ends and other threads read the arrays
+#if defined(__x86_64__)
+        _mm_sfence();
+#endif
+        std::atomic_thread_fence(std::memory_order_seq_cst);
         if (p.n_cells != counted.n_cells || p.n_unit_ints != counted.n_unit_ints ||
             p.n_big_unit_ints != counted.n_big_unit_ints || p.n_groups != counted.n_groups)
             mismatch = true;  // both passes walk the same share: cannot happen
@@ -681,20 +812,36 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     t->item_group.resize(size_t(nt));
     t->item_pos_of.resize(size_t(n));
     {
-        const int64_t kChunk = 1 << 16;
+        const int64_t kChunk = item_chunk(n);
         parallel_for(int((n + kChunk - 1) / kChunk), [&](int c) {
             std::fill(t->item_pos_of.begin() + c * kChunk,
                       t->item_pos_of.begin() + std::min<int64_t>(n, (c + 1) * kChunk), int64_t(-1));
         });
     }
-    std::vector<int> max_len_part(static_cast<size_t>(n_threads), 0);
+    // task items in balanced chunks of task positions; a chunk may start inside
+    // a group, whose first frame offset then comes from the frame prefix
     const int64_t G = int64_t(t->groups.size());
-    parallel_for(n_threads, [&](int k) {
+    const int64_t q_chunk = item_chunk(nt);
+    const int n_qc = int(std::max<int64_t>(1, (nt + q_chunk - 1) / q_chunk));
+    std::vector<int> max_len_part(static_cast<size_t>(n_qc), 0);
+    parallel_for(n_qc, [&](int k) {
+        const int64_t q0 = int64_t(k) * q_chunk, q1 = std::min<int64_t>(nt, q0 + q_chunk);
+        if (q0 >= q1) return;
+        // group holding task position q0: the last with item0 <= q0
+        int64_t lo = 0, hi = G;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (t->groups[size_t(mid)].item0 <= q0) lo = mid; else hi = mid;
+        }
         int ml = 0;
-        for (int64_t gi = G * k / n_threads; gi < G * (k + 1) / n_threads; ++gi) {
+        int64_t q = q0;
+        for (int64_t gi = lo; q < q1; ++gi) {
             const Group &g = t->groups[size_t(gi)];
-            int64_t frame = g.frame0, q = g.item0;
-            for (int64_t s = kept[size_t(gi)].first; s < kept[size_t(gi)].second; ++s, ++q) {
+            const int64_t s_first = kept[size_t(gi)].first;
+            const int64_t s0 = s_first + (q - g.item0);
+            const int64_t s1 = std::min<int64_t>(kept[size_t(gi)].second, s_first + (q1 - g.item0));
+            int64_t frame = g.frame0 + (pf[s0] - pf[s_first]);
+            for (int64_t s = s0; s < s1; ++s, ++q) {
                 const int64_t it = order[s];
                 t->items[q] = it;
                 t->item_pos_of[it] = q;
