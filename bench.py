@@ -53,6 +53,10 @@ WORKLOADS = {
 }
 
 
+# extra score options (a forced fused-kernel configuration, --fused-config)
+SCORE_KW = {}
+
+
 def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True):
     """n steps with host and device work overlapped across steps: while the
     device scores step i (fabx_score_async), the host builds the task of step
@@ -74,7 +78,7 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True)
     with cf.ThreadPoolExecutor(max_workers=1) as side:
         for _ in range(n):
             task = fx.Task(ds, w.on, w.by, w.across)
-            res = task.score_async(mode=mode, precision=precision)
+            res = task.score_async(mode=mode, precision=precision, **SCORE_KW)
             if prev is not None:
                 if side_collapse:
                     if fut is not None:
@@ -106,7 +110,7 @@ def run_steps(fx, ds, w, precision, n, sync, mode="dtw"):
         ta = time.perf_counter()
         task = fx.Task(ds, w.on, w.by, w.across)
         tb = time.perf_counter()
-        res = task.score(mode=mode, precision=precision)
+        res = task.score(mode=mode, precision=precision, **SCORE_KW)
         tc = time.perf_counter()
         errs.append(res.collapse(w.levels))
         td = time.perf_counter()
@@ -205,10 +209,11 @@ def cpu_baseline(oracle, w, target_seconds=20.0):
                       f"triplets) of the same workload, FP64 DTW + scoring, {dt:.1f} s"}
 
 
-def committed_traffic(kernel_file, profile_file):
-    """HBM bytes per launch of the dominant kernel, from the committed rocprofv3
-    byte-counter summary, used only while the kernel source is the one that was
-    measured (its SHA-256 prefix is recorded beside the figure)."""
+def committed_traffic(kernel_file, profile_file, cols, blocks_per_cu):
+    """HBM bytes per launch of the dominant kernel in the configuration that ran,
+    from the committed rocprofv3 byte-counter summary, used only while the kernel
+    source is the one that was measured (its SHA-256 prefix is recorded beside
+    the figure)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -216,24 +221,32 @@ def committed_traffic(kernel_file, profile_file):
         lines = open(os.path.join(root, profile_file)).read().splitlines()
     except OSError:
         return None
-    sha = hashlib.sha256(src).hexdigest()[:16]
+    want = {"source_sha256": hashlib.sha256(src).hexdigest()[:16],
+            "kernel": f"k_fused<{cols},true>", "blocks_per_cu": str(blocks_per_cu)}
     for line in lines:
         f = line.strip().strip("`").split()
-        if len(f) == 4 and f[0] == "traffic" and f[2] == "source_sha256=" + sha:
-            return float(f[1].split("=")[1])
+        if not f or f[0] != "traffic":
+            continue
+        kv = dict(x.split("=", 1) for x in f[1:] if "=" in x)
+        if all(kv.get(k) == v for k, v in want.items()):
+            return float(kv["bytes_per_launch"])
     return None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 for c2, whose steps take about 2 ms, else 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 10 for c2, else 1)")
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default fused-kernel tiles")
+    ap.add_argument("--fused-config", default=None, metavar="COLS,BLOCKS_PER_CU",
+                    help="run the fused kernel with this column width and grid (e.g. 128,0) "
+                         "instead of autotuning")
     ap.add_argument("--collapse-inline", action="store_true",
                     help="pipelined steps collapse on the main thread instead of a second host thread")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
@@ -241,6 +254,10 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run 3 plain device copies of this many MiB (to scale HBM byte counters)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 200 if args.workload == "c2" else 3
+    if args.warmup is None:
+        args.warmup = 10 if args.workload == "c2" else 1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the ABX hot path here is "
               "single-GPU; see DESIGN.md for how it would shard across GPUs.", file=sys.stderr)
@@ -273,11 +290,15 @@ def main():
     log(f"workload {args.workload} ready: {w.n_items} items, {w.n_frames} frames, dim {w.dim}")
 
     side = not args.collapse_inline
+    if args.fused_config:
+        cols, bpc = (int(v) for v in args.fused_config.split(","))
+        SCORE_KW.update(fused_cols=cols, fused_blocks_per_cu=bpc)
     run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, side)
     sync()
     log("warmup done")
     # untimed: pick the fused kernel's tiles / grid for this task shape
-    tune = fx.Task(ds, w.on, w.by, w.across).autotune(mode=mode) if not args.no_autotune else None
+    tune = (fx.Task(ds, w.on, w.by, w.across).autotune(mode=mode)
+            if not (args.no_autotune or args.fused_config) else None)
     log(f"autotune: {tune}")
     dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, side)
     ms_step = dt / args.steps * 1e3
@@ -325,9 +346,9 @@ def main():
                 "algorithmic_bytes_per_launch": norm_bytes}
     else:
         ach = dist_flops / (stages["ms_distance"] / 1e3) / 1e12
-        traffic = (committed_traffic("paper_2505_02692_amd/csrc/k_fused.hip", "profiles/hbm_bytes_within_c2.md")
-                   if (headline and mode == "dtw" and st0["fused_cols"] == 128 and st0["fused_blocks_per_cu"] == 0)
-                   else None)
+        traffic = (committed_traffic("paper_2505_02692_amd/csrc/k_fused.hip", "profiles/hbm_bytes_within_c2.md",
+                                     st0["fused_cols"], st0["fused_blocks_per_cu"])
+                   if (headline and mode == "dtw") else None)
         roof = {"kernel": "k_fused" if mode == "dtw" else "k_gram_angular_bf16", "bound": "mfma",
                 "achieved": ach, "peak": MFMA_BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / MFMA_BF16_PEAK_TFLOPS, "traffic": traffic,

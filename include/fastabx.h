@@ -166,10 +166,17 @@ typedef struct fabx_score_opts {
                             else the pair is recomputed in FP64; < 0 selects the default
                             4e-2 / sqrt(dim) */
     int32_t keep_pairs;  /* nonzero: keep the per-pair distances for fabx_result_pairs */
+    int32_t fused_cols;  /* BF16 DTW: fused kernel column block width, 128 or 256; 0 takes
+                            the context's tuning table (fabx_autotune), as does a width
+                            of 0 with a nonzero grid.  Results do not depend on it. */
+    int32_t fused_blocks_per_cu; /* its grid: 0 = one block per work unit, 1..64 = a
+                                    persistent grid of that many blocks per CU */
 } fabx_score_opts;
 
 /* Defaults: ANGULAR, DTW, BF16_RECHECK, PATH, margin/delta = -1 (library
- * defaults), keep_pairs = 0. */
+ * defaults), keep_pairs = 0, fused_cols = fused_blocks_per_cu = 0 (tuning
+ * table).  FABX_EINVAL for a width other than 0, 128, 256 or a grid outside
+ * 0..64. */
 int fabx_score_opts_default(fabx_score_opts *opts);
 
 /* Score every cell: for each cell C and each triple (a, b, x) in it, compare

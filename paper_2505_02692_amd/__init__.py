@@ -239,7 +239,8 @@ def fabx_server_stats_get(srv) -> dict:
 # ----------------------------------------------------------- convenience --
 
 def make_opts(mode: str = "dtw", precision: str = "bf16", norm: str = "path", margin: float = -1.0,
-              delta: float = -1.0, keep_pairs: bool = False) -> fabx_score_opts:
+              delta: float = -1.0, keep_pairs: bool = False, fused_cols: int = 0,
+              fused_blocks_per_cu: int = 0) -> fabx_score_opts:
     o = fabx_score_opts_default()
     o.mode = {"dtw": FABX_MODE_DTW, "pooled": FABX_MODE_POOLED}[mode]
     o.precision = {"fp32": FABX_PREC_FP32, "bf16": FABX_PREC_BF16_RECHECK}[precision]
@@ -247,6 +248,8 @@ def make_opts(mode: str = "dtw", precision: str = "bf16", norm: str = "path", ma
     o.margin = float(margin)
     o.delta = float(delta)
     o.keep_pairs = 1 if keep_pairs else 0
+    o.fused_cols = int(fused_cols)
+    o.fused_blocks_per_cu = int(fused_blocks_per_cu)
     return o
 
 

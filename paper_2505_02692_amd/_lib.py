@@ -40,7 +40,8 @@ class fabx_dataset_desc(ctypes.Structure):
 class fabx_score_opts(ctypes.Structure):
     _fields_ = [("distance", ctypes.c_int32), ("mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dtw_norm", ctypes.c_int32), ("margin", ctypes.c_double), ("delta", ctypes.c_double),
-                ("keep_pairs", ctypes.c_int32)]
+                ("keep_pairs", ctypes.c_int32), ("fused_cols", ctypes.c_int32),
+                ("fused_blocks_per_cu", ctypes.c_int32)]
 
 
 class fabx_stats(ctypes.Structure):

@@ -335,6 +335,8 @@ int fabx_score_opts_default(fabx_score_opts *o) {
     o->margin = -1.0;
     o->delta = -1.0;
     o->keep_pairs = 0;
+    o->fused_cols = 0;
+    o->fused_blocks_per_cu = 0;
     return FABX_OK;
 }
 

@@ -219,22 +219,37 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                                                   int64_t n_groups, int64_t n_units, int64_t grid_q,
                                                   float delta, float *__restrict__ p32,
                                                   uint8_t *__restrict__ flags,
-                                                  unsigned int *__restrict__ nonrobust_n) {
+                                                  unsigned int *__restrict__ nonrobust_n,
+                                                  unsigned int *__restrict__ unit_ctr) {
     using T = Tile<kC>;
     constexpr int kDStride = T::kDStride, kFlagLen = T::kFlagLen;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kSmemBytes];
     __shared__ uint16_t colflag[4][kFlagLen];
     __shared__ __attribute__((aligned(16))) float norm_s[kRows + kC];  // row then column inverse norms
-    // Persistent blocks, XCD-aware order: the 8 XCDs take blocks round-robin,
-    // so XCD x works through the contiguous unit range [x * grid_q, (x+1) * grid_q)
-    // (units of one group share its frames in that XCD's L2).  gridDim.x is a
-    // multiple of 8.
-    const int64_t xcd = blockIdx.x % 8, m = blockIdx.x / 8, n_m = gridDim.x / 8;
+    // XCD-aware order: the 8 XCDs take blocks round-robin, so XCD x works
+    // through the contiguous unit range [x * grid_q, (x+1) * grid_q) (units of
+    // one group share its frames in that XCD's L2).  gridDim.x is a multiple
+    // of 8.  With a block per unit the block's index gives its unit; with
+    // fewer blocks (a persistent grid) the blocks of an XCD take the range's
+    // units in order from the XCD's counter (zero at launch), so the units in
+    // flight stay together; each block stops once its counter passes the range.
+    const int64_t xcd = blockIdx.x % 8, n_m = gridDim.x / 8;
+    const bool take = n_m < grid_q;
+    __shared__ int64_t taken_s;
+    // next unit index for this block: read by every thread after a barrier; the
+    // write happens after the unit's last barrier, when all threads have read
+    // the previous value
+    auto next = [&](int64_t j) -> int64_t {
+        if (!take) return j + n_m;
+        if (threadIdx.x == 0) taken_s = int64_t(atomicAdd(unit_ctr + xcd, 1u));
+        __syncthreads();
+        return taken_s;
+    };
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    for (int64_t j = m; j < grid_q; j += n_m) {
+    for (int64_t j = take ? next(0) : int64_t(blockIdx.x / 8); j < grid_q; j = next(j)) {
     const int64_t unit = xcd * grid_q + j;
-    if (unit >= n_units) continue;  // uniform across the block
+    if (unit >= n_units) break;  // uniform across the block; later units are larger
 
     const int64_t g = dev::find_segment_wave(unit_prefix, n_groups, unit);
     const int64_t local = unit - unit_prefix[g];
@@ -453,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
 template <int kC>
 void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad, const GroupTables &g,
                   const ItemTables &it, const FusedPlan &plan, int norm, float delta, float *p32,
-                  uint8_t *flags, unsigned int *nonrobust_n) {
+                  uint8_t *flags, unsigned int *nonrobust_n, unsigned int *unit_ctr) {
     // units are split into 8 contiguous ranges, one per XCD; blocks of XCD x take
     // the units of range x in turn
     const int64_t q = (plan.n_units + 7) / 8;
@@ -465,25 +480,26 @@ void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_
         hipLaunchKernelGGL((k_fused<kC, true>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
                            g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.g_rb0,
                            plan.g_cb0, plan.g_ncb, g.n_groups, plan.n_units, q, delta, p32, flags,
-                           nonrobust_n);
+                           nonrobust_n, unit_ctr);
     else
         hipLaunchKernelGGL((k_fused<kC, false>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
                            g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.g_rb0,
                            plan.g_cb0, plan.g_ncb, g.n_groups, plan.n_units, q, delta, p32, flags,
-                           nonrobust_n);
+                           nonrobust_n, unit_ctr);
 }
 
 }  // namespace
 
 void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                 const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,
-                float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n) {
+                float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n,
+                unsigned int *unit_ctr) {
     if (plan.n_units <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
     if (plan.cols == 128)
-        launch_fused<128>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n);
+        launch_fused<128>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n, unit_ctr);
     else if (plan.cols == 256)
-        launch_fused<256>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n);
+        launch_fused<256>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n, unit_ctr);
     else
         fail(FABX_EINVAL, "fused kernel column block must be 128 or 256 frames");
     FABX_HIP(hipGetLastError());

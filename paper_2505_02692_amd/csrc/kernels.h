@@ -76,9 +76,11 @@ struct FusedPlan {
     int blocks_per_cu;   // persistent grid of blocks_per_cu * n_cu blocks; 0: one block per unit
     int n_cu;
 };
+// unit_ctr: 8 counters, zero at launch (the XCDs' next units of a persistent grid)
 void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                 const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,
-                float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n);
+                float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n,
+                unsigned int *unit_ctr);
 
 // Pooled mode, BF16 MFMA: theta/pi between pooled item vectors of each group.
 void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,

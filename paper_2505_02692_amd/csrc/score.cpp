@@ -126,6 +126,11 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     p.margin = o.margin < 0 ? kMarginK / std::sqrt(double(ds.dim)) : o.margin;
     p.delta = o.delta < 0 ? kDeltaK / std::sqrt(double(ds.dim)) : o.delta;
     p.keep_pairs = o.keep_pairs != 0;
+    if (o.fused_cols != 0 && o.fused_cols != 128 && o.fused_cols != 256)
+        fail(FABX_EINVAL, "fused_cols must be 0, 128 or 256");
+    if (o.fused_blocks_per_cu < 0 || o.fused_blocks_per_cu > 64)
+        fail(FABX_EINVAL, "fused_blocks_per_cu must be in 0..64");
+    p.fused = FusedConfig{o.fused_cols, o.fused_blocks_per_cu};  // cols 0: the tuning table
     if (p.mode == FABX_MODE_DTW && ds.max_len > FABX_MAX_ITEM_FRAMES)
         fail(FABX_EINVAL, "an item is longer than FABX_MAX_ITEM_FRAMES frames (DTW mode)");
     if (ds.dim > 2048) fail(FABX_EINVAL, "feature dim above 2048 is not supported");
@@ -344,6 +349,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     unsigned int *recount_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 16);
     unsigned int *marked_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 20);
     unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 24);
+    unsigned int *unit_ctr = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 32);  // [8]
     st.workspace_bytes = int64_t(ws.total());
     pend->host_bytes = size_t(n_cells) * 8 + 64;
     pend->host = ds.ctx->pinned.get(pend->host_bytes, &pend->host_bytes);
@@ -387,7 +393,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
                            ds.ctx->n_cu};
         kern::fused_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt, it, fp,
                          p.dtw_norm, float(p.delta), ws.p32.as<float>(), ws.flags.as<uint8_t>(),
-                         nonrobust_n);
+                         nonrobust_n, unit_ctr);
         st.computed_dtw_cells = t.fused_cells;
     } else if (!bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.item0, gt.n_items, gt.pair_base,

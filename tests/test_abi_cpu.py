@@ -145,6 +145,22 @@ def test_bad_score_options():
     o.distance = 3
     with pytest.raises(fx.FabxError):
         fx.fabx_score(t.h, o)
+    # a forced fused-kernel configuration must be one the kernel has
+    for cols, bpc, msg in ((100, 0, "fused_cols"), (128, -1, "fused_blocks_per_cu"),
+                           (256, 65, "fused_blocks_per_cu")):
+        with pytest.raises(fx.FabxError) as e:
+            fx.fabx_score(t.h, fx.make_opts(fused_cols=cols, fused_blocks_per_cu=bpc))
+        assert e.value.code == L.FABX_EINVAL and msg in str(e.value)
+
+
+def test_score_opts_layout_and_defaults():
+    """The ctypes mirror of fabx_score_opts matches the C defaults field by field."""
+    o = fx.fabx_score_opts_default()
+    assert (o.mode, o.precision, o.dtw_norm, o.keep_pairs) == (L.FABX_MODE_DTW, L.FABX_PREC_BF16_RECHECK,
+                                                                L.FABX_NORM_PATH, 0)
+    assert (o.margin, o.delta, o.fused_cols, o.fused_blocks_per_cu) == (-1.0, -1.0, 0, 0)
+    o2 = fx.make_opts(fused_cols=256, fused_blocks_per_cu=2)
+    assert (o2.fused_cols, o2.fused_blocks_per_cu) == (256, 2)
 
 
 def test_long_items_rejected_in_dtw_mode():

@@ -498,6 +498,23 @@ def test_autotune_tiles_give_identical_counts_and_persist(tmp_path, monkeypatch)
         mode="pooled")["tried"] == []                    # nothing to tune outside the fused kernel
 
 
+def test_forced_fused_configs_equal_default():
+    """Every column width and grid forced through the score options (including
+    persistent grids whose blocks take units from the per-XCD counters, down to
+    one block per CU) gives the per-cell counts of the default, which is exact."""
+    _say("forced fused-kernel configurations")
+    w = workloads.batched_c4(n_groups=24, size_hi=150, centroid_std=0.3, seed=12)
+    feats = w.features.to("cuda")
+    t = fx.Task(fx.Dataset(fx.Context(0), feats, w.offsets, w.attrs), w.on, w.by, w.across)
+    ref = t.score()
+    assert np.array_equal(ref.half_units, oracle_score(w).half_units)
+    for cols, bpc in ((128, 0), (128, 1), (128, 4), (256, 0), (256, 2)):
+        r = t.score(fused_cols=cols, fused_blocks_per_cu=bpc)
+        print(f"  cols {cols} blocks/CU {bpc}: distance {r.stats['ms_distance']:.3f} ms", flush=True)
+        assert (r.stats["fused_cols"], r.stats["fused_blocks_per_cu"]) == (cols, bpc)
+        assert np.array_equal(r.half_units, ref.half_units)
+
+
 # ------------------------------------------------------- stream ordering --
 
 def _slow_producer(dst, src):
