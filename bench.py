@@ -57,6 +57,24 @@ WORKLOADS = {
 SCORE_KW = {}
 
 
+class _NoCyclicGC:
+    """Timed loops run with Python's cyclic garbage collector paused (after a
+    collection), as timeit does: a full collection over torch's objects takes
+    tens of ms and would land inside one step.  The library's objects are freed
+    by reference counting either way."""
+
+    def __enter__(self):
+        import gc
+        gc.collect()
+        self.was = gc.isenabled()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        import gc
+        if self.was:
+            gc.enable()
+
+
 def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True):
     """n steps with host and device work overlapped across steps: while the
     device scores step i (fabx_score_async), the host builds the task of step
@@ -73,9 +91,9 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True)
         st = res.stats           # waits for the score
         return res.collapse(w.levels), st
 
-    t0 = time.perf_counter()
     prev, fut = None, None
-    with cf.ThreadPoolExecutor(max_workers=1) as side:
+    with cf.ThreadPoolExecutor(max_workers=1) as side, _NoCyclicGC():
+        t0 = time.perf_counter()
         for _ in range(n):
             task = fx.Task(ds, w.on, w.by, w.across)
             res = task.score_async(mode=mode, precision=precision, **SCORE_KW)
@@ -105,19 +123,20 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True)
 
 def run_steps(fx, ds, w, precision, n, sync, mode="dtw"):
     stats, errs = [], []
-    t0 = time.perf_counter()
-    for _ in range(n):
-        ta = time.perf_counter()
-        task = fx.Task(ds, w.on, w.by, w.across)
-        tb = time.perf_counter()
-        res = task.score(mode=mode, precision=precision, **SCORE_KW)
-        tc = time.perf_counter()
-        errs.append(res.collapse(w.levels))
-        td = time.perf_counter()
-        st = res.stats
-        st.update(ms_task_build=(tb - ta) * 1e3, ms_score_call=(tc - tb) * 1e3, ms_collapse=(td - tc) * 1e3)
-        stats.append(st)
-    sync()
+    with _NoCyclicGC():
+        t0 = time.perf_counter()
+        for _ in range(n):
+            ta = time.perf_counter()
+            task = fx.Task(ds, w.on, w.by, w.across)
+            tb = time.perf_counter()
+            res = task.score(mode=mode, precision=precision, **SCORE_KW)
+            tc = time.perf_counter()
+            errs.append(res.collapse(w.levels))
+            td = time.perf_counter()
+            st = res.stats
+            st.update(ms_task_build=(tb - ta) * 1e3, ms_score_call=(tc - tb) * 1e3, ms_collapse=(td - tc) * 1e3)
+            stats.append(st)
+        sync()
     return time.perf_counter() - t0, stats, errs
 
 
@@ -339,20 +358,23 @@ def main():
     rows = nf if mode == "dtw" else st0["n_items"]
     norm_bytes = (nf * dim * in_bytes) + rows * dim_pad * 2 + rows * 4
     dist_flops = 2.0 * dim * (st0["dtw_cells"] if mode == "dtw" else st0["n_pairs"])
-    if stages["ms_normalize"] >= stages["ms_distance"]:
-        ach = norm_bytes / (stages["ms_normalize"] / 1e3) / 1e9
+    # kernel durations of the timed (pipelined) steps, HIP events on the stream
+    # the kernels run on; the serial steps (idle GPU between them) run slower
+    pk = {k: float(np.mean([s_[k] for s_ in pstats_])) for k in ("ms_normalize", "ms_distance")}
+    if pk["ms_normalize"] >= pk["ms_distance"]:
+        ach = norm_bytes / (pk["ms_normalize"] / 1e3) / 1e9
         roof = {"kernel": "k_normalize", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_bytes_per_launch": norm_bytes}
+                "algorithmic_bytes_per_launch": norm_bytes, "ms_per_launch": pk["ms_normalize"]}
     else:
-        ach = dist_flops / (stages["ms_distance"] / 1e3) / 1e12
+        ach = dist_flops / (pk["ms_distance"] / 1e3) / 1e12
         traffic = (committed_traffic("paper_2505_02692_amd/csrc/k_fused.hip", "profiles/hbm_bytes_within_c2.md",
                                      st0["fused_cols"], st0["fused_blocks_per_cu"])
                    if (headline and mode == "dtw") else None)
         roof = {"kernel": "k_fused" if mode == "dtw" else "k_gram_angular_bf16", "bound": "mfma",
                 "achieved": ach, "peak": MFMA_BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / MFMA_BF16_PEAK_TFLOPS, "traffic": traffic,
-                "algorithmic_flops_per_launch": dist_flops}
+                "algorithmic_flops_per_launch": dist_flops, "ms_per_launch": pk["ms_distance"]}
 
     serving = None
     if args.serve_jobs > 0 and headline:
@@ -374,6 +396,9 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "ms_per_step_serial": ms_step_serial,
+        # device time (first kernel to per-cell results, HIP events) of the
+        # pipelined steps themselves, median: the part of a step the GPU is busy
+        "gpu_ms_pipelined": float(np.median([s_["ms_total"] for s_ in pstats_])) if pstats_ else None,
         "triplets_per_s_serial": n_trip / (ms_step_serial / 1e3),
         "pipelined": ("host work of neighbouring steps overlaps device work (fabx_score_async)"
                       + ("; the collapse of step i - 1 runs on a second host thread beside the build of "
