@@ -256,6 +256,9 @@ typedef struct fabx_stats {
     double delta;               /* path-length window used (BF16 form, DTW; else 0) */
     int32_t fused_cols;         /* fused kernel column block width used (BF16 DTW; else 0) */
     int32_t fused_blocks_per_cu;/* its grid: blocks per CU, 0 = one block per work unit */
+    int64_t dtw_cells_sym;      /* sum over the unordered pairs {x, y} of which some cell needs
+                                   (x, y) or (y, x) of len(x) * len(y): the DTW cells needed
+                                   when each pair's DTW, which is symmetric, is evaluated once */
 } fabx_stats;
 
 int fabx_result_stats(const fabx_result *res, fabx_stats *stats);

@@ -50,7 +50,8 @@ class fabx_stats(ctypes.Structure):
         "n_nonrobust_pairs", "n_recheck_pairs", "n_recount_rows", "workspace_bytes")] + \
         [(n, ctypes.c_double) for n in ("ms_total", "ms_normalize", "ms_distance", "ms_triplets",
                                          "ms_recheck", "ms_host_setup", "ms_host_finish", "margin", "delta")] + \
-        [("fused_cols", ctypes.c_int32), ("fused_blocks_per_cu", ctypes.c_int32)]
+        [("fused_cols", ctypes.c_int32), ("fused_blocks_per_cu", ctypes.c_int32),
+         ("dtw_cells_sym", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

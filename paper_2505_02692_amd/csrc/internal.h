@@ -225,10 +225,18 @@ struct ColPlan {
     int cols = 0;
     hvec<int32_t> cb;                    // [n_cb][4] = group, first item (task), n items, n frames
     std::vector<int32_t> g_cb0, g_ncb;   // per group: first column block, count
-    hvec<int64_t> unit_prefix;           // per group: work units prefix [n_groups + 1]
+    // Work units: the (row block, column block) pairs of a group whose column
+    // block ends after the row block's first item.  A group's pair matrix is
+    // symmetric, so the units wholly below its diagonal are not computed: the
+    // kernel writes each pair (x, y) with x before y, or x = y, at both (x, y)
+    // and (y, x).  Per row block: its first kept column block (counted in the
+    // group) and the prefix of kept units over all row blocks.
+    hvec<int32_t> rb_cstart;             // [n_rb]
+    hvec<int64_t> rb_unit_prefix;        // [n_rb + 1]
+    int64_t cells = 0;                   // frame pairs the kept units cover
     DevBuf dev;                          // device copy of the above, made on first use
-    const int32_t *d_cb = nullptr, *d_g_cb0 = nullptr, *d_g_ncb = nullptr;
-    const int64_t *d_unit_prefix = nullptr;
+    const int32_t *d_cb = nullptr, *d_g_cb0 = nullptr, *d_rb_cstart = nullptr;
+    const int64_t *d_rb_unit_prefix = nullptr;
 };
 
 struct TaskImpl {
@@ -271,6 +279,7 @@ struct TaskImpl {
     int64_t n_dmat = 0;             // sum over groups of n_frames^2
     int64_t n_pairs_needed = 0;     // unique ordered pairs some cell uses
     int64_t dtw_cells_needed = 0;   // sum of len(x) * len(y) over those pairs
+    int64_t dtw_cells_sym = 0;      // the same over unordered pairs {x, y} needed in either order
     int64_t total_triplets = 0;
     int max_len = 0;
 

@@ -212,11 +212,10 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                                                   const int64_t *__restrict__ item_dst,
                                                   const int32_t *__restrict__ rb,
                                                   const int32_t *__restrict__ cb,
-                                                  const int64_t *__restrict__ unit_prefix,
-                                                  const int32_t *__restrict__ g_rb0,
+                                                  const int64_t *__restrict__ rb_unit_prefix,
                                                   const int32_t *__restrict__ g_cb0,
-                                                  const int32_t *__restrict__ g_ncb,
-                                                  int64_t n_groups, int64_t n_units, int64_t grid_q,
+                                                  const int32_t *__restrict__ rb_cstart,
+                                                  int64_t n_rb, int64_t n_units, int64_t grid_q,
                                                   float delta, float *__restrict__ p32,
                                                   uint8_t *__restrict__ flags,
                                                   unsigned int *__restrict__ nonrobust_n,
@@ -251,10 +250,11 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const int64_t unit = xcd * grid_q + j;
     if (unit >= n_units) break;  // uniform across the block; later units are larger
 
-    const int64_t g = dev::find_segment_wave(unit_prefix, n_groups, unit);
-    const int64_t local = unit - unit_prefix[g];
-    const int ncb = g_ncb[g];
-    const int rbi = g_rb0[g] + int(local / ncb), cbi = g_cb0[g] + int(local % ncb);
+    // the unit's row block, its group, and its column block (the row block's
+    // units are its group's column blocks from rb_cstart on)
+    const int64_t rbi = dev::find_segment_wave(rb_unit_prefix, n_rb, unit);
+    const int64_t g = rb[4 * rbi];
+    const int cbi = g_cb0[g] + rb_cstart[rbi] + int(unit - rb_unit_prefix[rbi]);
     const int r_item0 = rb[4 * rbi + 1], r_nitems = rb[4 * rbi + 2], r_frames = rb[4 * rbi + 3];
     const int c_item0 = cb[4 * cbi + 1], c_nitems = cb[4 * cbi + 2], c_frames = cb[4 * cbi + 3];
     const int64_t r_frame0 = item_dst[r_item0], c_frame0 = item_dst[c_item0];
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const float top_pen = top ? kInf : 0.0f;
     const float diag_first = top ? 0.0f : kInf;       // virtual c[-1][-1] = 0 at an item start
     const uint32_t pd_first = top ? 0x0000FFFFu : 0u;  // its length interval: Lmin = Lmax = 0
-    const int64_t x_row = row_valid ? (int64_t(x_task) - gitem0) * gn : 0;
+    const int64_t px = row_valid ? int64_t(x_task) - gitem0 : 0;  // row item's position in the group
     // at step t the lane is on column t - ir of the wave's span: distance
     // dcol[t], flags fcol[t], read a pair of steps ahead.  ir <= lane, so dcol[0]
     // is inside the tile; the last read-ahead is at most max_n <= 64 columns past
@@ -385,16 +385,32 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
         c = dv + m;
         up_prev = up;
         Pup_prev = Pup;
+        // Pair (x, y) of the group, x the row item: kept when x comes before y
+        // (or is y) and written at (x, y) and (y, x), the distance being
+        // symmetric (a pair whose path length is ambiguous is flagged in both
+        // slots and recomputed in FP64 in each orientation).  Each slot has one
+        // writer: the pairs with x after y are written by the unit holding
+        // (y, x).
         if (cf >= out_min) {
-            const int64_t slot = pbase + x_row + (int64_t(c_item0) + ((cf >> 1) & 0x3FFF) - gitem0);
-            if (kPath) {
-                const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
-                p32[slot] = c * __builtin_amdgcn_rcpf(float(lmin));
-                flags[slot] = lmin == lmax ? 0 : 1;
-                if (lmin != lmax) atomicAdd(nonrobust_n, 1u);
-            } else {
-                p32[slot] = c;
-                flags[slot] = 0;
+            const int64_t py = int64_t(c_item0) + ((cf >> 1) & 0x3FFF) - gitem0;
+            if (px <= py) {
+                const int64_t slot = pbase + px * gn + py, mirror = pbase + py * gn + px;
+                float v;
+                uint8_t fl = 0;
+                if (kPath) {
+                    const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
+                    v = c * __builtin_amdgcn_rcpf(float(lmin));
+                    fl = lmin == lmax ? 0 : 1;
+                    if (fl) atomicAdd(nonrobust_n, px < py ? 2u : 1u);
+                } else {
+                    v = c;
+                }
+                p32[slot] = v;
+                flags[slot] = fl;
+                if (px < py) {
+                    p32[mirror] = v;
+                    flags[mirror] = fl;
+                }
             }
         }
     };
@@ -478,14 +494,14 @@ void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_
     const dim3 grid(unsigned(8 * per_xcd)), block(256);
     if (norm == FABX_NORM_PATH)
         hipLaunchKernelGGL((k_fused<kC, true>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
-                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.g_rb0,
-                           plan.g_cb0, plan.g_ncb, g.n_groups, plan.n_units, q, delta, p32, flags,
-                           nonrobust_n, unit_ctr);
+                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.rb_unit_prefix, plan.g_cb0,
+                           plan.rb_cstart, plan.n_rb, plan.n_units, q, delta, p32, flags, nonrobust_n,
+                           unit_ctr);
     else
         hipLaunchKernelGGL((k_fused<kC, false>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
-                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.g_rb0,
-                           plan.g_cb0, plan.g_ncb, g.n_groups, plan.n_units, q, delta, p32, flags,
-                           nonrobust_n, unit_ctr);
+                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.rb_unit_prefix, plan.g_cb0,
+                           plan.rb_cstart, plan.n_rb, plan.n_units, q, delta, p32, flags, nonrobust_n,
+                           unit_ctr);
 }
 
 }  // namespace

@@ -68,9 +68,11 @@ void dtw_plain(hipStream_t s, const float *dmat, const GroupTables &g, const Ite
 struct FusedPlan {
     const int32_t *rb;        // row blocks: [n_rb][4] = group, first item (task), n items, n frames
     const int32_t *cb;        // col blocks: same layout
-    const int64_t *unit_prefix;  // per group: work units (rb x cb) prefix, n_groups + 1
-    const int32_t *g_rb0, *g_cb0;  // per group: first row / col block, and counts
-    const int32_t *g_nrb, *g_ncb;
+    const int64_t *rb_unit_prefix;  // per row block: prefix of its work units, n_rb + 1
+    const int32_t *g_cb0;       // per group: first column block
+    const int32_t *rb_cstart;   // per row block: its first column block (counted in the group);
+                                // the units of a row block are its group's column blocks from there
+    int64_t n_rb;
     int64_t n_units;
     int cols;            // column block width the blocks were packed for: 128 or 256
     int blocks_per_cu;   // persistent grid of blocks_per_cu * n_cu blocks; 0: one block per unit

@@ -216,6 +216,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     st.n_frames = t.n_frames;
     st.n_pairs = t.n_pairs_needed;
     st.dtw_cells = p.mode == FABX_MODE_DTW ? t.dtw_cells_needed : 0;
+    st.dtw_cells_sym = p.mode == FABX_MODE_DTW ? t.dtw_cells_sym : 0;
     st.margin = p.precision == FABX_PREC_BF16_RECHECK ? p.margin : 0.0;
     st.delta = p.precision == FABX_PREC_BF16_RECHECK && p.mode == FABX_MODE_DTW ? p.delta : 0.0;
     if (n_cells == 0) return res;
@@ -261,13 +262,14 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         st.fused_blocks_per_cu = fcfg.blocks_per_cu;
     }
     auto add_col_plan = [](Packer &pc, ColPlan &cp) {
-        return std::array<size_t, 4>{pc.add(cp.cb), pc.add(cp.unit_prefix), pc.add(cp.g_cb0), pc.add(cp.g_ncb)};
+        return std::array<size_t, 4>{pc.add(cp.cb), pc.add(cp.rb_unit_prefix), pc.add(cp.g_cb0),
+                                     pc.add(cp.rb_cstart)};
     };
     auto set_col_plan = [](ColPlan &cp, const DevBuf &buf, const std::array<size_t, 4> &o) {
         cp.d_cb = Packer::at<int32_t>(buf, o[0]);
-        cp.d_unit_prefix = Packer::at<int64_t>(buf, o[1]);
+        cp.d_rb_unit_prefix = Packer::at<int64_t>(buf, o[1]);
         cp.d_g_cb0 = Packer::at<int32_t>(buf, o[2]);
-        cp.d_g_ncb = Packer::at<int32_t>(buf, o[3]);
+        cp.d_rb_cstart = Packer::at<int32_t>(buf, o[3]);
     };
     if (!dv.uploaded) {
         // one DMA for the task's tables (and the column plan this score uses)
@@ -388,13 +390,13 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         kern::dtw_plain(stream, ws.dmat.as<float>(), gt, it, p.dtw_norm, ws.p32.as<float>());
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw) {
-        kern::FusedPlan fp{dv.rb, cplan->d_cb, cplan->d_unit_prefix, dv.g_rb0, cplan->d_g_cb0, nullptr,
-                           cplan->d_g_ncb, cplan->unit_prefix.back(), fcfg.cols, fcfg.blocks_per_cu,
-                           ds.ctx->n_cu};
+        kern::FusedPlan fp{dv.rb, cplan->d_cb, cplan->d_rb_unit_prefix, cplan->d_g_cb0, cplan->d_rb_cstart,
+                           int64_t(t.rb.size() / 4), cplan->rb_unit_prefix.back(), fcfg.cols,
+                           fcfg.blocks_per_cu, ds.ctx->n_cu};
         kern::fused_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt, it, fp,
                          p.dtw_norm, float(p.delta), ws.p32.as<float>(), ws.flags.as<uint8_t>(),
                          nonrobust_n, unit_ctr);
-        st.computed_dtw_cells = t.fused_cells;
+        st.computed_dtw_cells = cplan->cells;
     } else if (!bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.item0, gt.n_items, gt.pair_base,
                                tiles_p, G, tiles.back(), ws.p32.as<float>());

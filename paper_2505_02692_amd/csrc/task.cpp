@@ -203,7 +203,7 @@ void parallel_for(int n, F &&f) {
 // at the share's offsets.
 struct Sink {
     size_t n_cells = 0, n_unit_ints = 0, n_big_unit_ints = 0, n_groups = 0;
-    int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, pair_slots = 0, sum_nx = 0;
+    int64_t total_triplets = 0, pairs_needed = 0, dtw_needed = 0, dtw_sym = 0, pair_slots = 0, sum_nx = 0;
     // write pass: destinations, and the share's first cell / unit int / group / pair slot
     CellDev *cells = nullptr;
     int64_t *ntrip = nullptr;
@@ -402,22 +402,43 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
                     out.dtw_needed += frames(ix) * frames(iy);
                 }
             };
+            // unordered class pair {ix, iy} (ix <= iy) needed in either order
+            auto count_sym = [&](int64_t ix, int64_t iy) {
+                out.dtw_sym += ix == iy ? (frames(ix) * frames(ix) - sq(ix)) / 2 : frames(ix) * frames(iy);
+            };
             if (w.n_across == 0) {
                 // every item of a class with >= 2 items is an x; it needs every other item
                 const int64_t all_items = g1 - g0, all_frames = pf[g1] - pf[g0];
+                const int64_t all_sq = pq[g1] - pq[g0];
+                int64_t single_frames = 0, single_sq = 0;  // items of one-item classes
                 for (int64_t ix = 0; ix < K; ++ix) {
-                    if (cnt(ix) < 2) continue;
+                    if (cnt(ix) < 2) {
+                        single_frames += frames(ix);
+                        single_sq += sq(ix);
+                        continue;
+                    }
                     out.pairs_needed += cnt(ix) * (all_items - 1);
                     out.dtw_needed += frames(ix) * all_frames - sq(ix);
                 }
+                // unordered pairs of distinct items with at least one in a class of >= 2
+                out.dtw_sym += (all_frames * all_frames - all_sq) / 2 -
+                               (single_frames * single_frames - single_sq) / 2;
             } else if (use_need) {
                 for (int64_t ix = 0; ix < K; ++ix)
                     for (int64_t iy = 0; iy < K; ++iy)
                         if (need[size_t(ix * K + iy)]) count_pair(ix, iy);
+                for (int64_t ix = 0; ix < K; ++ix)
+                    for (int64_t iy = ix; iy < K; ++iy)
+                        if (need[size_t(ix * K + iy)] || need[size_t(iy * K + ix)]) count_sym(ix, iy);
             } else {
                 std::sort(need_list.begin(), need_list.end());
                 need_list.erase(std::unique(need_list.begin(), need_list.end()), need_list.end());
                 for (auto &pr : need_list) count_pair(pr.first, pr.second);
+                for (auto &pr : need_list)
+                    if (pr.first > pr.second) std::swap(pr.first, pr.second);
+                std::sort(need_list.begin(), need_list.end());
+                need_list.erase(std::unique(need_list.begin(), need_list.end()), need_list.end());
+                for (auto &pr : need_list) count_sym(pr.first, pr.second);
             }
         }
         g0 = g1;
@@ -464,6 +485,49 @@ void cell_keys(const TaskImpl &t, int32_t *out) {
     });
 }
 
+// Kept work units of a column plan (see ColPlan): for each row block, the
+// first column block of its group that ends after the row block's first item
+// (a suffix of the group's column blocks; row blocks ascend, so one pointer
+// per group walks the column blocks), the prefix of kept units, and the frame
+// pairs they cover.
+void plan_units(const TaskImpl &t, ColPlan &cp) {
+    const int64_t G = int64_t(t.groups.size());
+    const size_t n_rb = t.rb.size() / 4;
+    cp.rb_cstart.resize(n_rb);
+    cp.rb_unit_prefix.resize(n_rb + 1);
+    cp.rb_unit_prefix[0] = 0;
+    const int64_t kGroups = 2048;
+    const int n_gc = int((G + kGroups - 1) / kGroups);
+    std::vector<int64_t> part_cells(static_cast<size_t>(std::max(n_gc, 1)), 0);
+    parallel_for(n_gc, [&](int c) {
+        int64_t cells = 0;
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
+            const size_t r0 = size_t(t.g_rb0[size_t(gi)]), c0 = size_t(cp.g_cb0[size_t(gi)]);
+            const int32_t nr = t.g_nrb[size_t(gi)], nc = cp.g_ncb[size_t(gi)];
+            int64_t suffix = 0;  // frames of column blocks [k, nc)
+            for (int32_t k = 0; k < nc; ++k) suffix += cp.cb[4 * (c0 + size_t(k)) + 3];
+            int32_t k = 0;
+            for (int32_t r = 0; r < nr; ++r) {
+                const int32_t *rbe = t.rb.data() + 4 * (r0 + size_t(r));
+                const int32_t ri0 = rbe[1];
+                while (k < nc) {
+                    const int32_t *cbe = cp.cb.data() + 4 * (c0 + size_t(k));
+                    if (cbe[1] + cbe[2] > ri0) break;   // ends after the row block starts: kept
+                    suffix -= cbe[3];
+                    ++k;
+                }
+                cp.rb_cstart[r0 + size_t(r)] = k;
+                cp.rb_unit_prefix[r0 + size_t(r) + 1] = nc - k;
+                cells += int64_t(rbe[3]) * suffix;
+            }
+        }
+        part_cells[size_t(c)] = cells;
+    });
+    for (size_t i = 0; i < n_rb; ++i) cp.rb_unit_prefix[i + 1] += cp.rb_unit_prefix[i];
+    cp.cells = 0;
+    for (int64_t v : part_cells) cp.cells += v;
+}
+
 ColPlan &col_plan(TaskImpl &t, int cols) {
     for (auto &p : t.col_plans)
         if (p->cols == cols) return *p;
@@ -478,19 +542,17 @@ ColPlan &col_plan(TaskImpl &t, int cols) {
         for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
             cp->g_ncb[size_t(gi)] = pack_blocks(t, gi, cols, nullptr);
     });
-    cp->unit_prefix.assign(size_t(G) + 1, 0);
     int32_t total = 0;
     for (int64_t gi = 0; gi < G; ++gi) {
         cp->g_cb0[size_t(gi)] = total;
         total += cp->g_ncb[size_t(gi)];
-        cp->unit_prefix[size_t(gi) + 1] =
-            cp->unit_prefix[size_t(gi)] + int64_t(t.g_nrb[size_t(gi)]) * cp->g_ncb[size_t(gi)];
     }
     cp->cb.resize(4 * size_t(total));
     parallel_for(n_gc, [&](int c) {
         for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
             pack_blocks(t, gi, cols, cp->cb.data() + 4 * size_t(cp->g_cb0[size_t(gi)]));
     });
+    plan_units(t, *cp);
     t.col_plans.push_back(std::move(cp));
     return *t.col_plans.back();
 }
@@ -755,6 +817,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         t->total_triplets += p.total_triplets;
         t->n_pairs_needed += p.pairs_needed;
         t->dtw_cells_needed += p.dtw_needed;
+        t->dtw_cells_sym += p.dtw_sym;
     }
     t->n_pair_slots = n_slots;
     t->cells.resize(n_cells);
@@ -878,15 +941,12 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     tr.mark("blocks.count");
     t->g_rb0.assign(size_t(G), 0);
     t->g_nrb.assign(nrb.begin(), nrb.end());
-    cp->unit_prefix.assign(size_t(G) + 1, 0);
     int32_t rb_total = 0, cb_total = 0;
     for (int64_t gi = 0; gi < G; ++gi) {
         t->g_rb0[size_t(gi)] = rb_total;
         cp->g_cb0[size_t(gi)] = cb_total;
         rb_total += nrb[size_t(gi)];
         cb_total += cp->g_ncb[size_t(gi)];
-        cp->unit_prefix[size_t(gi) + 1] = cp->unit_prefix[size_t(gi)] + int64_t(nrb[size_t(gi)]) * cp->g_ncb[size_t(gi)];
-        t->fused_cells += t->groups[size_t(gi)].n_frames * t->groups[size_t(gi)].n_frames;
     }
     tr.mark("blocks.prefix");
     t->rb.resize(4 * size_t(rb_total));
@@ -897,6 +957,8 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
             pack_blocks(*t, gi, kFusedColFrames, cp->cb.data() + 4 * size_t(cp->g_cb0[size_t(gi)]));
         }
     });
+    plan_units(*t, *cp);
+    t->fused_cells = cp->cells;
     t->col_plans.push_back(std::move(cp));
     t->n_frames = frame;
     tr.mark("blocks.write");

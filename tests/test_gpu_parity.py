@@ -498,6 +498,33 @@ def test_autotune_tiles_give_identical_counts_and_persist(tmp_path, monkeypatch)
         mode="pooled")["tried"] == []                    # nothing to tune outside the fused kernel
 
 
+@pytest.mark.parametrize("make", [
+    lambda: workloads.within_c2(n_items=3000, dim=64, n_labels=8, n_speakers=6, seed=21),
+    lambda: workloads.across_c3(n_items=3000, dim=64, n_labels=8, n_speakers=6, seed=22),
+])
+def test_needed_pair_counts_match_oracle(make):
+    """n_pairs, dtw_cells (ordered pairs some cell needs) and dtw_cells_sym
+    (unordered pairs needed in either order, the cells of a symmetric
+    evaluation) against the pairs the oracle's cells use."""
+    w = make()
+    _say(f"needed pairs {w.name}")
+    _, res = gpu_score(w)
+    orc = oracle_score(w)
+    lens = np.diff(np.asarray(w.offsets))
+    n_pairs = dtw = sym = 0
+    for items, M in orc.groups.values():
+        i, j = np.nonzero(~np.isnan(M))
+        n_pairs += len(i)
+        dtw += int(np.sum(lens[items[i]] * lens[items[j]]))
+        a, b = np.minimum(i, j), np.maximum(i, j)
+        u = np.unique(a * len(items) + b)
+        sym += int(np.sum(lens[items[u // len(items)]] * lens[items[u % len(items)]]))
+    st = res.stats
+    print(f"  pairs {n_pairs} dtw {dtw} sym {sym} computed {st['computed_dtw_cells']}", flush=True)
+    assert (st["n_pairs"], st["dtw_cells"], st["dtw_cells_sym"]) == (n_pairs, dtw, sym)
+    assert sym <= st["computed_dtw_cells"] <= dtw + sum(int(lens[it].sum()) ** 2 for it, _ in orc.groups.values())
+
+
 def test_forced_fused_configs_equal_default():
     """Every column width and grid forced through the score options (including
     persistent grids whose blocks take units from the per-XCD counters, down to
