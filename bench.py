@@ -12,7 +12,8 @@ BF16-MFMA + FP64-recheck form; the plain FP32 form is timed beside it on the
 same data.  A short serving stream (jobs of 1k-50k items, dims 256-1280,
 within / across, Poisson arrivals) reports p50 / p99 job latency.
 
-Prints one JSON line ("Measurement").
+Prints one JSON line: the metric and its value, the step time, device time,
+the roofline of the dominant kernel and a CPU baseline of the oracle.
 """
 from __future__ import annotations
 
@@ -279,7 +280,7 @@ def main():
         args.warmup = 10 if args.workload == "c2" else 1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the ABX hot path here is "
-              "single-GPU; see DESIGN.md for how it would shard across GPUs.", file=sys.stderr)
+              "single-GPU (it would shard by BY groups, each GPU scoring its groups' cells).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -409,7 +410,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
-        "data": "synthetic (seeded Gaussian SSL-like features, see DESIGN.md)",
+        "data": "synthetic (seeded Gaussian SSL-like features: label centroid + speaker offset + frame noise)",
         "config": {"workload": wl_desc,
                    "cells": st0["n_cells"], "triplets": n_trip, "dtw_cells": st0["dtw_cells"],
                    "dtw_cells_unordered": st0["dtw_cells_sym"],

@@ -18,7 +18,7 @@ Every function follows a passage of the paper (Poli, Chemla, Dupoux,
 * ``collapse``         -- the weighted average of D_C, or averaging across
                           attributes level by level (Score / collapse).
 
-Readings where the paper is silent (all listed in the design doc):
+Readings where the paper is silent:
 a == x is excluded when A and X are the same set; cells are ordered (o1, o2);
 with several ACROSS attributes x differs from a in every one of them; the DTW
 boundary is the cumulative first row / column; the path length used for

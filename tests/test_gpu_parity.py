@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars ("Parity"):
+Bars:
 * BF16 + FP64-recheck form: per-cell half-unit counts W equal the oracle's
   exactly (near ties are re-decided in FP64), hence identical ABX error.
 * plain FP32 form: ABX error within 1e-4 absolute of the oracle, per-cell
