@@ -118,11 +118,12 @@ struct Chunk {
 // past nc skip their MFMAs, and so does the second row half when nr <= 32
 // (those accumulators are never read).  Every product accumulates its K
 // range in the same order whatever the tile width, so results do not depend
-// on it.  `stash` runs once, after the first chunk is stored and before the
+// on it.  Column tiles wholly below c_lo (columns nobody reads) skip their
+// MFMAs too.  `stash` runs once, after the first chunk is stored and before the
 // barrier that publishes it, so LDS it writes is visible to the epilogue.
 template <int kC, typename Stash>
 __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__restrict__ xn, int dim_pad,
-                                          int64_t r0, int nr, int64_t c0, int nc,
+                                          int64_t r0, int nr, int64_t c0, int nc, int c_lo,
                                           f32x16 (&acc)[2][Tile<kC>::kCT], Stash &&stash) {
     using T = Tile<kC>;
     const int lane = threadIdx.x % kWave;
@@ -149,7 +150,7 @@ __device__ __forceinline__ void gram_tile(uint16_t *smem, const uint16_t *__rest
 #pragma unroll
         for (int ct = 0; ct < T::kCT; ++ct) {
             const int col0 = T::kWaveCols * w + 32 * ct;
-            if (col0 < nc) {
+            if (col0 < nc && col0 + 32 > c_lo) {
 #pragma unroll
                 for (int ks = 0; ks < kKc / 16; ++ks) {
                     const int kk = ks * 16 + (lane / 32) * 8;
@@ -262,9 +263,15 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     // 1. Gram tile
     NormStage<kC> ns;
     ns.load(rinv, r_frame0, r_frames, c_frame0, c_frames);
+    // column items before the row block's first item pair only with rows after
+    // them, which other units write: their columns (the first c_skip of the
+    // block) are not needed
+    const int k_first = max(0, r_item0 - c_item0);
+    int c_skip = 0;
+    for (int k = 0; k < min(k_first, c_nitems); ++k) c_skip += item_len[c_item0 + k];
     f32x16 acc[2][T::kCT];
     gram_tile<kC>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
-                  c_frames, acc, [&] { ns.store(norm_s); });
+                  c_frames, c_skip, acc, [&] { ns.store(norm_s); });
 
     // 2. epilogue -> LDS distance tile (the staging buffers are dead now).  Only
     // the rows and column waves that hold frames are written; the DTW reads the
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
 #pragma unroll
     for (int ct = 0; ct < T::kCT; ++ct) {
         const int col0 = T::kWaveCols * w + 32 * ct;
-        if (col0 >= c_frames) continue;
+        if (col0 >= c_frames || col0 + 32 <= c_skip) continue;
         const int col = col0 + lane % 32;
         const float rc = norm_s[kRows + col];
 #pragma unroll
@@ -305,14 +312,20 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     }
     int max_n = 0;
     for (int k = 0; k < r_nitems; ++k) max_n = max(max_n, item_len[r_item0 + k]);
-    // this wave's column items: those whose first frame falls in its quarter
+    // this wave's column items: those whose first frame falls in its quarter of
+    // the needed columns (from item k_first on).  A lane reads distances at most
+    // 63 columns left of its span's start only in steps whose cells are never
+    // used (an item's first column resets the left and diagonal neighbours);
+    // those columns may hold stale values when their tiles were skipped.
     int y_begin = 0, y_end = 0, s_begin = 0, s_end = 0;
     {
-        int start = 0;
+        const int skip = c_skip;
+        const int kept = max(c_frames - skip, 1);
+        int start = skip;
         bool seen = false;
-        for (int k = 0; k < c_nitems; ++k) {
+        for (int k = k_first; k < c_nitems; ++k) {
             const int L = item_len[c_item0 + k];
-            const int owner = (4 * start) / max(c_frames, 1);
+            const int owner = (4 * (start - skip)) / kept;
             if (owner == w) {
                 if (!seen) { y_begin = k; s_begin = start; seen = true; }
                 y_end = k + 1;
@@ -346,9 +359,13 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const bool row_valid = x_task >= 0;
     const bool top = ir == 0;
     const bool last_row = row_valid && ir == nx - 1;
-    // The first row of an item has no row above: it adds +inf to the cost it
-    // receives from lane - 1 (a row of another item, or nothing for lane 0).
-    const float top_pen = top ? kInf : 0.0f;
+    // The first row of an item has no row above.  The lane above it (the last
+    // row of another item, or a row past the block's frames) sends +inf
+    // instead of its cost: that lane may be on columns outside its span, where
+    // the tile holds values of no use (possibly stale LDS), so its cost must
+    // not be combined.  Lane 0 has no lane above: it reads 0 and adds +inf.
+    const bool send_inf = !row_valid || ir == nx - 1;
+    const float lane0_pen = lane == 0 ? kInf : 0.0f;
     const float diag_first = top ? 0.0f : kInf;       // virtual c[-1][-1] = 0 at an item start
     const uint32_t pd_first = top ? 0x0000FFFFu : 0u;  // its length interval: Lmin = Lmax = 0
     const int64_t px = row_valid ? int64_t(x_task) - gitem0 : 0;  // row item's position in the group
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const int steps = S + max_n - 1;
     auto step = [&](const uint32_t cf, const float dv) {
         const bool first = cf & 1;
-        up = shr1z(c) + top_pen;
+        up = shr1z(send_inf ? kInf : c) + lane0_pen;
         if (kPath) Pup = shr1u(Pup, P);
         const float diag = first ? diag_first : up_prev;
         const float left = first ? kInf : c;
@@ -458,7 +475,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     NormStage<128> ns;
     ns.load(rinv, row0[g] + r0, nr, row0[g] + c0, nc);
     f32x16 acc[2][1];
-    gram_tile<128>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc,
+    gram_tile<128>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc, 0,
                    acc, [&] { ns.store(norm_s); });
     const f32x16 &acc0 = acc[0][0], &acc1 = acc[1][0];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
