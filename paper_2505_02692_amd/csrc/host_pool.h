@@ -13,6 +13,7 @@
 #include <sys/resource.h>
 #include <thread>
 #include <type_traits>
+#include <unistd.h>
 #include <utility>
 #include <vector>
 
@@ -21,8 +22,10 @@ namespace fabx {
 // Process-wide cache of large host blocks.  Task tables and builder / collapse
 // scratch are rebuilt for every task; keeping their freed blocks mapped lets
 // the next task of similar size reuse them without page faults.  Blocks are
-// rounded up to size classes (four per power of two); at most kCap bytes stay
-// cached, the rest go back to the system allocator.
+// rounded up to size classes (four per power of two); at most a quarter of
+// the physical memory (between 2 and 32 GiB) stays cached, the rest goes back
+// to the system allocator.  A pipelined caller keeps a few tasks alive at once,
+// each with its per-cell arrays (about 80 bytes per cell).
 class HostBlockCache {
 public:
     static HostBlockCache &get() {
@@ -52,7 +55,7 @@ public:
         const int k = size_class(bytes);
         {
             std::lock_guard<std::mutex> lk(mu_);
-            if (cached_ + class_bytes(k) <= kCap) {
+            if (cached_ + class_bytes(k) <= cap_) {
                 free_[size_t(k)].push_back(p);
                 cached_ += class_bytes(k);
                 return;
@@ -67,7 +70,11 @@ public:
 
 private:
     static constexpr size_t kMin = size_t(64) << 10;
-    static constexpr size_t kCap = size_t(2) << 30;
+    const size_t cap_ = [] {
+        const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGESIZE);
+        const size_t phys = pages > 0 && page > 0 ? size_t(pages) * size_t(page) : 0;
+        return std::min(std::max(phys / 4, size_t(2) << 30), size_t(32) << 30);
+    }();
     // class k covers (class_bytes(k - 1), class_bytes(k)]; sizes 64 KiB * 2^(k/4) * (1 + (k%4)/4)
     static size_t class_bytes(int k) { return (kMin << (k / 4)) / 4 * size_t(4 + k % 4); }
     static int size_class(size_t bytes) {
