@@ -76,14 +76,17 @@ class _NoCyclicGC:
             gc.enable()
 
 
-def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True):
+def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch"):
     """n steps with host and device work overlapped across steps: while the
-    device scores step i (fabx_score_async), the host builds the task of step
-    i + 1 and collapses the result of step i - 1.  With side_collapse the
-    collapse (and the wait for its result) runs on a second host thread, beside
-    the next build; the library's thread pool runs a region issued while
-    another thread's region is active in place on the issuing thread.  Every
-    step still runs the whole path on its own task."""
+    device scores step i, the host builds the task of step i + 1 and collapses
+    the result of step i - 1.  `side` picks what runs on a second host thread:
+    "launch" (default) leaves the main thread only the task builds, the side
+    thread enqueueing each step's score (fabx_score_async) and then waiting for
+    and collapsing the step before it; "collapse" keeps the launch on the main
+    thread; "none" runs everything on the main thread.  The library's thread
+    pool runs a region issued while another thread's region is active in place
+    on the issuing thread.  Every step still runs the whole path on its own
+    task."""
     import concurrent.futures as cf
 
     stats, errs = [], []
@@ -92,32 +95,42 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side_collapse=True)
         st = res.stats           # waits for the score
         return res.collapse(w.levels), st
 
-    prev, fut = None, None
-    with cf.ThreadPoolExecutor(max_workers=1) as side, _NoCyclicGC():
+    def take(out):
+        if out is not None:
+            errs.append(out[0])
+            stats.append(out[1])
+
+    prev = [None]
+
+    def launch_then_finish_prev(task):
+        res = task.score_async(mode=mode, precision=precision, **SCORE_KW)
+        out = finish(prev[0]) if prev[0] is not None else None
+        prev[0] = res
+        return out
+
+    fut = None
+    with cf.ThreadPoolExecutor(max_workers=1) as pool, _NoCyclicGC():
         t0 = time.perf_counter()
         for _ in range(n):
             task = fx.Task(ds, w.on, w.by, w.across)
+            if side == "launch":
+                if fut is not None:
+                    take(fut.result())
+                fut = pool.submit(launch_then_finish_prev, task)
+                continue
             res = task.score_async(mode=mode, precision=precision, **SCORE_KW)
-            if prev is not None:
-                if side_collapse:
+            if prev[0] is not None:
+                if side == "collapse":
                     if fut is not None:
-                        e, st = fut.result()
-                        errs.append(e)
-                        stats.append(st)
-                    fut = side.submit(finish, prev)
+                        take(fut.result())
+                    fut = pool.submit(finish, prev[0])
                 else:
-                    e, st = finish(prev)
-                    errs.append(e)
-                    stats.append(st)
-            prev = res
+                    take(finish(prev[0]))
+            prev[0] = res
         if fut is not None:
-            e, st = fut.result()
-            errs.append(e)
-            stats.append(st)
-        if prev is not None:
-            e, st = finish(prev)
-            errs.append(e)
-            stats.append(st)
+            take(fut.result())
+        if prev[0] is not None:
+            take(finish(prev[0]))
     sync()
     return time.perf_counter() - t0, stats, errs
 
@@ -267,8 +280,9 @@ def main():
     ap.add_argument("--fused-config", default=None, metavar="COLS,BLOCKS_PER_CU",
                     help="run the fused kernel with this column width and grid (e.g. 128,0) "
                          "instead of autotuning")
-    ap.add_argument("--collapse-inline", action="store_true",
-                    help="pipelined steps collapse on the main thread instead of a second host thread")
+    ap.add_argument("--side", choices=("launch", "collapse", "none"), default="launch",
+                    help="work of the pipelined steps on a second host thread: score launch and "
+                         "collapse (default), collapse only, or none")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
                     help="c2 (default) is the headline workload; c3 / c4 / c4-pooled profile large groups")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -309,7 +323,7 @@ def main():
     ds = fx.Dataset(ctx, w.features, w.offsets, w.attrs)
     log(f"workload {args.workload} ready: {w.n_items} items, {w.n_frames} frames, dim {w.dim}")
 
-    side = not args.collapse_inline
+    side = args.side
     if args.fused_config:
         cols, bpc = (int(v) for v in args.fused_config.split(","))
         SCORE_KW.update(fused_cols=cols, fused_blocks_per_cu=bpc)
@@ -404,8 +418,11 @@ def main():
         "gpu_ms_pipelined": float(np.median([s_["ms_total"] for s_ in pstats_])) if pstats_ else None,
         "triplets_per_s_serial": n_trip / (ms_step_serial / 1e3),
         "pipelined": ("host work of neighbouring steps overlaps device work (fabx_score_async)"
-                      + ("; the collapse of step i - 1 runs on a second host thread beside the build of "
-                         "step i + 1" if side else "")),
+                      + {"launch": "; the main thread builds step i + 1 while a second host thread "
+                                   "launches step i and collapses step i - 1",
+                         "collapse": "; the collapse of step i - 1 runs on a second host thread beside "
+                                     "the build of step i + 1",
+                         "none": ""}[side]),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

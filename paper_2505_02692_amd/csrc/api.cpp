@@ -178,6 +178,18 @@ PinnedPool::~PinnedPool() {
     for (auto &b : free_blocks) (void)hipHostFree(b.second);
 }
 
+PinnedBlock::PinnedBlock(std::shared_ptr<CtxImpl> c, size_t n) : ctx(std::move(c)) {
+    p = ctx->pinned.get(n, &cap);
+}
+
+PinnedBlock::~PinnedBlock() {
+    if (done) {
+        (void)hipEventSynchronize(done);
+        ctx->events.put(done);
+    }
+    if (p) ctx->pinned.put(p, cap);
+}
+
 Staging::~Staging() {
     if (in_flight) (void)hipEventSynchronize(done);
     if (host) (void)hipHostFree(host);
@@ -294,6 +306,7 @@ int fabx_task_create(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_
         if (!ds || !out) fail(FABX_EINVAL, "null argument");
         *out = nullptr;
         auto t = build_task(ds->p, on, by, n_by, across, n_across);
+        prepack_tables(*t);
         *out = new fabx_task{t};
     });
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <cstdint>
 #include <map>
@@ -71,8 +72,6 @@ struct EventPool {
     ~EventPool();
 };
 
-// Pinned host buffer through which a score's tables reach the device with one
-// DMA copy.  One user at a time (the copy is waited for before release).
 // Pinned host buffer that uploads go through.  An upload returns once its DMA
 // is enqueued; the next one waits for that DMA before writing the buffer.
 struct Staging {
@@ -148,6 +147,19 @@ struct CtxImpl {
     ~CtxImpl();
 };
 
+// A block of a context's pinned pool and the last DMA out of it; the block
+// goes back to the pool once that DMA has completed.
+struct PinnedBlock {
+    std::shared_ptr<CtxImpl> ctx;
+    void *p = nullptr;
+    size_t cap = 0, bytes = 0;
+    hipEvent_t done = nullptr;  // from ctx->events, recorded after the DMA
+    PinnedBlock(std::shared_ptr<CtxImpl> c, size_t n);
+    PinnedBlock(const PinnedBlock &) = delete;
+    PinnedBlock &operator=(const PinnedBlock &) = delete;
+    ~PinnedBlock();
+};
+
 struct DatasetImpl {
     std::shared_ptr<CtxImpl> ctx;
     const void *features = nullptr;   // borrowed device pointer
@@ -190,6 +202,15 @@ static_assert(sizeof(CellDev) == 32, "CellDev layout");
 
 // Device copy of the task tables: one buffer, uploaded with one copy on the
 // task's first score; the pointers below point into it.
+// Byte offsets of the task tables in their device buffer.
+struct TableLayout {
+    size_t item_src = 0, item_len = 0, item_dst = 0, item_group = 0;
+    std::array<size_t, 6> g{};  // item0, n_items (+ sentinel), frame0, n_frames, dmat_base, pair_base (+ total)
+    size_t cells = 0, units = 0, rb = 0, g_rb0 = 0;
+    std::array<size_t, 4> plan{};  // cb, rb_unit_prefix, g_cb0, rb_cstart of `plan_cols`
+    int plan_cols = 0;             // 0: no column plan in the buffer
+};
+
 struct TaskDevice {
     DevBuf blob;
     const int64_t *item_src = nullptr, *item_dst = nullptr;
@@ -284,6 +305,10 @@ struct TaskImpl {
     int max_len = 0;
 
     TaskDevice dev;
+    // device tables packed in pinned memory when the task is made (tables up
+    // to a few tens of MB), so that the first score only enqueues their DMA
+    std::unique_ptr<PinnedBlock> packed;
+    TableLayout packed_layout;
     Workspace ws;
     std::mutex mu;                  // one score launch at a time per task
     std::weak_ptr<ResultImpl> pending;  // the score whose kernels may still use ws
@@ -316,6 +341,9 @@ void cell_keys(const TaskImpl &t, int32_t *out);
 // The task's column plan for `cols` (128 or 256), built on first use; the caller
 // holds the task's mutex.
 ColPlan &col_plan(TaskImpl &t, int cols);
+// score.cpp: packs the task's device tables (and its default column plan) into
+// a pinned block of the context, for a task on a device context.
+void prepack_tables(TaskImpl &t);
 std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,
                                      const int32_t *by, int32_t n_by, const int32_t *across,
                                      int32_t n_across);

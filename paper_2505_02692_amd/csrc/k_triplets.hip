@@ -2,12 +2,14 @@
 // the Background section), in integer half units: each triple adds
 // 2 [d(x,a) < d(x,b)] + [d(x,a) == d(x,b)].
 //
-// Work unit = (cell, range of x).  A wave walks the flattened |A| x |B| grid
-// of one x with one (a, b) per lane, so short B sets still fill the wave;
-// both distances come from the row of x in the group's pair matrix (the row
-// is a few hundred bytes and stays in L1/L2).  Counts are reduced in the wave
-// and added once per unit with a 64-bit atomic, so the result does not depend
-// on scheduling.
+// Work unit = (cell, range of x), one wave each.  When |A| x |B| fits the
+// wave, a pass covers as many whole rows x as fit, |A| x |B| lanes per row;
+// otherwise a row's grid is walked in passes of 64 lanes.  Both distances come
+// from the row of x in the group's pair matrix (a few hundred bytes, in L1/L2).
+// A row with a near tie or a non-robust pair is left to the FP64 recount (one
+// ballot per pass finds it); the other rows' counts stay in the lanes and are
+// reduced once per unit, then added with one 64-bit atomic, so the result does
+// not depend on scheduling.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -39,48 +41,84 @@ __global__ __launch_bounds__(256) void k_triplets(const CellDev *__restrict__ ce
     const CellDev c = cells[cell_id];
     const int64_t base = g_pair_base[c.group];
     const int64_t n = g_n[c.group];
-    const int nb = c.nb;
-    const int step_a = kWave / nb, step_b = kWave % nb;
+    const int na = c.na, nb = c.nb;
+    if (na <= 0 || nb <= 0) continue;  // uniform: no comparisons
+    // lane sums of 2 [d_xa < d_xb] + [d_xa == d_xb] over the rows kept
     unsigned long long acc = 0;
-    for (int xi = xb; xi < xe; ++xi) {
-        const int xl = c.x0 + xi;
+    // one comparison of row xl at (al, bl); returns its half units, sets dirty
+    auto compare = [&](int xl, int al, int bl, int &dirty) -> unsigned int {
         const float *row = p32 + base + int64_t(xl) * n;
-        uint8_t *frow = flags ? flags + base + int64_t(xl) * n : nullptr;
-        int a = lane / nb, b = lane % nb;
+        const float da = row[al], db = row[bl];
+        if (flags) {
+            uint8_t *frow = flags + base + int64_t(xl) * n;
+            const uint8_t fa = frow[al], fb = frow[bl];
+            if (fabsf(da - db) <= margin || ((fa | fb) & kNonRobust)) {
+                dirty = 1;
+                if (!(fa & kMarked)) frow[al] = fa | kMarked;
+                if (!(fb & kMarked)) frow[bl] = fb | kMarked;
+            }
+        }
+        return da < db ? 2u : (da == db ? 1u : 0u);
+    };
+    auto push_row = [&](int xi) {
+        const unsigned int k = atomicAdd(recount_n, 1u);
+        if (int64_t(k) < recount_cap) {
+            recount[2 * int64_t(k)] = cell_id;
+            recount[2 * int64_t(k) + 1] = xi;
+        }
+    };
+    const int per_x = na * nb;
+    if (per_x <= kWave) {
+        // `rows` whole rows per pass: lane = r * per_x + (a * nb + b)
+        const int rows = kWave / per_x;
+        const int r = lane / per_x, kk = lane - r * per_x;
+        const int a = kk / nb, b = kk - a * nb;
+        const bool lane_on = r < rows;
+        const unsigned long long seg =
+            lane_on ? (per_x == kWave ? ~0ull : ((1ull << per_x) - 1ull) << (r * per_x)) : 0ull;
+        const int al = c.a0 + a, bl = c.b0 + b;
         unsigned int cnt = 0;
-        int dirty = 0;
-        while (a < c.na) {
-            const int al = c.a0 + a, bl = c.b0 + b;
-            if (!(c.exclude_self && al == xl)) {
-                const float da = row[al], db = row[bl];
-                cnt += da < db ? 2u : (da == db ? 1u : 0u);
-                if (frow) {
-                    const uint8_t fa = frow[al], fb = frow[bl];
-                    if (fabsf(da - db) <= margin || ((fa | fb) & kNonRobust)) {
-                        dirty = 1;
-                        if (!(fa & kMarked)) frow[al] = fa | kMarked;
-                        if (!(fb & kMarked)) frow[bl] = fb | kMarked;
-                    }
+        for (int x0 = xb; x0 < xe; x0 += rows) {
+            const int xi = x0 + r;
+            const bool row_on = lane_on && xi < xe;
+            const int xl = c.x0 + xi;
+            int dirty = 0;
+            unsigned int add = 0;
+            if (row_on && !(c.exclude_self && al == xl)) add = compare(xl, al, bl, dirty);
+            if (flags) {
+                const unsigned long long dmask = __ballot(dirty);
+                if (dmask & seg) {
+                    add = 0;
+                    if (row_on && kk == 0) push_row(xi);
                 }
             }
-            a += step_a;
-            b += step_b;
-            if (b >= nb) { b -= nb; ++a; }
+            cnt += add;
         }
-        const unsigned long long row_total = dev::wave_sum_u64(cnt);
-        if (flags && dev::wave_any(dirty)) {
-            if (lane == 0) {
-                const unsigned int k = atomicAdd(recount_n, 1u);
-                if (int64_t(k) < recount_cap) {
-                    recount[2 * int64_t(k)] = cell_id;
-                    recount[2 * int64_t(k) + 1] = xi;
-                }
+        acc = cnt;
+    } else {
+        // one row at a time, its |A| x |B| grid in passes of 64 lanes
+        const int step_a = kWave / nb, step_b = kWave % nb;
+        for (int xi = xb; xi < xe; ++xi) {
+            const int xl = c.x0 + xi;
+            int a = lane / nb, b = lane % nb;
+            unsigned long long cnt = 0;
+            int dirty = 0;
+            while (a < na) {
+                const int al = c.a0 + a, bl = c.b0 + b;
+                if (!(c.exclude_self && al == xl)) cnt += compare(xl, al, bl, dirty);
+                a += step_a;
+                b += step_b;
+                if (b >= nb) { b -= nb; ++a; }
             }
-            continue;
+            if (flags && dev::wave_any(dirty)) {
+                if (lane == 0) push_row(xi);
+                continue;
+            }
+            acc += cnt;
         }
-        acc += row_total;
     }
-    if (lane == 0 && acc) atomicAdd(&W[cell_id], acc);
+    const unsigned long long total = dev::wave_sum_u64(acc);
+    if (lane == 0 && total) atomicAdd(&W[cell_id], total);
     }
 }
 

@@ -46,12 +46,8 @@ struct Packer {
     }
     template <typename T, typename A>
     size_t add(const std::vector<T, A> &v) { return add(v.data(), v.size()); }
-    void upload(DevBuf &dst, Staging &stg, hipStream_t copy, hipStream_t compute) {
-        dst.ensure(total);
-        std::lock_guard<std::mutex> lk(stg.mu);
-        stg.reserve(total);
-        char *h = static_cast<char *>(stg.host);
-        // host copy into the pinned buffer in 1 MiB slices on the host pool
+    // host copy of all pieces to h [total], in 1 MiB slices on the host pool
+    void copy_to(char *h) const {
         constexpr size_t kSlice = size_t(1) << 20;
         std::vector<std::pair<size_t, size_t>> slices;  // (piece, offset in piece)
         for (size_t i = 0; i < pieces.size(); ++i)
@@ -61,6 +57,13 @@ struct Packer {
             const size_t o = slices[size_t(k)].second;
             std::memcpy(h + p.off + o, static_cast<const char *>(p.src) + o, std::min(kSlice, p.bytes - o));
         });
+    }
+    void upload(DevBuf &dst, Staging &stg, hipStream_t copy, hipStream_t compute) {
+        dst.ensure(total);
+        std::lock_guard<std::mutex> lk(stg.mu);
+        stg.reserve(total);
+        char *h = static_cast<char *>(stg.host);
+        copy_to(h);
         FABX_HIP(hipMemcpyAsync(dst.ptr, h, total, hipMemcpyHostToDevice, copy));
         FABX_HIP(hipEventRecord(stg.done, copy));
         stg.in_flight = true;  // the next upload waits for this DMA before reusing the buffer
@@ -71,6 +74,77 @@ struct Packer {
         return reinterpret_cast<const T *>(b.as<char>() + off);
     }
 };
+
+// Host side of the task tables: adds them (and `plan`, if any) to `pk`; the
+// group columns are built in `gcols`, which must live until the copy is made.
+TableLayout add_task_tables(const TaskImpl &t, const ColPlan *plan, Packer &pk,
+                            std::array<std::vector<int64_t>, 6> &gcols) {
+    const size_t G = t.groups.size();
+    for (auto &v : gcols) v.resize(G);
+    gcols[1].resize(G + 1);
+    gcols[5].resize(G + 1);
+    for (size_t i = 0; i < G; ++i) {
+        const Group &g = t.groups[i];
+        gcols[0][i] = g.item0;
+        gcols[1][i] = g.n_items;
+        gcols[2][i] = g.frame0;
+        gcols[3][i] = g.n_frames;
+        gcols[4][i] = g.dmat_base;
+        gcols[5][i] = g.pair_base;
+    }
+    gcols[1][G] = 0;
+    gcols[5][G] = t.n_pair_slots;
+    TableLayout L;
+    L.item_src = pk.add(t.item_src);
+    L.item_len = pk.add(t.item_len);
+    L.item_dst = pk.add(t.item_dst);
+    L.item_group = pk.add(t.item_group);
+    for (size_t k = 0; k < 6; ++k) L.g[k] = pk.add(gcols[k]);
+    L.cells = pk.add(t.cells);
+    L.units = pk.add(t.units);
+    L.rb = pk.add(t.rb);
+    L.g_rb0 = pk.add(t.g_rb0);
+    if (plan) {
+        L.plan = {pk.add(plan->cb), pk.add(plan->rb_unit_prefix), pk.add(plan->g_cb0),
+                  pk.add(plan->rb_cstart)};
+        L.plan_cols = plan->cols;
+    }
+    return L;
+}
+
+void set_col_plan(ColPlan &cp, const DevBuf &buf, const std::array<size_t, 4> &o) {
+    cp.d_cb = Packer::at<int32_t>(buf, o[0]);
+    cp.d_rb_unit_prefix = Packer::at<int64_t>(buf, o[1]);
+    cp.d_g_cb0 = Packer::at<int32_t>(buf, o[2]);
+    cp.d_rb_cstart = Packer::at<int32_t>(buf, o[3]);
+}
+
+// Device pointers of the task tables in dv.blob (and of the column plan packed
+// with them).
+void set_task_tables(TaskImpl &t, const TableLayout &L) {
+    TaskDevice &dv = t.dev;
+    dv.item_src = Packer::at<int64_t>(dv.blob, L.item_src);
+    dv.item_len = Packer::at<int32_t>(dv.blob, L.item_len);
+    dv.item_dst = Packer::at<int64_t>(dv.blob, L.item_dst);
+    dv.item_group = Packer::at<int32_t>(dv.blob, L.item_group);
+    dv.g_item0 = Packer::at<int64_t>(dv.blob, L.g[0]);
+    dv.g_n = Packer::at<int64_t>(dv.blob, L.g[1]);
+    dv.g_frame0 = Packer::at<int64_t>(dv.blob, L.g[2]);
+    dv.g_nframes = Packer::at<int64_t>(dv.blob, L.g[3]);
+    dv.g_dmat_base = Packer::at<int64_t>(dv.blob, L.g[4]);
+    dv.g_pair_base = Packer::at<int64_t>(dv.blob, L.g[5]);
+    dv.cells = Packer::at<CellDev>(dv.blob, L.cells);
+    dv.units = Packer::at<int32_t>(dv.blob, L.units);
+    dv.rb = Packer::at<int32_t>(dv.blob, L.rb);
+    dv.g_rb0 = Packer::at<int32_t>(dv.blob, L.g_rb0);
+    if (L.plan_cols)
+        for (auto &cp : t.col_plans)
+            if (cp->cols == L.plan_cols && !cp->d_cb) set_col_plan(*cp, dv.blob, L.plan);
+}
+
+// Task tables larger than this are sent through the staging buffer on the
+// first score instead of being packed when the task is made.
+constexpr size_t kPrepackMaxBytes = size_t(64) << 20;
 
 // Gram tile prefix per group for the plain form (64 x 64 tiles of frames) or
 // the pooled mode (64 x 64 FP32 or 64 x 128 BF16 tiles of items).
@@ -173,6 +247,7 @@ struct PendingScore {
     DevBuf plan_d;                 // Gram tile prefix read by the plain / pooled kernels
     void *host = nullptr;          // pinned: half_units [n_cells] then 64 counter bytes
     size_t host_bytes = 0;
+    std::unique_ptr<PinnedBlock> packed;  // the task's packed tables, if this score sent them
     bool bf16 = false, dtw = false, keep_pairs = false;
     std::chrono::steady_clock::time_point t_enter, t_launch;
     ~PendingScore() {
@@ -188,6 +263,27 @@ ResultImpl::~ResultImpl() {
         finish_score(*this);
     } catch (...) {
     }
+}
+
+void prepack_tables(TaskImpl &t) {
+    const std::shared_ptr<CtxImpl> &ctx = t.ds->ctx;
+    if (!ctx || ctx->device < 0 || t.cells.empty()) return;
+    Packer pk;
+    std::array<std::vector<int64_t>, 6> gcols;
+    const ColPlan *plan = t.col_plans.empty() ? nullptr : t.col_plans.front().get();
+    const TableLayout L = add_task_tables(t, plan, pk, gcols);
+    if (pk.total > kPrepackMaxBytes) return;
+    FABX_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<PinnedBlock> blk;
+    try {
+        blk = std::make_unique<PinnedBlock>(ctx, pk.total);
+    } catch (const Error &) {
+        return;  // no pinned memory to spare: the first score sends the tables through the staging buffer
+    }
+    blk->bytes = pk.total;
+    pk.copy_to(static_cast<char *>(blk->p));
+    t.packed = std::move(blk);
+    t.packed_layout = L;
 }
 
 std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,
@@ -261,59 +357,30 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         st.fused_cols = fcfg.cols;
         st.fused_blocks_per_cu = fcfg.blocks_per_cu;
     }
-    auto add_col_plan = [](Packer &pc, ColPlan &cp) {
-        return std::array<size_t, 4>{pc.add(cp.cb), pc.add(cp.rb_unit_prefix), pc.add(cp.g_cb0),
-                                     pc.add(cp.rb_cstart)};
-    };
-    auto set_col_plan = [](ColPlan &cp, const DevBuf &buf, const std::array<size_t, 4> &o) {
-        cp.d_cb = Packer::at<int32_t>(buf, o[0]);
-        cp.d_rb_unit_prefix = Packer::at<int64_t>(buf, o[1]);
-        cp.d_g_cb0 = Packer::at<int32_t>(buf, o[2]);
-        cp.d_rb_cstart = Packer::at<int32_t>(buf, o[3]);
-    };
     if (!dv.uploaded) {
         // one DMA for the task's tables (and the column plan this score uses)
-        Packer pk;
-        const size_t ng = static_cast<size_t>(G);
-        std::vector<int64_t> a(ng), b(ng + 1), c(ng), d(ng), e(ng), f(ng + 1);
-        for (int64_t i = 0; i < G; ++i) {
-            a[i] = t.groups[i].item0;
-            b[i] = t.groups[i].n_items;
-            c[i] = t.groups[i].frame0;
-            d[i] = t.groups[i].n_frames;
-            e[i] = t.groups[i].dmat_base;
-            f[i] = t.groups[i].pair_base;
+        if (t.packed) {
+            PinnedBlock &pb = *t.packed;
+            dv.blob.ensure(pb.bytes);
+            FABX_HIP(hipMemcpyAsync(dv.blob.ptr, pb.p, pb.bytes, hipMemcpyHostToDevice, ds.ctx->copy_stream));
+            pb.done = ds.ctx->events.get();
+            FABX_HIP(hipEventRecord(pb.done, ds.ctx->copy_stream));
+            FABX_HIP(hipStreamWaitEvent(stream, pb.done, 0));
+            set_task_tables(t, t.packed_layout);
+            pend->packed = std::move(t.packed);  // back to the pool when this score is done
+        } else {
+            Packer pk;
+            std::array<std::vector<int64_t>, 6> gcols;
+            const TableLayout L = add_task_tables(t, cplan && !cplan->d_cb ? cplan : nullptr, pk, gcols);
+            pk.upload(dv.blob, ds.ctx->staging, ds.ctx->copy_stream, stream);
+            set_task_tables(t, L);
         }
-        b[G] = 0;
-        f[G] = t.n_pair_slots;
-        const size_t o_src = pk.add(t.item_src), o_len = pk.add(t.item_len), o_dst = pk.add(t.item_dst),
-                     o_grp = pk.add(t.item_group), o_a = pk.add(a), o_b = pk.add(b), o_c = pk.add(c),
-                     o_d = pk.add(d), o_e = pk.add(e), o_f = pk.add(f), o_cells = pk.add(t.cells),
-                     o_units = pk.add(t.units), o_rb = pk.add(t.rb), o_grb = pk.add(t.g_rb0);
-        const bool with_plan = cplan && !cplan->d_cb;
-        std::array<size_t, 4> o_plan{};
-        if (with_plan) o_plan = add_col_plan(pk, *cplan);
-        pk.upload(dv.blob, ds.ctx->staging, ds.ctx->copy_stream, stream);
-        dv.item_src = Packer::at<int64_t>(dv.blob, o_src);
-        dv.item_len = Packer::at<int32_t>(dv.blob, o_len);
-        dv.item_dst = Packer::at<int64_t>(dv.blob, o_dst);
-        dv.item_group = Packer::at<int32_t>(dv.blob, o_grp);
-        dv.g_item0 = Packer::at<int64_t>(dv.blob, o_a);
-        dv.g_n = Packer::at<int64_t>(dv.blob, o_b);
-        dv.g_frame0 = Packer::at<int64_t>(dv.blob, o_c);
-        dv.g_nframes = Packer::at<int64_t>(dv.blob, o_d);
-        dv.g_dmat_base = Packer::at<int64_t>(dv.blob, o_e);
-        dv.g_pair_base = Packer::at<int64_t>(dv.blob, o_f);
-        dv.cells = Packer::at<CellDev>(dv.blob, o_cells);
-        dv.units = Packer::at<int32_t>(dv.blob, o_units);
-        dv.rb = Packer::at<int32_t>(dv.blob, o_rb);
-        dv.g_rb0 = Packer::at<int32_t>(dv.blob, o_grb);
-        if (with_plan) set_col_plan(*cplan, dv.blob, o_plan);
         dv.uploaded = true;
     }
     if (cplan && !cplan->d_cb) {  // another column width for an already uploaded task
         Packer pc;
-        const auto o = add_col_plan(pc, *cplan);
+        const std::array<size_t, 4> o{pc.add(cplan->cb), pc.add(cplan->rb_unit_prefix), pc.add(cplan->g_cb0),
+                                      pc.add(cplan->rb_cstart)};
         cplan->dev.pool = pool;
         pc.upload(cplan->dev, ds.ctx->staging, ds.ctx->copy_stream, stream);
         set_col_plan(*cplan, cplan->dev, o);

@@ -211,6 +211,7 @@ int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int
         if (job.footprint > s.budget)
             fail(FABX_ENOMEM, "job footprint " + std::to_string(job.footprint) +
                                   " bytes exceeds the server budget");
+        prepack_tables(*job.task);
         FABX_HIP(hipSetDevice(s.ctx->device));
         job.ready = s.ctx->events.get();
         if (hipEventRecord(job.ready, s.ctx->stream) != hipSuccess) {

@@ -381,6 +381,28 @@ def test_large_cells_many_exact_ties():
     assert np.array_equal(res.half_units, orc.half_units)
 
 
+@pytest.mark.parametrize("margin", [0.05, 1.0])
+def test_margin_sends_rows_to_fp64_recount(margin):
+    """A wider near-tie margin sends more rows of the brute-force count (rows of
+    several x per wave pass and rows walked in passes) to the FP64 recount; at
+    1.0 every row with a comparison goes (theta / pi and its path average lie
+    in [0, 1]).  The counts stay those of the FP64 definition."""
+    _say(f"near-tie margin {margin}")
+    w = workloads.batched_c4(n_groups=24, size_hi=150, centroid_std=0.3, seed=11)
+    t, res = gpu_score(w, margin=margin)
+    st = res.stats
+    assert st["margin"] == margin
+    orc = oracle_score(w)
+    assert np.array_equal(res.half_units, orc.half_units)
+    rows_with_work = sum(len(c.X) for c in orc.cells if (len(c.A) - int(c.exclude_self)) * len(c.B) > 0)
+    per_x = [len(c.A) * len(c.B) for c in orc.cells]
+    assert min(per_x) <= 64 < max(per_x)
+    if margin == 1.0:
+        assert st["n_recount_rows"] == rows_with_work
+    else:
+        assert 0 < st["n_recount_rows"] < rows_with_work
+
+
 # ---------------------------------------------------------- async score --
 
 def test_score_async_equals_sync():
@@ -540,6 +562,12 @@ def test_forced_fused_configs_equal_default():
         print(f"  cols {cols} blocks/CU {bpc}: distance {r.stats['ms_distance']:.3f} ms", flush=True)
         assert (r.stats["fused_cols"], r.stats["fused_blocks_per_cu"]) == (cols, bpc)
         assert np.array_equal(r.half_units, ref.half_units)
+    # a fresh task whose first score uses the other width: its tables come from
+    # the block packed at task creation, that width's column plan separately
+    t2 = fx.Task(fx.Dataset(fx.Context(0), feats, w.offsets, w.attrs), w.on, w.by, w.across)
+    r2 = t2.score(fused_cols=256, fused_blocks_per_cu=2)
+    assert np.array_equal(r2.half_units, ref.half_units)
+    assert np.array_equal(t2.score().half_units, ref.half_units)
 
 
 # ------------------------------------------------------- stream ordering --
