@@ -76,7 +76,7 @@ class _NoCyclicGC:
             gc.enable()
 
 
-def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch"):
+def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side_serial=True):
     """n steps with host and device work overlapped across steps: while the
     device scores step i, the host builds the task of step i + 1 and collapses
     the result of step i - 1.  `side` picks what runs on a second host thread:
@@ -85,7 +85,9 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch"):
     and collapsing the step before it; "collapse" keeps the launch on the main
     thread; "none" runs everything on the main thread.  The library's thread
     pool runs a region issued while another thread's region is active in place
-    on the issuing thread.  Every step still runs the whole path on its own
+    on the issuing thread; with side_serial the second thread's host work
+    always runs in place there (fabx_set_thread_serial), so that it never takes
+    the pool from a build.  Every step still runs the whole path on its own
     task."""
     import concurrent.futures as cf
 
@@ -109,7 +111,8 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch"):
         return out
 
     fut = None
-    with cf.ThreadPoolExecutor(max_workers=1) as pool, _NoCyclicGC():
+    with cf.ThreadPoolExecutor(max_workers=1, initializer=fx.fabx_set_thread_serial,
+                               initargs=(side_serial,)) as pool, _NoCyclicGC():
         t0 = time.perf_counter()
         for _ in range(n):
             task = fx.Task(ds, w.on, w.by, w.across)
@@ -283,6 +286,8 @@ def main():
     ap.add_argument("--side", choices=("launch", "collapse", "none"), default="launch",
                     help="work of the pipelined steps on a second host thread: score launch and "
                          "collapse (default), collapse only, or none")
+    ap.add_argument("--side-pool", action="store_true",
+                    help="let the second host thread's work use the shared host thread pool")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
                     help="c2 (default) is the headline workload; c3 / c4 / c4-pooled profile large groups")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -327,14 +332,14 @@ def main():
     if args.fused_config:
         cols, bpc = (int(v) for v in args.fused_config.split(","))
         SCORE_KW.update(fused_cols=cols, fused_blocks_per_cu=bpc)
-    run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, side)
+    run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, side, not args.side_pool)
     sync()
     log("warmup done")
     # untimed: pick the fused kernel's tiles / grid for this task shape
     tune = (fx.Task(ds, w.on, w.by, w.across).autotune(mode=mode)
             if not (args.no_autotune or args.fused_config) else None)
     log(f"autotune: {tune}")
-    dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, side)
+    dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, side, not args.side_pool)
     ms_step = dt / args.steps * 1e3
     log(f"bf16 form, pipelined: {ms_step:.2f} ms/step")
     # the same steps one after another, for the per-stage breakdown
@@ -354,8 +359,8 @@ def main():
 
     plain = None
     if not args.no_plain and headline:
-        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side)
-        pdt, _, perrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side)
+        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool)
+        pdt, _, perrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side, not args.side_pool)
         pms = pdt / args.steps * 1e3
         psdt, pstats, _ = run_steps(fx, ds, w, "fp32", args.steps, sync, mode)
         pst = _stage_means(pstats)

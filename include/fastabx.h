@@ -74,6 +74,17 @@ const char *fabx_last_error(void);
 /* Library version string. */
 const char *fabx_version(void);
 
+/* Host threads.  The library runs the parallel parts of its host work (task
+ * builds, collapses, table packing) on one shared pool of host threads; a
+ * call made while another thread's parallel region runs does its part on the
+ * calling thread.  fabx_set_thread_serial(1) makes every later call from the
+ * calling thread run its host work on that thread alone, so that it never
+ * takes the pool from another thread (e.g. a thread that collapses results
+ * beside a thread that builds the next tasks); 0 restores the default.
+ * Returns the previous setting of the calling thread.  Results do not depend
+ * on it. */
+int fabx_set_thread_serial(int serial);
+
 /* --------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t on

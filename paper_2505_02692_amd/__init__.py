@@ -24,7 +24,8 @@ from ._lib import (FABX_DTYPE_BF16, FABX_DTYPE_F32, FABX_MODE_DTW, FABX_MODE_POO
                    FABX_NORM_PATH, FABX_PREC_BF16_RECHECK, FABX_PREC_FP32, fabx_dataset_desc,
                    fabx_score_opts, fabx_server_stats, fabx_stats)
 
-__all__ = ["FabxError", "Context", "Dataset", "Task", "Result", "Server", "make_opts", "lib"]
+__all__ = ["FabxError", "Context", "Dataset", "Task", "Result", "Server", "make_opts", "lib",
+           "fabx_set_thread_serial"]
 
 
 class FabxError(RuntimeError):
@@ -51,6 +52,13 @@ def _i64p(a):
 
 
 # --------------------------------------------------------- same-name calls --
+
+def fabx_set_thread_serial(serial: bool) -> bool:
+    """Run the library's host work issued from the calling thread on that
+    thread alone (True), instead of on the shared host thread pool; returns
+    the previous setting."""
+    return bool(lib().fabx_set_thread_serial(1 if serial else 0))
+
 
 def fabx_create(device: int = 0, stream=None) -> ctypes.c_void_p:
     h = ctypes.c_void_p()

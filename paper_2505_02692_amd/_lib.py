@@ -92,6 +92,7 @@ _i64 = ctypes.c_int64
 SIGNATURES = {
     "fabx_last_error": (ctypes.c_char_p, []),
     "fabx_version": (ctypes.c_char_p, []),
+    "fabx_set_thread_serial": (ctypes.c_int, [ctypes.c_int]),
     "fabx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _vp]),
     "fabx_destroy": (None, [_vp]),
     "fabx_dataset_create": (ctypes.c_int, [_vp, _P(fabx_dataset_desc), _P(_vp)]),

@@ -188,6 +188,7 @@ PinnedBlock::~PinnedBlock() {
         ctx->events.put(done);
     }
     if (p) ctx->pinned.put(p, cap);
+    if (packed) ctx->pinned.packed_bytes -= cap;
 }
 
 Staging::~Staging() {
@@ -235,6 +236,13 @@ extern "C" {
 const char *fabx_last_error(void) { return last_error_cstr(); }
 
 const char *fabx_version(void) { return "fastabx-hip 0.1.0 (gfx950)"; }
+
+int fabx_set_thread_serial(int serial) {
+    bool &f = HostPool::caller_serial();
+    const int prev = f ? 1 : 0;
+    f = serial != 0;
+    return prev;
+}
 
 int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
     return guarded([&] {

@@ -130,8 +130,8 @@ using hvec = std::vector<T, CachedAlloc<T>>;
 //
 // One region runs at a time.  A parallel_for issued while another thread's
 // region is running (say a collapse on one thread while a task is built on
-// another), or from inside a region, runs its items in place on the calling
-// thread.  The pool leaves one hardware thread to such callers: it uses at
+// another), or from inside a region, or from a thread marked serial, runs its
+// items in place on the calling thread.  The pool leaves one hardware thread to such callers: it uses at
 // most 16 threads and, on machines with 8 or more, one fewer than there are.
 class HostPool {
 public:
@@ -143,10 +143,17 @@ public:
     // Whether a parallel_for issued now from this thread would run on the
     // workers (a hint: another thread may start a region meanwhile, and then
     // the call still completes, in place).
-    bool would_run_parallel() const { return !workers_.empty() && !in_region() && !busy_.load(); }
+    bool would_run_parallel() const {
+        return !workers_.empty() && !in_region() && !caller_serial() && !busy_.load();
+    }
+    // Set for the calling thread: its regions always run in place.
+    static bool &caller_serial() {
+        thread_local bool flag = false;
+        return flag;
+    }
 
     void parallel_for(int n, const std::function<void(int)> &f) {
-        if (n <= 1 || workers_.empty() || in_region()) {
+        if (n <= 1 || workers_.empty() || in_region() || caller_serial()) {
             for (int k = 0; k < n; ++k) f(k);
             return;
         }

@@ -91,6 +91,10 @@ struct PinnedPool {
     std::mutex mu;
     std::vector<std::pair<size_t, void *>> free_blocks;  // (bytes, ptr)
     size_t cached = 0;
+    // bytes held by tasks' packed tables (PinnedBlock with `packed`): kept
+    // below what the cache takes back, so that returning them frees nothing
+    // (hipHostFree waits for the device)
+    std::atomic<size_t> packed_bytes{0};
     void *get(size_t n, size_t *got);
     void put(void *p, size_t n);
     ~PinnedPool();
@@ -154,6 +158,7 @@ struct PinnedBlock {
     void *p = nullptr;
     size_t cap = 0, bytes = 0;
     hipEvent_t done = nullptr;  // from ctx->events, recorded after the DMA
+    bool packed = false;        // counted in ctx->pinned.packed_bytes (cap bytes)
     PinnedBlock(std::shared_ptr<CtxImpl> c, size_t n);
     PinnedBlock(const PinnedBlock &) = delete;
     PinnedBlock &operator=(const PinnedBlock &) = delete;

@@ -143,8 +143,10 @@ void set_task_tables(TaskImpl &t, const TableLayout &L) {
 }
 
 // Task tables larger than this are sent through the staging buffer on the
-// first score instead of being packed when the task is made.
+// first score instead of being packed when the task is made; so are those of
+// a task made while other tasks' packed tables already hold kPrepackBudget.
 constexpr size_t kPrepackMaxBytes = size_t(64) << 20;
+constexpr size_t kPrepackBudget = size_t(128) << 20;
 
 // Gram tile prefix per group for the plain form (64 x 64 tiles of frames) or
 // the pooled mode (64 x 64 FP32 or 64 x 128 BF16 tiles of items).
@@ -268,11 +270,12 @@ ResultImpl::~ResultImpl() {
 void prepack_tables(TaskImpl &t) {
     const std::shared_ptr<CtxImpl> &ctx = t.ds->ctx;
     if (!ctx || ctx->device < 0 || t.cells.empty()) return;
+    Trace tr("prepack");
     Packer pk;
     std::array<std::vector<int64_t>, 6> gcols;
     const ColPlan *plan = t.col_plans.empty() ? nullptr : t.col_plans.front().get();
     const TableLayout L = add_task_tables(t, plan, pk, gcols);
-    if (pk.total > kPrepackMaxBytes) return;
+    if (pk.total > kPrepackMaxBytes || ctx->pinned.packed_bytes.load() + pk.total > kPrepackBudget) return;
     FABX_HIP(hipSetDevice(ctx->device));
     std::unique_ptr<PinnedBlock> blk;
     try {
@@ -280,8 +283,12 @@ void prepack_tables(TaskImpl &t) {
     } catch (const Error &) {
         return;  // no pinned memory to spare: the first score sends the tables through the staging buffer
     }
+    blk->packed = true;
+    ctx->pinned.packed_bytes += blk->cap;
     blk->bytes = pk.total;
+    tr.mark("alloc");
     pk.copy_to(static_cast<char *>(blk->p));
+    tr.mark("copy");
     t.packed = std::move(blk);
     t.packed_layout = L;
 }

@@ -197,3 +197,33 @@ def test_concurrent_task_builds_agree():
     with ThreadPoolExecutor(4) as ex:
         for keys, sizes in ex.map(build, range(12)):
             assert np.array_equal(keys, ref_keys) and np.array_equal(sizes, ref_sizes)
+
+
+def test_thread_serial_switch():
+    """fabx_set_thread_serial is per thread and returns the previous setting;
+    task builds from a serial thread (beside builds on the pool) give the same
+    cells."""
+    from concurrent.futures import ThreadPoolExecutor
+    import workloads
+    w = workloads.within_c2(n_items=20000, dim=8, seed=6)
+    ds = fx.Dataset(fx.Context(-1), None, w.offsets, w.attrs)
+    ref = fx.Task(ds, w.on, w.by, w.across)
+    ref_keys, ref_sizes = ref.keys, ref.sizes[0]
+    assert fx.fabx_set_thread_serial(True) is False
+    assert fx.fabx_set_thread_serial(True) is True
+    t = fx.Task(ds, w.on, w.by, w.across)
+    assert np.array_equal(t.keys, ref_keys) and np.array_equal(t.sizes[0], ref_sizes)
+    assert fx.fabx_set_thread_serial(False) is True
+    def serial_build(_):
+        fx.fabx_set_thread_serial(True)
+        t = fx.Task(ds, w.on, w.by, w.across)
+        return t.keys, t.sizes[0]
+    with ThreadPoolExecutor(1) as side:
+        futs = [side.submit(serial_build, k) for k in range(3)]
+        for _ in range(3):
+            t = fx.Task(ds, w.on, w.by, w.across)  # on the pool, beside the serial builds
+            assert np.array_equal(t.keys, ref_keys)
+        for f in futs:
+            keys, sizes = f.result()
+            assert np.array_equal(keys, ref_keys) and np.array_equal(sizes, ref_sizes)
+    assert fx.fabx_set_thread_serial(False) is False  # this thread's setting is its own

@@ -490,6 +490,29 @@ def test_threaded_pipeline_equals_serial():
         assert np.array_equal(hu, want[k % len(ws)])
 
 
+def test_many_tasks_made_before_scoring():
+    """A task holds its packed device tables from its creation to its first
+    score; once the tasks made ahead hold the context's budget for them, later
+    tasks send their tables through the staging buffer on their first score.
+    Both give the same counts, also with the scores launched on a second
+    thread while the first one makes tasks."""
+    from concurrent.futures import ThreadPoolExecutor
+    _say("many tasks made before scoring")
+    w = workloads.within_c2(n_items=40000, dim=64, centroid_std=0.08, seed=90, device="cuda")
+    ds = fx.Dataset(ctx(), w.features, w.offsets, w.attrs)
+    want = fx.Task(ds, w.on, w.by, w.across).score().half_units.copy()
+    tasks = [fx.Task(ds, w.on, w.by, w.across) for _ in range(48)]
+    while tasks:
+        t = tasks.pop()
+        assert np.array_equal(t.score().half_units, want)
+        del t
+    with ThreadPoolExecutor(1) as helper:
+        futs = [helper.submit(lambda t: t.score_async().half_units.copy(), fx.Task(ds, w.on, w.by, w.across))
+                for _ in range(6)]
+        for f in futs:
+            assert np.array_equal(f.result(), want)
+
+
 # ------------------------------------------------------------- autotune --
 
 def test_autotune_tiles_give_identical_counts_and_persist(tmp_path, monkeypatch):
