@@ -235,8 +235,7 @@ struct Workspace {
     DevBuf p32;         // F32 [n_pair_slots]
     DevBuf flags;       // uint8 [n_pair_slots]: bit0 non-robust, bit1 marked for FP64
     DevBuf p64;         // F64 [n_pair_slots]
-    DevBuf half_units;  // uint64 [n_cells]
-    DevBuf counters;    // misc device counters
+    DevBuf half_units;  // uint64 [n_cells], then the score's 64 counter bytes
     DevBuf recheck_list, recount_list;
     size_t total() const;
     void release();

@@ -254,9 +254,23 @@ __global__ __launch_bounds__(256) void k_triplets_sorted(const CellDev *__restri
     }
 }
 
+// Zeroes the per-cell counts W [n_cells] and the score's 64 counter bytes
+// that follow them, except the error item (the word at byte 8), which starts
+// at all ones.
+__global__ __launch_bounds__(256) void k_init(unsigned long long *__restrict__ W, int64_t n_cells) {
+    const int64_t n = n_cells + 8;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        W[i] = i == n_cells + 1 ? ~0ull : 0ull;
+}
+
+// Marked pairs into `list`.  Every pair the triplet kernels mark belongs to a
+// row they also send to the recount, so with no such row there is nothing to
+// collect.
 __global__ __launch_bounds__(256) void k_collect_marked(const uint8_t *__restrict__ flags, int64_t n_slots,
                                                         int64_t *__restrict__ list,
-                                                        unsigned int *__restrict__ count, int64_t cap) {
+                                                        unsigned int *__restrict__ count, int64_t cap,
+                                                        const unsigned int *__restrict__ recount_n) {
+    if (*recount_n == 0) return;
     const int lane = threadIdx.x % kWave;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
          i - lane < n_slots; i += int64_t(gridDim.x) * blockDim.x) {
@@ -337,12 +351,18 @@ void triplets_sorted(hipStream_t s, const CellDev *cells, const int32_t *units, 
     FABX_HIP(hipGetLastError());
 }
 
+void init_score(hipStream_t s, unsigned long long *W, int64_t n_cells) {
+    const int64_t blocks = std::min<int64_t>((n_cells + 8 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_init, dim3(unsigned(blocks)), dim3(256), 0, s, W, n_cells);
+    FABX_HIP(hipGetLastError());
+}
+
 void collect_marked(hipStream_t s, const uint8_t *flags, int64_t n_slots, int64_t *list,
-                    unsigned int *count, int64_t cap) {
+                    unsigned int *count, int64_t cap, const unsigned int *recount_n) {
     if (n_slots <= 0) return;
     const int64_t blocks = std::min<int64_t>((n_slots + 255) / 256, 4096);
     hipLaunchKernelGGL(k_collect_marked, dim3(unsigned(blocks)), dim3(256), 0, s, flags, n_slots,
-                       list, count, cap);
+                       list, count, cap, recount_n);
     FABX_HIP(hipGetLastError());
 }
 

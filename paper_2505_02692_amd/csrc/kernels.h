@@ -103,9 +103,14 @@ void triplets_sorted(hipStream_t s, const CellDev *cells, const int32_t *units, 
               const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
               float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap);
 
-// Pair slots whose flag bit 1 is set -> list (order unspecified).
+// Zeroes W [n_cells] and the 64 counter bytes after it (the u64 at byte 8 of
+// those, the error item, is set to all ones).
+void init_score(hipStream_t s, unsigned long long *W, int64_t n_cells);
+
+// Pair slots whose flag bit 1 is set -> list (order unspecified); nothing when
+// *recount_n is 0 (no row was sent to the recount, so no pair is marked).
 void collect_marked(hipStream_t s, const uint8_t *flags, int64_t n_slots, int64_t *list,
-                    unsigned int *count, int64_t cap);
+                    unsigned int *count, int64_t cap, const unsigned int *recount_n);
 
 // Re-count rows (cell, x): a comparison of two recomputed pairs (flag bit 1 on both)
 // uses their FP64 values, any other comparison the FP32 ones.

@@ -227,7 +227,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
 }
 
 size_t Workspace::total() const {
-    const DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units, &counters,
+    const DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units,
                            &recheck_list, &recount_list};
     size_t s = 0;
     for (auto *b : all) s += b->bytes;
@@ -235,7 +235,7 @@ size_t Workspace::total() const {
 }
 
 void Workspace::release() {
-    DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units, &counters,
+    DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units,
                      &recheck_list, &recount_list};
     for (auto *b : all) b->release();
 }
@@ -351,7 +351,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     Pool *pool = &ds.ctx->pool;
     if (!dv.blob.ptr) dv.blob.pool = pool;
     for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
-                      &t.ws.half_units, &t.ws.counters, &t.ws.recheck_list, &t.ws.recount_list})
+                      &t.ws.half_units, &t.ws.recheck_list, &t.ws.recount_list})
         if (!b->ptr) b->pool = pool;
     // fused kernel: tile width and grid from the tuning table (or the caller),
     // and the task's column blocks for that width (uploaded on first use)
@@ -418,14 +418,15 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         ws.recheck_list.ensure(size_t(t.n_pair_slots) * 8);
         ws.recount_list.ensure(size_t(std::max<int64_t>(t.sum_nx, 1)) * 8);
     }
-    ws.half_units.ensure(size_t(n_cells) * 8);
-    ws.counters.ensure(64);
-    int *err = ws.counters.as<int>();
-    unsigned long long *err_item = reinterpret_cast<unsigned long long *>(ws.counters.as<char>() + 8);
-    unsigned int *recount_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 16);
-    unsigned int *marked_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 20);
-    unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 24);
-    unsigned int *unit_ctr = reinterpret_cast<unsigned int *>(ws.counters.as<char>() + 32);  // [8]
+    // per-cell counts, then 64 counter bytes: both come back with one copy
+    ws.half_units.ensure(size_t(n_cells) * 8 + 64);
+    char *counters = ws.half_units.as<char>() + size_t(n_cells) * 8;
+    int *err = reinterpret_cast<int *>(counters);
+    unsigned long long *err_item = reinterpret_cast<unsigned long long *>(counters + 8);
+    unsigned int *recount_n = reinterpret_cast<unsigned int *>(counters + 16);
+    unsigned int *marked_n = reinterpret_cast<unsigned int *>(counters + 20);
+    unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(counters + 24);
+    unsigned int *unit_ctr = reinterpret_cast<unsigned int *>(counters + 32);  // [8]
     st.workspace_bytes = int64_t(ws.total());
     pend->host_bytes = size_t(n_cells) * 8 + 64;
     pend->host = ds.ctx->pinned.get(pend->host_bytes, &pend->host_bytes);
@@ -446,9 +447,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         }
     } drain{stream};
     tm.mark();  // 0
-    FABX_HIP(hipMemsetAsync(ws.counters.ptr, 0, 64, stream));
-    FABX_HIP(hipMemsetAsync(err_item, 0xFF, 8, stream));
-    FABX_HIP(hipMemsetAsync(ws.half_units.ptr, 0, size_t(n_cells) * 8, stream));
+    kern::init_score(stream, ws.half_units.as<unsigned long long>(), n_cells);
     if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(ws.flags.ptr, 0, size_t(t.n_pair_slots), stream));
     tm.mark();  // 1
     if (dtw)
@@ -491,7 +490,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     tm.mark();  // 4
     if (bf16) {
         kern::collect_marked(stream, ws.flags.as<uint8_t>(), t.n_pair_slots, ws.recheck_list.as<int64_t>(),
-                             marked_n, t.n_pair_slots);
+                             marked_n, t.n_pair_slots, recount_n);
         kern::recheck_fp64(stream, ds.features, ds.dtype, dim, gt, it, ws.recheck_list.as<int64_t>(),
                            marked_n, t.n_pair_slots, p.mode, p.dtw_norm, ws.p64.as<double>());
         kern::recount(stream, dv.cells, ws.recount_list.as<int32_t>(), recount_n, t.sum_nx,
@@ -499,8 +498,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
                       ws.half_units.as<unsigned long long>());
     }
     tm.mark();  // 5
-    FABX_HIP(hipMemcpyAsync(host, ws.half_units.ptr, size_t(n_cells) * 8, hipMemcpyDeviceToHost, stream));
-    FABX_HIP(hipMemcpyAsync(host + size_t(n_cells) * 8, ws.counters.ptr, 64, hipMemcpyDeviceToHost, stream));
+    FABX_HIP(hipMemcpyAsync(host, ws.half_units.ptr, size_t(n_cells) * 8 + 64, hipMemcpyDeviceToHost, stream));
     tm.mark();  // 6
     tr.mark("launch");
     pend->t_launch = clock::now();
