@@ -40,6 +40,14 @@ int64_t item_chunk(int64_t n) {
     return std::max<int64_t>(1024, (n + parts - 1) / parts);
 }
 
+// Groups per chunk of a loop over BY groups: about 8 chunks per pool thread
+// (group sizes vary), at least 16 groups each.  Per-group results do not
+// depend on it.
+int64_t group_chunk(int64_t n_groups) {
+    const int64_t parts = 8 * int64_t(HostPool::get().size());
+    return std::max<int64_t>(16, (n_groups + parts - 1) / parts);
+}
+
 // Dense ranks of attribute columns `cols`, all columns per pass over the
 // item rows, each pass parallel over fixed row chunks: per-chunk minima and
 // maxima; then, for a column whose value range is small, the values present
@@ -496,7 +504,7 @@ void plan_units(const TaskImpl &t, ColPlan &cp) {
     cp.rb_cstart.resize(n_rb);
     cp.rb_unit_prefix.resize(n_rb + 1);
     cp.rb_unit_prefix[0] = 0;
-    const int64_t kGroups = 2048;
+    const int64_t kGroups = group_chunk(G);
     const int n_gc = int((G + kGroups - 1) / kGroups);
     std::vector<int64_t> part_cells(static_cast<size_t>(std::max(n_gc, 1)), 0);
     parallel_for(n_gc, [&](int c) {
@@ -536,7 +544,7 @@ ColPlan &col_plan(TaskImpl &t, int cols) {
     const int64_t G = int64_t(t.groups.size());
     cp->g_cb0.assign(size_t(G), 0);
     cp->g_ncb.assign(size_t(G), 0);
-    const int64_t kGroups = 2048;
+    const int64_t kGroups = group_chunk(G);
     const int n_gc = int((G + kGroups - 1) / kGroups);
     parallel_for(n_gc, [&](int c) {
         for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
@@ -930,7 +938,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     std::vector<int32_t> nrb(static_cast<size_t>(G));
     cp->g_ncb.assign(size_t(G), 0);
     cp->g_cb0.assign(size_t(G), 0);
-    const int64_t kGroups = 2048;
+    const int64_t kGroups = group_chunk(G);
     const int n_gc = int((G + kGroups - 1) / kGroups);
     parallel_for(n_gc, [&](int c) {
         for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
