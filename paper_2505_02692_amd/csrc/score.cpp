@@ -25,11 +25,13 @@ constexpr double kMarginK = 2e-2;
 constexpr double kDeltaK = 4e-2;
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Collects host arrays (256-byte aligned pieces) and sends them to one device
-// buffer with a single DMA copy through the context's pinned staging buffer.
-// The copy runs on the context's copy stream; the compute stream waits for it.
-// The destination is a buffer of this task or score, so no earlier kernel
-// still on the compute stream can be reading it.
+// Collects host arrays (256-byte aligned pieces) into one layout.  copy_to
+// writes them to pinned memory (a task's packed block, made when the task is
+// built); upload sends them to one device buffer with a single DMA copy
+// through the context's pinned staging buffer.  Either copy runs on the
+// context's copy stream and the compute stream waits for it.  The destination
+// is a buffer of this task or score, so no earlier kernel still on the compute
+// stream can be reading it.
 struct Packer {
     struct Piece {
         const void *src;
