@@ -10,7 +10,8 @@ Every function follows a passage of the paper (Poli, Chemla, Dupoux,
 
 * ``cells``            -- Background section: the ON / BY / ACROSS conditions
                           (Fig. 1 caption, Table 1) and the cell A x B x X.
-* ``frame_distance``   -- the "angular" distance named with the Score class.
+* ``frame_distance``   -- the "angular" distance named with the Score class,
+                          or the "euclidean" one named beside it.
 * ``dtw``              -- the DTW recurrence of "Dynamic Time Warping on GPU".
 * ``pair_distances``   -- DTW over frame distances, or time pooling (same
                           section: "pool along the time domain").
@@ -63,13 +64,14 @@ def _lib():
         lib = ctypes.CDLL(_SO)
         P = ctypes.POINTER
         lib.oracle_frame_distance.argtypes = [P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int,
-                                              P(ctypes.c_double)]
+                                              ctypes.c_int, P(ctypes.c_double)]
         lib.oracle_dtw.argtypes = [P(ctypes.c_double), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    P(ctypes.c_double), P(ctypes.c_int64)]
         lib.oracle_pair_distances.argtypes = [
             P(ctypes.c_float), P(ctypes.c_int64), ctypes.c_int, ctypes.c_int64,
             P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int32),
-            P(ctypes.c_int32), ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_int64)]
+            P(ctypes.c_int32), ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+            P(ctypes.c_int64)]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib_handle = lib
     return _lib_handle
@@ -86,13 +88,17 @@ def num_threads() -> int:
 
 # ---------------------------------------------------------------- distances --
 
-def frame_distance(u: Sequence[float], v: Sequence[float]) -> float:
-    """Angular distance theta(u, v) / pi of two raw vectors, in FP64."""
+DISTANCES = {"angular": 0, "euclidean": 1}
+
+
+def frame_distance(u: Sequence[float], v: Sequence[float], distance: str = "angular") -> float:
+    """Distance of two raw vectors in FP64: the angle theta(u, v) / pi
+    ("angular") or the length of u - v ("euclidean")."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.float64)
     out = ctypes.c_double()
     rc = _lib().oracle_frame_distance(_ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double),
-                                      int(u.shape[0]), ctypes.byref(out))
+                                      int(u.shape[0]), DISTANCES[distance], ctypes.byref(out))
     if rc != 0:
         raise ValueError(f"frame_distance failed ({rc}): zero vector has no angle")
     return out.value
@@ -256,7 +262,7 @@ class OracleResult:
 
 def pair_distances(features: np.ndarray, offsets: np.ndarray,
                    group_items: List[np.ndarray], group_pairs: List[Tuple[np.ndarray, np.ndarray]],
-                   mode: str = "dtw", norm: str = "path") -> List[np.ndarray]:
+                   mode: str = "dtw", norm: str = "path", distance: str = "angular") -> List[np.ndarray]:
     """FP64 distances of the given (x, y) pairs, listed per group as local positions."""
     feats = np.ascontiguousarray(features, dtype=np.float32)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -274,8 +280,8 @@ def pair_distances(features: np.ndarray, offsets: np.ndarray,
         _ptr(feats, ctypes.c_float), _ptr(offsets, ctypes.c_int64), D, len(group_items),
         _ptr(gptr, ctypes.c_int64), _ptr(gitems, ctypes.c_int64), _ptr(pptr, ctypes.c_int64),
         _ptr(px, ctypes.c_int32), _ptr(py, ctypes.c_int32),
-        0 if mode == "dtw" else 1, 0 if norm == "path" else 1, _ptr(out, ctypes.c_double),
-        ctypes.byref(bad))
+        0 if mode == "dtw" else 1, 0 if norm == "path" else 1, DISTANCES[distance],
+        _ptr(out, ctypes.c_double), ctypes.byref(bad))
     if rc == EDOMAIN:
         raise ValueError(f"zero-norm frame or mean in item {bad.value}: angle undefined")
     if rc != 0:
@@ -285,7 +291,7 @@ def pair_distances(features: np.ndarray, offsets: np.ndarray,
 
 def score(features: np.ndarray, offsets: np.ndarray, attrs: np.ndarray, on: int,
           by: Sequence[int], across: Sequence[int], mode: str = "dtw", norm: str = "path",
-          cell_filter=None) -> OracleResult:
+          cell_filter=None, distance: str = "angular") -> OracleResult:
     """Per-cell half-unit counts W and triplet counts |C| for the whole task.
 
     ``cell_filter`` (optional) keeps a subset of the cells, e.g. a sample of
@@ -314,7 +320,7 @@ def score(features: np.ndarray, offsets: np.ndarray, attrs: np.ndarray, on: int,
         group_items.append(items)
         group_pairs.append((xi.astype(np.int32), yi.astype(np.int32)))
         need_mats.append(need)
-    dists = pair_distances(features, offsets, group_items, group_pairs, mode, norm)
+    dists = pair_distances(features, offsets, group_items, group_pairs, mode, norm, distance)
     groups = {}
     for g, items, (xi, yi), dv in zip(gkeys, group_items, group_pairs, dists):
         M = np.full((len(items), len(items)), np.nan)

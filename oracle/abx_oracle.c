@@ -13,7 +13,10 @@
  *     the "Dynamic Time Warping on GPU" section), optionally divided by the
  *     length of the optimal alignment path;
  *   - the time-pooled alternative (same section: "pool along the time
- *     domain"): angular distance of the per-item mean frames.
+ *     domain"): angular distance of the per-item mean frames;
+ *   - the Euclidean distance between two frames (the Score interface names
+ *     "euclidean" beside "angular"): the square root of the sequential sum of
+ *     squared differences, on the raw frames (or raw means), in either mode.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction,
  * so every sum is the plain sequential sum written below).
@@ -83,11 +86,28 @@ static double angular_unit(const double *u, const double *v, int D)
     return theta / ORACLE_PI;
 }
 
-/* Exported for the closed-form pins: angular distance of two raw vectors. */
-int oracle_frame_distance(const double *u, const double *v, int D, double *out)
+/* Euclidean distance of two raw vectors: sqrt of the sequential sum of
+ * (u_k - v_k)^2. */
+static double euclidean(const double *u, const double *v, int D)
 {
-    if (D <= 0)
+    double s = 0.0;
+    for (int k = 0; k < D; ++k) {
+        double d = u[k] - v[k];
+        s += d * d;
+    }
+    return sqrt(s);
+}
+
+/* Exported for the closed-form pins: distance of two raw vectors
+ * (distance 0 = angular, 1 = Euclidean). */
+int oracle_frame_distance(const double *u, const double *v, int D, int distance, double *out)
+{
+    if (D <= 0 || distance < 0 || distance > 1)
         return ORACLE_EINVAL;
+    if (distance == 1) {
+        *out = euclidean(u, v, D);
+        return ORACLE_OK;
+    }
     double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)D);
     if (!buf)
         return ORACLE_ENOMEM;
@@ -169,8 +189,10 @@ int oracle_dtw(const double *d, int N, int M, int norm, double *out, int64_t *le
  * gitems    int64 item ids
  * pptr      int64 [n_groups + 1] into px / py / out: the pairs of group g
  * px, py    int32 positions inside the group's item list (x = rows, y = cols)
- * mode      0 = DTW over frames, 1 = angular distance of mean frames
+ * mode      0 = DTW over frames, 1 = distance of mean frames
  * norm      0 = divide by path length, 1 = raw cost (DTW mode only)
+ * distance  0 = angular (frames or means made unit first), 1 = Euclidean
+ *           (raw frames or means)
  * out       float64 distances, one per pair
  * bad_item  on ORACLE_EDOMAIN, an item holding a zero frame (or zero mean)
  *
@@ -179,10 +201,10 @@ int oracle_dtw(const double *d, int N, int M, int norm, double *out, int64_t *le
 int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                           int64_t n_groups, const int64_t *gptr, const int64_t *gitems,
                           const int64_t *pptr, const int32_t *px, const int32_t *py,
-                          int mode, int norm, double *out, int64_t *bad_item)
+                          int mode, int norm, int distance, double *out, int64_t *bad_item)
 {
     int status = ORACLE_OK;
-    if (D <= 0 || n_groups < 0)
+    if (D <= 0 || n_groups < 0 || distance < 0 || distance > 1)
         return ORACLE_EINVAL;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t g = 0; g < n_groups; ++g) {
@@ -193,7 +215,8 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
             continue;
         int64_t n = gptr[g + 1] - gptr[g];
         const int64_t *items = gitems + gptr[g];
-        /* unit frames (DTW) or unit means (pooled) of every item in the group */
+        /* frames (DTW) or means (pooled) of every item in the group: made
+           unit for the angular distance, kept raw for the Euclidean one */
         int64_t *ustart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
         ustart[0] = 0;
         for (int64_t a = 0; a < n; ++a) {
@@ -207,9 +230,15 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
             int64_t it = items[a];
             int64_t f0 = offsets[it], L = offsets[it + 1] - offsets[it];
             if (mode == 0) {
-                for (int64_t t = 0; t < L && rc == ORACLE_OK; ++t)
-                    rc = unit_from_f32(feat + (size_t)(f0 + t) * D, D, tmp,
-                                       uf + (size_t)(ustart[a] + t) * D);
+                for (int64_t t = 0; t < L && rc == ORACLE_OK; ++t) {
+                    const float *f = feat + (size_t)(f0 + t) * D;
+                    double *u = uf + (size_t)(ustart[a] + t) * D;
+                    if (distance == 1)
+                        for (int k = 0; k < D; ++k)
+                            u[k] = (double)f[k];
+                    else
+                        rc = unit_from_f32(f, D, tmp, u);
+                }
             } else {
                 for (int k = 0; k < D; ++k)
                     tmp[k] = 0.0;
@@ -218,7 +247,11 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                         tmp[k] += (double)feat[(size_t)(f0 + t) * D + k];
                 for (int k = 0; k < D; ++k)
                     tmp[k] = tmp[k] / (double)L;
-                rc = unit_from_f64(tmp, D, uf + (size_t)ustart[a] * D);
+                double *u = uf + (size_t)ustart[a] * D;
+                if (distance == 1)
+                    memcpy(u, tmp, sizeof(double) * (size_t)D);
+                else
+                    rc = unit_from_f64(tmp, D, u);
             }
             if (rc != ORACLE_OK && bad_item) {
 #pragma omp critical
@@ -233,7 +266,7 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                 const double *ux = uf + (size_t)ustart[a] * D;
                 const double *uy = uf + (size_t)ustart[b] * D;
                 if (mode == 1) {
-                    out[p] = angular_unit(ux, uy, D);
+                    out[p] = distance == 1 ? euclidean(ux, uy, D) : angular_unit(ux, uy, D);
                     continue;
                 }
                 int N = (int)(ustart[a + 1] - ustart[a]);
@@ -245,7 +278,9 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                 }
                 for (int i = 0; i < N; ++i)
                     for (int j = 0; j < M; ++j)
-                        dm[(size_t)i * M + j] = angular_unit(ux + (size_t)i * D, uy + (size_t)j * D, D);
+                        dm[(size_t)i * M + j] = distance == 1
+                                                    ? euclidean(ux + (size_t)i * D, uy + (size_t)j * D, D)
+                                                    : angular_unit(ux + (size_t)i * D, uy + (size_t)j * D, D);
                 oracle_dtw(dm, N, M, norm, &out[p], NULL);
             }
             free(dm);

@@ -197,6 +197,51 @@ def test_pooled_mean_closed_form():
     assert abs(d[2] - 0.25) < 1e-15
 
 
+# ------------------------------------------------ Euclidean distance (NEXT) --
+
+def test_euclidean_frame_distance_closed_forms():
+    """The "euclidean" distance named beside "angular" in the Score interface:
+    the length of u - v.  A 3-4-5 triangle placed away from the origin (so
+    |u + v| or a missing square root would fail), identity, symmetry,
+    translation and power-of-two scale invariance, and a zero vector, which
+    has a length but no angle."""
+    e = lambda u, v: oracle.frame_distance(u, v, "euclidean")
+    assert e([1.0, 1.0], [4.0, 5.0]) == 5.0
+    assert e([0.0, 0.0, 0.0], [1.0, 2.0, 2.0]) == 3.0
+    assert e([2.0, -1.0, 7.0, 3.0], [2.0, -1.0, 7.0, 3.0]) == 0.0
+    rng = np.random.default_rng(61)
+    for D in (2, 7, 64, 768):
+        u = np.round(rng.standard_normal(D) * 64) / 64       # multiples of 1/64: sums stay exact
+        v = np.round(rng.standard_normal(D) * 64) / 64
+        t = np.round(rng.standard_normal(D) * 64) / 64
+        d = e(u, v)
+        assert d == e(v, u)
+        assert d == e(u + t, v + t)
+        assert e(4.0 * u, 4.0 * v) == 4.0 * d
+        assert d == math.sqrt(float(np.sum((u - v) ** 2)))     # exact sums of exact squares here
+        assert e(u, u) == 0.0
+
+
+def test_euclidean_dtw_and_pooled_worked_examples():
+    """Worked by hand.  x = [(0,0), (1,0)], y = [(0,0), (0,1), (1,1)]: frame
+    distances [[0, 1, r2], [1, r2, 1]] (r2 = sqrt 2), cumulative costs
+    [[0, 1, 1 + r2], [1, r2, 2]]; the last cell comes from the diagonal (0, 1),
+    so the path is (0,0) (0,1) (1,2): raw cost 2, path length 3, distance 2/3.
+    Pooled: the means (1/2, 0) and (1/3, 2/3) are sqrt(1/36 + 4/9) = sqrt(17)/6
+    apart.  A zero frame is allowed."""
+    x = [[0.0, 0.0], [1.0, 0.0]]
+    y = [[0.0, 0.0], [0.0, 1.0], [1.0, 1.0]]
+    feats, off = _dataset([x, y])
+    items = [np.arange(2)]
+    pairs = [(np.array([0, 1], np.int32), np.array([1, 0], np.int32))]
+    raw = oracle.pair_distances(feats, off, items, pairs, "dtw", "none", "euclidean")[0]
+    assert raw[0] == 2.0 and raw[1] == 2.0
+    d = oracle.pair_distances(feats, off, items, pairs, "dtw", "path", "euclidean")[0]
+    assert abs(d[0] - 2.0 / 3.0) < 1e-15 and abs(d[1] - 2.0 / 3.0) < 1e-15
+    p = oracle.pair_distances(feats, off, items, pairs, "pooled", "path", "euclidean")[0]
+    assert abs(p[0] - math.sqrt(17.0) / 6.0) < 1e-15 and p[0] == p[1]
+
+
 def test_zero_frame_is_rejected():
     feats, off = _dataset([[[1.0, 0.0]], [[0.0, 0.0]]])
     with pytest.raises(ValueError):
