@@ -76,7 +76,7 @@ class _NoCyclicGC:
             gc.enable()
 
 
-def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side_serial=True):
+def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side_serial=True, **kw):
     """n steps with host and device work overlapped across steps: while the
     device scores step i, the host builds the task of step i + 1 and collapses
     the result of step i - 1.  `side` picks what runs on a second host thread:
@@ -105,7 +105,7 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side
     prev = [None]
 
     def launch_then_finish_prev(task):
-        res = task.score_async(mode=mode, precision=precision, **SCORE_KW)
+        res = task.score_async(mode=mode, precision=precision, **SCORE_KW, **kw)
         out = finish(prev[0]) if prev[0] is not None else None
         prev[0] = res
         return out
@@ -121,7 +121,7 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side
                     take(fut.result())
                 fut = pool.submit(launch_then_finish_prev, task)
                 continue
-            res = task.score_async(mode=mode, precision=precision, **SCORE_KW)
+            res = task.score_async(mode=mode, precision=precision, **SCORE_KW, **kw)
             if prev[0] is not None:
                 if side == "collapse":
                     if fut is not None:
@@ -357,7 +357,7 @@ def main():
         fx.Task(ds, w.on, w.by, w.across)
         t_build.append((time.perf_counter() - t0) * 1e3)
 
-    plain = None
+    plain = euclid = None
     if not args.no_plain and headline:
         run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool)
         pdt, _, perrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side, not args.side_pool)
@@ -370,6 +370,15 @@ def main():
                  "gcups": pstats[-1]["dtw_cells_sym"] / (pms / 1e3) / 1e9,
                  "gpu_ms": pst["ms_total"], "gpu_triplets_per_s": n_trip / (pst["ms_total"] / 1e3),
                  "abx_error": perrs[-1], "stages_ms": pst}
+        # the other distance the Score interface names, in the FP32 form
+        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool, distance="euclidean")
+        edt, estats, eerrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side,
+                                           not args.side_pool, distance="euclidean")
+        ems = edt / args.steps * 1e3
+        egpu = float(np.median([s_["ms_total"] for s_ in estats]))
+        log(f"euclidean fp32 form: {ems:.2f} ms/step pipelined, device {egpu:.2f} ms")
+        euclid = {"triplets_per_s": n_trip / (ems / 1e3), "ms_per_step": ems, "gpu_ms_pipelined": egpu,
+                  "gpu_triplets_per_s": n_trip / (egpu / 1e3), "abx_error": eerrs[-1]}
 
     # roofline of the dominant kernel, from the live HIP-event stage times
     dim, dim_pad = w.dim, (w.dim + 63) // 64 * 64
@@ -445,6 +454,7 @@ def main():
         "abx_error": errs[-1],
         "recheck_pairs": st0["n_recheck_pairs"], "nonrobust_pairs": st0["n_nonrobust_pairs"],
         "plain_fp32": plain,
+        "euclidean_fp32": euclid,
         "autotune": tune,
         "fused_config": {"cols": st0["fused_cols"], "blocks_per_cu": st0["fused_blocks_per_cu"]},
         "roofline": roof,

@@ -50,6 +50,7 @@ extern "C" {
 #define FABX_DTYPE_BF16 1
 
 #define FABX_DISTANCE_ANGULAR 0      /* theta(u, v) / pi, in [0, 1] */
+#define FABX_DISTANCE_EUCLIDEAN 1    /* |u - v| (FABX_PREC_FP32 only) */
 
 #define FABX_MODE_DTW 0              /* align frames with DTW */
 #define FABX_MODE_POOLED 1           /* mean over time, one vector per item */
@@ -165,7 +166,8 @@ int fabx_task_cell_sizes(const fabx_task *task, int64_t *n_triplets, int32_t *ab
 /* ----------------------------------------------------------------- score */
 
 typedef struct fabx_score_opts {
-    int32_t distance;    /* FABX_DISTANCE_ANGULAR */
+    int32_t distance;    /* FABX_DISTANCE_ANGULAR, or FABX_DISTANCE_EUCLIDEAN with
+                            FABX_PREC_FP32 (other precisions: FABX_EINVAL) */
     int32_t mode;        /* FABX_MODE_DTW | FABX_MODE_POOLED */
     int32_t precision;   /* FABX_PREC_FP32 | FABX_PREC_BF16_RECHECK */
     int32_t dtw_norm;    /* FABX_NORM_PATH | FABX_NORM_NONE */
@@ -195,14 +197,16 @@ int fabx_score_opts_default(fabx_score_opts *opts);
  * [d(x,a) = d(x,b)] in int64 "half units", so that D_C = W_C / (2 |C|)
  * (the cell discriminability formula of the Background section).
  *
- * d is the angular distance between frames (theta / pi), aligned with DTW
- * (c[0][0] = d00, cumulative first row and column, c[i][j] = d[i][j] +
- * min(c[i-1][j-1], c[i][j-1], c[i-1][j]), "Dynamic Time Warping on GPU"
- * section) and divided by the optimal path length for FABX_NORM_PATH, or the
- * angular distance between time-averaged frames for FABX_MODE_POOLED.
+ * d is the distance between frames named by opts->distance (angular: theta /
+ * pi; Euclidean: |u - v|, the other distance the Score interface names),
+ * aligned with DTW (c[0][0] = d00, cumulative first row and column, c[i][j] =
+ * d[i][j] + min(c[i-1][j-1], c[i][j-1], c[i-1][j]), "Dynamic Time Warping on
+ * GPU" section) and divided by the optimal path length for FABX_NORM_PATH, or
+ * the distance between time-averaged frames for FABX_MODE_POOLED.
  *
  * Synchronous on the context stream.  Errors: EINVAL (bad opts), EDOMAIN
- * (zero-norm frame / mean), ENOMEM (device workspace), EHIP. */
+ * (zero-norm frame / mean with the angular distance), ENOMEM (device
+ * workspace), EHIP. */
 int fabx_score(fabx_task *task, const fabx_score_opts *opts, fabx_result **out);
 
 /* The same score, returned as soon as its work is enqueued on the context

@@ -20,7 +20,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib as L
-from ._lib import (FABX_DTYPE_BF16, FABX_DTYPE_F32, FABX_MODE_DTW, FABX_MODE_POOLED, FABX_NORM_NONE,
+from ._lib import (FABX_DISTANCE_ANGULAR, FABX_DISTANCE_EUCLIDEAN, FABX_DTYPE_BF16, FABX_DTYPE_F32,
+                   FABX_MODE_DTW, FABX_MODE_POOLED, FABX_NORM_NONE,
                    FABX_NORM_PATH, FABX_PREC_BF16_RECHECK, FABX_PREC_FP32, fabx_dataset_desc,
                    fabx_score_opts, fabx_server_stats, fabx_stats)
 
@@ -248,8 +249,9 @@ def fabx_server_stats_get(srv) -> dict:
 
 def make_opts(mode: str = "dtw", precision: str = "bf16", norm: str = "path", margin: float = -1.0,
               delta: float = -1.0, keep_pairs: bool = False, fused_cols: int = 0,
-              fused_blocks_per_cu: int = 0) -> fabx_score_opts:
+              fused_blocks_per_cu: int = 0, distance: str = "angular") -> fabx_score_opts:
     o = fabx_score_opts_default()
+    o.distance = {"angular": FABX_DISTANCE_ANGULAR, "euclidean": FABX_DISTANCE_EUCLIDEAN}[distance]
     o.mode = {"dtw": FABX_MODE_DTW, "pooled": FABX_MODE_POOLED}[mode]
     o.precision = {"fp32": FABX_PREC_FP32, "bf16": FABX_PREC_BF16_RECHECK}[precision]
     o.dtw_norm = {"path": FABX_NORM_PATH, "none": FABX_NORM_NONE}[norm]

@@ -355,6 +355,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
 // score.cpp
 struct ScoreParams {
     int mode, precision, dtw_norm;
+    int distance;  // FABX_DISTANCE_*
     double margin, delta;
     bool keep_pairs;
     FusedConfig fused;  // cols > 0: use this instead of the tuning table

@@ -3,7 +3,9 @@
 //
 //  gram_angular_f32: per BY group, every pair of unit rows -> theta / pi in FP32
 //    (64 x 64 output tile per 256-thread block, 4 x 4 per thread, K staged
-//    through LDS in steps of 16), written to HBM.
+//    through LDS in steps of 16), written to HBM.  For the Euclidean distance
+//    the same tiles sum (u_k - v_k)^2 over raw rows (no cancellation of a
+//    norms-minus-dot form) and take the square root.
 //  dtw_plain: one wave per ordered item pair; lane i owns row i of the DTW
 //    matrix and the wave sweeps the anti-diagonals t = i + j, reading the
 //    distance matrix from HBM: the paper's wavefront scheme (one pair per
@@ -22,6 +24,7 @@ using dev::kWave;
 constexpr int kTile = 64;
 constexpr int kK = 16;
 
+template <bool kEuclid>
 __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restrict__ xn, int dim_pad,
                                                           const int64_t *__restrict__ row0,
                                                           const int64_t *__restrict__ nrows,
@@ -60,7 +63,14 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) {
+                    if (kEuclid) {
+                        const float d = av[i] - bv[j];
+                        acc[i][j] = fmaf(d, d, acc[i][j]);
+                    } else {
+                        acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+                    }
+                }
         }
         __syncthreads();
     }
@@ -73,8 +83,12 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
         for (int j = 0; j < 4; ++j) {
             const int64_t c = c0 + tx * 4 + j;
             if (c >= n) continue;
-            const float cs = fminf(fmaxf(acc[i][j], -1.0f), 1.0f);
-            o[r * n + c] = acosf(cs) * dev::kInvPi;
+            if (kEuclid) {
+                o[r * n + c] = __builtin_sqrtf(acc[i][j]);
+            } else {
+                const float cs = fminf(fmaxf(acc[i][j], -1.0f), 1.0f);
+                o[r * n + c] = acosf(cs) * dev::kInvPi;
+            }
         }
     }
     }
@@ -141,11 +155,15 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
 
 void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t *row0,
                       const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
-                      int64_t n_groups, int64_t n_tiles, float *out) {
+                      int64_t n_groups, int64_t n_tiles, float *out, int euclid) {
     if (n_tiles <= 0) return;
     if (dim_pad % kK) fail(FABX_EINVAL, "padded dim must be a multiple of 16");
-    hipLaunchKernelGGL(k_gram_angular_f32, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn, dim_pad,
-                       row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
+    if (euclid)
+        hipLaunchKernelGGL(k_gram_angular_f32<true>, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn,
+                           dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
+    else
+        hipLaunchKernelGGL(k_gram_angular_f32<false>, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn,
+                           dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
     FABX_HIP(hipGetLastError());
 }
 

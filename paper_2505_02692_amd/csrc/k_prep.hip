@@ -3,7 +3,12 @@
 // The angular distance only depends on directions, so every frame is scaled
 // to unit length once and packed in task order (frames of a BY group are
 // contiguous, row stride padded to a multiple of 64 with zeros) so that a
-// group's frame-distance matrix is one dense Gram product.
+// group's frame-distance matrix is one dense Gram product.  For the Euclidean
+// distance the frames (or means) are packed the same way, unscaled.
+//
+// out_form: kUnitF32 (FP32 unit rows), kUnitBF16 (BF16 unit rows + 1 / norm
+// of the rounded row), kRawF32 (FP32 rows as they are; no zero-norm check,
+// since a zero vector has a length).
 //
 // HBM-bound: one read of each feature row, one write of the packed row.
 // One 256-thread block per task item, each wave takes every 4th frame.
@@ -15,6 +20,8 @@ namespace kern {
 namespace {
 
 using dev::kWave;
+
+constexpr int kUnitF32 = 0, kUnitBF16 = 1, kRawF32 = 2;
 
 template <typename Tin>
 __device__ __forceinline__ void load_row_chunk(const Tin *row, int k, int dim, float v[4]);
@@ -47,10 +54,10 @@ __device__ __forceinline__ void load_row_chunk<uint16_t>(const uint16_t *row, in
 // Scale one row held as 4-element chunks (k = 4 * (lane + 64 * c)) and store it.
 template <int kChunks>
 __device__ __forceinline__ void store_unit_row(float (&v)[kChunks][4], float ss, int lane, int dim_pad,
-                                               int64_t out_row, void *out, int out_bf16,
+                                               int64_t out_row, void *out, int out_form,
                                                float *rinv) {
-    const float r = 1.0f / __builtin_sqrtf(ss);
-    if (!out_bf16) {
+    const float r = out_form == kRawF32 ? 1.0f : 1.0f / __builtin_sqrtf(ss);
+    if (out_form != kUnitBF16) {
         float *o = static_cast<float *>(out) + out_row * dim_pad;
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
                                                    const int64_t *__restrict__ item_src,
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst,
-                                                   void *out, int out_bf16, float *rinv, int *err,
+                                                   void *out, int out_form, float *rinv, int *err,
                                                    int64_t n_items, unsigned long long *err_item) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -118,7 +125,7 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
             }
         ss = dev::wave_sum(ss);
         su = dev::wave_sum(su);
-        if (!(ss > 0.0f) || !(su > 0.0f)) {
+        if (out_form != kRawF32 && (!(ss > 0.0f) || !(su > 0.0f))) {
             if (lane == 0) {
                 atomicExch(err, 1);
                 atomicMin(err_item, (unsigned long long)item);
@@ -126,8 +133,8 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
             ss = ss > 0.0f ? ss : 1.0f;
             su = su > 0.0f ? su : 1.0f;
         }
-        store_unit_row<kChunks>(v, ss, lane, dim_pad, d0 + t, out, out_bf16, rinv);
-        if (two) store_unit_row<kChunks>(u, su, lane, dim_pad, d0 + t + 4, out, out_bf16, rinv);
+        store_unit_row<kChunks>(v, ss, lane, dim_pad, d0 + t, out, out_form, rinv);
+        if (two) store_unit_row<kChunks>(u, su, lane, dim_pad, d0 + t + 4, out, out_form, rinv);
     }
     }
 }
@@ -136,7 +143,7 @@ template <typename Tin, int kChunks>
 __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ src, int dim, int dim_pad,
                                                         const int64_t *__restrict__ item_src,
                                                         const int32_t *__restrict__ item_len,
-                                                        int64_t n_items, void *out, int out_bf16,
+                                                        int64_t n_items, void *out, int out_form,
                                                         float *rinv, int *err,
                                                         unsigned long long *err_item) {
     // one wave per item
@@ -170,60 +177,60 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
             ss = fmaf(v[c][e], v[c][e], ss);
         }
     ss = dev::wave_sum(ss);
-    if (!(ss > 0.0f)) {
+    if (out_form != kRawF32 && !(ss > 0.0f)) {
         if (lane == 0) {
             atomicExch(err, 1);
             atomicMin(err_item, (unsigned long long)item);
         }
         ss = 1.0f;
     }
-    store_unit_row<kChunks>(v, ss, lane, dim_pad, item, out, out_bf16, rinv);
+    store_unit_row<kChunks>(v, ss, lane, dim_pad, item, out, out_form, rinv);
     }
 }
 
 template <int kChunks>
 void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
-                 const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+                 const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                  unsigned long long *err_item, bool pooled) {
     if (pooled) {
         dim3 grid(grid_for(it.n_items, 4));
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL((k_pool_normalize<float, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
-                               it.n_items, out, out_bf16, rinv, err, err_item);
+                               it.n_items, out, out_form, rinv, err, err_item);
         else
             hipLaunchKernelGGL((k_pool_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
-                               it.len, it.n_items, out, out_bf16, rinv, err, err_item);
+                               it.len, it.n_items, out, out_form, rinv, err, err_item);
     } else {
         dim3 grid(grid_for(it.n_items, 1));
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL((k_normalize<float, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
-                               it.dst, out, out_bf16, rinv, err, it.n_items, err_item);
+                               it.dst, out, out_form, rinv, err, it.n_items, err_item);
         else
             hipLaunchKernelGGL((k_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
-                               it.len, it.dst, out, out_bf16, rinv, err, it.n_items, err_item);
+                               it.len, it.dst, out, out_form, rinv, err, it.n_items, err_item);
     }
     FABX_HIP(hipGetLastError());
 }
 
 void dispatch(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
-              const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+              const ItemTables &it, void *out, int out_form, float *rinv, int *err,
               unsigned long long *err_item, bool pooled) {
     if (it.n_items <= 0) return;
     // chunks of 256 elements per wave pass
     const int chunks = (dim_pad + 255) / 256;
     switch (chunks) {
-        case 1: launch_norm<1>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 2: launch_norm<2>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 3: launch_norm<3>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 4: launch_norm<4>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 5: launch_norm<5>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 6: launch_norm<6>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 7: launch_norm<7>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
-        case 8: launch_norm<8>(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, pooled); break;
+        case 1: launch_norm<1>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 2: launch_norm<2>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 3: launch_norm<3>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 4: launch_norm<4>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 5: launch_norm<5>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 6: launch_norm<6>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 7: launch_norm<7>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 8: launch_norm<8>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
         default: fail(FABX_EINVAL, "feature dim above 2048 is not supported");
     }
 }
@@ -231,15 +238,15 @@ void dispatch(hipStream_t s, const void *features, int dtype, int dim, int dim_p
 }  // namespace
 
 void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
-               const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+               const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                unsigned long long *err_item) {
-    dispatch(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, false);
+    dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, false);
 }
 
 void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
-                    const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+                    const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                     unsigned long long *err_item) {
-    dispatch(s, features, dtype, dim, dim_pad, it, out, out_bf16, rinv, err, err_item, true);
+    dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, true);
 }
 
 }  // namespace kern

@@ -36,27 +36,30 @@ struct GroupTables {
 };
 
 // --- k_prep.hip
-// Unit-normalise every frame of every task item into the packed buffer
-// (row stride dim_pad, zero padded).  out_bf16 = 0: F32 rows; 1: BF16 rows plus
-// rinv[f] = 1 / ||bf16 row|| (F32).  A zero-norm frame sets err[0] = 1 and
-// lowers err_item (unsigned long long) to its task item.
+// Pack every frame of every task item into the packed buffer (row stride
+// dim_pad, zero padded).  out_form = 0: F32 unit rows; 1: BF16 unit rows plus
+// rinv[f] = 1 / ||bf16 row|| (F32); 2: F32 rows unscaled (Euclidean distance).
+// In forms 0 and 1 a zero-norm frame sets err[0] = 1 and lowers err_item
+// (unsigned long long) to its task item.
 void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
-               const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+               const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                unsigned long long *err_item);
 
 // Time pooling: mean of each item's frames (F32 accumulation), then the same
-// normalisation; one packed row per task item.
+// packing; one packed row per task item.
 void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
-                    const ItemTables &it, void *out, int out_bf16, float *rinv, int *err,
+                    const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                     unsigned long long *err_item);
 
 // --- k_plain.hip (plain FP32 form)
-// Per group: theta/pi of every pair of packed rows [row0, row0 + n) of the
-// group, into out[base + r * n + c].  rows/row0/base come from `frame0`,
-// `n_frames`, `dmat_base` (DTW mode) or item0 / n_items / pair_base (pooled mode).
+// Per group: the distance of every pair of packed rows [row0, row0 + n) of the
+// group, into out[base + r * n + c]: theta/pi of unit rows (euclid = 0) or the
+// length of the difference of raw rows (euclid = 1).  rows/row0/base come from
+// `frame0`, `n_frames`, `dmat_base` (DTW mode) or item0 / n_items / pair_base
+// (pooled mode).
 void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t *row0,
                       const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
-                      int64_t n_groups, int64_t n_tiles, float *out);
+                      int64_t n_groups, int64_t n_tiles, float *out, int euclid);
 
 // One wave per ordered item pair of each group: anti-diagonal DTW over the
 // group's F32 distance matrix (lane = row), exact diagonal > left > up

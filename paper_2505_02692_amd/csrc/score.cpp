@@ -191,7 +191,10 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     fabx_score_opts o;
     fabx_score_opts_default(&o);
     if (opts) o = *opts;
-    if (o.distance != FABX_DISTANCE_ANGULAR) fail(FABX_EINVAL, "only the angular distance is implemented");
+    if (o.distance != FABX_DISTANCE_ANGULAR && o.distance != FABX_DISTANCE_EUCLIDEAN)
+        fail(FABX_EINVAL, "bad distance");
+    if (o.distance == FABX_DISTANCE_EUCLIDEAN && o.precision != FABX_PREC_FP32)
+        fail(FABX_EINVAL, "the Euclidean distance is implemented in the FP32 form only");
     if (o.mode != FABX_MODE_DTW && o.mode != FABX_MODE_POOLED) fail(FABX_EINVAL, "bad mode");
     if (o.precision != FABX_PREC_FP32 && o.precision != FABX_PREC_BF16_RECHECK)
         fail(FABX_EINVAL, "bad precision");
@@ -201,6 +204,7 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     p.mode = o.mode;
     p.precision = o.precision;
     p.dtw_norm = o.dtw_norm;
+    p.distance = o.distance;
     p.margin = o.margin < 0 ? kMarginK / std::sqrt(double(ds.dim)) : o.margin;
     p.delta = o.delta < 0 ? kDeltaK / std::sqrt(double(ds.dim)) : o.delta;
     p.keep_pairs = o.keep_pairs != 0;
@@ -452,16 +456,18 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     kern::init_score(stream, ws.half_units.as<unsigned long long>(), n_cells);
     if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(ws.flags.ptr, 0, size_t(t.n_pair_slots), stream));
     tm.mark();  // 1
+    const bool euclid = p.distance == FABX_DISTANCE_EUCLIDEAN;  // FP32 form only
+    const int out_form = bf16 ? 1 : euclid ? 2 : 0;
     if (dtw)
-        kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, bf16 ? 1 : 0,
+        kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, out_form,
                         ws.rinv.as<float>(), err, err_item);
     else
-        kern::pool_normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, bf16 ? 1 : 0,
+        kern::pool_normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, out_form,
                              ws.rinv.as<float>(), err, err_item);
     tm.mark();  // 2
     if (dtw && !bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.frame0, gt.n_frames, gt.dmat_base,
-                               tiles_p, G, tiles.back(), ws.dmat.as<float>());
+                               tiles_p, G, tiles.back(), ws.dmat.as<float>(), euclid ? 1 : 0);
         kern::dtw_plain(stream, ws.dmat.as<float>(), gt, it, p.dtw_norm, ws.p32.as<float>());
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw) {
@@ -474,7 +480,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         st.computed_dtw_cells = cplan->cells;
     } else if (!bf16) {
         kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.item0, gt.n_items, gt.pair_base,
-                               tiles_p, G, tiles.back(), ws.p32.as<float>());
+                               tiles_p, G, tiles.back(), ws.p32.as<float>(), euclid ? 1 : 0);
     } else {
         kern::gram_angular_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt.item0,
                                 gt.n_items, gt.pair_base, tiles_p, G,

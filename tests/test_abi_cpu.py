@@ -145,6 +145,10 @@ def test_bad_score_options():
     o.distance = 3
     with pytest.raises(fx.FabxError):
         fx.fabx_score(t.h, o)
+    # the Euclidean distance exists in the FP32 form only
+    with pytest.raises(fx.FabxError) as e:
+        fx.fabx_score(t.h, fx.make_opts(distance="euclidean", precision="bf16"))
+    assert e.value.code == L.FABX_EINVAL and "Euclidean" in str(e.value)
     # a forced fused-kernel configuration must be one the kernel has
     for cols, bpc, msg in ((100, 0, "fused_cols"), (128, -1, "fused_blocks_per_cu"),
                            (256, 65, "fused_blocks_per_cu")):

@@ -593,6 +593,38 @@ def test_forced_fused_configs_equal_default():
     assert np.array_equal(t2.score().half_units, ref.half_units)
 
 
+# ------------------------------------------------- Euclidean distance --
+
+@pytest.mark.parametrize("mode,norm", [("dtw", "path"), ("dtw", "none"), ("pooled", "path")])
+def test_euclidean_fp32(mode, norm):
+    """The Euclidean distance in the FP32 form against the FP64 oracle: same
+    cells, ABX error within 1e-4 (the FP32 form's bar), every needed pair
+    distance within a relative 4 (dim + 64) 2^-24 (sums of non-negative
+    squares and costs in FP32), and no cell count off beyond rare near-tie
+    flips.  One frame is zero: it has a length, so it is scored."""
+    w = workloads.plain_c1(centroid_std=0.15)
+    feats = w.features.clone()
+    feats[int(w.offsets[5])] = 0.0
+    w.features = feats
+    _say(f"euclidean fp32 {mode} {norm} n_items={w.n_items}")
+    t, res = gpu_score(w, mode=mode, precision="fp32", norm=norm, distance="euclidean", keep_pairs=True)
+    orc = oracle.score(w.features_f32_host(), w.offsets, w.attrs, w.on, w.by, w.across, mode, norm,
+                       distance="euclidean")
+    assert np.array_equal(t.keys, orc.keys.astype(np.int32))
+    assert np.array_equal(t.sizes[0], orc.n_triplets)
+    xs, ys, want = all_oracle_pairs(orc)
+    f32, _, _ = res.pairs(xs, ys)
+    rel = np.abs(f32.astype(np.float64) - want) / np.maximum(want, 1e-30)
+    tol = 4 * (w.dim + 64) * 2.0 ** -24
+    mism = int(np.count_nonzero(res.half_units != orc.half_units))
+    e_gpu, e_orc = res.collapse(w.levels), oracle.error_rate(orc, w.levels)
+    print(f"  pairs={len(want)} max_rel={rel.max():.2e} tol={tol:.1e} mism={mism}/{len(orc.cells)} "
+          f"err={e_gpu:.6f} oracle_err={e_orc:.6f}", flush=True)
+    assert rel.max() <= tol
+    assert abs(e_gpu - e_orc) <= 1e-4
+    assert mism <= max(2, len(orc.cells) // 1000)
+
+
 # ------------------------------------------------------- stream ordering --
 
 def _slow_producer(dst, src):
