@@ -129,7 +129,33 @@ typedef struct fabx_dataset_desc {
 } fabx_dataset_desc;
 
 int fabx_dataset_create(fabx_ctx *ctx, const fabx_dataset_desc *desc, fabx_dataset **out);
+
+/* The same dataset with items given as windows of the feature rows: item i
+ * owns frames item_start[i] .. item_start[i] + item_len[i] - 1.  Windows may
+ * overlap and need not cover every row (say consecutive triphones sliced
+ * from the features of whole utterances, see fabx_slice_frames): nothing is
+ * copied.  features / dtype / n_frames / dim / attrs / n_attr as in
+ * fabx_dataset_desc (features BORROWED, item arrays and attrs copied).
+ * Errors: EINVAL for a null pointer, n_items < 1, dim < 1, n_attr < 1, an
+ * unknown dtype, an item_len < 1, or a window outside [0, n_frames). */
+int fabx_dataset_create_windows(fabx_ctx *ctx, const void *features, int32_t dtype, int64_t n_frames,
+                                int32_t dim, const int64_t *item_start, const int64_t *item_len,
+                                int64_t n_items, const int32_t *attrs, int32_t n_attr, fabx_dataset **out);
 void fabx_dataset_destroy(fabx_dataset *ds);
+
+/* Frames of aligned units (the "Slicing features" appendix).  Frame i of an
+ * utterance stands for time t_i = dt / 2 + i dt (dt: the constant step
+ * between feature frames, e.g. 0.02 s); unit k, [onset[k], offset[k]] in
+ * seconds, keeps the frames with onset <= t_i <= offset, i.e. i_start =
+ * ceil(onset / dt - 1/2) .. i_end = floor(offset / dt - 1/2), both included,
+ * computed in FP64 (i_start no lower than 0).  libri_light != 0 reproduces
+ * the slicing of the Libri-Light evaluation, which dropped frame i_end.
+ * Outputs start[k] = i_start and len[k] = frames kept (0 when none; the
+ * caller decides what an empty unit means).  Errors: EINVAL for a null
+ * pointer, n < 0, dt not positive and finite, or a unit without 0 <= onset
+ * <= offset (finite). */
+int fabx_slice_frames(const double *onset, const double *offset, int64_t n, double dt, int libri_light,
+                      int64_t *start, int64_t *len);
 
 /* ------------------------------------------------------------------ task */
 

@@ -18,6 +18,8 @@ Every function follows a passage of the paper (Poli, Chemla, Dupoux,
 * ``cell_half_units``  -- the cell discriminability formula D_C (Background).
 * ``collapse``         -- the weighted average of D_C, or averaging across
                           attributes level by level (Score / collapse).
+* ``slice_frames``     -- the frames kept for an aligned unit ("Slicing
+                          features" appendix), from the set definition.
 
 Readings where the paper is silent:
 a == x is excluded when A and X are the same set; cells are ordered (o1, o2);
@@ -115,6 +117,23 @@ def dtw(d: np.ndarray, norm: str = "path") -> Tuple[float, int]:
     if rc != 0:
         raise ValueError("dtw: empty matrix")
     return out.value, int(ln.value)
+
+
+# ------------------------------------------------------------------ slicing --
+
+def slice_frames(onset: float, offset: float, dt: float, libri_light: bool = False) -> Tuple[int, int]:
+    """(first frame, frame count) of a unit [onset, offset]: the set
+    {i in N : onset <= t_i <= offset} with t_i = dt / 2 + i dt, scanned frame by
+    frame in FP64; the Libri-Light slicing drops the last frame of the set."""
+    kept = []
+    i = 0
+    while dt / 2 + i * dt <= offset:
+        if onset <= dt / 2 + i * dt:
+            kept.append(i)
+        i += 1
+    if libri_light and kept:
+        kept = kept[:-1]
+    return (kept[0] if kept else 0), len(kept)
 
 
 # -------------------------------------------------------------------- cells --

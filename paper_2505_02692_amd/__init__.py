@@ -26,7 +26,7 @@ from ._lib import (FABX_DISTANCE_ANGULAR, FABX_DISTANCE_EUCLIDEAN, FABX_DTYPE_BF
                    fabx_score_opts, fabx_server_stats, fabx_stats)
 
 __all__ = ["FabxError", "Context", "Dataset", "Task", "Result", "Server", "make_opts", "lib",
-           "fabx_set_thread_serial"]
+           "fabx_set_thread_serial", "fabx_slice_frames", "read_item_file"]
 
 
 class FabxError(RuntimeError):
@@ -84,8 +84,62 @@ def fabx_dataset_create(ctx, features_ptr: int, dtype: int, n_frames: int, dim: 
     return h
 
 
+def fabx_dataset_create_windows(ctx, features_ptr: int, dtype: int, n_frames: int, dim: int,
+                                item_start: np.ndarray, item_len: np.ndarray,
+                                attrs: np.ndarray) -> ctypes.c_void_p:
+    item_start = np.ascontiguousarray(item_start, dtype=np.int64)
+    item_len = np.ascontiguousarray(item_len, dtype=np.int64)
+    attrs = np.ascontiguousarray(attrs, dtype=np.int32)
+    if attrs.ndim == 1:
+        attrs = attrs[:, None]
+    if not (len(item_start) == len(item_len) == attrs.shape[0]):
+        raise ValueError("item_start, item_len and attrs must have one entry per item")
+    h = ctypes.c_void_p()
+    _check(lib().fabx_dataset_create_windows(ctx, features_ptr, dtype, int(n_frames), int(dim), _i64p(item_start),
+                                             _i64p(item_len), int(attrs.shape[0]), _i32p(attrs),
+                                             int(attrs.shape[1]), ctypes.byref(h)))
+    return h
+
+
 def fabx_dataset_destroy(ds) -> None:
     lib().fabx_dataset_destroy(ds)
+
+
+def fabx_slice_frames(onset, offset, frame_step: float, libri_light: bool = False):
+    """Frames kept for aligned units [onset, offset] (seconds): (start, len) int64 arrays."""
+    onset = np.ascontiguousarray(onset, dtype=np.float64)
+    offset = np.ascontiguousarray(offset, dtype=np.float64)
+    if onset.shape != offset.shape or onset.ndim != 1:
+        raise ValueError("onset and offset must be 1-D arrays of one length")
+    start = np.zeros(len(onset), np.int64)
+    length = np.zeros(len(onset), np.int64)
+    _check(lib().fabx_slice_frames(onset.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   offset.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(onset),
+                                   float(frame_step), 1 if libri_light else 0, _i64p(start), _i64p(length)))
+    return start, length
+
+
+def read_item_file(path: str):
+    """An item file: a header "#file onset offset #<attr> <attr> ..." and one
+    line per unit "<file> <onset> <offset> <value> ...".  Returns (attribute
+    names, files, onsets, offsets, values [n_units][n_attr] as strings)."""
+    with open(path) as f:
+        header = f.readline().split()
+        if len(header) < 4 or header[0] != "#file" or header[1:3] != ["onset", "offset"]:
+            raise ValueError(f"{path}: the header must start with '#file onset offset'")
+        names = [h.lstrip("#") for h in header[3:]]
+        files, on, off, vals = [], [], [], []
+        for ln, line in enumerate(f, start=2):
+            parts = line.split()
+            if not parts:
+                continue
+            if len(parts) != 3 + len(names):
+                raise ValueError(f"{path}:{ln}: expected {3 + len(names)} columns, got {len(parts)}")
+            files.append(parts[0])
+            on.append(float(parts[1]))
+            off.append(float(parts[2]))
+            vals.append(parts[3:])
+    return names, files, np.array(on, np.float64), np.array(off, np.float64), vals
 
 
 def fabx_task_create(ds, on: int, by: Sequence[int], across: Sequence[int]) -> ctypes.c_void_p:
@@ -308,6 +362,64 @@ class Dataset:
             dtype = {torch.float32: FABX_DTYPE_F32, torch.bfloat16: FABX_DTYPE_BF16}[features.dtype]
             ptr, nf, dim = features.data_ptr(), int(features.shape[0]), int(features.shape[1])
         self.h = fabx_dataset_create(ctx.h, ptr, dtype, nf, dim, offsets, attrs)
+
+    @classmethod
+    def windows(cls, ctx: Context, features, item_start, item_len, attrs) -> "Dataset":
+        """Items as windows features[item_start[i] : item_start[i] + item_len[i]]
+        of one feature tensor; windows may overlap (no copy is made)."""
+        import torch
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.features = features
+        if not features.is_contiguous():
+            raise ValueError("features must be contiguous")
+        dtype = {torch.float32: FABX_DTYPE_F32, torch.bfloat16: FABX_DTYPE_BF16}[features.dtype]
+        self.h = fabx_dataset_create_windows(ctx.h, features.data_ptr(), dtype, int(features.shape[0]),
+                                             int(features.shape[1]), item_start, item_len, attrs)
+        return self
+
+    @classmethod
+    def from_item_file(cls, ctx: Context, item_path: str, features, frame_step: float,
+                       libri_light: bool = False):
+        """A dataset from an item file and the features of whole files.
+
+        ``features`` maps each file name of the item file to its feature tensor
+        [n_frames, dim] on the context's device (frame i at time frame_step / 2
+        + i frame_step).  Each unit keeps the frames fabx_slice_frames gives
+        (libri_light: the Libri-Light slicing, one frame fewer); a unit with no
+        frame, or one past the end of its file's frames, raises ValueError.
+        The file tensors are concatenated once on the device and every unit is
+        a window of the result.  Attribute columns are label-encoded in sorted
+        order of their values.  Returns (dataset, names, vocab): vocab[j][v] is
+        the value behind code v of attribute column j (names[j])."""
+        import torch
+        names, files, onset, offset, vals = read_item_file(item_path)
+        if not files:
+            raise ValueError(f"{item_path}: no unit")
+        order = sorted(set(files))
+        missing = [f for f in order if f not in features]
+        if missing:
+            raise ValueError(f"no features for file {missing[0]!r}")
+        base, n = {}, 0
+        for f in order:
+            base[f] = n
+            n += int(features[f].shape[0])
+        start, length = fabx_slice_frames(onset, offset, frame_step, libri_light)
+        for k, f in enumerate(files):
+            if length[k] < 1:
+                raise ValueError(f"unit {k} ({f} {onset[k]} {offset[k]}) keeps no frame")
+            if start[k] + length[k] > int(features[f].shape[0]):
+                raise ValueError(f"unit {k} ({f} {onset[k]} {offset[k]}) ends past the file's "
+                                 f"{int(features[f].shape[0])} frames")
+        feats = torch.cat([features[f] for f in order]).contiguous()
+        item_start = np.array([base[f] for f in files], np.int64) + start
+        cols = np.array(vals, dtype=object).reshape(len(files), len(names))
+        vocab, codes = [], np.zeros((len(files), len(names)), np.int32)
+        for j in range(len(names)):
+            v, c = np.unique(cols[:, j].astype(str), return_inverse=True)
+            vocab.append(v)
+            codes[:, j] = c
+        return cls.windows(ctx, feats, item_start, length, codes), names, vocab
 
     def __del__(self):
         if getattr(self, "h", None) and L is not None and L._lib is not None:

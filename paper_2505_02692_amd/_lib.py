@@ -97,7 +97,11 @@ SIGNATURES = {
     "fabx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _vp]),
     "fabx_destroy": (None, [_vp]),
     "fabx_dataset_create": (ctypes.c_int, [_vp, _P(fabx_dataset_desc), _P(_vp)]),
+    "fabx_dataset_create_windows": (ctypes.c_int, [_vp, _vp, _i32, _i64, _i32, _P(_i64), _P(_i64), _i64,
+                                                   _P(_i32), _i32, _P(_vp)]),
     "fabx_dataset_destroy": (None, [_vp]),
+    "fabx_slice_frames": (ctypes.c_int, [_P(ctypes.c_double), _P(ctypes.c_double), _i64, ctypes.c_double,
+                                         ctypes.c_int, _P(_i64), _P(_i64)]),
     "fabx_task_create": (ctypes.c_int, [_vp, _i32, _P(_i32), _i32, _P(_i32), _i32, _P(_vp)]),
     "fabx_task_destroy": (None, [_vp]),
     "fabx_task_num_cells": (_i64, [_vp]),

@@ -1,5 +1,7 @@
 // C ABI of fastabx-hip: argument checks, handle management, error codes.
 #include <algorithm>
+#include <cstdint>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -275,34 +277,86 @@ int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
 
 void fabx_destroy(fabx_ctx *ctx) { delete ctx; }
 
+namespace {
+
+// The checks and fields common to both dataset constructors; items are filled
+// by the caller.
+std::shared_ptr<DatasetImpl> new_dataset(fabx_ctx *ctx, const void *features, int32_t dtype, int64_t n_frames,
+                                         int32_t dim, int64_t n_items, const int32_t *attrs, int32_t n_attr) {
+    if (n_items < 1) fail(FABX_EINVAL, "n_items must be >= 1");
+    if (dim < 1) fail(FABX_EINVAL, "dim must be >= 1");
+    if (n_attr < 1) fail(FABX_EINVAL, "n_attr must be >= 1");
+    if (dtype != FABX_DTYPE_F32 && dtype != FABX_DTYPE_BF16) fail(FABX_EINVAL, "unknown dtype");
+    if (!attrs) fail(FABX_EINVAL, "attrs is NULL");
+    if (!features && ctx->p->device >= 0) fail(FABX_EINVAL, "features is NULL");
+    auto ds = std::make_shared<DatasetImpl>();
+    ds->ctx = ctx->p;
+    ds->features = features;
+    ds->dtype = dtype;
+    ds->n_frames = n_frames;
+    ds->dim = dim;
+    ds->n_items = n_items;
+    ds->n_attr = n_attr;
+    ds->attrs.assign(attrs, attrs + n_items * int64_t(n_attr));
+    ds->item_start.resize(size_t(n_items));
+    ds->item_len.resize(size_t(n_items));
+    return ds;
+}
+
+void set_item(DatasetImpl &ds, int64_t i, int64_t start, int64_t len) {
+    if (len < 1) fail(FABX_EINVAL, "item " + std::to_string(i) + " has no frame");
+    if (len > INT32_MAX) fail(FABX_EINVAL, "item " + std::to_string(i) + " is too long");
+    if (start < 0 || start > ds.n_frames - len)
+        fail(FABX_EINVAL, "item " + std::to_string(i) + " lies outside the feature rows");
+    ds.item_start[size_t(i)] = start;
+    ds.item_len[size_t(i)] = int32_t(len);
+    if (len > ds.max_len) ds.max_len = int(len);
+}
+
+}  // namespace
+
 int fabx_dataset_create(fabx_ctx *ctx, const fabx_dataset_desc *d, fabx_dataset **out) {
     return guarded([&] {
         if (!ctx || !d || !out) fail(FABX_EINVAL, "null argument");
         *out = nullptr;
-        if (d->n_items < 1) fail(FABX_EINVAL, "n_items must be >= 1");
-        if (d->dim < 1) fail(FABX_EINVAL, "dim must be >= 1");
-        if (d->n_attr < 1) fail(FABX_EINVAL, "n_attr must be >= 1");
-        if (d->dtype != FABX_DTYPE_F32 && d->dtype != FABX_DTYPE_BF16) fail(FABX_EINVAL, "unknown dtype");
-        if (!d->offsets || !d->attrs) fail(FABX_EINVAL, "offsets / attrs is NULL");
-        if (!d->features && ctx->p->device >= 0) fail(FABX_EINVAL, "features is NULL");
+        if (!d->offsets) fail(FABX_EINVAL, "offsets is NULL");
+        auto ds = new_dataset(ctx, d->features, d->dtype, d->n_frames, d->dim, d->n_items, d->attrs, d->n_attr);
         if (d->offsets[0] != 0) fail(FABX_EINVAL, "offsets[0] must be 0");
-        auto ds = std::make_shared<DatasetImpl>();
-        ds->ctx = ctx->p;
-        ds->features = d->features;
-        ds->dtype = d->dtype;
-        ds->n_frames = d->n_frames;
-        ds->dim = d->dim;
-        ds->n_items = d->n_items;
-        ds->n_attr = d->n_attr;
-        ds->offsets.assign(d->offsets, d->offsets + d->n_items + 1);
-        for (int64_t i = 0; i < d->n_items; ++i) {
-            const int64_t L = ds->offsets[i + 1] - ds->offsets[i];
-            if (L < 1) fail(FABX_EINVAL, "item " + std::to_string(i) + " has no frame");
-            if (L > ds->max_len) ds->max_len = int(L);
-        }
-        if (ds->offsets[d->n_items] != d->n_frames) fail(FABX_EINVAL, "offsets[n_items] != n_frames");
-        ds->attrs.assign(d->attrs, d->attrs + d->n_items * int64_t(d->n_attr));
+        for (int64_t i = 0; i < d->n_items; ++i) set_item(*ds, i, d->offsets[i], d->offsets[i + 1] - d->offsets[i]);
+        if (d->offsets[d->n_items] != d->n_frames) fail(FABX_EINVAL, "offsets[n_items] != n_frames");
         *out = new fabx_dataset{ds};
+    });
+}
+
+int fabx_dataset_create_windows(fabx_ctx *ctx, const void *features, int32_t dtype, int64_t n_frames,
+                                int32_t dim, const int64_t *item_start, const int64_t *item_len,
+                                int64_t n_items, const int32_t *attrs, int32_t n_attr, fabx_dataset **out) {
+    return guarded([&] {
+        if (!ctx || !out || !item_start || !item_len) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        auto ds = new_dataset(ctx, features, dtype, n_frames, dim, n_items, attrs, n_attr);
+        for (int64_t i = 0; i < n_items; ++i) set_item(*ds, i, item_start[i], item_len[i]);
+        *out = new fabx_dataset{ds};
+    });
+}
+
+int fabx_slice_frames(const double *onset, const double *offset, int64_t n, double dt, int libri_light,
+                      int64_t *start, int64_t *len) {
+    return guarded([&] {
+        if (n < 0 || (n > 0 && (!onset || !offset || !start || !len))) fail(FABX_EINVAL, "null argument");
+        if (!(dt > 0.0) || !std::isfinite(dt)) fail(FABX_EINVAL, "the frame step must be positive and finite");
+        for (int64_t k = 0; k < n; ++k) {
+            const double a = onset[k], b = offset[k];
+            if (!std::isfinite(a) || !std::isfinite(b) || a < 0.0 || a > b)
+                fail(FABX_EINVAL, "unit " + std::to_string(k) + ": need 0 <= onset <= offset");
+            // frame i has time dt / 2 + i dt; kept when onset <= t_i <= offset
+            const double first = std::ceil(a / dt - 0.5), last = std::floor(b / dt - 0.5);
+            if (first > 9.0e15 || last > 9.0e15) fail(FABX_EINVAL, "unit " + std::to_string(k) + " is too far");
+            const int64_t i0 = std::max<int64_t>(0, int64_t(first));
+            const int64_t i1 = int64_t(last) - (libri_light ? 1 : 0);
+            start[k] = i0;
+            len[k] = std::max<int64_t>(0, i1 - i0 + 1);
+        }
     });
 }
 

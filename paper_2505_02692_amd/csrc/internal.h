@@ -174,7 +174,8 @@ struct DatasetImpl {
     int64_t n_items = 0;
     int n_attr = 0;
     int max_len = 0;
-    std::vector<int64_t> offsets;     // [n_items + 1]
+    std::vector<int64_t> item_start;  // [n_items]: first frame of each item
+    std::vector<int32_t> item_len;    // [n_items]: its frames (>= 1); items may overlap
     std::vector<int32_t> attrs;       // [n_items * n_attr]
 };
 

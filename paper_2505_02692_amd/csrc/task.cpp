@@ -753,7 +753,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         parallel_for(nc, [&](int c) {
             int64_t f = 0, q = 0;
             for (int64_t s = c * kChunk; s < std::min<int64_t>(n, (c + 1) * kChunk); ++s) {
-                const int64_t L = ds->offsets[order[s] + 1] - ds->offsets[order[s]];
+                const int64_t L = ds->item_len[size_t(order[s])];
                 len_s[s] = int32_t(L);
                 f += L;
                 q += L * L;
@@ -916,7 +916,7 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
                 const int64_t it = order[s];
                 t->items[q] = it;
                 t->item_pos_of[it] = q;
-                t->item_src[q] = ds->offsets[it];
+                t->item_src[q] = ds->item_start[size_t(it)];
                 t->item_len[q] = len_s[s];
                 t->item_dst[q] = frame;
                 t->item_group[q] = int32_t(gi);
