@@ -625,6 +625,60 @@ def test_euclidean_fp32(mode, norm):
     assert mism <= max(2, len(orc.cells) // 1000)
 
 
+# ----------------------------------------------------- item-file front end --
+
+@pytest.mark.parametrize("libri_light", [False, True])
+def test_item_file_dataset_scores_like_its_copy(tmp_path, libri_light):
+    """Units sliced from whole-utterance features through an item file
+    (overlapping windows, no copy) give the per-cell counts of a contiguous
+    copy of their frames, and the oracle's on that copy."""
+    _say(f"item file front end libri_light={libri_light}")
+    rng = np.random.default_rng(91)
+    dt, dim = 0.02, 32
+    cent = {p: rng.standard_normal(dim).astype(np.float32) for p in "aeioumn"}
+    utts, rows = {}, []
+    for k in range(12):
+        T = int(rng.integers(60, 160))
+        name, spk = f"utt{k}", f"s{k % 3}"
+        labels = rng.choice(list(cent), (T + 3) // 4)
+        frames = np.stack([cent[labels[i // 4]] for i in range(T)]) + \
+            0.8 * rng.standard_normal((T, dim)).astype(np.float32)
+        utts[name] = torch.tensor(frames)
+        t = 0.0
+        while True:
+            dur = float(rng.uniform(0.05, 0.2))
+            if t + dur > T * dt - dt:
+                break
+            mid = labels[min(int((t + dur / 2) / dt) // 4, len(labels) - 1)]
+            rows.append((name, round(t, 4), round(t + dur, 4), mid, spk))
+            t += float(rng.uniform(0.03, 0.08))      # steps shorter than units: windows overlap
+    path = str(tmp_path / "units.item")
+    with open(path, "w") as f:
+        f.write("#file onset offset #phone speaker\n")
+        for r in rows:
+            f.write(" ".join(str(v) for v in r) + "\n")
+    ds, names, vocab = fx.Dataset.from_item_file(ctx(), path, {k: v.cuda() for k, v in utts.items()}, dt,
+                                                 libri_light)
+    on, spk = names.index("phone"), names.index("speaker")
+    t = fx.Task(ds, on, [spk], [])
+    res = t.score()
+    # the same units as a contiguous copy, on the host
+    files = [r[0] for r in rows]
+    start, length = fx.fabx_slice_frames([r[1] for r in rows], [r[2] for r in rows], dt, libri_light)
+    copy = np.concatenate([utts[f].numpy()[s0:s0 + n] for f, s0, n in zip(files, start, length)])
+    off = np.concatenate([[0], np.cumsum(length)]).astype(np.int64)
+    codes = np.stack([np.unique(np.array([r[3] for r in rows]), return_inverse=True)[1],
+                      np.unique(np.array([r[4] for r in rows]), return_inverse=True)[1]], 1).astype(np.int32)
+    tc = fx.Task(fx.Dataset(ctx(), torch.tensor(copy).cuda(), off, codes), on, [spk], [])
+    rc = tc.score()
+    orc = oracle.score(copy, off, codes, on, [spk], [])
+    print(f"  units={len(rows)} cells={len(orc.cells)} frames kept={int(length.sum())}", flush=True)
+    assert len(orc.cells) > 50
+    assert np.array_equal(t.keys, tc.keys)
+    assert np.array_equal(res.half_units, rc.half_units)
+    assert np.array_equal(res.half_units, orc.half_units)
+
+
 # ------------------------------------------------------- stream ordering --
 
 def _slow_producer(dst, src):
