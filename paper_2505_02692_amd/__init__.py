@@ -26,7 +26,7 @@ from ._lib import (FABX_DISTANCE_ANGULAR, FABX_DISTANCE_EUCLIDEAN, FABX_DTYPE_BF
                    fabx_score_opts, fabx_server_stats, fabx_stats)
 
 __all__ = ["FabxError", "Context", "Dataset", "Task", "Result", "Server", "make_opts", "lib",
-           "fabx_set_thread_serial", "fabx_slice_frames", "read_item_file"]
+           "fabx_set_thread_serial", "fabx_slice_frames", "read_item_file", "zerospeech_abx"]
 
 
 class FabxError(RuntimeError):
@@ -538,3 +538,37 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def zerospeech_abx(ctx: Context, item_path: str, features, frame_step: float, speaker: str = "within",
+                   context: str = "within", distance: str = "angular", mode: str = "dtw",
+                   precision: Optional[str] = None, libri_light: bool = False) -> float:
+    """The phoneme / triphone ABX error rate as the ZeroSpeech challenges
+    computed it, from an item file with columns phone, prev-phone, next-phone
+    and speaker (and the features of whole utterances, as in
+    Dataset.from_item_file).
+
+    ON phone, BY context (prev-phone, next-phone) when ``context`` is
+    "within" (none for "any"), and BY speaker ("within") or ACROSS speaker
+    ("across"); cell scores are averaged over contexts, then over speakers,
+    then over phone pairs (the collapse levels [context], [speaker]).
+    ``precision`` defaults to "bf16" for the angular distance and "fp32" for
+    the Euclidean one (the only form it has)."""
+    if speaker not in ("within", "across"):
+        raise ValueError("speaker must be 'within' or 'across'")
+    if context not in ("within", "any"):
+        raise ValueError("context must be 'within' or 'any'")
+    ds, names, _ = Dataset.from_item_file(ctx, item_path, features, frame_step, libri_light)
+    need = ["phone", "speaker"] + (["prev-phone", "next-phone"] if context == "within" else [])
+    missing = [n for n in need if n not in names]
+    if missing:
+        raise ValueError(f"{item_path}: no column {missing[0]!r} (columns: {names})")
+    on, spk = names.index("phone"), names.index("speaker")
+    ctx_cols = [names.index("prev-phone"), names.index("next-phone")] if context == "within" else []
+    by = ctx_cols + ([spk] if speaker == "within" else [])
+    across = [spk] if speaker == "across" else []
+    if precision is None:
+        precision = "fp32" if distance == "euclidean" else "bf16"
+    res = Task(ds, on, by, across).score(mode=mode, precision=precision, distance=distance)
+    levels = ([ctx_cols] if ctx_cols else []) + [[spk]]
+    return res.collapse(levels)

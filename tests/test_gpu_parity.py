@@ -679,6 +679,79 @@ def test_item_file_dataset_scores_like_its_copy(tmp_path, libri_light):
     assert np.array_equal(res.half_units, orc.half_units)
 
 
+def _triphone_items(rng, path, n_utts=16, phones="aei", dim=32, dt=0.02):
+    """Synthetic utterances of 4-frame phone segments and an item file of
+    overlapping triphone-like units over them (phone, prev-phone, next-phone,
+    speaker columns); returns the per-utterance features and the rows."""
+    cent = {p: 0.3 * rng.standard_normal(dim).astype(np.float32) for p in phones}
+    utts, rows = {}, []
+    for k in range(n_utts):
+        T = int(rng.integers(80, 200))
+        name, spk = f"utt{k}", f"s{k % 4}"
+        labels = rng.choice(list(phones), (T + 3) // 4)
+        utts[name] = torch.tensor(np.stack([cent[labels[i // 4]] for i in range(T)]) +
+                                  0.8 * rng.standard_normal((T, dim)).astype(np.float32))
+        for j in range(1, len(labels) - 2):
+            on, off = 4 * j * dt + float(rng.uniform(-0.01, 0.01)), 4 * (j + 1) * dt + float(rng.uniform(-0.01, 0.01))
+            rows.append((name, round(max(on, 0.0), 4), round(off, 4), labels[j], labels[j - 1], labels[j + 1], spk))
+    with open(path, "w") as f:
+        f.write("#file onset offset #phone prev-phone next-phone speaker\n")
+        for r in rows:
+            f.write(" ".join(str(v) for v in r) + "\n")
+    return utts, rows
+
+
+@pytest.mark.parametrize("speaker,context", [("within", "within"), ("across", "within"), ("within", "any")])
+def test_zerospeech_abx_matches_oracle(tmp_path, speaker, context):
+    """zerospeech_abx (item file -> slices -> ON phone, BY context, BY / ACROSS
+    speaker -> averages over contexts, then speakers, then phone pairs) equals
+    the oracle's error rate on a contiguous copy of the sliced units."""
+    _say(f"zerospeech_abx speaker={speaker} context={context}")
+    rng = np.random.default_rng(92)
+    dt = 0.02
+    path = str(tmp_path / "tri.item")
+    utts, rows = _triphone_items(rng, path, dt=dt)
+    err = fx.zerospeech_abx(ctx(), path, {k: v.cuda() for k, v in utts.items()}, dt, speaker, context)
+    start, length = fx.fabx_slice_frames([r[1] for r in rows], [r[2] for r in rows], dt)
+    copy = np.concatenate([utts[r[0]].numpy()[s0:s0 + n] for r, s0, n in zip(rows, start, length)])
+    off = np.concatenate([[0], np.cumsum(length)]).astype(np.int64)
+    codes = np.stack([np.unique(np.array([r[c] for r in rows]), return_inverse=True)[1] for c in (3, 4, 5, 6)],
+                     1).astype(np.int32)
+    phone, prev, nxt, spk = 0, 1, 2, 3
+    ctx_cols = [prev, nxt] if context == "within" else []
+    by = ctx_cols + ([spk] if speaker == "within" else [])
+    across = [spk] if speaker == "across" else []
+    orc = oracle.score(copy, off, codes, phone, by, across)
+    levels = ([ctx_cols] if ctx_cols else []) + [[spk]]
+    e_orc = oracle.error_rate(orc, levels)
+    print(f"  units={len(rows)} cells={len(orc.cells)} err={err:.6f} oracle_err={e_orc:.6f}", flush=True)
+    assert len(orc.cells) > 20
+    assert abs(err - e_orc) <= 1e-12
+
+
+def test_zerospeech_command_line(tmp_path):
+    """python -m paper_2505_02692_amd ITEM DIR --frame-step: the same error rate
+    as zerospeech_abx, from per-utterance .npy files."""
+    import json
+    import os
+    import subprocess
+    _say("zerospeech command line")
+    rng = np.random.default_rng(93)
+    path = str(tmp_path / "tri.item")
+    utts, _ = _triphone_items(rng, path, n_utts=8)
+    fdir = tmp_path / "feats"
+    fdir.mkdir()
+    for k, v in utts.items():
+        np.save(str(fdir / (k + ".npy")), v.numpy())
+    want = fx.zerospeech_abx(ctx(), path, {k: v.cuda() for k, v in utts.items()}, 0.02, "across")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-m", "paper_2505_02692_amd", path, str(fdir), "--frame-step", "0.02",
+                          "--speaker", "across"], capture_output=True, text=True, timeout=240, cwd=root)
+    assert out.returncode == 0, out.stderr[-2000:]
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    assert got["abx_error"] == want and got["speaker"] == "across"
+
+
 # ------------------------------------------------------- stream ordering --
 
 def _slow_producer(dst, src):

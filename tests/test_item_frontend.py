@@ -120,3 +120,20 @@ def test_bad_windows_are_rejected(start, length):
         fx.Dataset.windows(fx.Context(-1), torch.zeros(10, 4), np.array(start), np.array(length),
                            np.zeros((2, 1), np.int32))
     assert e.value.code == L.FABX_EINVAL
+
+
+def test_zerospeech_abx_checks_arguments_and_columns(tmp_path):
+    import torch
+    p = str(tmp_path / "a.item")
+    with open(p, "w") as f:
+        f.write("#file onset offset #phone speaker\nu1 0.0 0.1 a s1\n")
+    feats = {"u1": torch.zeros(10, 4)}
+    ctx = fx.Context(-1)
+    with pytest.raises(ValueError, match="speaker"):
+        fx.zerospeech_abx(ctx, p, feats, 0.02, speaker="both")
+    with pytest.raises(ValueError, match="context"):
+        fx.zerospeech_abx(ctx, p, feats, 0.02, context="none")
+    with pytest.raises(ValueError, match="prev-phone"):
+        fx.zerospeech_abx(ctx, p, feats, 0.02)              # context 'within' needs the context columns
+    with pytest.raises(ValueError, match="no features"):
+        fx.zerospeech_abx(ctx, p, {}, 0.02, context="any")
