@@ -836,6 +836,52 @@ def test_large_groups_sampled_pairs(n_items):
 
 # ----------------------------------------------- full-size bench workload --
 
+def _groups_subset(w, by_values):
+    """The items of the given BY groups (tuples of w.by values) as a small
+    host dataset: frames (float32), offsets, attrs."""
+    mask = np.zeros(w.n_items, bool)
+    for v in by_values:
+        m = np.ones(w.n_items, bool)
+        for col, val in zip(w.by, v):
+            m &= w.attrs[:, col] == val
+        mask |= m
+    items = np.nonzero(mask)[0]
+    feats = w.features.float()
+    frames = [feats[int(w.offsets[i]):int(w.offsets[i + 1])].cpu().numpy() for i in items]
+    off = np.concatenate([[0], np.cumsum([len(f) for f in frames])]).astype(np.int64)
+    return np.concatenate(frames), off, np.ascontiguousarray(w.attrs[items])
+
+
+def test_across_c3_full_size_sampled_groups():
+    """The across-speaker workload at full size (200k items, dim 1024, 30.9M
+    cells) in the bench's configuration: every cell of 2 sampled BY groups
+    equals the oracle's, run on those groups' items (cells never span BY
+    groups)."""
+    w = workloads.across_c3(device="cuda")
+    _say(f"across-c3 full size n_items={w.n_items}")
+    t, res = gpu_score(w)
+    keys, hu = t.keys, res.half_units
+    nb = len(w.by)
+    gkeys = [tuple(int(v) for v in k[2:2 + nb]) for k in keys]
+    per_group = {}
+    for g in gkeys:
+        per_group[g] = per_group.get(g, 0) + 1
+    mid = sorted(g for g, n in per_group.items() if 2000 <= n <= 15000)   # groups of moderate size
+    rng = np.random.default_rng(5)
+    chosen = [mid[i] for i in rng.choice(len(mid), 2, replace=False)]
+    feats, off, attrs = _groups_subset(w, chosen)
+    print(f"  scored {len(keys)} cells on the GPU; oracle on {len(off) - 1} items of groups {chosen}", flush=True)
+    orc = oracle.score(feats, off, attrs, w.on, w.by, w.across)
+    where = {tuple(int(v) for v in k): c for c, k in enumerate(keys)}
+    idx = np.array([where[tuple(int(v) for v in k)] for k in orc.keys])
+    in_chosen = np.array([g in set(chosen) for g in gkeys])
+    print(f"  cells={len(keys)} sampled groups={chosen} their cells={len(idx)} "
+          f"recheck={res.stats['n_recheck_pairs']} recount={res.stats['n_recount_rows']}", flush=True)
+    assert len(idx) >= 4000 and int(in_chosen.sum()) == len(idx)
+    assert np.array_equal(hu[idx], orc.half_units)
+    assert np.array_equal(t.sizes[0][idx], orc.n_triplets)
+
+
 def test_within_c2_full_size_bf16():
     """The bench workload at full size (100k items, dim 768): every cell exact."""
     w = workloads.within_c2(device="cuda")
