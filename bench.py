@@ -76,7 +76,7 @@ class _NoCyclicGC:
             gc.enable()
 
 
-def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side_serial=True, **kw):
+def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side_serial=True, depth=2, **kw):
     """n steps with host and device work overlapped across steps: while the
     device scores step i, the host builds the task of step i + 1 and collapses
     the result of step i - 1.  `side` picks what runs on a second host thread:
@@ -87,8 +87,11 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side
     pool runs a region issued while another thread's region is active in place
     on the issuing thread; with side_serial the second thread's host work
     always runs in place there (fabx_set_thread_serial), so that it never takes
-    the pool from a build.  Every step still runs the whole path on its own
-    task."""
+    the pool from a build.  With side "launch", `depth` scores stay enqueued on
+    the device: the second thread waits for and collapses step i - depth after
+    launching step i, and the main thread builds up to `depth` steps ahead, so
+    a host stall shorter than a step leaves the device busy.  Every step still
+    runs the whole path on its own task."""
     import concurrent.futures as cf
 
     stats, errs = [], []
@@ -104,22 +107,27 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side
 
     prev = [None]
 
-    def launch_then_finish_prev(task):
-        res = task.score_async(mode=mode, precision=precision, **SCORE_KW, **kw)
-        out = finish(prev[0]) if prev[0] is not None else None
-        prev[0] = res
-        return out
+    import collections
+    pending = collections.deque()   # launched, not yet finished (second thread only)
+
+    def launch_then_finish_old(task):
+        pending.append(task.score_async(mode=mode, precision=precision, **SCORE_KW, **kw))
+        return finish(pending.popleft()) if len(pending) > depth else None
+
+    def finish_rest():
+        return [finish(pending.popleft()) for _ in range(len(pending))]
 
     fut = None
+    futs = collections.deque()
     with cf.ThreadPoolExecutor(max_workers=1, initializer=fx.fabx_set_thread_serial,
                                initargs=(side_serial,)) as pool, _NoCyclicGC():
         t0 = time.perf_counter()
         for _ in range(n):
             task = fx.Task(ds, w.on, w.by, w.across)
             if side == "launch":
-                if fut is not None:
-                    take(fut.result())
-                fut = pool.submit(launch_then_finish_prev, task)
+                futs.append(pool.submit(launch_then_finish_old, task))
+                if len(futs) > depth:
+                    take(futs.popleft().result())
                 continue
             res = task.score_async(mode=mode, precision=precision, **SCORE_KW, **kw)
             if prev[0] is not None:
@@ -130,6 +138,10 @@ def run_pipelined(fx, ds, w, precision, n, sync, mode="dtw", side="launch", side
                 else:
                     take(finish(prev[0]))
             prev[0] = res
+        while futs:
+            take(futs.popleft().result())
+        for out in pool.submit(finish_rest).result():
+            take(out)
         if fut is not None:
             take(fut.result())
         if prev[0] is not None:
@@ -286,6 +298,8 @@ def main():
     ap.add_argument("--side", choices=("launch", "collapse", "none"), default="launch",
                     help="work of the pipelined steps on a second host thread: score launch and "
                          "collapse (default), collapse only, or none")
+    ap.add_argument("--depth", type=int, default=2,
+                    help="scores kept enqueued on the device by the pipelined loop (side 'launch')")
     ap.add_argument("--side-pool", action="store_true",
                     help="let the second host thread's work use the shared host thread pool")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
@@ -332,14 +346,14 @@ def main():
     if args.fused_config:
         cols, bpc = (int(v) for v in args.fused_config.split(","))
         SCORE_KW.update(fused_cols=cols, fused_blocks_per_cu=bpc)
-    run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, side, not args.side_pool)
+    run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, side, not args.side_pool, args.depth)
     sync()
     log("warmup done")
     # untimed: pick the fused kernel's tiles / grid for this task shape
     tune = (fx.Task(ds, w.on, w.by, w.across).autotune(mode=mode)
             if not (args.no_autotune or args.fused_config) else None)
     log(f"autotune: {tune}")
-    dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, side, not args.side_pool)
+    dt, pstats_, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, side, not args.side_pool, args.depth)
     ms_step = dt / args.steps * 1e3
     log(f"bf16 form, pipelined: {ms_step:.2f} ms/step")
     # the same steps one after another, for the per-stage breakdown
@@ -359,8 +373,8 @@ def main():
 
     plain = euclid = None
     if not args.no_plain and headline:
-        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool)
-        pdt, _, perrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side, not args.side_pool)
+        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool, args.depth)
+        pdt, _, perrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side, not args.side_pool, args.depth)
         pms = pdt / args.steps * 1e3
         psdt, pstats, _ = run_steps(fx, ds, w, "fp32", args.steps, sync, mode)
         pst = _stage_means(pstats)
@@ -371,9 +385,9 @@ def main():
                  "gpu_ms": pst["ms_total"], "gpu_triplets_per_s": n_trip / (pst["ms_total"] / 1e3),
                  "abx_error": perrs[-1], "stages_ms": pst}
         # the other distance the Score interface names, in the FP32 form
-        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool, distance="euclidean")
+        run_pipelined(fx, ds, w, "fp32", 1, sync, mode, side, not args.side_pool, args.depth, distance="euclidean")
         edt, estats, eerrs = run_pipelined(fx, ds, w, "fp32", args.steps, sync, mode, side,
-                                           not args.side_pool, distance="euclidean")
+                                           not args.side_pool, args.depth, distance="euclidean")
         ems = edt / args.steps * 1e3
         egpu = float(np.median([s_["ms_total"] for s_ in estats]))
         log(f"euclidean fp32 form: {ems:.2f} ms/step pipelined, device {egpu:.2f} ms")
@@ -432,8 +446,9 @@ def main():
         "gpu_ms_pipelined": float(np.median([s_["ms_total"] for s_ in pstats_])) if pstats_ else None,
         "triplets_per_s_serial": n_trip / (ms_step_serial / 1e3),
         "pipelined": ("host work of neighbouring steps overlaps device work (fabx_score_async)"
-                      + {"launch": "; the main thread builds step i + 1 while a second host thread "
-                                   "launches step i and collapses step i - 1",
+                      + {"launch": f"; the main thread builds up to {args.depth} steps ahead while a second "
+                                   f"host thread launches step i and collapses step i - {args.depth} "
+                                   f"({args.depth} scores stay enqueued on the device)",
                          "collapse": "; the collapse of step i - 1 runs on a second host thread beside "
                                      "the build of step i + 1",
                          "none": ""}[side]),

@@ -314,7 +314,7 @@ int fabx_result_stats(const fabx_result *res, fabx_stats *stats);
 typedef struct fabx_tune_entry {
     int32_t cols;
     int32_t blocks_per_cu;
-    double ms_distance;   /* best of two runs, distance + DTW stage, device time */
+    double ms_distance;   /* best of three runs, distance + DTW stage, device time */
 } fabx_tune_entry;
 
 typedef struct fabx_tune_report {
@@ -324,9 +324,11 @@ typedef struct fabx_tune_report {
     fabx_tune_entry tried[8];
 } fabx_tune_report;
 
-/* Score the task once per candidate configuration (twice, keeping the faster
- * run), check that every candidate gives identical per-cell counts, and keep
- * the fastest for the task's shape class (padded dim, longest item rounded up
+/* Score the task with every candidate configuration in three interleaved
+ * rounds (keeping each one's fastest run), check that every candidate gives
+ * identical per-cell counts, and keep the default (tried[0]) unless another
+ * candidate is faster by more than 2%, then the fastest, for the task's
+ * shape class (padded dim, longest item rounded up
  * to 8 frames, log2 of mean frames per BY group, DTW normalisation) in the
  * context's table; later scores of tasks in that class use it.  If the
  * environment variable FABX_AUTOTUNE_CACHE names a file when the context is
