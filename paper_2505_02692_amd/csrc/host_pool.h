@@ -132,7 +132,8 @@ using hvec = std::vector<T, CachedAlloc<T>>;
 // region is running (say a collapse on one thread while a task is built on
 // another), or from inside a region, or from a thread marked serial, runs its
 // items in place on the calling thread.  The pool leaves one hardware thread to such callers: it uses at
-// most 16 threads and, on machines with 8 or more, one fewer than there are.
+// most 16 threads and, on machines with 8 or more, one fewer than there are
+// (FABX_HOST_THREADS sets the count instead).
 class HostPool {
 public:
     static HostPool &get() {
@@ -201,6 +202,12 @@ private:
         int n = int(hw == 0 ? 1 : hw);
         if (n >= 8) n -= 1;
         if (n > 16) n = 16;
+        // FABX_HOST_THREADS: threads of a region, the caller included (1..64),
+        // e.g. to leave CPUs of a shared or quota-limited machine to other threads
+        if (const char *v = std::getenv("FABX_HOST_THREADS")) {
+            const int k = std::atoi(v);
+            if (k >= 1 && k <= 64) n = k;
+        }
         for (int i = 1; i < n; ++i) workers_.emplace_back([this] { worker(); });
     }
     // Claim and run items of open generation g until none is left or g is over.
