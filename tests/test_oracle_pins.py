@@ -333,3 +333,40 @@ def test_collapse_equal_scores_any_aggregation():
     W = n.copy()                                  # every D_C = 1/2
     for lv in (None, [[1]], [[1], [2, 3]], [[3], [1], [2]]):
         assert oracle.collapse(keys, [0, 0, 1, 2, 3], W, n, lv) == 0.5
+
+
+def test_collapse_across_level_hand_table():
+    """Z14 / P11: an ACROSS attribute named in a collapse level removes its
+    ``_ab`` and ``_x`` key columns together, in one averaging pass (Background:
+    averaged over contexts, then speakers, then phonemes; Score.collapse).
+
+    Task ON phone BY context ACROSS speaker -> key columns
+    (on_ax, on_b, ctx, spk_ab, spk_x).  Cells (W, |C|) -> D_C = W / 2|C|:
+      (0,1,c0,s0,s1) 1/1 -> 1/2     (0,1,c0,s0,s2) 1/3 -> 1/6
+      (0,1,c0,s1,s0) 2/3 -> 1/3     (0,1,c1,s0,s1) 1/4 -> 1/8
+      (1,0,c0,s1,s0) 2/4 -> 1/4     (0,1,c0,s2,s1) 3/4 -> 3/8
+      (1,0,c1,s1,s2) 3/2 -> 3/4
+    levels [ctx], [spk]:
+      after ctx: (0,1,s0,s1) = (1/2 + 1/8)/2 = 5/16, (0,1,s0,s2) = 1/6,
+                 (0,1,s1,s0) = 1/3, (0,1,s2,s1) = 3/8,
+                 (1,0,s1,s0) = 1/4, (1,0,s1,s2) = 3/4
+      after spk (spk_ab and spk_x together):
+                 (0,1) = (5/16 + 1/6 + 1/3 + 3/8)/4 = 19/64, (1,0) = (1/4 + 3/4)/2 = 1/2
+      D = (19/64 + 1/2)/2 = 51/128 -> error 77/128
+    weighted: sum W / (2 sum |C|) = 13/42 -> error 29/42 (differs from the levels).
+
+    Plausible mistakes give other values on this table, so each fails here:
+    dropping only spk_ab -> 101/160, only spk_x -> 245/384; removing spk_ab then
+    spk_x in two passes -> 39/64, spk_x then spk_ab -> 341/576; the speaker level
+    before the context level -> 81/128; both levels in one pass -> 3/5.
+    """
+    keys = np.array([[0, 1, 0, 0, 1], [0, 1, 0, 0, 2], [0, 1, 0, 1, 0], [0, 1, 1, 0, 1],
+                     [1, 0, 0, 1, 0], [0, 1, 0, 2, 1], [1, 0, 1, 1, 2]])
+    ka = [0, 0, 1, 2, 2]
+    W = np.array([1, 1, 2, 1, 2, 3, 3])
+    n = np.array([1, 3, 3, 4, 4, 4, 2])
+    assert oracle.collapse(keys, ka, W, n, [[1], [2]]) == pytest.approx(77 / 128, abs=1e-15)
+    assert oracle.collapse(keys, ka, W, n) == pytest.approx(29 / 42, abs=1e-15)
+    # the other orders of the same levels, worked the same way
+    assert oracle.collapse(keys, ka, W, n, [[2], [1]]) == pytest.approx(81 / 128, abs=1e-15)
+    assert oracle.collapse(keys, ka, W, n, [[1, 2]]) == pytest.approx(3 / 5, abs=1e-15)
