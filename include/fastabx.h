@@ -325,7 +325,8 @@ typedef struct fabx_tune_report {
 } fabx_tune_report;
 
 /* Score the task with every candidate configuration in three interleaved
- * rounds (keeping each one's fastest run), check that every candidate gives
+ * rounds (one when the default's distance stage takes 100 ms or more),
+ * keeping each one's fastest run, check that every candidate gives
  * identical per-cell counts, and keep the default (tried[0]) unless another
  * candidate is faster by more than 2%, then the fastest, for the task's
  * shape class (padded dim, longest item rounded up
@@ -354,15 +355,19 @@ int fabx_collapse(const fabx_result *res, const int32_t *level_attr, const int32
 /* ---------------------------------------------------------------- server */
 
 /* Continuous-batching job server on one context.  Jobs (dataset + task spec
- * + options) are queued by fabx_server_submit and admitted, in arrival order,
- * when their device-memory footprint fits in `hbm_budget_bytes` next to the
- * jobs already running; admitted jobs run concurrently on `n_streams` HIP
- * streams of the context's device.  A job's result is identical to what
- * fabx_score returns for it alone.
+ * + options) are queued by fabx_server_submit.  Whenever one of `n_streams`
+ * HIP streams of the context's device is free, the first queued job whose
+ * device-memory footprint fits in `hbm_budget_bytes` next to the jobs already
+ * running is admitted: a smaller job may start before a larger one queued
+ * ahead of it, but a job passed over 8 times is not passed again (it starts
+ * as soon as it fits).  Admitted jobs run concurrently.  A job's result is
+ * identical to what fabx_score returns for it alone, and a job that fails
+ * (say EDOMAIN) does not change the others.  When a job ends, its device
+ * memory goes back to the context's pool.
  *
  * Thread rules: submit / poll / wait / cancel may be called from any thread.
  * A dataset passed to submit must stay alive until the job completes or is
- * cancelled (the job holds a reference to it). */
+ * cancelled (the job holds a reference to it; the features are borrowed). */
 typedef struct fabx_server fabx_server;
 
 int fabx_server_create(fabx_ctx *ctx, int64_t hbm_budget_bytes, int32_t n_streams,
@@ -379,7 +384,9 @@ int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int
                        int32_t n_by, const int32_t *across, int32_t n_across,
                        const fabx_score_opts *opts, uint64_t *job_id);
 /* FABX_OK and *out set when finished (caller frees the result); EAGAIN while
- * queued or running; ECANCELED; ENOTFOUND; or the job's own error code. */
+ * queued or running; ECANCELED; ENOTFOUND; or the job's own error code.  Once
+ * an outcome other than EAGAIN has been returned, the server forgets the job:
+ * asking again gives ENOTFOUND. */
 int fabx_server_poll(fabx_server *srv, uint64_t job_id, fabx_result **out);
 /* Like poll, but blocks until the job is no longer queued or running. */
 int fabx_server_wait(fabx_server *srv, uint64_t job_id, fabx_result **out);
@@ -390,7 +397,11 @@ int fabx_server_cancel(fabx_server *srv, uint64_t job_id);
 typedef struct fabx_server_stats {
     int64_t submitted, completed, cancelled, failed, queued, running;
     int64_t hbm_in_use, hbm_high_water;
-    double p50_ms, p99_ms;        /* completion - submission, over completed jobs */
+    double p50_ms, p99_ms;        /* completion - entry into fabx_server_submit, over completed jobs */
+    double p50_queue_ms, p99_queue_ms; /* queue wait: end of the submit call -> admission */
+    double mean_build_ms;         /* task build inside fabx_server_submit */
+    double mean_queue_ms;         /* queue wait */
+    double mean_run_ms;           /* admission -> completion (device work and result copy) */
 } fabx_server_stats;
 
 int fabx_server_stats_get(fabx_server *srv, fabx_server_stats *st);

@@ -513,11 +513,34 @@ class Server:
         self._tasks = {}
 
     def submit(self, ds: Dataset, on, by=(), across=(), **kw) -> int:
-        return fabx_server_submit(self.h, ds.h, on, by, across, make_opts(**kw))
+        job = fabx_server_submit(self.h, ds.h, on, by, across, make_opts(**kw))
+        # the dataset owns (a reference to) the borrowed feature tensor: keep it
+        # alive until the job's outcome has been fetched
+        self._tasks[job] = ds
+        return job
 
     def wait(self, job_id: int):
-        """Block until the job ends; returns (keys, W, |C|, D_C) and frees the native result."""
+        """Block until the job ends; returns (keys, W, |C|, D_C) and frees the native result.
+        The server forgets the job once its outcome has been returned (raised)."""
         rc, h = fabx_server_wait(self.h, job_id)
+        if rc != -4:   # EAGAIN cannot come from wait; any other outcome ends the job
+            self._tasks.pop(job_id, None)
+        if rc != 0:
+            raise FabxError(rc, lib().fabx_last_error().decode())
+        try:
+            keys = fabx_result_cell_keys(h)
+            w, n, s = fabx_result_cells(h)
+        finally:
+            fabx_result_free(h)
+        return keys, w, n, s
+
+    def poll(self, job_id: int):
+        """(keys, W, |C|, D_C) if the job has finished, None while it is queued or
+        running; raises the job's error (the server then forgets the job)."""
+        rc, h = fabx_server_poll(self.h, job_id)
+        if rc == -4:
+            return None
+        self._tasks.pop(job_id, None)
         if rc != 0:
             raise FabxError(rc, lib().fabx_last_error().decode())
         try:
@@ -535,6 +558,7 @@ class Server:
         if getattr(self, "h", None):
             fabx_server_destroy(self.h)
             self.h = None
+            self._tasks.clear()
 
     def __del__(self):
         self.close()

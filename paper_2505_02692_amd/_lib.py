@@ -78,7 +78,8 @@ class fabx_tune_report(ctypes.Structure):
 class fabx_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "cancelled", "failed", "queued",
                                               "running", "hbm_in_use", "hbm_high_water")] + \
-        [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double)]
+        [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "p50_queue_ms", "p99_queue_ms", "mean_build_ms",
+                                         "mean_queue_ms", "mean_run_ms")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

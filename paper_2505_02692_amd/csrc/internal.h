@@ -193,7 +193,6 @@ struct Group {
     int64_t frame0;     // first packed frame
     int64_t n_frames;
     int64_t pair_base;  // offset of the group's [n_items x n_items] pair matrix
-    int64_t dmat_base;  // offset of the group's [n_frames x n_frames] distance matrix (plain form)
 };
 
 // A cell on the device: item positions are local to the group.
@@ -211,7 +210,7 @@ static_assert(sizeof(CellDev) == 32, "CellDev layout");
 // Byte offsets of the task tables in their device buffer.
 struct TableLayout {
     size_t item_src = 0, item_len = 0, item_dst = 0, item_group = 0;
-    std::array<size_t, 6> g{};  // item0, n_items (+ sentinel), frame0, n_frames, dmat_base, pair_base (+ total)
+    std::array<size_t, 5> g{};  // item0, n_items (+ sentinel), frame0, n_frames, pair_base (+ total)
     size_t cells = 0, units = 0, rb = 0, g_rb0 = 0;
     std::array<size_t, 4> plan{};  // cb, rb_unit_prefix, g_cb0, rb_cstart of `plan_cols`
     int plan_cols = 0;             // 0: no column plan in the buffer
@@ -222,7 +221,7 @@ struct TaskDevice {
     const int64_t *item_src = nullptr, *item_dst = nullptr;
     const int32_t *item_len = nullptr, *item_group = nullptr;
     const int64_t *g_item0 = nullptr, *g_n = nullptr, *g_frame0 = nullptr, *g_nframes = nullptr,
-                  *g_pair_base = nullptr, *g_dmat_base = nullptr;
+                  *g_pair_base = nullptr;
     const CellDev *cells = nullptr;
     const int32_t *units = nullptr, *rb = nullptr, *g_rb0 = nullptr;
     bool uploaded = false;
@@ -232,7 +231,7 @@ struct TaskDevice {
 struct Workspace {
     DevBuf xn;          // packed normalised frames (F32 or BF16) [n_frames x dim_pad]
     DevBuf rinv;        // F32 [n_frames]: 1 / ||bf16 frame|| (BF16 form)
-    DevBuf dmat;        // plain form: F32 frame distances per group
+    DevBuf dmat;        // plain form: F32 frame distances of one batch of group strips
     DevBuf p32;         // F32 [n_pair_slots]
     DevBuf flags;       // uint8 [n_pair_slots]: bit0 non-robust, bit1 marked for FP64
     DevBuf p64;         // F64 [n_pair_slots]
@@ -302,7 +301,7 @@ struct TaskImpl {
 
     int64_t n_frames = 0;
     int64_t n_pair_slots = 0;       // sum over groups of n_items^2
-    int64_t n_dmat = 0;             // sum over groups of n_frames^2
+    int64_t n_dmat = 0;             // sum over groups of n_frames^2 (frame pairs of the plain form)
     int64_t n_pairs_needed = 0;     // unique ordered pairs some cell uses
     int64_t dtw_cells_needed = 0;   // sum of len(x) * len(y) over those pairs
     int64_t dtw_cells_sym = 0;      // the same over unordered pairs {x, y} needed in either order
@@ -374,6 +373,10 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &task, con
                                       hipStream_t stream);
 // Device bytes a score of this task would hold (admission control).
 int64_t footprint_bytes(const TaskImpl &task, const ScoreParams &p);
+// Gives the task's device memory (workspace, tables, column plans) and its
+// pinned packed tables back to the context's pools, after waiting for its
+// pending score.  A later score uploads the tables again.
+void release_device(TaskImpl &task);
 
 // collapse.cpp
 double collapse(const ResultImpl &res, const int32_t *level_attr, const int32_t *level_len,

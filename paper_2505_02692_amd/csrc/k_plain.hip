@@ -1,16 +1,20 @@
 // Plain FP32 form: the straightforward GPU pipeline the BF16 form is
 // measured against.
 //
-//  gram_angular_f32: per BY group, every pair of unit rows -> theta / pi in FP32
-//    (64 x 64 output tile per 256-thread block, 4 x 4 per thread, K staged
-//    through LDS in steps of 16), written to HBM.  For the Euclidean distance
+//  gram_angular_f32: per segment (a BY group's pooled items, or a strip of a
+//    group's frames against all its frames), every pair of unit rows ->
+//    theta / pi in FP32 (64 x 64 output tile per 256-thread block, 4 x 4 per
+//    thread, K staged through LDS in steps of 16), written to HBM.  For the Euclidean distance
 //    the same tiles sum (u_k - v_k)^2 over raw rows (no cancellation of a
 //    norms-minus-dot form) and take the square root.
 //  dtw_plain: one wave per ordered item pair; lane i owns row i of the DTW
 //    matrix and the wave sweeps the anti-diagonals t = i + j, reading the
 //    distance matrix from HBM: the paper's wavefront scheme (one pair per
 //    block, the cells of a diagonal in parallel), with the previous two
-//    diagonals held in registers of neighbouring lanes.
+//    diagonals held in registers of neighbouring lanes.  The distance
+//    matrices of a task can far exceed device memory (the sum of the squared
+//    frame counts of its groups), so they are made and consumed in batches
+//    of strips that fit one buffer.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -28,19 +32,22 @@ template <bool kEuclid>
 __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restrict__ xn, int dim_pad,
                                                           const int64_t *__restrict__ row0,
                                                           const int64_t *__restrict__ nrows,
+                                                          const int64_t *__restrict__ col0,
+                                                          const int64_t *__restrict__ ncols,
                                                           const int64_t *__restrict__ base,
                                                           const int64_t *__restrict__ tile_prefix,
-                                                          int64_t n_groups, int64_t n_tiles,
-                                                          float *__restrict__ out) {
+                                                          int64_t n_seg, float *__restrict__ out) {
     __shared__ float As[kK][kTile + 4];
     __shared__ float Bs[kK][kTile + 4];
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t g = dev::find_segment(tile_prefix, n_groups, tile);
-    const int64_t n = nrows[g];
-    const int64_t nt = (n + kTile - 1) / kTile;
-    const int64_t local = tile - tile_prefix[g];
-    const int64_t r0 = (local / nt) * kTile, c0 = (local % nt) * kTile;
-    const float *rows = xn + row0[g] * int64_t(dim_pad);
+    const int64_t t_hi = tile_prefix[n_seg];
+    for (int64_t tile = tile_prefix[0] + blockIdx.x; tile < t_hi; tile += gridDim.x) {
+    const int64_t sg = dev::find_segment(tile_prefix, n_seg, tile);
+    const int64_t nr = nrows[sg], nc = ncols[sg];
+    const int64_t ntc = (nc + kTile - 1) / kTile;
+    const int64_t local = tile - tile_prefix[sg];
+    const int64_t r0 = (local / ntc) * kTile, c0 = (local % ntc) * kTile;
+    const float *rows = xn + row0[sg] * int64_t(dim_pad);
+    const float *cols = xn + col0[sg] * int64_t(dim_pad);
     const int tid = threadIdx.x;
     const int ty = tid / 16, tx = tid % 16;
     float acc[4][4] = {};
@@ -48,8 +55,8 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
     const int lr = tid / 4, lk = (tid % 4) * 4;
     for (int k0 = 0; k0 < dim_pad; k0 += kK) {
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-        if (r0 + lr < n) a = *reinterpret_cast<const float4 *>(rows + (r0 + lr) * dim_pad + k0 + lk);
-        if (c0 + lr < n) b = *reinterpret_cast<const float4 *>(rows + (c0 + lr) * dim_pad + k0 + lk);
+        if (r0 + lr < nr) a = *reinterpret_cast<const float4 *>(rows + (r0 + lr) * dim_pad + k0 + lk);
+        if (c0 + lr < nc) b = *reinterpret_cast<const float4 *>(cols + (c0 + lr) * dim_pad + k0 + lk);
         As[lk + 0][lr] = a.x; As[lk + 1][lr] = a.y; As[lk + 2][lr] = a.z; As[lk + 3][lr] = a.w;
         Bs[lk + 0][lr] = b.x; Bs[lk + 1][lr] = b.y; Bs[lk + 2][lr] = b.z; Bs[lk + 3][lr] = b.w;
         __syncthreads();
@@ -74,20 +81,20 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
         }
         __syncthreads();
     }
-    float *o = out + base[g];
+    float *o = out + base[sg];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t r = r0 + ty * 4 + i;
-        if (r >= n) continue;
+        if (r >= nr) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t c = c0 + tx * 4 + j;
-            if (c >= n) continue;
+            if (c >= nc) continue;
             if (kEuclid) {
-                o[r * n + c] = __builtin_sqrtf(acc[i][j]);
+                o[r * nc + c] = __builtin_sqrtf(acc[i][j]);
             } else {
                 const float cs = fminf(fmaxf(acc[i][j], -1.0f), 1.0f);
-                o[r * n + c] = acosf(cs) * dev::kInvPi;
+                o[r * nc + c] = acosf(cs) * dev::kInvPi;
             }
         }
     }
@@ -95,27 +102,31 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
 }
 
 __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dmat,
+                                                   const int64_t *__restrict__ s_group,
+                                                   const int64_t *__restrict__ s_slot0,
+                                                   const int64_t *__restrict__ s_row0,
+                                                   const int64_t *__restrict__ s_base, int64_t n_strips,
                                                    const int64_t *__restrict__ g_item0,
                                                    const int64_t *__restrict__ g_n,
                                                    const int64_t *__restrict__ g_frame0,
                                                    const int64_t *__restrict__ g_nframes,
                                                    const int64_t *__restrict__ g_pair_base,
-                                                   const int64_t *__restrict__ g_dmat_base,
-                                                   int64_t n_groups, int64_t n_slots,
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst, int norm,
                                                    float *__restrict__ p32) {
     const int i = threadIdx.x % kWave;
+    const int64_t slot_lo = s_slot0[0], slot_hi = s_slot0[n_strips];
     // one wave per slot; the loop bound is uniform across the wave
-    for (int64_t slot = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; slot < n_slots;
+    for (int64_t slot = slot_lo + int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; slot < slot_hi;
          slot += int64_t(gridDim.x) * 4) {
-    const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
+    const int64_t sg = dev::find_segment(s_slot0, n_strips, slot);
+    const int64_t g = s_group[sg];
     const int64_t n = g_n[g];
     const int64_t local = slot - g_pair_base[g];
     const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
     const int N = item_len[x], M = item_len[y];
     const int64_t F = g_nframes[g];
-    const float *d = dmat + g_dmat_base[g] + (item_dst[x] - g_frame0[g]) * F + (item_dst[y] - g_frame0[g]);
+    const float *d = dmat + s_base[sg] + (item_dst[x] - s_row0[sg]) * F + (item_dst[y] - g_frame0[g]);
 
     float c = kInf;          // c[i][j-1] (own value of the previous step)
     int len = 0;
@@ -153,26 +164,26 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
 
 }  // namespace
 
-void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t *row0,
-                      const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
-                      int64_t n_groups, int64_t n_tiles, float *out, int euclid) {
-    if (n_tiles <= 0) return;
+void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const GramSegments &seg, float *out,
+                      int euclid) {
+    if (seg.n <= 0 || seg.n_tiles <= 0) return;
     if (dim_pad % kK) fail(FABX_EINVAL, "padded dim must be a multiple of 16");
+    const dim3 grid(grid_for(seg.n_tiles, 1)), block(256);
     if (euclid)
-        hipLaunchKernelGGL(k_gram_angular_f32<true>, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn,
-                           dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
+        hipLaunchKernelGGL(k_gram_angular_f32<true>, grid, block, 0, s, xn, dim_pad, seg.row0, seg.nrows,
+                           seg.col0, seg.ncols, seg.base, seg.tile_prefix, seg.n, out);
     else
-        hipLaunchKernelGGL(k_gram_angular_f32<false>, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn,
-                           dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
+        hipLaunchKernelGGL(k_gram_angular_f32<false>, grid, block, 0, s, xn, dim_pad, seg.row0, seg.nrows,
+                           seg.col0, seg.ncols, seg.base, seg.tile_prefix, seg.n, out);
     FABX_HIP(hipGetLastError());
 }
 
-void dtw_plain(hipStream_t s, const float *dmat, const GroupTables &g, const ItemTables &it,
-               int norm, float *p32) {
-    if (g.n_pair_slots <= 0) return;
-    hipLaunchKernelGGL(k_dtw_plain, dim3(grid_for(g.n_pair_slots, 4)), dim3(256), 0, s, dmat, g.item0,
-                       g.n_items, g.frame0, g.n_frames, g.pair_base, g.dmat_base, g.n_groups,
-                       g.n_pair_slots, it.len, it.dst, norm, p32);
+void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const GroupTables &g,
+               const ItemTables &it, int norm, float *p32) {
+    if (st.n <= 0 || st.n_slots <= 0) return;
+    hipLaunchKernelGGL(k_dtw_plain, dim3(grid_for(st.n_slots, 4)), dim3(256), 0, s, dmat, st.group,
+                       st.slot0, st.row0, st.base, st.n, g.item0, g.n_items, g.frame0, g.n_frames,
+                       g.pair_base, it.len, it.dst, norm, p32);
     FABX_HIP(hipGetLastError());
 }
 

@@ -30,7 +30,7 @@ struct ItemTables {
 
 // Per-group tables on the device (n_groups entries; *_prefix arrays have n_groups + 1).
 struct GroupTables {
-    const int64_t *item0, *n_items, *frame0, *n_frames, *pair_base, *dmat_base;
+    const int64_t *item0, *n_items, *frame0, *n_frames, *pair_base;
     int64_t n_groups;
     int64_t n_pair_slots;
 };
@@ -52,20 +52,38 @@ void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int
                     unsigned long long *err_item);
 
 // --- k_plain.hip (plain FP32 form)
-// Per group: the distance of every pair of packed rows [row0, row0 + n) of the
-// group, into out[base + r * n + c]: theta/pi of unit rows (euclid = 0) or the
-// length of the difference of raw rows (euclid = 1).  rows/row0/base come from
-// `frame0`, `n_frames`, `dmat_base` (DTW mode) or item0 / n_items / pair_base
-// (pooled mode).
-void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const int64_t *row0,
-                      const int64_t *nrows, const int64_t *base, const int64_t *tile_prefix,
-                      int64_t n_groups, int64_t n_tiles, float *out, int euclid);
+// Segments of Gram output: segment s holds the distances of packed rows
+// [row0[s], row0[s] + nrows[s]) against packed rows [col0[s], col0[s] + ncols[s])
+// at out[base[s] + r * ncols[s] + c].  Tiles are 64 x 64; tile_prefix has n + 1
+// entries, and the launch covers tiles [tile_prefix[0], tile_prefix[n]).
+struct GramSegments {
+    const int64_t *row0, *nrows, *col0, *ncols, *base, *tile_prefix;
+    int64_t n;
+    int64_t n_tiles;  // tile_prefix[n] - tile_prefix[0] (host copy, sizes the grid)
+};
+// theta/pi of unit rows (euclid = 0) or the length of the difference of raw
+// rows (euclid = 1) for every (row, column) of every segment.  Pooled mode:
+// one segment per group (its item vectors against themselves, base = the
+// group's pair matrix); DTW mode: one segment per strip (below).
+void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const GramSegments &seg, float *out,
+                      int euclid);
 
-// One wave per ordered item pair of each group: anti-diagonal DTW over the
-// group's F32 distance matrix (lane = row), exact diagonal > left > up
+// Plain DTW mode: a group's frame distance matrix is made in strips of rows
+// (the frames of consecutive items of the group) against all the group's
+// frames, and strips are processed in batches whose matrices fit the dmat
+// buffer.  Strip s: group[s], its first pair slot slot0[s] (n + 1 entries, a
+// prefix: the slots of the strip's row items), its first row's packed frame
+// row0[s] and its matrix offset base[s] in the batch's dmat buffer.
+struct PlainStrips {
+    const int64_t *group, *slot0, *row0, *base;
+    int64_t n;
+    int64_t n_slots;  // slot0[n] - slot0[0] (host copy, sizes the grid)
+};
+// One wave per ordered item pair of the strips' slots: anti-diagonal DTW over
+// the strip's F32 distance matrix (lane = row), exact diagonal > left > up
 // predecessor order.  norm: FABX_NORM_PATH / FABX_NORM_NONE.
-void dtw_plain(hipStream_t s, const float *dmat, const GroupTables &g, const ItemTables &it,
-               int norm, float *p32);
+void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const GroupTables &g,
+               const ItemTables &it, int norm, float *p32);
 
 // --- k_fused.hip (BF16 form)
 struct FusedPlan {

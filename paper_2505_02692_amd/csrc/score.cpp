@@ -4,6 +4,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 
@@ -80,28 +81,27 @@ struct Packer {
 // Host side of the task tables: adds them (and `plan`, if any) to `pk`; the
 // group columns are built in `gcols`, which must live until the copy is made.
 TableLayout add_task_tables(const TaskImpl &t, const ColPlan *plan, Packer &pk,
-                            std::array<std::vector<int64_t>, 6> &gcols) {
+                            std::array<std::vector<int64_t>, 5> &gcols) {
     const size_t G = t.groups.size();
     for (auto &v : gcols) v.resize(G);
     gcols[1].resize(G + 1);
-    gcols[5].resize(G + 1);
+    gcols[4].resize(G + 1);
     for (size_t i = 0; i < G; ++i) {
         const Group &g = t.groups[i];
         gcols[0][i] = g.item0;
         gcols[1][i] = g.n_items;
         gcols[2][i] = g.frame0;
         gcols[3][i] = g.n_frames;
-        gcols[4][i] = g.dmat_base;
-        gcols[5][i] = g.pair_base;
+        gcols[4][i] = g.pair_base;
     }
     gcols[1][G] = 0;
-    gcols[5][G] = t.n_pair_slots;
+    gcols[4][G] = t.n_pair_slots;
     TableLayout L;
     L.item_src = pk.add(t.item_src);
     L.item_len = pk.add(t.item_len);
     L.item_dst = pk.add(t.item_dst);
     L.item_group = pk.add(t.item_group);
-    for (size_t k = 0; k < 6; ++k) L.g[k] = pk.add(gcols[k]);
+    for (size_t k = 0; k < 5; ++k) L.g[k] = pk.add(gcols[k]);
     L.cells = pk.add(t.cells);
     L.units = pk.add(t.units);
     L.rb = pk.add(t.rb);
@@ -133,8 +133,7 @@ void set_task_tables(TaskImpl &t, const TableLayout &L) {
     dv.g_n = Packer::at<int64_t>(dv.blob, L.g[1]);
     dv.g_frame0 = Packer::at<int64_t>(dv.blob, L.g[2]);
     dv.g_nframes = Packer::at<int64_t>(dv.blob, L.g[3]);
-    dv.g_dmat_base = Packer::at<int64_t>(dv.blob, L.g[4]);
-    dv.g_pair_base = Packer::at<int64_t>(dv.blob, L.g[5]);
+    dv.g_pair_base = Packer::at<int64_t>(dv.blob, L.g[4]);
     dv.cells = Packer::at<CellDev>(dv.blob, L.cells);
     dv.units = Packer::at<int32_t>(dv.blob, L.units);
     dv.rb = Packer::at<int32_t>(dv.blob, L.rb);
@@ -150,20 +149,89 @@ void set_task_tables(TaskImpl &t, const TableLayout &L) {
 constexpr size_t kPrepackMaxBytes = size_t(64) << 20;
 constexpr size_t kPrepackBudget = size_t(128) << 20;
 
-// Gram tile prefix per group for the plain form (64 x 64 tiles of frames) or
-// the pooled mode (64 x 64 FP32 or 64 x 128 BF16 tiles of items).
+// Gram tile prefix per group for the pooled mode (64 x 64 FP32 or 64 x 128
+// BF16 tiles of items).
 std::vector<int64_t> tile_prefix(const TaskImpl &t, const ScoreParams &p) {
     const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
     const int64_t G = int64_t(t.groups.size());
     std::vector<int64_t> pre(size_t(G) + 1, 0);
     for (int64_t gi = 0; gi < G; ++gi) {
-        const Group &g = t.groups[size_t(gi)];
-        const int64_t n = p.mode == FABX_MODE_DTW ? g.n_frames : g.n_items;
+        const int64_t n = t.groups[size_t(gi)].n_items;
         const int64_t tr = (n + 63) / 64;
         const int64_t tc = bf16 ? (n + 127) / 128 : tr;
         pre[size_t(gi) + 1] = pre[size_t(gi)] + tr * tc;
     }
     return pre;
+}
+
+// Frame distances of the plain DTW form, per batch of strips: a strip is the
+// frames of consecutive items of one group (rows) against all the group's
+// frames (columns).  A group whose squared frame count fits `cap` cells is one
+// strip; consecutive strips form a batch while their matrices total at most
+// `cap` cells, so the distance buffer never holds more than that.
+struct PlainPlan {
+    // per strip; slot0 and tiles are prefixes with one more entry
+    std::vector<int64_t> group, slot0, row0, nrows, col0, ncols, base, tiles;
+    std::vector<std::pair<int64_t, int64_t>> batches;                          // strip ranges
+    int64_t max_cells = 0;                                                     // largest batch
+};
+
+PlainPlan plain_plan(const TaskImpl &t, int64_t cap) {
+    PlainPlan pl;
+    pl.tiles.push_back(0);
+    int64_t batch_cells = 0, batch_first = 0;
+    // strip of group g: its items from local position x0 on, rows r0 .. r0 + nr - 1
+    auto add_strip = [&](size_t g, int64_t x0, int64_t r0, int64_t nr) {
+        const Group &gr = t.groups[g];
+        const int64_t cells = nr * gr.n_frames;
+        const int64_t k = int64_t(pl.group.size());
+        if (batch_cells > 0 && batch_cells + cells > cap) {
+            pl.batches.push_back({batch_first, k});
+            batch_first = k;
+            batch_cells = 0;
+        }
+        pl.group.push_back(int64_t(g));
+        pl.slot0.push_back(gr.pair_base + x0 * gr.n_items);
+        pl.row0.push_back(r0);
+        pl.nrows.push_back(nr);
+        pl.col0.push_back(gr.frame0);
+        pl.ncols.push_back(gr.n_frames);
+        pl.base.push_back(batch_cells);
+        pl.tiles.push_back(pl.tiles.back() + ((nr + 63) / 64) * ((gr.n_frames + 63) / 64));
+        batch_cells += cells;
+        pl.max_cells = std::max(pl.max_cells, batch_cells);
+    };
+    for (size_t g = 0; g < t.groups.size(); ++g) {
+        const Group &gr = t.groups[g];
+        const int64_t rows_cap = std::max<int64_t>(1, cap / std::max<int64_t>(gr.n_frames, 1));
+        int64_t x0 = 0, r0 = gr.frame0, nr = 0;
+        for (int64_t k = 0; k < gr.n_items; ++k) {
+            const int64_t L = t.item_len[size_t(gr.item0 + k)];
+            if (nr > 0 && nr + L > rows_cap) {
+                add_strip(g, x0, r0, nr);
+                x0 = k;
+                r0 += nr;
+                nr = 0;
+            }
+            nr += L;
+        }
+        add_strip(g, x0, r0, nr);
+    }
+    if (!pl.group.empty()) pl.batches.push_back({batch_first, int64_t(pl.group.size())});
+    pl.slot0.push_back(t.n_pair_slots);  // n + 1 entries: the slots of strip k are [slot0[k], slot0[k+1])
+    return pl;
+}
+
+// Cells (4 bytes each) of the plain form's distance buffer: 4 GiB.  The
+// environment variable FABX_PLAIN_DMAT_CELLS (read when a score starts, at
+// least 4096) sets another size, so that small tasks can run in many batches.
+constexpr int64_t kPlainDmatCells = int64_t(1) << 30;
+int64_t plain_dmat_cells() {
+    if (const char *e = std::getenv("FABX_PLAIN_DMAT_CELLS")) {
+        const long long v = std::atoll(e);
+        if (v >= 4096) return int64_t(v);
+    }
+    return kPlainDmatCells;
 }
 
 struct Timer {
@@ -224,7 +292,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
     const int64_t dim_pad = round_up(t.ds->dim, 64);
     const int64_t rows = p.mode == FABX_MODE_DTW ? t.n_frames : int64_t(t.items.size());
     int64_t b = rows * dim_pad * (bf16 ? 2 : 4) + rows * 4;
-    if (p.mode == FABX_MODE_DTW && !bf16) b += t.n_dmat * 4;
+    if (p.mode == FABX_MODE_DTW && !bf16) b += std::min(t.n_dmat, plain_dmat_cells()) * 4;
     b += t.n_pair_slots * 4;
     if (bf16) b += t.n_pair_slots * (1 + 8 + 8);
     b += int64_t(t.cells.size()) * (8 + 32) + int64_t(t.units.size()) * 4 + t.sum_nx * 8 +
@@ -278,7 +346,7 @@ void prepack_tables(TaskImpl &t) {
     if (!ctx || ctx->device < 0 || t.cells.empty()) return;
     Trace tr("prepack");
     Packer pk;
-    std::array<std::vector<int64_t>, 6> gcols;
+    std::array<std::vector<int64_t>, 5> gcols;
     const ColPlan *plan = t.col_plans.empty() ? nullptr : t.col_plans.front().get();
     const TableLayout L = add_task_tables(t, plan, pk, gcols);
     if (pk.total > kPrepackMaxBytes || ctx->pinned.packed_bytes.load() + pk.total > kPrepackBudget) return;
@@ -298,6 +366,201 @@ void prepack_tables(TaskImpl &t) {
     t.packed = std::move(blk);
     t.packed_layout = L;
 }
+
+namespace {
+
+// Device addresses a score's kernels use: the task tables, the column plan of
+// the fused kernel, the plan of the pooled / plain kernels, and the workspace.
+struct DevPtrs {
+    kern::ItemTables it{};
+    kern::GroupTables gt{};
+    const CellDev *cells = nullptr;
+    const int32_t *units = nullptr, *rb = nullptr;
+    const int32_t *cb = nullptr, *g_cb0 = nullptr, *rb_cstart = nullptr;
+    const int64_t *rb_unit_prefix = nullptr;
+    const int64_t *tiles = nullptr;             // pooled: Gram tile prefix per group
+    std::array<const int64_t *, 8> strips{};    // plain DTW: group, slot0, row0, nrows, col0, ncols, base, tiles
+    void *xn = nullptr;
+    float *rinv = nullptr, *dmat = nullptr, *p32 = nullptr;
+    uint8_t *flags = nullptr;
+    double *p64 = nullptr;
+    int64_t *recheck_list = nullptr;
+    int32_t *recount_list = nullptr;
+    unsigned long long *half_units = nullptr;   // [n_cells], then the score's 64 counter bytes
+};
+
+// Byte offsets of the pooled tile prefix or of the plain form's strip columns.
+struct PlanLayout {
+    size_t tiles = 0;
+    std::array<size_t, 8> strips{};
+    bool has_tiles = false, has_strips = false;
+};
+
+PlanLayout add_plan(Packer &pk, const std::vector<int64_t> &tiles, const PlainPlan &strips) {
+    PlanLayout L;
+    if (!tiles.empty()) {
+        L.tiles = pk.add(tiles);
+        L.has_tiles = true;
+    }
+    if (!strips.group.empty()) {
+        const std::vector<int64_t> *cols[8] = {&strips.group, &strips.slot0, &strips.row0, &strips.nrows,
+                                               &strips.col0,  &strips.ncols, &strips.base, &strips.tiles};
+        for (size_t k = 0; k < 8; ++k) L.strips[k] = pk.add(*cols[k]);
+        L.has_strips = true;
+    }
+    return L;
+}
+
+void set_plan(DevPtrs &d, const char *base, const PlanLayout &L) {
+    if (L.has_tiles) d.tiles = reinterpret_cast<const int64_t *>(base + L.tiles);
+    if (L.has_strips)
+        for (size_t k = 0; k < 8; ++k) d.strips[k] = reinterpret_cast<const int64_t *>(base + L.strips[k]);
+}
+
+// Workspace bytes of one score (0 for buffers the form does not use).
+struct WorkspaceSizes {
+    size_t xn = 0, rinv = 0, dmat = 0, p32 = 0, flags = 0, p64 = 0, recheck_list = 0, recount_list = 0,
+           half_units = 0;
+    size_t total_aligned() const {
+        size_t s = 0;
+        for (size_t b : {xn, rinv, dmat, p32, flags, p64, recheck_list, recount_list, half_units})
+            s += (b + 255) & ~size_t(255);
+        return s;
+    }
+};
+
+WorkspaceSizes workspace_sizes(const TaskImpl &t, const ScoreParams &p, const PlainPlan &strips) {
+    const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
+    const bool dtw = p.mode == FABX_MODE_DTW;
+    const int64_t dim_pad = round_up(t.ds->dim, 64);
+    const int64_t rows = dtw ? t.n_frames : int64_t(t.items.size());
+    WorkspaceSizes w;
+    w.xn = size_t(rows) * size_t(dim_pad) * (bf16 ? 2 : 4);
+    if (bf16) w.rinv = size_t(rows) * 4;
+    if (dtw && !bf16) w.dmat = size_t(std::max<int64_t>(strips.max_cells, 1)) * 4;
+    w.p32 = size_t(t.n_pair_slots) * 4;
+    if (bf16) {
+        w.flags = size_t(t.n_pair_slots);
+        w.p64 = size_t(t.n_pair_slots) * 8;
+        w.recheck_list = size_t(t.n_pair_slots) * 8;
+        w.recount_list = size_t(std::max<int64_t>(t.sum_nx, 1)) * 8;
+    }
+    // per-cell counts, then 64 counter bytes: both come back with one copy
+    w.half_units = t.cells.size() * 8 + 64;
+    return w;
+}
+
+// Enqueues every kernel of a score on `stream` and the copy of the per-cell
+// counts and the 64 counter bytes into `host` [n_cells * 8 + 64].  `tm` (may
+// be null) records the stage events 0..6.
+void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &fcfg, const ColPlan *cplan,
+                   const std::vector<int64_t> &tiles, const PlainPlan &strips, const DevPtrs &d,
+                   hipStream_t stream, Timer *tm, void *host, fabx_stats &st) {
+    const DatasetImpl &ds = *t.ds;
+    const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
+    const bool dtw = p.mode == FABX_MODE_DTW;
+    const bool plain_dtw = dtw && !bf16;
+    const int dim = ds.dim;
+    const int dim_pad = int(round_up(dim, 64));
+    const int64_t n_cells = int64_t(t.cells.size());
+    const int64_t n_units = int64_t(t.units.size() / 3);
+    const int64_t G = int64_t(t.groups.size());
+    const kern::ItemTables &it = d.it;
+    const kern::GroupTables &gt = d.gt;
+    char *counters = reinterpret_cast<char *>(d.half_units) + size_t(n_cells) * 8;
+    int *err = reinterpret_cast<int *>(counters);
+    unsigned long long *err_item = reinterpret_cast<unsigned long long *>(counters + 8);
+    unsigned int *recount_n = reinterpret_cast<unsigned int *>(counters + 16);
+    unsigned int *marked_n = reinterpret_cast<unsigned int *>(counters + 20);
+    unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(counters + 24);
+    unsigned int *unit_ctr = reinterpret_cast<unsigned int *>(counters + 32);  // [8]
+    auto mark = [&] {
+        if (tm) tm->mark();
+    };
+    mark();  // 0
+    kern::init_score(stream, d.half_units, n_cells);
+    if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(d.flags, 0, size_t(t.n_pair_slots), stream));
+    mark();  // 1
+    const bool euclid = p.distance == FABX_DISTANCE_EUCLIDEAN;  // FP32 form only
+    const int out_form = bf16 ? 1 : euclid ? 2 : 0;
+    if (dtw)
+        kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, d.xn, out_form, d.rinv, err, err_item);
+    else
+        kern::pool_normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, d.xn, out_form, d.rinv, err,
+                             err_item);
+    mark();  // 2
+    const auto &sp = d.strips;
+    if (plain_dtw) {
+        // one batch of strips at a time through the distance buffer (stream order
+        // keeps a batch's Gram from overwriting the previous batch's DTW input)
+        for (const auto &b : strips.batches) {
+            const size_t k0 = size_t(b.first);
+            const int64_t ns = b.second - b.first;
+            const kern::GramSegments seg{sp[2] + k0, sp[3] + k0, sp[4] + k0, sp[5] + k0, sp[6] + k0, sp[7] + k0, ns,
+                                         strips.tiles[size_t(b.second)] - strips.tiles[k0]};
+            kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.dmat, euclid ? 1 : 0);
+            const kern::PlainStrips ps{sp[0] + k0, sp[1] + k0, sp[2] + k0, sp[6] + k0, ns,
+                                       strips.slot0[size_t(b.second)] - strips.slot0[k0]};
+            kern::dtw_plain(stream, d.dmat, ps, gt, it, p.dtw_norm, d.p32);
+        }
+        st.computed_dtw_cells = t.n_dmat;
+    } else if (dtw) {
+        kern::FusedPlan fp{d.rb, d.cb, d.rb_unit_prefix, d.g_cb0, d.rb_cstart, int64_t(t.rb.size() / 4),
+                           cplan->rb_unit_prefix.back(), fcfg.cols, fcfg.blocks_per_cu, ds.ctx->n_cu};
+        kern::fused_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt, it, fp, p.dtw_norm,
+                         float(p.delta), d.p32, d.flags, nonrobust_n, unit_ctr);
+        st.computed_dtw_cells = cplan->cells;
+    } else if (!bf16) {
+        const kern::GramSegments seg{gt.item0, gt.n_items, gt.item0, gt.n_items, gt.pair_base, d.tiles, G,
+                                     tiles.back()};
+        kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.p32, euclid ? 1 : 0);
+    } else {
+        kern::gram_angular_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt.item0,
+                                gt.n_items, gt.pair_base, d.tiles, G, tiles.back(), d.p32);
+    }
+    mark();  // 3
+    uint8_t *flags = bf16 ? d.flags : nullptr;
+    int32_t *recount = bf16 ? d.recount_list : nullptr;
+    kern::triplets(stream, d.cells, d.units, t.n_units_small, gt, d.p32, d.half_units, flags, float(p.margin),
+                   recount, recount_n, t.sum_nx);
+    kern::triplets_sorted(stream, d.cells, d.units + 3 * t.n_units_small, n_units - t.n_units_small, gt, d.p32,
+                          d.half_units, flags, float(p.margin), recount, recount_n, t.sum_nx);
+    mark();  // 4
+    if (bf16) {
+        kern::collect_marked(stream, d.flags, t.n_pair_slots, d.recheck_list, marked_n, t.n_pair_slots, recount_n);
+        kern::recheck_fp64(stream, ds.features, ds.dtype, dim, gt, it, d.recheck_list, marked_n, t.n_pair_slots,
+                           p.mode, p.dtw_norm, d.p64);
+        kern::recount(stream, d.cells, d.recount_list, recount_n, t.sum_nx, gt, d.p32, d.p64, d.flags,
+                      d.half_units);
+    }
+    mark();  // 5
+    FABX_HIP(hipMemcpyAsync(host, d.half_units, size_t(n_cells) * 8 + 64, hipMemcpyDeviceToHost, stream));
+    mark();  // 6
+}
+
+// The score's counters in the host copy (after the per-cell counts): EDOMAIN
+// if a zero-norm frame was met, else the recheck / recount / non-robust counts.
+void read_counters(const TaskImpl &t, const char *host, size_t n_cells, bool dtw, fabx_stats &st) {
+    const unsigned char *counters = reinterpret_cast<const unsigned char *>(host + n_cells * 8);
+    int err_h;
+    unsigned long long err_item_h;
+    unsigned int recount_h, marked_h, nonrobust_h;
+    std::memcpy(&err_h, counters, 4);
+    std::memcpy(&err_item_h, counters + 8, 8);
+    std::memcpy(&recount_h, counters + 16, 4);
+    std::memcpy(&marked_h, counters + 20, 4);
+    std::memcpy(&nonrobust_h, counters + 24, 4);
+    if (err_h) {
+        const int64_t bad = err_item_h < uint64_t(t.items.size()) ? t.items[size_t(err_item_h)] : -1;
+        fail(FABX_EDOMAIN, "zero-norm " + std::string(dtw ? "frame" : "mean") + " in item " + std::to_string(bad) +
+                               ": its angle is undefined");
+    }
+    st.n_recheck_pairs = marked_h;
+    st.n_recount_rows = recount_h;
+    st.n_nonrobust_pairs = nonrobust_h;
+}
+
+}  // namespace
 
 std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,
                                          hipStream_t stream) {
@@ -348,8 +611,10 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     const int64_t G = int64_t(t.groups.size());
     Trace tr("score");
     const int64_t n_units = int64_t(t.units.size() / 3);
-    const bool plain_tiles = !(dtw && bf16);
-    const std::vector<int64_t> tiles = plain_tiles ? tile_prefix(t, p) : std::vector<int64_t>();
+    const bool pooled = !dtw;
+    const bool plain_dtw = dtw && !bf16;
+    const std::vector<int64_t> tiles = pooled ? tile_prefix(t, p) : std::vector<int64_t>();
+    const PlainPlan strips = plain_dtw ? plain_plan(t, plain_dmat_cells()) : PlainPlan();
     tr.mark("plans");
 
     // ---- device tables (items / groups / cells are fixed for the task): one copy
@@ -383,7 +648,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
             pend->packed = std::move(t.packed);  // back to the pool when this score is done
         } else {
             Packer pk;
-            std::array<std::vector<int64_t>, 6> gcols;
+            std::array<std::vector<int64_t>, 5> gcols;
             const TableLayout L = add_task_tables(t, cplan && !cplan->d_cb ? cplan : nullptr, pk, gcols);
             pk.upload(dv.blob, ds.ctx->staging, ds.ctx->copy_stream, stream);
             set_task_tables(t, L);
@@ -398,52 +663,55 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         pc.upload(cplan->dev, ds.ctx->staging, ds.ctx->copy_stream, stream);
         set_col_plan(*cplan, cplan->dev, o);
     }
-    // Gram tile prefix of this score (plain form / pooled mode only)
+    // Gram tile prefix of this score (pooled mode), or the strips of the plain DTW form
     DevBuf &plan_d = pend->plan_d;
     plan_d.pool = pool;
-    const int64_t *tiles_p = nullptr;
-    if (plain_tiles) {
+    DevPtrs d;
+    if (pooled || plain_dtw) {
         Packer pp;
-        const size_t o_tiles = pp.add(tiles);
+        const PlanLayout pl = add_plan(pp, tiles, strips);
         pp.upload(plan_d, ds.ctx->staging, ds.ctx->copy_stream, stream);
-        tiles_p = Packer::at<int64_t>(plan_d, o_tiles);
+        set_plan(d, plan_d.as<char>(), pl);
     }
     tr.mark("upload");
-    const int32_t *units_p = dv.units;
 
     // ---- workspace
     Workspace &ws = t.ws;
-    const int64_t rows = dtw ? t.n_frames : n_items;
-    ws.xn.ensure(size_t(rows) * dim_pad * (bf16 ? 2 : 4));
-    if (bf16) ws.rinv.ensure(size_t(rows) * 4);
-    if (dtw && !bf16) ws.dmat.ensure(size_t(std::max<int64_t>(t.n_dmat, 1)) * 4);
-    ws.p32.ensure(size_t(t.n_pair_slots) * 4);
-    if (bf16) {
-        ws.flags.ensure(size_t(t.n_pair_slots));
-        ws.p64.ensure(size_t(t.n_pair_slots) * 8);
-        ws.recheck_list.ensure(size_t(t.n_pair_slots) * 8);
-        ws.recount_list.ensure(size_t(std::max<int64_t>(t.sum_nx, 1)) * 8);
-    }
-    // per-cell counts, then 64 counter bytes: both come back with one copy
-    ws.half_units.ensure(size_t(n_cells) * 8 + 64);
-    char *counters = ws.half_units.as<char>() + size_t(n_cells) * 8;
-    int *err = reinterpret_cast<int *>(counters);
-    unsigned long long *err_item = reinterpret_cast<unsigned long long *>(counters + 8);
-    unsigned int *recount_n = reinterpret_cast<unsigned int *>(counters + 16);
-    unsigned int *marked_n = reinterpret_cast<unsigned int *>(counters + 20);
-    unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(counters + 24);
-    unsigned int *unit_ctr = reinterpret_cast<unsigned int *>(counters + 32);  // [8]
+    const WorkspaceSizes wz = workspace_sizes(t, p, strips);
+    // buffers the form does not use keep what an earlier score left (or nothing)
+    for (auto bs : {std::make_pair(&ws.xn, wz.xn), std::make_pair(&ws.rinv, wz.rinv),
+                    std::make_pair(&ws.dmat, wz.dmat), std::make_pair(&ws.p32, wz.p32),
+                    std::make_pair(&ws.flags, wz.flags), std::make_pair(&ws.p64, wz.p64),
+                    std::make_pair(&ws.recheck_list, wz.recheck_list),
+                    std::make_pair(&ws.recount_list, wz.recount_list),
+                    std::make_pair(&ws.half_units, wz.half_units)})
+        if (bs.second) bs.first->ensure(bs.second);
     st.workspace_bytes = int64_t(ws.total());
     pend->host_bytes = size_t(n_cells) * 8 + 64;
     pend->host = ds.ctx->pinned.get(pend->host_bytes, &pend->host_bytes);
-    char *host = static_cast<char *>(pend->host);
 
-    kern::ItemTables it{dv.item_src, dv.item_len, dv.item_dst, n_items};
-    kern::GroupTables gt{dv.g_item0, dv.g_n, dv.g_frame0, dv.g_nframes, dv.g_pair_base, dv.g_dmat_base,
-                         G, t.n_pair_slots};
+    d.it = kern::ItemTables{dv.item_src, dv.item_len, dv.item_dst, n_items};
+    d.gt = kern::GroupTables{dv.g_item0, dv.g_n, dv.g_frame0, dv.g_nframes, dv.g_pair_base, G, t.n_pair_slots};
+    d.cells = dv.cells;
+    d.units = dv.units;
+    d.rb = dv.rb;
+    if (cplan) {
+        d.cb = cplan->d_cb;
+        d.g_cb0 = cplan->d_g_cb0;
+        d.rb_cstart = cplan->d_rb_cstart;
+        d.rb_unit_prefix = cplan->d_rb_unit_prefix;
+    }
+    d.xn = ws.xn.ptr;
+    d.rinv = ws.rinv.as<float>();
+    d.dmat = ws.dmat.as<float>();
+    d.p32 = ws.p32.as<float>();
+    d.flags = ws.flags.as<uint8_t>();
+    d.p64 = ws.p64.as<double>();
+    d.recheck_list = ws.recheck_list.as<int64_t>();
+    d.recount_list = ws.recount_list.as<int32_t>();
+    d.half_units = ws.half_units.as<unsigned long long>();
 
     pend->tm = std::make_unique<Timer>(stream, ds.ctx->events);
-    Timer &tm = *pend->tm;
     tr.mark("workspace");
     // on an error after launches, drain the stream before plan_d goes back to the pool
     struct DrainOnError {
@@ -452,62 +720,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
             if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s);
         }
     } drain{stream};
-    tm.mark();  // 0
-    kern::init_score(stream, ws.half_units.as<unsigned long long>(), n_cells);
-    if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(ws.flags.ptr, 0, size_t(t.n_pair_slots), stream));
-    tm.mark();  // 1
-    const bool euclid = p.distance == FABX_DISTANCE_EUCLIDEAN;  // FP32 form only
-    const int out_form = bf16 ? 1 : euclid ? 2 : 0;
-    if (dtw)
-        kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, out_form,
-                        ws.rinv.as<float>(), err, err_item);
-    else
-        kern::pool_normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, ws.xn.ptr, out_form,
-                             ws.rinv.as<float>(), err, err_item);
-    tm.mark();  // 2
-    if (dtw && !bf16) {
-        kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.frame0, gt.n_frames, gt.dmat_base,
-                               tiles_p, G, tiles.back(), ws.dmat.as<float>(), euclid ? 1 : 0);
-        kern::dtw_plain(stream, ws.dmat.as<float>(), gt, it, p.dtw_norm, ws.p32.as<float>());
-        st.computed_dtw_cells = t.n_dmat;
-    } else if (dtw) {
-        kern::FusedPlan fp{dv.rb, cplan->d_cb, cplan->d_rb_unit_prefix, cplan->d_g_cb0, cplan->d_rb_cstart,
-                           int64_t(t.rb.size() / 4), cplan->rb_unit_prefix.back(), fcfg.cols,
-                           fcfg.blocks_per_cu, ds.ctx->n_cu};
-        kern::fused_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt, it, fp,
-                         p.dtw_norm, float(p.delta), ws.p32.as<float>(), ws.flags.as<uint8_t>(),
-                         nonrobust_n, unit_ctr);
-        st.computed_dtw_cells = cplan->cells;
-    } else if (!bf16) {
-        kern::gram_angular_f32(stream, ws.xn.as<float>(), dim_pad, gt.item0, gt.n_items, gt.pair_base,
-                               tiles_p, G, tiles.back(), ws.p32.as<float>(), euclid ? 1 : 0);
-    } else {
-        kern::gram_angular_bf16(stream, ws.xn.as<uint16_t>(), ws.rinv.as<float>(), dim_pad, gt.item0,
-                                gt.n_items, gt.pair_base, tiles_p, G,
-                                tiles.back(), ws.p32.as<float>());
-    }
-    tm.mark();  // 3
-    kern::triplets(stream, dv.cells, units_p, t.n_units_small, gt,
-                   ws.p32.as<float>(), ws.half_units.as<unsigned long long>(),
-                   bf16 ? ws.flags.as<uint8_t>() : nullptr, float(p.margin),
-                   bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, t.sum_nx);
-    kern::triplets_sorted(stream, dv.cells, units_p + 3 * t.n_units_small, n_units - t.n_units_small, gt,
-                          ws.p32.as<float>(), ws.half_units.as<unsigned long long>(),
-                          bf16 ? ws.flags.as<uint8_t>() : nullptr, float(p.margin),
-                          bf16 ? ws.recount_list.as<int32_t>() : nullptr, recount_n, t.sum_nx);
-    tm.mark();  // 4
-    if (bf16) {
-        kern::collect_marked(stream, ws.flags.as<uint8_t>(), t.n_pair_slots, ws.recheck_list.as<int64_t>(),
-                             marked_n, t.n_pair_slots, recount_n);
-        kern::recheck_fp64(stream, ds.features, ds.dtype, dim, gt, it, ws.recheck_list.as<int64_t>(),
-                           marked_n, t.n_pair_slots, p.mode, p.dtw_norm, ws.p64.as<double>());
-        kern::recount(stream, dv.cells, ws.recount_list.as<int32_t>(), recount_n, t.sum_nx,
-                      gt, ws.p32.as<float>(), ws.p64.as<double>(), ws.flags.as<uint8_t>(),
-                      ws.half_units.as<unsigned long long>());
-    }
-    tm.mark();  // 5
-    FABX_HIP(hipMemcpyAsync(host, ws.half_units.ptr, size_t(n_cells) * 8 + 64, hipMemcpyDeviceToHost, stream));
-    tm.mark();  // 6
+    enqueue_score(t, p, fcfg, cplan, tiles, strips, d, stream, pend->tm.get(), pend->host, st);
     tr.mark("launch");
     pend->t_launch = clock::now();
     res->pending = std::move(pend);
@@ -532,29 +745,13 @@ void finish_score(ResultImpl &res) {
         const size_t n_cells = res.half_units.size();
         const char *host = static_cast<const char *>(pend->host);
         std::memcpy(res.half_units.data(), host, n_cells * 8);
-        const unsigned char *counters = reinterpret_cast<const unsigned char *>(host + n_cells * 8);
-        int err_h;
-        unsigned long long err_item_h;
-        unsigned int recount_h, marked_h, nonrobust_h;
-        std::memcpy(&err_h, counters, 4);
-        std::memcpy(&nonrobust_h, counters + 24, 4);
-        std::memcpy(&err_item_h, counters + 8, 8);
-        std::memcpy(&recount_h, counters + 16, 4);
-        std::memcpy(&marked_h, counters + 20, 4);
-        if (err_h) {
-            const int64_t bad = err_item_h < uint64_t(t.items.size()) ? t.items[size_t(err_item_h)] : -1;
-            fail(FABX_EDOMAIN, "zero-norm " + std::string(pend->dtw ? "frame" : "mean") + " in item " +
-                                   std::to_string(bad) + ": its angle is undefined");
-        }
         fabx_stats &st = res.stats;
+        read_counters(t, host, n_cells, pend->dtw, st);
         st.ms_normalize = tm.ms(1, 2);
         st.ms_distance = tm.ms(2, 3);
         st.ms_triplets = tm.ms(3, 4);
         st.ms_recheck = tm.ms(4, 5);
         st.ms_total = tm.ms(0, 6);
-        st.n_recheck_pairs = marked_h;
-        st.n_recount_rows = recount_h;
-        st.n_nonrobust_pairs = nonrobust_h;
         if (pend->keep_pairs) {
             // the task's workspace still holds this score: a later score on the task
             // finishes this one before it touches the workspace
@@ -577,6 +774,29 @@ void finish_score(ResultImpl &res) {
         res.status_msg = e.msg;
         throw;
     }
+}
+
+void release_device(TaskImpl &t) {
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (auto prev = t.pending.lock()) {
+        try {
+            finish_score(*prev);
+        } catch (const Error &) {
+            // that score's error stays with its own result
+        }
+    }
+    t.ws.release();
+    TaskDevice &dv = t.dev;
+    dv.blob.release();
+    dv.uploaded = false;
+    for (auto &cp : t.col_plans) {
+        cp->dev.release();
+        cp->d_cb = nullptr;
+        cp->d_g_cb0 = nullptr;
+        cp->d_rb_cstart = nullptr;
+        cp->d_rb_unit_prefix = nullptr;
+    }
+    t.packed.reset();
 }
 
 std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &tp, const ScoreParams &p,

@@ -1,12 +1,18 @@
 // Continuous-batching job server.
 //
-// Jobs are queued in arrival order.  A job is admitted when its device
-// footprint (workspace + tables of its task, as computed by footprint_bytes)
-// fits in the budget next to the jobs already running and a stream is free;
-// admitted jobs run concurrently, one per HIP stream, so the kernels of
-// several jobs overlap on the device.  Each job runs the same code path as
-// fabx_score with its own task and workspace, so its result does not depend
-// on what else is running.
+// Jobs are queued in arrival order.  When a stream is free, the first queued
+// job whose device footprint (workspace + tables of its task, as computed by
+// footprint_bytes) fits in the budget next to the jobs already running is
+// admitted, so a small job does not wait behind a large one that does not fit
+// yet.  Each time a job is passed over that way it counts one bypass; a job
+// passed over kMaxBypass times stops later jobs from passing it, so it runs as
+// soon as memory frees up (no starvation).  Admitted jobs run concurrently,
+// one per HIP stream, so the kernels of several jobs overlap on the device.
+// Each job runs the same code path as fabx_score with its own task and
+// workspace, so its result does not depend on what else is running; a job
+// that fails leaves the others untouched.  When a job ends, its device
+// memory (workspace and task tables) goes back to the context's pool; the
+// result keeps the per-cell counts on the host.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -24,6 +30,13 @@ using Clock = std::chrono::steady_clock;
 
 enum class JobState { Queued, Running, Done, Failed, Cancelled };
 
+// Times a queued job may be passed over by later jobs that fit before it.
+constexpr int kMaxBypass = 8;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
 struct Job {
     std::shared_ptr<TaskImpl> task;
     ScoreParams params{};
@@ -32,7 +45,9 @@ struct Job {
     std::shared_ptr<ResultImpl> result;
     int code = FABX_OK;
     std::string msg;
-    Clock::time_point t_submit, t_done;
+    int bypassed = 0;
+    // submit entry, end of the task build (queued), admission, completion
+    Clock::time_point t_submit, t_queued, t_admit, t_done;
     // recorded on the context's stream at submit: the job's stream waits for it,
     // so the job reads features produced there before the submit call
     hipEvent_t ready = nullptr;
@@ -52,8 +67,21 @@ struct ServerImpl {
     uint64_t next_id = 1;
     int64_t in_use = 0, high_water = 0;
     int64_t submitted = 0, completed = 0, cancelled = 0, failed = 0, running = 0;
-    std::vector<double> latencies_ms;
+    // per completed job: completion - submit entry, and its parts
+    std::vector<double> latencies_ms, build_ms, queue_ms, run_ms;
     bool stop = false;
+
+    // The queued job to admit now, or queue.end(): the first that fits, unless
+    // a job before it has been passed over kMaxBypass times already.  Called
+    // with mu held.
+    std::deque<uint64_t>::iterator pick() {
+        for (auto it = queue.begin(); it != queue.end(); ++it) {
+            Job &j = jobs[*it];
+            if (j.footprint <= budget - in_use) return it;
+            if (j.bypassed >= kMaxBypass) break;
+        }
+        return queue.end();
+    }
 
     void drop_event(Job &j) {
         if (j.ready) ctx->events.put(j.ready);
@@ -64,10 +92,11 @@ struct ServerImpl {
         (void)hipSetDevice(ctx->device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
+            std::deque<uint64_t>::iterator chosen;
             cv.wait(lk, [&] {
                 if (stop) return true;
-                if (queue.empty()) return false;
-                return jobs[queue.front()].footprint <= budget - in_use;
+                chosen = pick();
+                return chosen != queue.end();
             });
             if (stop && queue.empty()) return;
             if (stop) {
@@ -81,10 +110,12 @@ struct ServerImpl {
                 cv.notify_all();
                 return;
             }
-            const uint64_t id = queue.front();
-            queue.pop_front();
+            const uint64_t id = *chosen;
+            for (auto it = queue.begin(); it != chosen; ++it) ++jobs[*it].bypassed;
+            queue.erase(chosen);
             Job &job = jobs[id];
             job.state = JobState::Running;
+            job.t_admit = Clock::now();
             in_use += job.footprint;
             high_water = std::max(high_water, in_use);
             ++running;
@@ -108,23 +139,24 @@ struct ServerImpl {
             // nothing of the job may still run on the stream (a failed call can leave
             // launches behind) before its memory and its event are reused
             (void)hipStreamSynchronize(streams[k]);
-            // the result keeps per-cell counts on the host; give the device memory back
-            {
-                std::lock_guard<std::mutex> g(task->mu);
-                task->ws.release();
-            }
+            // the result keeps per-cell counts on the host; give the device memory
+            // (workspace, task tables, column plans) back to the context's pool
+            release_device(*task);
             lk.lock();
             Job &j2 = jobs[id];
             drop_event(j2);
             j2.t_done = Clock::now();
             in_use -= j2.footprint;
             --running;
+            j2.task.reset();  // the result (if any) keeps the task's host tables
             if (code == FABX_OK) {
                 j2.state = JobState::Done;
                 j2.result = res;
                 ++completed;
-                latencies_ms.push_back(
-                    std::chrono::duration<double, std::milli>(j2.t_done - j2.t_submit).count());
+                latencies_ms.push_back(ms_between(j2.t_submit, j2.t_done));
+                build_ms.push_back(ms_between(j2.t_submit, j2.t_queued));
+                queue_ms.push_back(ms_between(j2.t_queued, j2.t_admit));
+                run_ms.push_back(ms_between(j2.t_admit, j2.t_done));
             } else {
                 j2.state = JobState::Failed;
                 j2.code = code;
@@ -201,10 +233,12 @@ int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int
                        const int32_t *across, int32_t n_across, const fabx_score_opts *opts,
                        uint64_t *job_id) {
     return guarded_server([&] {
+        const Clock::time_point t_entry = Clock::now();
         if (!srv || !ds || !job_id) fail(FABX_EINVAL, "null argument");
         ServerImpl &s = *srv->p;
         if (ds->p->ctx->device != s.ctx->device) fail(FABX_EINVAL, "dataset is on another device");
         Job job;
+        job.t_submit = t_entry;
         job.params = resolve_opts(opts, *ds->p);
         job.task = build_task(ds->p, on, by, n_by, across, n_across);
         job.footprint = footprint_bytes(*job.task, job.params);
@@ -219,7 +253,7 @@ int fabx_server_submit(fabx_server *srv, fabx_dataset *ds, int32_t on, const int
             s.ctx->events.put(job.ready);
             fail(FABX_EHIP, "recording the submit event on the context's stream failed");
         }
-        job.t_submit = Clock::now();
+        job.t_queued = Clock::now();
         std::lock_guard<std::mutex> lk(s.mu);
         if (s.stop) {
             s.drop_event(job);
@@ -238,15 +272,16 @@ static int server_result(ServerImpl &s, uint64_t id, fabx_result **out, bool wai
     std::unique_lock<std::mutex> lk(s.mu);
     auto it = s.jobs.find(id);
     if (it == s.jobs.end()) {
-        set_last_error("unknown job id");
+        set_last_error("unknown job id (or its result was already fetched)");
         return FABX_ENOTFOUND;
     }
     if (wait)
         s.cv.wait(lk, [&] {
-            auto st = s.jobs[id].state;
+            auto st = it->second.state;
             return st != JobState::Queued && st != JobState::Running;
         });
-    Job &j = s.jobs[id];
+    Job &j = it->second;
+    int rc = FABX_OK;
     switch (j.state) {
         case JobState::Queued:
         case JobState::Running:
@@ -254,16 +289,20 @@ static int server_result(ServerImpl &s, uint64_t id, fabx_result **out, bool wai
             return FABX_EAGAIN;
         case JobState::Cancelled:
             set_last_error("job was cancelled");
-            return FABX_ECANCELED;
+            rc = FABX_ECANCELED;
+            break;
         case JobState::Failed:
             set_last_error(j.msg);
-            return j.code;
+            rc = j.code;
+            break;
         case JobState::Done:
             if (out) *out = new fabx_result{j.result};
             set_last_error("");
-            return FABX_OK;
+            break;
     }
-    return FABX_EINVAL;
+    // the outcome has been handed over: the server keeps nothing of the job
+    s.jobs.erase(it);
+    return rc;
 }
 
 int fabx_server_poll(fabx_server *srv, uint64_t job_id, fabx_result **out) {
@@ -311,13 +350,26 @@ int fabx_server_stats_get(fabx_server *srv, fabx_server_stats *st) {
     st->hbm_high_water = s.high_water;
     std::vector<double> l = s.latencies_ms;
     std::sort(l.begin(), l.end());
-    auto pct = [&](double q) {
-        if (l.empty()) return 0.0;
-        size_t i = size_t(std::min<double>(double(l.size() - 1), std::ceil(q * double(l.size())) - 1));
-        return l[i];
+    // nearest-rank percentile of a sorted vector
+    auto pct = [](const std::vector<double> &v, double q) {
+        if (v.empty()) return 0.0;
+        const double r = std::max(1.0, std::ceil(q * double(v.size())));
+        return v[size_t(std::min<double>(double(v.size()), r)) - 1];
     };
-    st->p50_ms = pct(0.50);
-    st->p99_ms = pct(0.99);
+    st->p50_ms = pct(l, 0.50);
+    st->p99_ms = pct(l, 0.99);
+    std::vector<double> q = s.queue_ms;
+    std::sort(q.begin(), q.end());
+    st->p50_queue_ms = pct(q, 0.50);
+    st->p99_queue_ms = pct(q, 0.99);
+    auto mean = [](const std::vector<double> &v) {
+        double a = 0.0;
+        for (double x : v) a += x;
+        return v.empty() ? 0.0 : a / double(v.size());
+    };
+    st->mean_build_ms = mean(s.build_ms);
+    st->mean_queue_ms = mean(s.queue_ms);
+    st->mean_run_ms = mean(s.run_ms);
     return FABX_OK;
 }
 

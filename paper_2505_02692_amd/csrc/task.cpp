@@ -870,7 +870,6 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
         g.n_items = kept[gi].second - kept[gi].first;
         g.frame0 = frame_total;
         g.n_frames = pf[kept[gi].second] - pf[kept[gi].first];
-        g.dmat_base = t->n_dmat;
         t->n_dmat += g.n_frames * g.n_frames;
         nt += g.n_items;
         frame_total += g.n_frames;

@@ -7,7 +7,8 @@
 // all candidates must give identical per-cell counts, and fabx_autotune checks
 // that they do.  Each candidate's distance stage is timed in three rounds
 // that run every candidate once in turn (so a drift of the clocks touches
-// them alike), keeping its best time.  The default (the first candidate)
+// them alike), keeping its best time; one round when the stage takes 100 ms
+// or more.  The default (the first candidate)
 // stays unless another is faster by more than 2%: closer times are within
 // what a score's surroundings move them (the same kernel runs a few percent
 // faster in back-to-back pipelined scores than in these isolated ones).  The
@@ -103,7 +104,10 @@ extern "C" int fabx_autotune(fabx_task *task, const fabx_score_opts *opts, fabx_
         hvec<int64_t> ref;
         double ms[kCands];
         for (double &m : ms) m = 1e300;
-        for (int round = 0; round < kRounds; ++round)
+        // a distance stage of 100 ms or more varies far less than the 2% the
+        // choice needs, so one round is enough there
+        constexpr double kOneRoundMs = 100.0;
+        for (int round = 0; round < kRounds && !(round > 0 && ms[0] >= kOneRoundMs); ++round)
             for (int i = 0; i < kCands; ++i) {
                 p.fused = cands[i];
                 auto r = run_score(t, p, t->ds->ctx->stream);

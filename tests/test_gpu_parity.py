@@ -8,7 +8,9 @@ Bars:
 * per-pair distances: FP32 within 2e-6, BF16 (robust pairs) within the
   stated margin / 3, FP64-rechecked pairs within 1e-12 of the oracle.
 """
+import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -886,3 +888,230 @@ def test_within_c2_full_size_bf16():
     """The bench workload at full size (100k items, dim 768): every cell exact."""
     w = workloads.within_c2(device="cuda")
     check(w, levels=True)
+
+
+# ------------------------------------------ plain form in strips / batches --
+
+def test_plain_fp32_in_strips_equals_whole(monkeypatch):
+    """The plain form makes a group's frame distance matrix in strips of item
+    rows and runs them in batches through one buffer.  With a buffer of 4096
+    cells, every group of this task (about 780 frames) is cut into strips of
+    a few items and every strip runs alone: the counts and pair distances must
+    equal those of the one-batch run bit for bit (the same sums in the same
+    order), and the oracle's within the plain form's bar."""
+    w = workloads.plain_c1(centroid_std=0.15, seed=3)
+    _say("plain fp32: strips vs whole groups")
+    feats = w.features.to("cuda").contiguous()
+    ds = fx.Dataset(ctx(), feats, w.offsets, w.attrs)
+    t = fx.Task(ds, w.on, w.by, w.across)
+    whole = t.score(precision="fp32", keep_pairs=True)
+    orc = oracle_score(w)
+    xs, ys, want = all_oracle_pairs(orc)
+    p_whole = whole.pairs(xs, ys)[0]
+    monkeypatch.setenv("FABX_PLAIN_DMAT_CELLS", "4096")
+    t2 = fx.Task(ds, w.on, w.by, w.across)
+    cut = t2.score(precision="fp32", keep_pairs=True)
+    p_cut = cut.pairs(xs, ys)[0]
+    assert np.array_equal(p_cut, p_whole)
+    assert np.array_equal(cut.half_units, whole.half_units)
+    assert np.abs(p_cut.astype(np.float64) - want).max() <= 2e-6
+    assert abs(cut.collapse() - oracle.error_rate(orc)) <= 1e-4
+    # pooled mode and the BF16 form are unaffected by the setting
+    _, res_b = gpu_score(w)
+    assert np.array_equal(res_b.half_units, orc.half_units)
+
+
+# ------------------------------------------------- batched workload, full size --
+
+def _groups_by_size(w):
+    col = w.attrs[:, w.by[0]]
+    ids, counts = np.unique(col, return_counts=True)
+    return ids, counts
+
+
+def _check_sampled_groups(w, t, res, chosen):
+    """Every cell of the chosen BY groups (values of the single BY column)
+    equals the oracle's, run on those groups' items only."""
+    keys, hu = t.keys, res.half_units
+    where = {tuple(int(v) for v in k): c for c, k in enumerate(keys)}
+    sizes = t.sizes[0]
+    n_checked = 0
+    # the oracle runs on a few groups at a time (about 8 groups, or one large
+    # group), and the progress is printed after each run
+    col = w.attrs[:, w.by[0]]
+    counts = {int(g): int(np.count_nonzero(col == g)) for g in chosen}
+    batches, cur = [], []
+    for g in chosen:
+        if cur and (len(cur) >= 8 or counts[int(g)] > 200):
+            batches.append(cur)
+            cur = []
+        cur.append(int(g))
+    batches.append(cur)
+    for b in batches:
+        feats, off, attrs = _groups_subset(w, [(g,) for g in b])
+        t0 = time.perf_counter()
+        orc = oracle.score(feats, off, attrs, w.on, w.by, w.across)
+        idx = np.array([where[tuple(int(v) for v in k)] for k in orc.keys])
+        bad = np.nonzero(hu[idx] != orc.half_units)[0]
+        print(f"  groups {b} ({len(off) - 1} items): {len(idx)} cells, oracle {time.perf_counter() - t0:.1f} s, "
+              f"{len(bad)} differ", flush=True)
+        for c in bad[:5]:
+            print(f"  cell {tuple(orc.keys[c])}: gpu {hu[idx][c]} oracle {orc.half_units[c]}", flush=True)
+        assert len(bad) == 0, f"{len(bad)} of {len(idx)} cells differ"
+        assert np.array_equal(sizes[idx], orc.n_triplets)
+        n_checked += len(idx)
+    in_chosen = np.isin(keys[:, 2], np.asarray(chosen, dtype=keys.dtype))
+    assert int(in_chosen.sum()) == n_checked
+    return n_checked
+
+
+def test_batched_c4_full_size_sampled_groups():
+    """The batched uneven workload at full size (5,000 BY groups of 2-2,000
+    items, 1.05M items, lengths 1-60, dim 512 BF16), scored in one persistent
+    launch as the bench runs it: every cell of 48 seeded groups of at most 200
+    items and 2 groups of 200-600 items equals the oracle's."""
+    w = workloads.batched_c4(device="cuda")
+    _say(f"batched-c4 full size n_items={w.n_items}")
+    t, res = gpu_score(w)
+    st = res.stats
+    print(f"  cells={st['n_cells']} triplets={st['n_triplets']} gpu={st['ms_total']:.0f}ms "
+          f"nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']}", flush=True)
+    ids, counts = _groups_by_size(w)
+    rng = np.random.default_rng(11)
+    small = ids[counts <= 200]
+    mid = ids[(counts > 200) & (counts <= 600)]
+    chosen = list(rng.choice(small, 48, replace=False)) + list(rng.choice(mid, 2, replace=False))
+    n = _check_sampled_groups(w, t, res, chosen)
+    print(f"  {n} cells equal the oracle's", flush=True)
+
+
+@pytest.mark.skipif(not os.environ.get("FABX_SLOW_TESTS"),
+                    reason="long oracle run (about 10 min on 16 cores): set FABX_SLOW_TESTS=1")
+def test_batched_c4_full_size_all_small_groups_and_largest():
+    """As above, on every group of at most 200 items (3,764 groups) and the two
+    largest groups (2,000 items each)."""
+    w = workloads.batched_c4(device="cuda")
+    _say(f"batched-c4 full size, all small groups n_items={w.n_items}")
+    t, res = gpu_score(w)
+    ids, counts = _groups_by_size(w)
+    order = np.argsort(counts)
+    chosen = list(ids[counts <= 200]) + list(ids[order[-2:]])
+    n = _check_sampled_groups(w, t, res, chosen)
+    print(f"  {n} cells equal the oracle's", flush=True)
+
+
+# ---------------------------------------------- serving jobs vs the oracle --
+
+def _stream_jobs_for_oracle(n_draws=100, max_items=5000, max_cost=2e11):
+    """Jobs of the serving stream (its own draws, seed 4) with at most
+    max_items items whose oracle cost (sum over BY groups of squared frame
+    counts x 2 dim) is at most max_cost; only the host-side draws are made."""
+    out = []
+    for j in range(n_draws):
+        rng = workloads._rng(4 * 100003 + j)
+        n = int(np.rint(np.exp(rng.uniform(np.log(1000), np.log(50000)))))
+        d = int(rng.choice([256, 512, 768, 1024, 1280]))
+        acr = bool(rng.random() < 0.5)
+        workloads._zipf_labels(rng, 1.0, 40, n)
+        ctxs = workloads._zipf_labels(rng, 1.0, 16, n)
+        spk = rng.integers(0, 20, size=n)
+        lens = rng.integers(1, 61, size=n)
+        key = ctxs if acr else ctxs * 20 + spk
+        cost = float((np.bincount(key, weights=lens) ** 2).sum()) * d * 2
+        if n <= max_items and cost <= max_cost:
+            out.append(j)
+    return out
+
+
+def test_serving_jobs_match_oracle():
+    """Jobs of the serving stream as drawn (BF16 features, dims 256-1280,
+    within and across speaker, lengths 1-60) with at most 5k items: scored
+    alone and then served together on 4 streams, every cell of every job
+    equals the oracle's in both."""
+    sel = _stream_jobs_for_oracle()
+    _say(f"serving jobs vs oracle: {len(sel)} jobs {sel}")
+    jobs = []
+    for j in sel:
+        w = workloads.serving_job(j, device="cuda")
+        jobs.append((w, fx.Dataset(ctx(), w.features, w.offsets, w.attrs)))
+    assert any(w.across for w, _ in jobs) and any(not w.across for w, _ in jobs)
+    alone = [fx.Task(ds, w.on, w.by, w.across).score().half_units.copy() for w, ds in jobs]
+    srv = fx.Server(ctx(), hbm_budget_bytes=32 << 30, n_streams=4)
+    ids = [srv.submit(ds, w.on, w.by, w.across) for w, ds in jobs]
+    served = [srv.wait(i) for i in ids]
+    srv.close()
+    for (w, ds), a, (keys, W, n, s) in zip(jobs, alone, served):
+        orc = oracle.score(w.features_f32_host(), w.offsets, w.attrs, w.on, w.by, w.across)
+        assert np.array_equal(keys, orc.keys.astype(np.int32))
+        ma, ms_ = int(np.count_nonzero(a != orc.half_units)), int(np.count_nonzero(W != orc.half_units))
+        print(f"  {w.name} n={w.n_items} dim={w.dim} cells={len(W)} alone-vs-oracle {ma} "
+              f"served-vs-oracle {ms_} err={oracle.error_rate(orc, w.levels):.4f}", flush=True)
+        assert ma == 0 and ms_ == 0
+
+
+def test_server_failing_job_leaves_others_intact():
+    """A job whose features hold a zero-norm frame fails with EDOMAIN in the
+    middle of a mix; every other job's counts equal its alone result."""
+    _say("server: failing job in a mix")
+    specs = [(1500, 512, False), (2200, 768, True), (1800, 256, False), (2600, 1024, True), (1200, 1280, False)]
+    jobs = []
+    for j, (n, d, a) in enumerate(specs):
+        w = workloads.serving_job(j, n_items=n, dim=d, across=a, centroid_std=0.1, device="cuda")
+        jobs.append((w, fx.Dataset(ctx(), w.features, w.offsets, w.attrs)))
+    alone = [fx.Task(ds, w.on, w.by, w.across).score().half_units.copy() for w, ds in jobs]
+    bad_w = workloads.serving_job(9, n_items=2000, dim=512, across=False, device="cuda")
+    feats = bad_w.features.clone()
+    feats[int(bad_w.offsets[700]) + 0].zero_()
+    bad_ds = fx.Dataset(ctx(), feats, bad_w.offsets, bad_w.attrs)
+    srv = fx.Server(ctx(), hbm_budget_bytes=16 << 30, n_streams=3)
+    ids = [srv.submit(ds, w.on, w.by, w.across) for w, ds in jobs[:2]]
+    bad_id = srv.submit(bad_ds, bad_w.on, bad_w.by, bad_w.across)
+    ids += [srv.submit(ds, w.on, w.by, w.across) for w, ds in jobs[2:]]
+    with pytest.raises(fx.FabxError) as e:
+        srv.wait(bad_id)
+    assert e.value.code == -3
+    for jid, a in zip(ids, alone):
+        assert np.array_equal(srv.wait(jid)[1], a)
+    st = srv.stats
+    assert st["failed"] == 1 and st["completed"] == len(jobs)
+    # an outcome is handed over once
+    with pytest.raises(fx.FabxError) as e2:
+        srv.wait(ids[0])
+    assert e2.value.code == -7
+    srv.close()
+
+
+def test_server_small_job_passes_a_waiting_large_one():
+    """Budget for one large job plus one small one: while a large job runs, a
+    second large job waits for memory, and a small job submitted after it is
+    admitted at once instead of queueing behind it.  Of the three queue waits
+    the median is then near zero (head-of-line admission would make it the
+    large job's run time)."""
+    _say("server: admission past a waiting job")
+    big = [workloads.serving_job(20 + k, n_items=16000, dim=1024, across=True, device="cuda") for k in range(2)]
+    small = workloads.serving_job(30, n_items=1000, dim=256, across=False, device="cuda")
+    dbig = [fx.Dataset(ctx(), w.features, w.offsets, w.attrs) for w in big]
+    dsmall = fx.Dataset(ctx(), small.features, small.offsets, small.attrs)
+    t0 = time.perf_counter()
+    ref_big = fx.Task(dbig[0], big[0].on, big[0].by, big[0].across).score().half_units.copy()
+    t_big = (time.perf_counter() - t0) * 1e3
+    ref_small = fx.Task(dsmall, small.on, small.by, small.across).score().half_units.copy()
+    # footprints from a first server with room for everything
+    probe = fx.Server(ctx(), hbm_budget_bytes=64 << 30, n_streams=1)
+    probe.wait(probe.submit(dbig[0], big[0].on, big[0].by, big[0].across))
+    fp_big = probe.stats["hbm_high_water"]
+    probe.wait(probe.submit(dsmall, small.on, small.by, small.across))
+    probe.close()
+    srv = fx.Server(ctx(), hbm_budget_bytes=int(fp_big * 1.6), n_streams=3)
+    j1 = srv.submit(dbig[0], big[0].on, big[0].by, big[0].across)
+    j2 = srv.submit(dbig[1], big[1].on, big[1].by, big[1].across)
+    j3 = srv.submit(dsmall, small.on, small.by, small.across)
+    assert np.array_equal(srv.wait(j3)[1], ref_small)
+    assert np.array_equal(srv.wait(j1)[1], ref_big)
+    srv.wait(j2)
+    st = srv.stats
+    print(f"  big alone {t_big:.1f} ms, footprint {fp_big / 2**30:.2f} GiB; queue p50 {st['p50_queue_ms']:.1f} ms "
+          f"p99 {st['p99_queue_ms']:.1f} ms, mean run {st['mean_run_ms']:.1f} ms", flush=True)
+    assert st["p50_queue_ms"] < 0.25 * t_big
+    assert st["p99_queue_ms"] > 0.25 * t_big   # the second large job did wait
+    srv.close()
