@@ -20,6 +20,9 @@ Every function follows a passage of the paper (Poli, Chemla, Dupoux,
                           attributes level by level (Score / collapse).
 * ``slice_frames``     -- the frames kept for an aligned unit ("Slicing
                           features" appendix), from the set definition.
+* ``subsample``        -- the Subsampler of the Task interface (caps on a, b
+                          and x per cell; distinct ACROSS values of x), with
+                          Philox4x32-10 draws (``philox4x32_10``).
 
 Readings where the paper is silent:
 a == x is excluded when A and X are the same set; cells are ordered (o1, o2);
@@ -310,13 +313,17 @@ def pair_distances(features: np.ndarray, offsets: np.ndarray,
 
 def score(features: np.ndarray, offsets: np.ndarray, attrs: np.ndarray, on: int,
           by: Sequence[int], across: Sequence[int], mode: str = "dtw", norm: str = "path",
-          cell_filter=None, distance: str = "angular") -> OracleResult:
+          cell_filter=None, distance: str = "angular", subsampler: Optional[dict] = None) -> OracleResult:
     """Per-cell half-unit counts W and triplet counts |C| for the whole task.
 
     ``cell_filter`` (optional) keeps a subset of the cells, e.g. a sample of
-    BY groups for workloads too large to score in full.
+    BY groups for workloads too large to score in full.  ``subsampler``
+    (optional): keyword arguments of ``subsample`` (seed, max_a, max_b,
+    max_x, max_x_across), applied to the full cell list before the filter.
     """
     cl = cells(attrs, on, by, across)
+    if subsampler is not None:
+        cl = subsample(cl, len(across), **subsampler)
     if cell_filter is not None:
         cl = [c for c in cl if cell_filter(c)]
     # the (x, y) pairs each BY group needs: X x A without a == x, and X x B
@@ -394,3 +401,100 @@ def collapse(keys: np.ndarray, key_attr: Sequence[int], half_units: np.ndarray,
 
 def error_rate(res: OracleResult, levels=None) -> float:
     return collapse(res.keys, res.key_attrs, res.half_units, res.n_triplets, levels)
+
+
+# --------------------------------------------------------------- subsampler --
+#
+# The Subsampler of the Task interface (library overview, "Task" paragraph):
+# it caps the number of a, b and x independently in each cell, and, with ACROSS
+# conditions, limits the number of distinct values x takes for the ACROSS
+# attribute (the text says "for the ON attribute", but x's ON value is fixed
+# within a cell; the limit that exists in the Libri-Light evaluation it
+# reproduces is on the ACROSS value, e.g. the speaker).  Random choices come
+# from the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+# "Parallel random numbers: as easy as 1, 2, 3", SC'11), so that a subsample
+# is a pure function of (seed, cell, set, position) and the GPU library can
+# draw the same one without sharing this code.
+
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)    # round multipliers
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)    # key increments (Weyl sequence)
+_U32 = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> Tuple[int, int, int, int]:
+    """Philox4x32 with 10 rounds: each round multiplies counter words 0 and 2
+    by the two multipliers (64-bit products split into high and low halves),
+    mixes the high halves with words 1 and 3 and the key, permutes, and bumps
+    the key by the Weyl increments."""
+    c0, c1, c2, c3 = (int(v) & _U32 for v in ctr)
+    k0, k1 = (int(v) & _U32 for v in key)
+    for _ in range(10):
+        p0, p1 = _PHILOX_M[0] * c0, _PHILOX_M[1] * c2
+        c0, c1, c2, c3 = ((p1 >> 32) ^ c1 ^ k0) & _U32, p1 & _U32, ((p0 >> 32) ^ c3 ^ k1) & _U32, p0 & _U32
+        k0 = (k0 + _PHILOX_W[0]) & _U32
+        k1 = (k1 + _PHILOX_W[1]) & _U32
+    return c0, c1, c2, c3
+
+
+def _draw(seed: int, a: int, b: int, c: int) -> int:
+    """First output word of Philox4x32-10 at counter (a, b, c, 0), key = the seed."""
+    return philox4x32_10((a, b, c, 0), (seed & _U32, (seed >> 32) & _U32))[0]
+
+
+def _pick(items: np.ndarray, cap: int, seed: int, cell: int, which: int) -> np.ndarray:
+    """At most `cap` of `items` (ascending item ids): the ones whose draws at
+    counter (cell, which, position) are smallest, position breaking ties; all
+    of them when cap <= 0 or there are not more than cap."""
+    if cap <= 0 or len(items) <= cap:
+        return items
+    r = [(_draw(seed, cell, which, i), i) for i in range(len(items))]
+    keep = sorted(i for _, i in sorted(r)[:cap])
+    return items[np.array(keep, dtype=np.int64)]
+
+
+def subsample(cl: List[Cell], n_across: int, seed: int, max_a: int = 0, max_b: int = 0, max_x: int = 0,
+              max_x_across: int = 0) -> List[Cell]:
+    """The cells of a subsampled task, from the full list `cl` (as ``cells``
+    returns it; position c in it is the cell's index in the draws).
+
+    1. ACROSS tasks with max_x_across > 0: the cells sharing (on_ax, on_b,
+       by..., across_ab...) differ only in across_x; of the m cells of such a
+       family, those with the max_x_across smallest draws at counter
+       (f, 3, j) are kept (f: index of the family's first cell, j: rank of
+       the cell in the family).
+    2. Each kept cell c caps A, B and X independently: A with the draws at
+       (c, 0, position), B at (c, 1, .), X at (c, 2, .).  Without ACROSS, X is
+       A itself: the one set is capped by both max_a and max_x, with the A
+       draws, and stays the same set.
+    3. Cells left without a triple (|A| < 2 without ACROSS) are dropped.
+    Caps <= 0 mean no cap."""
+    keep = [True] * len(cl)
+    if n_across > 0 and max_x_across > 0:
+        c = 0
+        while c < len(cl):
+            fam = cl[c].key[:len(cl[c].key) - n_across]
+            e = c + 1
+            while e < len(cl) and cl[e].key[:len(cl[e].key) - n_across] == fam:
+                e += 1
+            if e - c > max_x_across:
+                r = sorted((_draw(seed, c, 3, j), j) for j in range(e - c))
+                chosen = {j for _, j in r[:max_x_across]}
+                for j in range(e - c):
+                    keep[c + j] = j in chosen
+            c = e
+    out: List[Cell] = []
+    for c, cell in enumerate(cl):
+        if not keep[c]:
+            continue
+        B = _pick(cell.B, max_b, seed, c, 1)
+        if cell.exclude_self:
+            caps = [v for v in (max_a, max_x) if v > 0]
+            A = _pick(cell.A, min(caps) if caps else 0, seed, c, 0)
+            if len(A) < 2:
+                continue
+            out.append(Cell(cell.key, cell.by_key, A, B, A, True))
+        else:
+            A = _pick(cell.A, max_a, seed, c, 0)
+            X = _pick(cell.X, max_x, seed, c, 2)
+            out.append(Cell(cell.key, cell.by_key, A, B, X, False))
+    return out
