@@ -23,8 +23,13 @@
  *    is allowed (the child holds a reference).
  *  - Work runs on the context's HIP stream.  fabx_score blocks until the
  *    per-cell results are on the host.
- *  - Objects are not thread-safe: one thread per context at a time (the
- *    server object is the exception and documents its own rules).
+ *  - Threads: calls on different tasks and results may come from different
+ *    threads at once, also on one context (say one thread building the next
+ *    tasks while another launches scores and collapses results).  A task's
+ *    scores are serialised by the task itself (a new score first waits for
+ *    the one still pending), and a result completes once, whichever thread
+ *    asks first.  Destroying an object while another thread still uses it
+ *    is not allowed.  The server documents its own rules.
  */
 #ifndef FASTABX_H
 #define FASTABX_H
@@ -179,6 +184,48 @@ int fabx_task_create(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_
                      const int32_t *across, int32_t n_across, fabx_task **out);
 void fabx_task_destroy(fabx_task *task);
 
+/* The Subsampler of the Task interface (library overview, "Task" paragraph):
+ * it caps the number of a, b and x independently in each cell, and, when
+ * ACROSS attributes are given, limits the number of distinct values x takes
+ * for them (the paper writes "for the ON attribute"; x's ON value is fixed in
+ * a cell, and the Libri-Light evaluation this reproduces limits x's speaker,
+ * i.e. its ACROSS value).  A cap of 0 means no cap.
+ *
+ *  seed          key of the draws.
+ *  max_a, max_b  per cell, at most this many items of A / B.
+ *  max_x         per cell, at most this many items of X.  Without ACROSS, X is
+ *                A itself: the one set is capped by both max_a and max_x and
+ *                stays the same set.
+ *  max_x_across  ACROSS tasks: of the cells sharing (on_ax, on_b, by...,
+ *                across_ab...), which differ only in across_x, at most this
+ *                many are kept.
+ *
+ * Draws: Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as
+ * 1, 2, 3", SC'11) keyed by the seed (low word first), first output word, at
+ * counter (c, s, j, 0) where c is the cell's index in the full task (cells
+ * numbered as fabx_task_create numbers them), s = 0 / 1 / 2 for A / B / X
+ * and j the item's position in the set (items in ascending id), or s = 3 and
+ * j the cell's rank in its family for the ACROSS limit, with c the family's
+ * first cell.  A capped set keeps the items with the smallest draws (position
+ * breaking ties); the family keeps its cells with the smallest draws.  Cells
+ * left without a triple (fewer than 2 items in A without ACROSS) are dropped;
+ * the cells kept keep their order and keys. */
+typedef struct fabx_subsampler {
+    uint64_t seed;
+    int32_t max_a, max_b, max_x;
+    int32_t max_x_across;
+} fabx_subsampler;
+
+/* fabx_task_create followed by the Subsampler.  The task's cells are the
+ * kept cells with their capped sets (fabx_task_cell_sizes reports the capped
+ * |A|, |B|, |X| and |C|); a cell whose sets were reduced is scored on its own
+ * sampled items only.  fabx_result_pairs on such a task looks each item up
+ * where it first occurs.  Errors: those of fabx_task_create; EINVAL for a
+ * NULL subsampler or a negative cap. */
+int fabx_task_create_subsampled(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_by,
+                                const int32_t *across, int32_t n_across, const fabx_subsampler *sub,
+                                fabx_task **out);
+
 int64_t fabx_task_num_cells(const fabx_task *task);
 /* Number of int32 columns of a cell key: 2 + n_by + 2 * n_across. */
 int32_t fabx_task_key_width(const fabx_task *task);
@@ -199,23 +246,29 @@ typedef struct fabx_score_opts {
     int32_t dtw_norm;    /* FABX_NORM_PATH | FABX_NORM_NONE */
     double margin;       /* BF16_RECHECK: a comparison with |d(x,a) - d(x,b)| <= margin
                             is re-decided on FP64 distances; < 0 selects the default
-                            2e-2 / sqrt(dim) */
+                            2e-2 / sqrt(dim), times 2 L - 1 (L: the dataset's longest
+                            item) for the raw DTW cost (FABX_NORM_NONE), a sum of up
+                            to 2 L - 1 frame distances */
     double delta;        /* BF16_RECHECK + PATH: cumulative-cost window within which
                             alternative DTW predecessors must agree on the path length,
                             else the pair is recomputed in FP64; < 0 selects the default
                             4e-2 / sqrt(dim) */
     int32_t keep_pairs;  /* nonzero: keep the per-pair distances for fabx_result_pairs */
-    int32_t fused_cols;  /* BF16 DTW: fused kernel column block width, 128 or 256; 0 takes
-                            the context's tuning table (fabx_autotune), as does a width
-                            of 0 with a nonzero grid.  Results do not depend on it. */
-    int32_t fused_blocks_per_cu; /* its grid: 0 = one block per work unit, 1..64 = a
-                                    persistent grid of that many blocks per CU */
+    int32_t fused_cols;  /* BF16 DTW launch choice: 128 or 256 = the tile kernel with
+                            column blocks of that many frames; 512, 1024 or 2048 = the
+                            stream kernel, each wave streaming segments of about that
+                            many column frames; 0 takes the context's tuning table
+                            (fabx_autotune), as does 0 with a nonzero grid.  Results do
+                            not depend on it. */
+    int32_t fused_blocks_per_cu; /* its grid: 0 = one block per work unit (stream
+                                    kernel: a wave per segment), 1..64 = a persistent
+                                    grid of that many blocks per CU */
 } fabx_score_opts;
 
 /* Defaults: ANGULAR, DTW, BF16_RECHECK, PATH, margin/delta = -1 (library
  * defaults), keep_pairs = 0, fused_cols = fused_blocks_per_cu = 0 (tuning
- * table).  FABX_EINVAL for a width other than 0, 128, 256 or a grid outside
- * 0..64. */
+ * table).  FABX_EINVAL for a fused_cols other than 0, 128, 256, 512, 1024 or
+ * 2048, or a grid outside 0..64. */
 int fabx_score_opts_default(fabx_score_opts *opts);
 
 /* Score every cell: for each cell C and each triple (a, b, x) in it, compare

@@ -150,6 +150,17 @@ def fabx_task_create(ds, on: int, by: Sequence[int], across: Sequence[int]) -> c
     return h
 
 
+def fabx_task_create_subsampled(ds, on: int, by: Sequence[int], across: Sequence[int],
+                                sub: "Subsampler") -> ctypes.c_void_p:
+    b = np.ascontiguousarray(list(by), dtype=np.int32)
+    a = np.ascontiguousarray(list(across), dtype=np.int32)
+    s = L.fabx_subsampler(int(sub.seed), int(sub.max_a), int(sub.max_b), int(sub.max_x), int(sub.max_x_across))
+    h = ctypes.c_void_p()
+    _check(lib().fabx_task_create_subsampled(ds, int(on), _i32p(b), len(b), _i32p(a), len(a), ctypes.byref(s),
+                                             ctypes.byref(h)))
+    return h
+
+
 def fabx_task_destroy(t) -> None:
     lib().fabx_task_destroy(t)
 
@@ -427,11 +438,26 @@ class Dataset:
             self.h = None
 
 
+class Subsampler:
+    """The Subsampler of the Task interface (fabx_subsampler): per cell at most
+    max_a / max_b / max_x items of A / B / X, and with ACROSS attributes at most
+    max_x_across cells per (on_ax, on_b, by, across_ab); 0 means no cap."""
+
+    def __init__(self, seed: int = 0, max_a: int = 0, max_b: int = 0, max_x: int = 0, max_x_across: int = 0):
+        self.seed, self.max_a, self.max_b, self.max_x = int(seed), int(max_a), int(max_b), int(max_x)
+        self.max_x_across = int(max_x_across)
+
+
 class Task:
-    def __init__(self, ds: Dataset, on: int, by: Sequence[int] = (), across: Sequence[int] = ()):
+    def __init__(self, ds: Dataset, on: int, by: Sequence[int] = (), across: Sequence[int] = (),
+                 subsampler: Optional[Subsampler] = None):
         self.ds = ds
         self.on, self.by, self.across = int(on), list(by), list(across)
-        self.h = fabx_task_create(ds.h, on, by, across)
+        self.subsampler = subsampler
+        if subsampler is None:
+            self.h = fabx_task_create(ds.h, on, by, across)
+        else:
+            self.h = fabx_task_create_subsampled(ds.h, on, by, across, subsampler)
 
     def __len__(self):
         return fabx_task_num_cells(self.h)

@@ -45,6 +45,11 @@ class fabx_score_opts(ctypes.Structure):
                 ("fused_blocks_per_cu", ctypes.c_int32)]
 
 
+class fabx_subsampler(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("max_a", ctypes.c_int32), ("max_b", ctypes.c_int32),
+                ("max_x", ctypes.c_int32), ("max_x_across", ctypes.c_int32)]
+
+
 class fabx_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_cells", "n_triplets", "n_items", "n_frames", "n_pairs", "dtw_cells", "computed_dtw_cells",
@@ -104,6 +109,8 @@ SIGNATURES = {
     "fabx_slice_frames": (ctypes.c_int, [_P(ctypes.c_double), _P(ctypes.c_double), _i64, ctypes.c_double,
                                          ctypes.c_int, _P(_i64), _P(_i64)]),
     "fabx_task_create": (ctypes.c_int, [_vp, _i32, _P(_i32), _i32, _P(_i32), _i32, _P(_vp)]),
+    "fabx_task_create_subsampled": (ctypes.c_int, [_vp, _i32, _P(_i32), _i32, _P(_i32), _i32,
+                                                   _P(fabx_subsampler), _P(_vp)]),
     "fabx_task_destroy": (None, [_vp]),
     "fabx_task_num_cells": (_i64, [_vp]),
     "fabx_task_key_width": (_i32, [_vp]),

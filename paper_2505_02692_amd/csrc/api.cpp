@@ -373,6 +373,22 @@ int fabx_task_create(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_
     });
 }
 
+int fabx_task_create_subsampled(fabx_dataset *ds, int32_t on, const int32_t *by, int32_t n_by,
+                                const int32_t *across, int32_t n_across, const fabx_subsampler *sub,
+                                fabx_task **out) {
+    return guarded([&] {
+        if (!ds || !out || !sub) fail(FABX_EINVAL, "null argument");
+        *out = nullptr;
+        if (sub->max_a < 0 || sub->max_b < 0 || sub->max_x < 0 || sub->max_x_across < 0)
+            fail(FABX_EINVAL, "subsampler caps must be >= 0 (0: no cap)");
+        auto full = build_task(ds->p, on, by, n_by, across, n_across);
+        auto t = subsample_task(*full, *sub);
+        full.reset();
+        prepack_tables(*t);
+        *out = new fabx_task{t};
+    });
+}
+
 void fabx_task_destroy(fabx_task *t) { delete t; }
 
 int64_t fabx_task_num_cells(const fabx_task *t) { return t ? int64_t(t->p->cells.size()) : -1; }

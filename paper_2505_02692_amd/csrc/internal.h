@@ -100,6 +100,14 @@ struct PinnedPool {
     ~PinnedPool();
 };
 
+// BF16 DTW kernels: frames per row block (one DTW lane per frame row), and the
+// column widths of the launch choices.  Items are never split across row
+// blocks, so items are <= 64 frames.
+constexpr int kFusedRowFrames = 64;
+constexpr int kSortedMaxB = 4096;      // largest |B| counted from sorted rows (sorted in LDS)
+constexpr int kFusedColFrames = 128;  // default: tile kernel, 128-frame column blocks (the other is 256)
+constexpr int kStreamMinCols = 512;   // cols at or above this select the stream kernel
+
 // Launch choices of the fused kernel: column block width (128 or 256 frames)
 // and grid (blocks_per_cu > 0: a persistent grid of that many blocks per CU;
 // 0: one block per work unit).  Results do not depend on them.
@@ -127,7 +135,7 @@ public:
     void load(const std::string &path);
     FusedConfig lookup(const TuneKey &k);
     void record(const TuneKey &k, const FusedConfig &c);
-    static FusedConfig default_config() { return FusedConfig{128, 0}; }
+    static FusedConfig default_config() { return FusedConfig{kFusedColFrames, 0}; }
 
 private:
     std::mutex mu_;
@@ -178,12 +186,6 @@ struct DatasetImpl {
     std::vector<int32_t> item_len;    // [n_items]: its frames (>= 1); items may overlap
     std::vector<int32_t> attrs;       // [n_items * n_attr]
 };
-
-// Fused BF16 kernel tiling: frames per row block (one DTW lane per frame row)
-// and per column block.  Items are never split, so items are <= 64 frames.
-constexpr int kFusedRowFrames = 64;
-constexpr int kSortedMaxB = 4096;      // largest |B| counted from sorted rows (sorted in LDS)
-constexpr int kFusedColFrames = 128;  // default column block width (the other is 256)
 
 // One BY group that holds at least one cell.  Items of a group are
 // contiguous in task order, and so are their packed frames.
@@ -236,6 +238,7 @@ struct Workspace {
     DevBuf flags;       // uint8 [n_pair_slots]: bit0 non-robust, bit1 marked for FP64
     DevBuf p64;         // F64 [n_pair_slots]
     DevBuf half_units;  // uint64 [n_cells], then the score's 64 counter bytes
+    DevBuf finfo;       // uint32 [n_frames]: frame info of the stream kernel
     DevBuf recheck_list, recount_list;
     size_t total() const;
     void release();
@@ -243,9 +246,14 @@ struct Workspace {
 
 struct ResultImpl;
 
-// Column blocks of the fused kernel for one column block width: whole items
-// packed into <= cols frames per group, and the work units (row block x
-// column block) they make with the task's row blocks.
+// Work plan of the BF16 DTW kernel for one launch choice `cols`.
+//  cols 128 / 256 (tile kernel): column blocks of whole items packed into
+//    <= cols frames per group, and the work units (row block x column block)
+//    they make with the task's row blocks (below).
+//  cols 512 / 1024 / 2048 (stream kernel): each row block's column stream
+//    (the group's frames from the row block's first frame on) cut into
+//    segments of about `cols` frames; only rb_unit_prefix (segments per row
+//    block) and cells are used.
 struct ColPlan {
     int cols = 0;
     hvec<int32_t> cb;                    // [n_cb][4] = group, first item (task), n items, n frames
@@ -258,7 +266,8 @@ struct ColPlan {
     // group) and the prefix of kept units over all row blocks.
     hvec<int32_t> rb_cstart;             // [n_rb]
     hvec<int64_t> rb_unit_prefix;        // [n_rb + 1]
-    int64_t cells = 0;                   // frame pairs the kept units cover
+    int64_t cells = 0;                   // frame pairs the kept units cover (stream kernel: lanes x
+                                         // stream columns, 64 per column)
     DevBuf dev;                          // device copy of the above, made on first use
     const int32_t *d_cb = nullptr, *d_g_cb0 = nullptr, *d_rb_cstart = nullptr;
     const int64_t *d_rb_unit_prefix = nullptr;
@@ -307,6 +316,7 @@ struct TaskImpl {
     int64_t dtw_cells_sym = 0;      // the same over unordered pairs {x, y} needed in either order
     int64_t total_triplets = 0;
     int max_len = 0;
+    bool subsampled = false;        // made by the Subsampler: items may repeat across groups
 
     TaskDevice dev;
     // device tables packed in pinned memory when the task is made (tables up
@@ -351,6 +361,11 @@ void prepack_tables(TaskImpl &t);
 std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,
                                      const int32_t *by, int32_t n_by, const int32_t *across,
                                      int32_t n_across);
+// Row blocks of the DTW kernels and the default work plan, from the task's
+// groups and items (the last step of a task build).
+void plan_blocks(TaskImpl &t);
+// subsample.cpp: the task the Subsampler makes from a full task `t`.
+std::shared_ptr<TaskImpl> subsample_task(const TaskImpl &t, const fabx_subsampler &sub);
 
 // score.cpp
 struct ScoreParams {

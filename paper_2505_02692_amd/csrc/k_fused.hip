@@ -45,6 +45,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kRows = 64;             // row block frames = DTW lanes
+// Near-parallel (or antiparallel) frames: acos is ill-conditioned at
+// |cos| = 1, where the BF16 cosine's rounding (about 1e-7) moves the angle by
+// up to about 1e-4.  |cos| above kNearCos (an angle under about 3e-3 rad from
+// 0 or pi, a distance within kNearD of 0 or 1) sends the pair to the FP64
+// recheck.
+constexpr float kNearCos = 1.0f - 4.7e-6f;
+constexpr float kNearD = 9.8e-4f;
 constexpr int kKc = 64;               // K chunk (bf16 elements) staged in LDS
 constexpr int kLdsRow = kKc + 8;      // padded LDS row of a K chunk (bf16)
 
@@ -226,6 +233,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kSmemBytes];
     __shared__ uint16_t colflag[4][kFlagLen];
     __shared__ __attribute__((aligned(16))) float norm_s[kRows + kC];  // row then column inverse norms
+    __shared__ int near_s;  // the unit holds a near-parallel frame pair
     // XCD-aware order: the 8 XCDs take blocks round-robin, so XCD x works
     // through the contiguous unit range [x * grid_q, (x+1) * grid_q) (units of
     // one group share its frames in that XCD's L2).  gridDim.x is a multiple
@@ -260,6 +268,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const int c_item0 = cb[4 * cbi + 1], c_nitems = cb[4 * cbi + 2], c_frames = cb[4 * cbi + 3];
     const int64_t r_frame0 = item_dst[r_item0], c_frame0 = item_dst[c_item0];
 
+    if (threadIdx.x == 0) near_s = 0;  // read after the barriers of the Gram tile and the epilogue
     // 1. Gram tile
     NormStage<kC> ns;
     ns.load(rinv, r_frame0, r_frames, c_frame0, c_frames);
@@ -276,7 +285,10 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     // 2. epilogue -> LDS distance tile (the staging buffers are dead now).  Only
     // the rows and column waves that hold frames are written; the DTW reads the
     // others only in lanes and steps whose results are discarded.
+    // Rows and columns past the block's frames have zero inverse norms, so their
+    // cosines are 0 and never count as near-parallel.
     float *dt = reinterpret_cast<float *>(smem_raw);
+    float cmax = 0.0f;  // largest |cos| this lane wrote
 #pragma unroll
     for (int ct = 0; ct < T::kCT; ++ct) {
         const int col0 = T::kWaveCols * w + 32 * ct;
@@ -286,17 +298,43 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r0 = acc_row(i, lane);
-            dt[r0 * kDStride + col] =
-                dev::acos_over_pi(fminf(fmaxf(acc[0][ct][i] * norm_s[r0] * rc, -1.0f), 1.0f));
+            const float cs = fminf(fmaxf(acc[0][ct][i] * norm_s[r0] * rc, -1.0f), 1.0f);
+            cmax = fmaxf(cmax, fabsf(cs));
+            dt[r0 * kDStride + col] = dev::acos_over_pi(cs);
         }
         if (r_frames > 32) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r1 = 32 + acc_row(i, lane);
-                dt[r1 * kDStride + col] =
-                    dev::acos_over_pi(fminf(fmaxf(acc[1][ct][i] * norm_s[r1] * rc, -1.0f), 1.0f));
+                const float cs = fminf(fmaxf(acc[1][ct][i] * norm_s[r1] * rc, -1.0f), 1.0f);
+                cmax = fmaxf(cmax, fabsf(cs));
+                dt[r1 * kDStride + col] = dev::acos_over_pi(cs);
             }
         }
+    }
+    // A frame against itself (units on the diagonal of the group's pair
+    // matrix: the pair (x, x), never compared) is parallel by construction:
+    // when some |cos| is that high, look again without those elements.
+    if (__ballot(cmax > kNearCos) != 0) {
+        const int64_t diag = r_frame0 - c_frame0;  // column col is row col - diag's frame
+        bool near = false;
+#pragma unroll
+        for (int ct = 0; ct < T::kCT; ++ct) {
+            const int col0 = T::kWaveCols * w + 32 * ct;
+            if (col0 >= c_frames || col0 + 32 <= c_skip) continue;
+            const int col = col0 + lane % 32;
+            const float rc = norm_s[kRows + col];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int r = 32 * h + acc_row(i, lane);
+                    const float cs = fminf(fmaxf(acc[h][ct][i] * norm_s[r] * rc, -1.0f), 1.0f);
+                    near |= fabsf(cs) > kNearCos && int64_t(r) + diag != int64_t(col);
+                }
+            }
+        }
+        if (__ballot(near) != 0 && lane == 0) atomicOr(&near_s, 1);
     }
 
     // 3. DTW.  Column items of this block split over the 4 waves by start frame.
@@ -384,6 +422,12 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     float c = kInf, up = kInf, up_prev = kInf;
     uint32_t P = 0, Pup = 0, Pup_prev = 0;
     const int steps = S + max_n - 1;
+    // A unit with a near-parallel frame pair ORs a "near" bit over each pair's
+    // cells (the wavefront's left and up neighbours), and a pair with a near
+    // cell goes to the FP64 recheck.
+    uint32_t nz = 0;
+    auto run = [&](auto careful_tag) {
+    constexpr bool careful = decltype(careful_tag)::value;
     auto step = [&](const uint32_t cf, const float dv) {
         const bool first = cf & 1;
         up = shr1z(send_inf ? kInf : c) + lane0_pen;
@@ -398,6 +442,11 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             const uint32_t sl = left <= thr ? P : 0u;
             const uint32_t su = up <= thr ? Pup : 0u;
             P = pk_step(pk_max(pk_max(sd, sl), su));
+        }
+        if constexpr (careful) {
+            const uint32_t nup = top ? 0u : shr1u(0u, nz);
+            const uint32_t nq = (dv < kNearD || dv > 1.0f - kNearD) ? 1u : 0u;
+            nz = nq | nup | (first ? 0u : nz);
         }
         c = dv + m;
         up_prev = up;
@@ -418,10 +467,11 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                     const uint32_t lmax = P >> 16, lmin = 0xFFFFu - (P & 0xFFFFu);
                     v = c * __builtin_amdgcn_rcpf(float(lmin));
                     fl = lmin == lmax ? 0 : 1;
-                    if (fl) atomicAdd(nonrobust_n, px < py ? 2u : 1u);
                 } else {
                     v = c;
                 }
+                if (careful && nz && px != py) fl = 1;  // (x, x) is never compared
+                if (fl) atomicAdd(nonrobust_n, px < py ? 2u : 1u);
                 p32[slot] = v;
                 flags[slot] = fl;
                 if (px < py) {
@@ -445,13 +495,19 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
         step(cb2, db);
     }
     if (t < steps) step(cf0, dv0);
+    };
+    if (near_s != 0)  // uniform: written before the barrier above
+        run(std::true_type{});
+    else
+        run(std::false_type{});
     }  // S > 0
     __syncthreads();  // the next unit overwrites the LDS tile and column flags
     }
 }
 
 // Pooled mode: MFMA Gram tile of pooled unit vectors, angular distance straight
-// into the pair matrix (64 x 128 item tile per block).
+// into the pair matrix (64 x 128 item tile per block).  |cos| above kNearCos
+// flags the pair non-robust, for the FP64 recheck.
 __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__restrict__ xn,
                                                               const float *__restrict__ rinv,
                                                               int dim_pad,
@@ -460,7 +516,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
                                                               const int64_t *__restrict__ base,
                                                               const int64_t *__restrict__ tile_prefix,
                                                               int64_t n_groups, int64_t n_tiles,
-                                                              float *__restrict__ out) {
+                                                              float *__restrict__ out,
+                                                              uint8_t *__restrict__ flags) {
     using T = Tile<128>;
     constexpr int kCols = T::kCols;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kStageBytes];
@@ -483,15 +540,20 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     if (col < nc) {
         const float rc = norm_s[kRows + col];
         float *o = out + base[g];
+        uint8_t *fo = flags + base[g];
+        // near-parallel (or antiparallel) means: acos is ill-conditioned at
+        // |cos| = 1, so such a pair is flagged non-robust and recomputed in FP64
+        auto put = [&](int r, float a) {
+            const float cs = fminf(fmaxf(a * norm_s[r] * rc, -1.0f), 1.0f);
+            const int64_t at = (r0 + r) * n + c0 + col;
+            o[at] = dev::acos_over_pi(cs);
+            if (fabsf(cs) > kNearCos) fo[at] = 1;
+        };
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int ra = acc_row(i, lane), rb2 = 32 + ra;
-            if (ra < nr)
-                o[(r0 + ra) * n + c0 + col] =
-                    dev::acos_over_pi(fminf(fmaxf(acc0[i] * norm_s[ra] * rc, -1.0f), 1.0f));
-            if (rb2 < nr)
-                o[(r0 + rb2) * n + c0 + col] =
-                    dev::acos_over_pi(fminf(fmaxf(acc1[i] * norm_s[rb2] * rc, -1.0f), 1.0f));
+            if (ra < nr) put(ra, acc0[i]);
+            if (rb2 < nr) put(rb2, acc1[i]);
         }
     }
     __syncthreads();  // the next tile overwrites the inverse norms
@@ -540,11 +602,12 @@ void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pa
 
 void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                        const int64_t *row0, const int64_t *nrows, const int64_t *base,
-                       const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out) {
+                       const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out,
+                       uint8_t *flags) {
     if (n_tiles <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
     hipLaunchKernelGGL(k_gram_angular_bf16, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn, rinv,
-                       dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out);
+                       dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out, flags);
     FABX_HIP(hipGetLastError());
 }
 

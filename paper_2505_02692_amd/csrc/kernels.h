@@ -105,10 +105,34 @@ void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pa
                 float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n,
                 unsigned int *unit_ctr);
 
-// Pooled mode, BF16 MFMA: theta/pi between pooled item vectors of each group.
+// --- k_stream.hip (BF16 form, DTW mode: the column-stream kernel)
+// Per task frame: bit 31 first frame of its item, bit 30 last frame, bits
+// 6..29 the item's place in its BY group, bits 0..5 the frame's index in
+// its item.
+void frame_info(hipStream_t s, const ItemTables &it, const int32_t *item_group, const int64_t *g_item0,
+                uint32_t *finfo);
+struct StreamPlan {
+    const int32_t *rb;              // row blocks: [n_rb][4] = group, first item (task), n items, n frames
+    const int64_t *rb_unit_prefix;  // per row block: prefix of its stream segments, n_rb + 1
+    int64_t n_rb;
+    int64_t n_units;
+    int seg_len;         // nominal segment length (frames)
+    int blocks_per_cu;   // persistent grid of blocks_per_cu * n_cu blocks (4 waves each); 0: a wave per unit
+    int n_cu;
+};
+// unit_ctr: 8 counters, zero at launch.  delta_q: the path-length window in
+// units of 1 / 65535.
+void stream_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad, const uint32_t *finfo,
+                 const GroupTables &g, const ItemTables &it, const StreamPlan &plan, int norm, uint32_t delta_q,
+                 float *p32, uint8_t *flags, unsigned int *nonrobust_n, unsigned int *unit_ctr);
+
+// Pooled mode, BF16 MFMA: theta/pi between pooled item vectors of each group;
+// flags[slot] = 1 (non-robust) for a nearly parallel or antiparallel pair
+// (flags zeroed before).
 void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                        const int64_t *row0, const int64_t *nrows, const int64_t *base,
-                       const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out);
+                       const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out,
+                       uint8_t *flags);
 
 // --- k_triplets.hip
 // One wave per unit [cell, x_begin, x_end): W[cell] += sum over the unit's rows of

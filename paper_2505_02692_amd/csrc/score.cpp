@@ -273,11 +273,17 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     p.precision = o.precision;
     p.dtw_norm = o.dtw_norm;
     p.distance = o.distance;
-    p.margin = o.margin < 0 ? kMarginK / std::sqrt(double(ds.dim)) : o.margin;
+    // the raw DTW cost (FABX_NORM_NONE) sums up to 2 L - 1 frame distances
+    // (L: the longest item), each with its own error: its default margin is
+    // that many times the per-distance one
+    const double path_cells = p.mode == FABX_MODE_DTW && p.dtw_norm == FABX_NORM_NONE
+                                  ? double(2 * std::max(ds.max_len, 1) - 1) : 1.0;
+    p.margin = o.margin < 0 ? kMarginK / std::sqrt(double(ds.dim)) * path_cells : o.margin;
     p.delta = o.delta < 0 ? kDeltaK / std::sqrt(double(ds.dim)) : o.delta;
     p.keep_pairs = o.keep_pairs != 0;
-    if (o.fused_cols != 0 && o.fused_cols != 128 && o.fused_cols != 256)
-        fail(FABX_EINVAL, "fused_cols must be 0, 128 or 256");
+    if (o.fused_cols != 0 && o.fused_cols != 128 && o.fused_cols != 256 && o.fused_cols != 512 &&
+        o.fused_cols != 1024 && o.fused_cols != 2048)
+        fail(FABX_EINVAL, "fused_cols must be 0, 128, 256, 512, 1024 or 2048");
     if (o.fused_blocks_per_cu < 0 || o.fused_blocks_per_cu > 64)
         fail(FABX_EINVAL, "fused_blocks_per_cu must be in 0..64");
     p.fused = FusedConfig{o.fused_cols, o.fused_blocks_per_cu};  // cols 0: the tuning table
@@ -302,7 +308,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
 
 size_t Workspace::total() const {
     const DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units,
-                           &recheck_list, &recount_list};
+                           &recheck_list, &recount_list, &finfo};
     size_t s = 0;
     for (auto *b : all) s += b->bytes;
     return s;
@@ -310,7 +316,7 @@ size_t Workspace::total() const {
 
 void Workspace::release() {
     DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units,
-                     &recheck_list, &recount_list};
+                     &recheck_list, &recount_list, &finfo};
     for (auto *b : all) b->release();
 }
 
@@ -375,7 +381,7 @@ struct DevPtrs {
     kern::ItemTables it{};
     kern::GroupTables gt{};
     const CellDev *cells = nullptr;
-    const int32_t *units = nullptr, *rb = nullptr;
+    const int32_t *units = nullptr, *rb = nullptr, *item_group = nullptr;
     const int32_t *cb = nullptr, *g_cb0 = nullptr, *rb_cstart = nullptr;
     const int64_t *rb_unit_prefix = nullptr;
     const int64_t *tiles = nullptr;             // pooled: Gram tile prefix per group
@@ -387,6 +393,7 @@ struct DevPtrs {
     int64_t *recheck_list = nullptr;
     int32_t *recount_list = nullptr;
     unsigned long long *half_units = nullptr;   // [n_cells], then the score's 64 counter bytes
+    uint32_t *finfo = nullptr;                  // stream kernel: frame info [n_frames]
 };
 
 // Byte offsets of the pooled tile prefix or of the plain form's strip columns.
@@ -420,16 +427,16 @@ void set_plan(DevPtrs &d, const char *base, const PlanLayout &L) {
 // Workspace bytes of one score (0 for buffers the form does not use).
 struct WorkspaceSizes {
     size_t xn = 0, rinv = 0, dmat = 0, p32 = 0, flags = 0, p64 = 0, recheck_list = 0, recount_list = 0,
-           half_units = 0;
+           half_units = 0, finfo = 0;
     size_t total_aligned() const {
         size_t s = 0;
-        for (size_t b : {xn, rinv, dmat, p32, flags, p64, recheck_list, recount_list, half_units})
+        for (size_t b : {xn, rinv, dmat, p32, flags, p64, recheck_list, recount_list, half_units, finfo})
             s += (b + 255) & ~size_t(255);
         return s;
     }
 };
 
-WorkspaceSizes workspace_sizes(const TaskImpl &t, const ScoreParams &p, const PlainPlan &strips) {
+WorkspaceSizes workspace_sizes(const TaskImpl &t, const ScoreParams &p, const PlainPlan &strips, bool stream) {
     const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
     const bool dtw = p.mode == FABX_MODE_DTW;
     const int64_t dim_pad = round_up(t.ds->dim, 64);
@@ -447,6 +454,7 @@ WorkspaceSizes workspace_sizes(const TaskImpl &t, const ScoreParams &p, const Pl
     }
     // per-cell counts, then 64 counter bytes: both come back with one copy
     w.half_units = t.cells.size() * 8 + 64;
+    if (stream) w.finfo = size_t(t.n_frames) * 4;
     return w;
 }
 
@@ -504,6 +512,14 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
             kern::dtw_plain(stream, d.dmat, ps, gt, it, p.dtw_norm, d.p32);
         }
         st.computed_dtw_cells = t.n_dmat;
+    } else if (dtw && fcfg.cols >= kStreamMinCols) {
+        kern::frame_info(stream, it, d.item_group, gt.item0, d.finfo);
+        const kern::StreamPlan sp{d.rb, d.rb_unit_prefix, int64_t(t.rb.size() / 4), cplan->rb_unit_prefix.back(),
+                                  fcfg.cols, fcfg.blocks_per_cu, ds.ctx->n_cu};
+        const uint32_t delta_q = uint32_t(std::ceil(p.delta * 65535.0));
+        kern::stream_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, d.finfo, gt, it, sp,
+                          p.dtw_norm, delta_q, d.p32, d.flags, nonrobust_n, unit_ctr);
+        st.computed_dtw_cells = cplan->cells;
     } else if (dtw) {
         kern::FusedPlan fp{d.rb, d.cb, d.rb_unit_prefix, d.g_cb0, d.rb_cstart, int64_t(t.rb.size() / 4),
                            cplan->rb_unit_prefix.back(), fcfg.cols, fcfg.blocks_per_cu, ds.ctx->n_cu};
@@ -516,7 +532,7 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
         kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.p32, euclid ? 1 : 0);
     } else {
         kern::gram_angular_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt.item0,
-                                gt.n_items, gt.pair_base, d.tiles, G, tiles.back(), d.p32);
+                                gt.n_items, gt.pair_base, d.tiles, G, tiles.back(), d.p32, d.flags);
     }
     mark();  // 3
     uint8_t *flags = bf16 ? d.flags : nullptr;
@@ -622,7 +638,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     Pool *pool = &ds.ctx->pool;
     if (!dv.blob.ptr) dv.blob.pool = pool;
     for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
-                      &t.ws.half_units, &t.ws.recheck_list, &t.ws.recount_list})
+                      &t.ws.half_units, &t.ws.recheck_list, &t.ws.recount_list, &t.ws.finfo})
         if (!b->ptr) b->pool = pool;
     // fused kernel: tile width and grid from the tuning table (or the caller),
     // and the task's column blocks for that width (uploaded on first use)
@@ -677,14 +693,14 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
 
     // ---- workspace
     Workspace &ws = t.ws;
-    const WorkspaceSizes wz = workspace_sizes(t, p, strips);
+    const WorkspaceSizes wz = workspace_sizes(t, p, strips, cplan && fcfg.cols >= kStreamMinCols);
     // buffers the form does not use keep what an earlier score left (or nothing)
     for (auto bs : {std::make_pair(&ws.xn, wz.xn), std::make_pair(&ws.rinv, wz.rinv),
                     std::make_pair(&ws.dmat, wz.dmat), std::make_pair(&ws.p32, wz.p32),
                     std::make_pair(&ws.flags, wz.flags), std::make_pair(&ws.p64, wz.p64),
                     std::make_pair(&ws.recheck_list, wz.recheck_list),
                     std::make_pair(&ws.recount_list, wz.recount_list),
-                    std::make_pair(&ws.half_units, wz.half_units)})
+                    std::make_pair(&ws.half_units, wz.half_units), std::make_pair(&ws.finfo, wz.finfo)})
         if (bs.second) bs.first->ensure(bs.second);
     st.workspace_bytes = int64_t(ws.total());
     pend->host_bytes = size_t(n_cells) * 8 + 64;
@@ -695,6 +711,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     d.cells = dv.cells;
     d.units = dv.units;
     d.rb = dv.rb;
+    d.item_group = dv.item_group;
     if (cplan) {
         d.cb = cplan->d_cb;
         d.g_cb0 = cplan->d_g_cb0;
@@ -710,6 +727,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     d.recheck_list = ws.recheck_list.as<int64_t>();
     d.recount_list = ws.recount_list.as<int32_t>();
     d.half_units = ws.half_units.as<unsigned long long>();
+    d.finfo = ws.finfo.as<uint32_t>();
 
     pend->tm = std::make_unique<Timer>(stream, ds.ctx->events);
     tr.mark("workspace");

@@ -536,11 +536,47 @@ void plan_units(const TaskImpl &t, ColPlan &cp) {
     for (int64_t v : part_cells) cp.cells += v;
 }
 
+// Stream kernel: segments of about `cols` frames of each row block's column
+// stream (the group's frames from the row block's first frame on).
+void plan_stream(const TaskImpl &t, ColPlan &cp) {
+    const int64_t G = int64_t(t.groups.size());
+    for (const Group &g : t.groups)
+        if (g.n_items > 0xFFFFFF) fail(FABX_EINVAL, "a BY group holds more than 2^24 - 1 items");
+    const size_t n_rb = t.rb.size() / 4;
+    cp.rb_unit_prefix.resize(n_rb + 1);
+    cp.rb_unit_prefix[0] = 0;
+    const int64_t kGroups = group_chunk(G);
+    const int n_gc = int((G + kGroups - 1) / kGroups);
+    std::vector<int64_t> part_cells(static_cast<size_t>(std::max(n_gc, 1)), 0);
+    parallel_for(n_gc, [&](int c) {
+        int64_t cells = 0;
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
+            const Group &g = t.groups[size_t(gi)];
+            const size_t r0 = size_t(t.g_rb0[size_t(gi)]);
+            for (int32_t r = 0; r < t.g_nrb[size_t(gi)]; ++r) {
+                const int32_t *rbe = t.rb.data() + 4 * (r0 + size_t(r));
+                const int64_t S = g.frame0 + g.n_frames - t.item_dst[size_t(rbe[1])];
+                cp.rb_unit_prefix[r0 + size_t(r) + 1] = (S + cp.cols - 1) / cp.cols;
+                cells += int64_t(kFusedRowFrames) * S;
+            }
+        }
+        part_cells[size_t(c)] = cells;
+    });
+    for (size_t i = 0; i < n_rb; ++i) cp.rb_unit_prefix[i + 1] += cp.rb_unit_prefix[i];
+    cp.cells = 0;
+    for (int64_t v : part_cells) cp.cells += v;
+}
+
 ColPlan &col_plan(TaskImpl &t, int cols) {
     for (auto &p : t.col_plans)
         if (p->cols == cols) return *p;
     auto cp = std::make_unique<ColPlan>();
     cp->cols = cols;
+    if (cols >= kStreamMinCols) {
+        plan_stream(t, *cp);
+        t.col_plans.push_back(std::move(cp));
+        return *t.col_plans.back();
+    }
     const int64_t G = int64_t(t.groups.size());
     cp->g_cb0.assign(size_t(G), 0);
     cp->g_ncb.assign(size_t(G), 0);
@@ -563,6 +599,33 @@ ColPlan &col_plan(TaskImpl &t, int cols) {
     plan_units(t, *cp);
     t.col_plans.push_back(std::move(cp));
     return *t.col_plans.back();
+}
+
+void plan_blocks(TaskImpl &t) {
+    const int64_t G = int64_t(t.groups.size());
+    // DTW row blocks (whole items packed into <= 64 frames per group), counted
+    // in one parallel pass and written in another; then the default work plan
+    // (other launch choices are planned by col_plan on demand)
+    std::vector<int32_t> nrb(static_cast<size_t>(G));
+    const int64_t kGroups = group_chunk(G);
+    const int n_gc = int((G + kGroups - 1) / kGroups);
+    parallel_for(n_gc, [&](int c) {
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+            nrb[size_t(gi)] = pack_blocks(t, gi, kFusedRowFrames, nullptr);
+    });
+    t.g_rb0.assign(size_t(G), 0);
+    t.g_nrb.assign(nrb.begin(), nrb.end());
+    int32_t rb_total = 0;
+    for (int64_t gi = 0; gi < G; ++gi) {
+        t.g_rb0[size_t(gi)] = rb_total;
+        rb_total += nrb[size_t(gi)];
+    }
+    t.rb.resize(4 * size_t(rb_total));
+    parallel_for(n_gc, [&](int c) {
+        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi)
+            pack_blocks(t, gi, kFusedRowFrames, t.rb.data() + 4 * size_t(t.g_rb0[size_t(gi)]));
+    });
+    t.fused_cells = col_plan(t, Tuner::default_config().cols).cells;
 }
 
 std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,
@@ -929,46 +992,9 @@ std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int
     const int64_t frame = frame_total;
     tr.mark("items");
 
-    // fused-kernel row blocks (whole items packed into <= 64 frames per group)
-    // and the default column plan, counted in one parallel pass and written in
-    // another (other column widths are made by col_plan on demand)
-    auto cp = std::make_unique<ColPlan>();
-    cp->cols = kFusedColFrames;
-    std::vector<int32_t> nrb(static_cast<size_t>(G));
-    cp->g_ncb.assign(size_t(G), 0);
-    cp->g_cb0.assign(size_t(G), 0);
-    const int64_t kGroups = group_chunk(G);
-    const int n_gc = int((G + kGroups - 1) / kGroups);
-    parallel_for(n_gc, [&](int c) {
-        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
-            nrb[size_t(gi)] = pack_blocks(*t, gi, kFusedRowFrames, nullptr);
-            cp->g_ncb[size_t(gi)] = pack_blocks(*t, gi, kFusedColFrames, nullptr);
-        }
-    });
-    tr.mark("blocks.count");
-    t->g_rb0.assign(size_t(G), 0);
-    t->g_nrb.assign(nrb.begin(), nrb.end());
-    int32_t rb_total = 0, cb_total = 0;
-    for (int64_t gi = 0; gi < G; ++gi) {
-        t->g_rb0[size_t(gi)] = rb_total;
-        cp->g_cb0[size_t(gi)] = cb_total;
-        rb_total += nrb[size_t(gi)];
-        cb_total += cp->g_ncb[size_t(gi)];
-    }
-    tr.mark("blocks.prefix");
-    t->rb.resize(4 * size_t(rb_total));
-    cp->cb.resize(4 * size_t(cb_total));
-    parallel_for(n_gc, [&](int c) {
-        for (int64_t gi = c * kGroups; gi < std::min<int64_t>(G, (c + 1) * kGroups); ++gi) {
-            pack_blocks(*t, gi, kFusedRowFrames, t->rb.data() + 4 * size_t(t->g_rb0[size_t(gi)]));
-            pack_blocks(*t, gi, kFusedColFrames, cp->cb.data() + 4 * size_t(cp->g_cb0[size_t(gi)]));
-        }
-    });
-    plan_units(*t, *cp);
-    t->fused_cells = cp->cells;
-    t->col_plans.push_back(std::move(cp));
     t->n_frames = frame;
-    tr.mark("blocks.write");
+    plan_blocks(*t);
+    tr.mark("blocks");
     return t;
 }
 

@@ -97,6 +97,8 @@ extern "C" int fabx_autotune(fabx_task *task, const fabx_score_opts *opts, fabx_
             set_last_error("");
             return FABX_OK;  // only the fused kernel has choices
         }
+        // the default first; the stream kernel (cols >= 512) is selectable through
+        // the score options but not a candidate: it was slower on every workload
         const FusedConfig cands[] = {{128, 0}, {128, 4}, {256, 0}, {256, 2}};
         constexpr int kCands = int(sizeof(cands) / sizeof(cands[0]));
         constexpr int kRounds = 3;

@@ -231,3 +231,44 @@ def test_thread_serial_switch():
             keys, sizes = f.result()
             assert np.array_equal(keys, ref_keys) and np.array_equal(sizes, ref_sizes)
     assert fx.fabx_set_thread_serial(False) is False  # this thread's setting is its own
+
+
+# ------------------------------------------------------------- subsampler --
+
+@pytest.mark.parametrize("seed", range(12))
+def test_subsampled_task_cells_match_oracle(seed):
+    """The library's Subsampler (host task build) gives the oracle's subsampled
+    cells: same kept cells in the same order, same capped |A|, |B|, |X| and
+    |C| (the sets themselves are compared through the GPU scores)."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(40, 400))
+    card = rng.integers(2, 7, size=4)
+    attrs = np.stack([rng.integers(0, k, size=n) for k in card], axis=1).astype(np.int32)
+    specs = [(0, [1], []), (0, [1], [2]), (0, [], [1, 2]), (0, [1, 2], []), (3, [0], [1])]
+    on, by, across = specs[seed % len(specs)]
+    caps = [dict(max_a=2, max_b=3, max_x=2), dict(max_a=3), dict(max_b=1, max_x_across=2),
+            dict(max_a=4, max_b=4, max_x=1, max_x_across=1), dict(max_x=3), dict()][seed % 6]
+    sub = dict(seed=seed * 7919 + 1, **caps)
+    ctx = fx.Context(-1)
+    lengths = np.ones(n, np.int64)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(lengths)
+    ds = fx.Dataset(ctx, None, off, attrs)
+    t = fx.Task(ds, on, by, across, subsampler=fx.Subsampler(**sub))
+    want = oracle.subsample(oracle.cells(attrs, on, by, across), len(across), **sub)
+    assert len(t) == len(want)
+    keys = t.keys
+    nt, abx = t.sizes
+    for k, c in enumerate(want):
+        assert tuple(keys[k]) == tuple(int(v) for v in c.key)
+        assert nt[k] == c.n_triplets
+        assert tuple(abx[k]) == (len(c.A), len(c.B), len(c.X))
+
+
+def test_subsampler_rejects_negative_caps():
+    ctx = fx.Context(-1)
+    attrs = np.array([[0, 0], [0, 0], [1, 0]], np.int32)
+    ds = fx.Dataset(ctx, None, np.arange(4, dtype=np.int64), attrs)
+    with pytest.raises(fx.FabxError) as e:
+        fx.Task(ds, 0, [1], [], subsampler=fx.Subsampler(max_a=-1))
+    assert e.value.code == -1

@@ -61,9 +61,9 @@ def all_oracle_pairs(orc):
     return np.concatenate(xs), np.concatenate(ys), np.concatenate(vs)
 
 
-def check(w, mode="dtw", precision="bf16", norm="path", exact=None, pair_tol=None, levels=True):
-    _say(f"{w.name} n_items={w.n_items} dim={w.dim} mode={mode} precision={precision} norm={norm}")
-    t, res = gpu_score(w, mode=mode, precision=precision, norm=norm, keep_pairs=True)
+def check(w, mode="dtw", precision="bf16", norm="path", exact=None, pair_tol=None, levels=True, **kw):
+    _say(f"{w.name} n_items={w.n_items} dim={w.dim} mode={mode} precision={precision} norm={norm} {kw}")
+    t, res = gpu_score(w, mode=mode, precision=precision, norm=norm, keep_pairs=True, **kw)
     orc = oracle_score(w, mode, norm)
     assert np.array_equal(t.keys, orc.keys.astype(np.int32))
     nt, _ = t.sizes
@@ -573,16 +573,18 @@ def test_needed_pair_counts_match_oracle(make):
 
 
 def test_forced_fused_configs_equal_default():
-    """Every column width and grid forced through the score options (including
-    persistent grids whose blocks take units from the per-XCD counters, down to
-    one block per CU) gives the per-cell counts of the default, which is exact."""
+    """Every launch choice forced through the score options (the tile kernel's
+    column widths and grids, including persistent grids whose blocks take
+    units from the per-XCD counters, down to one block per CU, and the stream
+    kernel's segment lengths) gives the per-cell counts of the default, which
+    is exact."""
     _say("forced fused-kernel configurations")
     w = workloads.batched_c4(n_groups=24, size_hi=150, centroid_std=0.3, seed=12)
     feats = w.features.to("cuda")
     t = fx.Task(fx.Dataset(fx.Context(0), feats, w.offsets, w.attrs), w.on, w.by, w.across)
     ref = t.score()
     assert np.array_equal(ref.half_units, oracle_score(w).half_units)
-    for cols, bpc in ((128, 0), (128, 1), (128, 4), (256, 0), (256, 2)):
+    for cols, bpc in ((128, 0), (128, 1), (128, 4), (256, 0), (256, 2), (512, 2), (2048, 0), (1024, 1)):
         r = t.score(fused_cols=cols, fused_blocks_per_cu=bpc)
         print(f"  cols {cols} blocks/CU {bpc}: distance {r.stats['ms_distance']:.3f} ms", flush=True)
         assert (r.stats["fused_cols"], r.stats["fused_blocks_per_cu"]) == (cols, bpc)
@@ -1115,3 +1117,103 @@ def test_server_small_job_passes_a_waiting_large_one():
     assert st["p50_queue_ms"] < 0.25 * t_big
     assert st["p99_queue_ms"] > 0.25 * t_big   # the second large job did wait
     srv.close()
+
+
+# --------------------------------------------------- column-stream kernel --
+
+_STREAM_CASES = [
+    ("c1-hard", lambda: workloads.plain_c1(centroid_std=0.15, seed=31)),
+    ("c4-shape", lambda: workloads.batched_c4(n_groups=24, size_hi=150, centroid_std=0.3, seed=32)),
+    ("c2-shape", lambda: workloads.within_c2(n_items=4000, centroid_std=0.1, seed=33)),
+    ("c3-shape", lambda: workloads.across_c3(n_items=3000, centroid_std=0.1, seed=34)),
+    ("len-1-to-64", lambda: workloads.batched_c4(n_groups=10, size_hi=70, len_lo=1, len_hi=64, dim=64,
+                                                 centroid_std=0.3, seed=35)),
+    ("len-1", lambda: workloads.batched_c4(n_groups=10, size_hi=70, len_lo=1, len_hi=1, dim=64,
+                                           centroid_std=0.3, seed=36)),
+    ("dim-33", lambda: workloads.plain_c1(dim=33, centroid_std=0.2, seed=37)),
+]
+
+
+@pytest.mark.parametrize("name,make", _STREAM_CASES, ids=[c[0] for c in _STREAM_CASES])
+@pytest.mark.parametrize("cols,bpc", [(1024, 2), (512, 0)])
+def test_stream_kernel_exact(name, make, cols, bpc):
+    """The column-stream kernel (segments of 512 or 1024 frames per wave, a
+    persistent grid or a wave per segment): every cell equals the oracle's,
+    robust pairs within margin / 2, with both DTW normalisations."""
+    w = make()
+    check(w, fused_cols=cols, fused_blocks_per_cu=bpc)
+    if name in ("c1-hard", "len-1-to-64"):
+        check(w, norm="none", fused_cols=cols, fused_blocks_per_cu=bpc)
+
+
+# ------------------------------------------------- near-parallel frames --
+
+def _with_twins(w, eps, frac=0.5, seed=0):
+    """w plus a perturbed copy of a random `frac` of its items: the copy has
+    the item's attributes and its frames times (1 + eps N(0, 1)) per value
+    (eps = 0: exact copies), so the BY groups hold pairs of nearly parallel
+    frames all along their DTW paths."""
+    rng = np.random.default_rng(seed)
+    src = np.sort(rng.choice(w.n_items, int(frac * w.n_items), replace=False))
+    feats = w.features.float().cpu()
+    parts, lens = [feats], list(np.diff(w.offsets))
+    g = torch.Generator().manual_seed(seed)
+    for i in src:
+        f = feats[int(w.offsets[i]):int(w.offsets[i + 1])]
+        parts.append(f * (1.0 + eps * torch.randn(f.shape, generator=g)))
+        lens.append(len(f))
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    attrs = np.concatenate([w.attrs, w.attrs[src]]).astype(np.int32)
+    return workloads.Workload(f"{w.name}-twins{eps}", torch.cat(parts).contiguous(), off, attrs,
+                              list(w.attr_names), w.on, list(w.by), list(w.across),
+                              [list(l) for l in w.levels], w.seed)
+
+
+@pytest.mark.parametrize("dim", [768, 1024, 1280])
+@pytest.mark.parametrize("eps", [0.0, 1e-4, 1e-3])
+def test_near_parallel_frames_exact(dim, eps):
+    """Items and slightly perturbed copies of them (frames at angles of about
+    eps rad, down to exact copies), at the high dims where the margin is
+    smallest: acos of a BF16 cosine is off by up to about 1e-4 there, so the
+    kernels must flag these pairs for the FP64 recheck; every cell equals the
+    oracle's, in DTW and in pooled mode."""
+    base = workloads.within_c2(n_items=900, dim=dim, centroid_std=0.1, seed=50 + dim)
+    w = _with_twins(base, eps, seed=int(eps * 1e5) + dim)
+    _, res, _ = check(w)
+    st = res.stats
+    print(f"  nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']}", flush=True)
+    assert st["n_nonrobust_pairs"] > 0
+    check(w, mode="pooled")
+
+
+# ---------------------------------------------------------------- subsampler --
+
+@pytest.mark.parametrize("spec", ["within", "across"])
+def test_subsampled_tasks_match_oracle(spec):
+    """Subsampled tasks (caps on A, B, X per cell; at most 2 ACROSS values of x):
+    every kept cell's W equals the oracle's on the same draws, and caps that
+    bind nowhere give the full task's counts."""
+    if spec == "within":
+        w = workloads.within_c2(n_items=3000, dim=128, centroid_std=0.1, seed=61)
+        subs = [dict(seed=3, max_a=3, max_b=4), dict(seed=4, max_a=2, max_b=1, max_x=5)]
+    else:
+        w = workloads.across_c3(n_items=2500, dim=128, centroid_std=0.1, seed=62)
+        subs = [dict(seed=5, max_a=3, max_b=3, max_x=2, max_x_across=2), dict(seed=6, max_x=1, max_x_across=1)]
+    feats = w.features.to("cuda").contiguous()
+    ds = fx.Dataset(ctx(), feats, w.offsets, w.attrs)
+    host = w.features_f32_host()
+    for sub in subs:
+        _say(f"subsampled {spec} {sub}")
+        t = fx.Task(ds, w.on, w.by, w.across, subsampler=fx.Subsampler(**sub))
+        res = t.score()
+        orc = oracle.score(host, w.offsets, w.attrs, w.on, w.by, w.across, subsampler=sub)
+        assert np.array_equal(t.keys, orc.keys.astype(np.int32))
+        assert np.array_equal(t.sizes[0], orc.n_triplets)
+        mism = int(np.count_nonzero(res.half_units != orc.half_units))
+        print(f"  cells={len(t)} triplets={int(orc.n_triplets.sum())} mism={mism} "
+              f"err={res.collapse(w.levels):.5f} oracle={oracle.error_rate(orc, w.levels):.5f}", flush=True)
+        assert mism == 0
+        assert abs(res.collapse(w.levels) - oracle.error_rate(orc, w.levels)) <= 1e-12
+    big = fx.Subsampler(seed=1, max_a=10 ** 6, max_b=10 ** 6, max_x=10 ** 6, max_x_across=10 ** 6)
+    full = fx.Task(ds, w.on, w.by, w.across).score().half_units
+    assert np.array_equal(fx.Task(ds, w.on, w.by, w.across, subsampler=big).score().half_units, full)
