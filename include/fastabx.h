@@ -357,6 +357,35 @@ typedef struct fabx_stats {
 
 int fabx_result_stats(const fabx_result *res, fabx_stats *stats);
 
+/* Bytes of the per-device scratch array behind fabx_score_noalloc (256 MiB). */
+#define FABX_NOALLOC_SCRATCH_BYTES (256 * 1024 * 1024)
+
+/* fabx_score for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It computes
+ * exactly what fabx_score computes (same kernels, same per-cell counts W_C)
+ * but lays every device buffer of the score -- the task's tables, the fused
+ * kernel's column plan and the whole workspace -- in one library-owned
+ * scratch array of FABX_NOALLOC_SCRATCH_BYTES per device, which each device
+ * the library runs on holds until the process ends.  It calls no hipMalloc,
+ * hipFree, pinned-memory allocation or allocating library routine.
+ *
+ *  task        a task of a device context (the dataset's features are read
+ *              on the context's stream, as by fabx_score).
+ *  opts        as fabx_score (NULL: defaults); keep_pairs must be 0.
+ *  half_units  host int64 [num_cells], caller-owned: W_C of every cell.
+ *  stats       host, may be NULL: as fabx_result_stats, without stage times.
+ *
+ * Synchronous: returns once the counts are on the host.  Calls on one device
+ * share its scratch array, which keeps the last call's contents; they are
+ * serialised by a per-device lock held for the whole call, so calls from
+ * several threads do not overlap, but any other use of the same memory (a
+ * graph replay still running, say) would race.  Errors: EINVAL (bad opts,
+ * keep_pairs set, host-only context), ENOMEM (the task needs more scratch
+ * than FABX_NOALLOC_SCRATCH_BYTES; fabx_score has no such limit), EDOMAIN,
+ * EHIP. */
+int fabx_score_noalloc(fabx_task *task, const fabx_score_opts *opts, int64_t *half_units,
+                       fabx_stats *stats);
+
 /* ------------------------------------------------------------- autotune */
 
 /* Launch choices of the fused BF16 DTW kernel (batching of uneven cells in one

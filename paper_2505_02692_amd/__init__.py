@@ -206,6 +206,15 @@ def fabx_score_async(t, opts: fabx_score_opts) -> ctypes.c_void_p:
     return h
 
 
+def fabx_score_noalloc(t, opts: fabx_score_opts, n_cells: int):
+    """(W per cell as int64 [n_cells], stats dict) from fabx_score_noalloc."""
+    w = np.zeros(max(int(n_cells), 1), dtype=np.int64)
+    st = fabx_stats()
+    _check(lib().fabx_score_noalloc(t, ctypes.byref(opts), w.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    ctypes.byref(st)))
+    return w[:int(n_cells)], st.as_dict()
+
+
 def fabx_result_wait(r) -> None:
     _check(lib().fabx_result_wait(r))
 

@@ -26,6 +26,7 @@ FABX_PREC_BF16_RECHECK = 1
 FABX_NORM_PATH = 0
 FABX_NORM_NONE = 1
 FABX_MAX_ITEM_FRAMES = 64
+FABX_NOALLOC_SCRATCH_BYTES = 256 * 1024 * 1024
 
 STATUS_NAMES = {0: "FABX_OK", -1: "FABX_EINVAL", -2: "FABX_ENOMEM", -3: "FABX_EDOMAIN",
                 -4: "FABX_EAGAIN", -5: "FABX_EHIP", -6: "FABX_ECANCELED", -7: "FABX_ENOTFOUND"}
@@ -119,6 +120,7 @@ SIGNATURES = {
     "fabx_score_opts_default": (ctypes.c_int, [_P(fabx_score_opts)]),
     "fabx_score": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
     "fabx_score_async": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_vp)]),
+    "fabx_score_noalloc": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_i64), _P(fabx_stats)]),
     "fabx_result_wait": (ctypes.c_int, [_vp]),
     "fabx_autotune": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(fabx_tune_report)]),
     "fabx_result_free": (None, [_vp]),

@@ -263,6 +263,7 @@ int fabx_create(fabx_ctx **out, int device, void *hip_stream) {
             FABX_HIP(hipGetDeviceProperties(&prop, device));
             c->n_cu = prop.multiProcessorCount;
             FABX_HIP(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+            (void)scratch_setup(device);  // the device address of fabx_score_noalloc's scratch
             const char *tune_file = std::getenv("FABX_AUTOTUNE_CACHE");
             if (tune_file && *tune_file) c->tuner.load(tune_file);
             // NULL is the device's null stream, as everywhere in HIP: the context's

@@ -388,6 +388,16 @@ std::shared_ptr<ResultImpl> run_score(const std::shared_ptr<TaskImpl> &task, con
                                       hipStream_t stream);
 // Device bytes a score of this task would hold (admission control).
 int64_t footprint_bytes(const TaskImpl &task, const ScoreParams &p);
+// The whole score of fabx_score with every device buffer (task tables, column
+// plan, workspace) laid out in `base` [cap bytes] instead of the context's
+// pool: allocates no device or pinned memory.  Synchronous on `stream`; per-cell
+// counts into host half_units [n_cells]; stats (may be null) without stage
+// times.  ENOMEM if the task needs more than `cap` bytes.
+void score_in_scratch(TaskImpl &task, const ScoreParams &p, char *base, size_t cap, hipStream_t stream,
+                      int64_t *half_units, fabx_stats *stats);
+// noalloc.hip: device address of the fabx_score_noalloc scratch array on
+// `device` (looked up once per device, with that device current).
+char *scratch_setup(int device);
 // Gives the task's device memory (workspace, tables, column plans) and its
 // pinned packed tables back to the context's pools, after waiting for its
 // pending score.  A later score uploads the tables again.

@@ -794,6 +794,129 @@ void finish_score(ResultImpl &res) {
     }
 }
 
+void score_in_scratch(TaskImpl &t, const ScoreParams &p, char *base, size_t cap, hipStream_t stream,
+                      int64_t *half_units, fabx_stats *stats) {
+    std::lock_guard<std::mutex> lock(t.mu);
+    const DatasetImpl &ds = *t.ds;
+    if (ds.ctx->device < 0) fail(FABX_EINVAL, "context has no device (host-only context)");
+    fabx_stats st{};
+    const int64_t n_cells = int64_t(t.cells.size());
+    st.n_cells = n_cells;
+    st.n_triplets = t.total_triplets;
+    st.n_items = int64_t(t.items.size());
+    st.n_frames = t.n_frames;
+    st.n_pairs = t.n_pairs_needed;
+    st.dtw_cells = p.mode == FABX_MODE_DTW ? t.dtw_cells_needed : 0;
+    st.dtw_cells_sym = p.mode == FABX_MODE_DTW ? t.dtw_cells_sym : 0;
+    st.margin = p.precision == FABX_PREC_BF16_RECHECK ? p.margin : 0.0;
+    st.delta = p.precision == FABX_PREC_BF16_RECHECK && p.mode == FABX_MODE_DTW ? p.delta : 0.0;
+    if (n_cells == 0) {
+        if (stats) *stats = st;
+        return;
+    }
+    FABX_HIP(hipSetDevice(ds.ctx->device));
+    const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
+    const bool dtw = p.mode == FABX_MODE_DTW;
+    FusedConfig fcfg;
+    ColPlan *cplan = nullptr;
+    if (dtw && bf16) {
+        fcfg = p.fused.cols > 0 ? p.fused : ds.ctx->tuner.lookup(tune_key(t, p));
+        cplan = &col_plan(t, fcfg.cols);
+        st.fused_cols = fcfg.cols;
+        st.fused_blocks_per_cu = fcfg.blocks_per_cu;
+    }
+    const std::vector<int64_t> tiles = dtw ? std::vector<int64_t>() : tile_prefix(t, p);
+    const bool stream_k = cplan && fcfg.cols >= kStreamMinCols;
+    // Layout in the scratch buffer: tables (task, column plan, plan), then the
+    // workspace.  The plain DTW form's distance buffer takes what is left, at
+    // most its usual size; its strips are planned for that size.
+    auto layout = [&](const PlainPlan &strips, Packer &pk, TableLayout &tl, PlanLayout &pl,
+                      std::array<std::vector<int64_t>, 5> &gcols) {
+        tl = add_task_tables(t, cplan, pk, gcols);
+        pl = add_plan(pk, tiles, strips);
+        const size_t tables = (pk.total + 255) & ~size_t(255);
+        return tables + workspace_sizes(t, p, strips, stream_k).total_aligned();
+    };
+    Packer pk;
+    TableLayout tl;
+    PlanLayout pl;
+    std::array<std::vector<int64_t>, 5> gcols;
+    PlainPlan strips;
+    if (dtw && !bf16) {
+        strips = plain_plan(t, plain_dmat_cells());
+        Packer probe;
+        std::array<std::vector<int64_t>, 5> gc2;
+        const size_t need = layout(strips, probe, tl, pl, gc2);
+        if (need > cap) {
+            // the distance buffer gets what the rest leaves (1 MiB kept for the longer strip tables)
+            const size_t rest = need - ((size_t(std::max<int64_t>(strips.max_cells, 1)) * 4 + 255) & ~size_t(255));
+            const int64_t cells = rest + (size_t(1) << 20) < cap ? int64_t((cap - rest - (size_t(1) << 20)) / 4) : 0;
+            if (cells < 4096) fail(FABX_ENOMEM, "task needs more scratch than the no-allocation limit");
+            strips = plain_plan(t, cells);
+        }
+    }
+    const size_t need = layout(strips, pk, tl, pl, gcols);
+    if (need > cap)
+        fail(FABX_ENOMEM, "task needs " + std::to_string(need) + " bytes of scratch; the no-allocation limit is " +
+                              std::to_string(cap));
+    // tables: packed on the host, one copy (from pageable memory) into the scratch
+    std::vector<char> h(pk.total);
+    pk.copy_to(h.data());
+    FABX_HIP(hipMemcpyAsync(base, h.data(), pk.total, hipMemcpyHostToDevice, stream));
+    DevPtrs d;
+    auto at = [&](size_t off) { return base + off; };
+    d.it = kern::ItemTables{reinterpret_cast<const int64_t *>(at(tl.item_src)),
+                            reinterpret_cast<const int32_t *>(at(tl.item_len)),
+                            reinterpret_cast<const int64_t *>(at(tl.item_dst)), int64_t(t.items.size())};
+    d.gt = kern::GroupTables{reinterpret_cast<const int64_t *>(at(tl.g[0])),
+                             reinterpret_cast<const int64_t *>(at(tl.g[1])),
+                             reinterpret_cast<const int64_t *>(at(tl.g[2])),
+                             reinterpret_cast<const int64_t *>(at(tl.g[3])),
+                             reinterpret_cast<const int64_t *>(at(tl.g[4])), int64_t(t.groups.size()),
+                             t.n_pair_slots};
+    d.cells = reinterpret_cast<const CellDev *>(at(tl.cells));
+    d.units = reinterpret_cast<const int32_t *>(at(tl.units));
+    d.rb = reinterpret_cast<const int32_t *>(at(tl.rb));
+    d.item_group = reinterpret_cast<const int32_t *>(at(tl.item_group));
+    if (cplan) {
+        d.cb = reinterpret_cast<const int32_t *>(at(tl.plan[0]));
+        d.rb_unit_prefix = reinterpret_cast<const int64_t *>(at(tl.plan[1]));
+        d.g_cb0 = reinterpret_cast<const int32_t *>(at(tl.plan[2]));
+        d.rb_cstart = reinterpret_cast<const int32_t *>(at(tl.plan[3]));
+    }
+    set_plan(d, base, pl);
+    const WorkspaceSizes wz = workspace_sizes(t, p, strips, stream_k);
+    size_t off = (pk.total + 255) & ~size_t(255);
+    auto take = [&](size_t bytes) -> char * {
+        if (!bytes) return nullptr;
+        char *q = base + off;
+        off += (bytes + 255) & ~size_t(255);
+        return q;
+    };
+    d.xn = take(wz.xn);
+    d.rinv = reinterpret_cast<float *>(take(wz.rinv));
+    d.dmat = reinterpret_cast<float *>(take(wz.dmat));
+    d.p32 = reinterpret_cast<float *>(take(wz.p32));
+    d.flags = reinterpret_cast<uint8_t *>(take(wz.flags));
+    d.p64 = reinterpret_cast<double *>(take(wz.p64));
+    d.recheck_list = reinterpret_cast<int64_t *>(take(wz.recheck_list));
+    d.recount_list = reinterpret_cast<int32_t *>(take(wz.recount_list));
+    d.half_units = reinterpret_cast<unsigned long long *>(take(wz.half_units));
+    d.finfo = reinterpret_cast<uint32_t *>(take(wz.finfo));
+    st.workspace_bytes = int64_t(wz.total_aligned());
+    std::vector<char> host(size_t(n_cells) * 8 + 64);
+    try {
+        enqueue_score(t, p, fcfg, cplan, tiles, strips, d, stream, nullptr, host.data(), st);
+        FABX_HIP(hipStreamSynchronize(stream));
+    } catch (...) {
+        (void)hipStreamSynchronize(stream);  // nothing may still use the scratch or `h`
+        throw;
+    }
+    read_counters(t, host.data(), size_t(n_cells), dtw, st);
+    std::memcpy(half_units, host.data(), size_t(n_cells) * 8);
+    if (stats) *stats = st;
+}
+
 void release_device(TaskImpl &t) {
     std::lock_guard<std::mutex> lock(t.mu);
     if (auto prev = t.pending.lock()) {

@@ -1,0 +1,69 @@
+"""fabx_score_noalloc (the score for callers that cannot allocate) against
+fabx_score, through the C ABI: the per-cell counts must be identical, on two
+calls in a row, the second with a smaller task than the first (the scratch
+array keeps the first call's contents), for every form of the score."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+import paper_2505_02692_amd as fx
+from paper_2505_02692_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+_CTX = {}
+
+
+def ctx():
+    if "c" not in _CTX:
+        _CTX["c"] = fx.Context(0)
+    return _CTX["c"]
+
+
+def _task(w):
+    ds = fx.Dataset(ctx(), w.features.to("cuda").contiguous(), w.offsets, w.attrs)
+    return ds, fx.Task(ds, w.on, w.by, w.across)
+
+
+@pytest.mark.parametrize("mode,precision,norm", [("dtw", "bf16", "path"), ("dtw", "bf16", "none"),
+                                                 ("dtw", "fp32", "path"), ("pooled", "bf16", "path"),
+                                                 ("pooled", "fp32", "path")])
+def test_noalloc_equals_score_on_two_calls(mode, precision, norm):
+    big = workloads.within_c2(n_items=3000, dim=256, centroid_std=0.1, seed=7)
+    small = workloads.plain_c1(centroid_std=0.15, seed=2)
+    for w in (big, small):
+        _say(f"noalloc {mode} {precision} {norm} {w.name} n_items={w.n_items}")
+        ds, t = _task(w)
+        ref = t.score(mode=mode, precision=precision, norm=norm)
+        opts = fx.make_opts(mode=mode, precision=precision, norm=norm)
+        got, st = fx.fabx_score_noalloc(t.h, opts, len(t))
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.half_units)
+        assert st["n_cells"] == len(t) and st["n_triplets"] == ref.stats["n_triplets"]
+        assert st["n_recheck_pairs"] == ref.stats["n_recheck_pairs"]
+        assert 0 < st["workspace_bytes"] <= L.FABX_NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_a_task_beyond_the_scratch():
+    _say("noalloc: task over the scratch limit")
+    w = workloads.within_c2(n_items=30000, dim=768, centroid_std=0.1, seed=8)
+    ds, t = _task(w)
+    with pytest.raises(fx.FabxError) as e:
+        fx.fabx_score_noalloc(t.h, fx.make_opts(precision="fp32"), len(t))
+    assert e.value.code == -2
+    # the regular entry point has no such limit, and the no-allocation one
+    # still works on a small task afterwards
+    ref = t.score(precision="fp32")
+    assert ref.stats["n_cells"] == len(t)
+    w2 = workloads.plain_c1(seed=4)
+    ds2, t2 = _task(w2)
+    got, _ = fx.fabx_score_noalloc(t2.h, fx.make_opts(), len(t2))
+    assert np.array_equal(got, t2.score().half_units)
