@@ -288,7 +288,15 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     // Rows and columns past the block's frames have zero inverse norms, so their
     // cosines are 0 and never count as near-parallel.
     float *dt = reinterpret_cast<float *>(smem_raw);
-    float cmax = 0.0f;  // largest |cos| this lane wrote
+    // Largest |cos| this lane wrote, leaving out a frame against itself: that
+    // element (row frame = column frame, only in units on the diagonal of the
+    // group's pair matrix, for the pair (x, x) that is never compared) is
+    // parallel by construction.  In the sub-tile of rows 32h + acc_row(i, lane)
+    // and columns col0 + lane % 32 the element is a frame against itself when
+    // acc_row(i, lane) - lane % 32 equals e = (column block start + col0) -
+    // (row block start + 32h); two operations per element.
+    float cmax = 0.0f;
+    const int lane_term = 4 * (lane / 32) - lane % 32;
 #pragma unroll
     for (int ct = 0; ct < T::kCT; ++ct) {
         const int col0 = T::kWaveCols * w + 32 * ct;
@@ -296,46 +304,20 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
         const int col = col0 + lane % 32;
         const float rc = norm_s[kRows + col];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r0 = acc_row(i, lane);
-            const float cs = fminf(fmaxf(acc[0][ct][i] * norm_s[r0] * rc, -1.0f), 1.0f);
-            cmax = fmaxf(cmax, fabsf(cs));
-            dt[r0 * kDStride + col] = dev::acos_over_pi(cs);
-        }
-        if (r_frames > 32) {
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && r_frames <= 32) break;
+            const int64_t e = c_frame0 - r_frame0 + col0 - 32 * h;
+            const int q = e > -32 && e < 32 ? int(e) - lane_term : 1 << 20;  // 1 << 20: no such element
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int r1 = 32 + acc_row(i, lane);
-                const float cs = fminf(fmaxf(acc[1][ct][i] * norm_s[r1] * rc, -1.0f), 1.0f);
-                cmax = fmaxf(cmax, fabsf(cs));
-                dt[r1 * kDStride + col] = dev::acos_over_pi(cs);
+                const int r = 32 * h + acc_row(i, lane);
+                const float cs = fminf(fmaxf(acc[h][ct][i] * norm_s[r] * rc, -1.0f), 1.0f);
+                cmax = fmaxf(cmax, 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs));
+                dt[r * kDStride + col] = dev::acos_over_pi(cs);
             }
         }
     }
-    // A frame against itself (units on the diagonal of the group's pair
-    // matrix: the pair (x, x), never compared) is parallel by construction:
-    // when some |cos| is that high, look again without those elements.
-    if (__ballot(cmax > kNearCos) != 0) {
-        const int64_t diag = r_frame0 - c_frame0;  // column col is row col - diag's frame
-        bool near = false;
-#pragma unroll
-        for (int ct = 0; ct < T::kCT; ++ct) {
-            const int col0 = T::kWaveCols * w + 32 * ct;
-            if (col0 >= c_frames || col0 + 32 <= c_skip) continue;
-            const int col = col0 + lane % 32;
-            const float rc = norm_s[kRows + col];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int r = 32 * h + acc_row(i, lane);
-                    const float cs = fminf(fmaxf(acc[h][ct][i] * norm_s[r] * rc, -1.0f), 1.0f);
-                    near |= fabsf(cs) > kNearCos && int64_t(r) + diag != int64_t(col);
-                }
-            }
-        }
-        if (__ballot(near) != 0 && lane == 0) atomicOr(&near_s, 1);
-    }
+    if (__ballot(cmax > kNearCos) != 0 && lane == 0) atomicOr(&near_s, 1);
 
     // 3. DTW.  Column items of this block split over the 4 waves by start frame.
     // Lane constants: the row item of lane `lane`.
