@@ -66,8 +66,13 @@ extern "C" {
 #define FABX_NORM_PATH 0             /* DTW cost divided by the optimal path's length */
 #define FABX_NORM_NONE 1             /* raw DTW cost */
 
-/* Longest item (in frames) the DTW kernels accept. */
-#define FABX_MAX_ITEM_FRAMES 64
+/* Longest item (in frames) DTW mode accepts.  The BF16 kernels evaluate pairs
+ * of items of at most 64 frames; a pair with a longer item is computed in FP64
+ * from the raw features instead (rows in chunks of 64, each chunk handing its
+ * last row of costs and path lengths to the next), and the plain FP32 form
+ * runs its DTW in the same row chunks.  The streaming kernel (fused_cols 512,
+ * 1024, 2048) takes items of at most 64 frames. */
+#define FABX_MAX_ITEM_FRAMES 1024
 
 typedef struct fabx_ctx fabx_ctx;
 typedef struct fabx_dataset fabx_dataset;

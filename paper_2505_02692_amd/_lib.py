@@ -25,7 +25,7 @@ FABX_PREC_FP32 = 0
 FABX_PREC_BF16_RECHECK = 1
 FABX_NORM_PATH = 0
 FABX_NORM_NONE = 1
-FABX_MAX_ITEM_FRAMES = 64
+FABX_MAX_ITEM_FRAMES = 1024
 FABX_NOALLOC_SCRATCH_BYTES = 256 * 1024 * 1024
 
 STATUS_NAMES = {0: "FABX_OK", -1: "FABX_EINVAL", -2: "FABX_ENOMEM", -3: "FABX_EDOMAIN",

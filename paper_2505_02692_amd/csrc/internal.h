@@ -304,6 +304,7 @@ struct TaskImpl {
     int64_t n_units_small = 0;
     int64_t sum_nx = 0;             // sum over cells of |X|
     hvec<int32_t> rb;               // fused kernel row blocks [n][4] (<= 64 frames)
+    std::vector<int64_t> long_slots;  // pair slots with an item of more than 64 frames (FP64 kernel)
     std::vector<int32_t> g_rb0, g_nrb;
     std::vector<std::unique_ptr<ColPlan>> col_plans;  // by column block width, made on demand
     int64_t fused_cells = 0;        // frame pairs the fused kernel covers

@@ -101,6 +101,12 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
     }
 }
 
+// One wave per pair slot of a strip: lane i is on row i, column t - i at step
+// t (anti-diagonals), reading the strip's frame distances.  kLong: items may
+// have more than 64 frames; rows then go in chunks of 64, each sweeping all
+// columns, and a chunk hands its last row's costs and path lengths to the
+// next one through the wave's LDS row buffer.
+template <bool kLong>
 __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dmat,
                                                    const int64_t *__restrict__ s_group,
                                                    const int64_t *__restrict__ s_slot0,
@@ -114,10 +120,15 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst, int norm,
                                                    float *__restrict__ p32) {
-    const int i = threadIdx.x % kWave;
+    constexpr int kRowBuf = kLong ? FABX_MAX_ITEM_FRAMES : 1;
+    __shared__ float rowc_s[4][kRowBuf];  // per wave: the previous chunk's last row (costs)
+    __shared__ int rowl_s[4][kRowBuf];    // and path lengths
+    const int i = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    float *rowc = rowc_s[wv];
+    int *rowl = rowl_s[wv];
     const int64_t slot_lo = s_slot0[0], slot_hi = s_slot0[n_strips];
     // one wave per slot; the loop bound is uniform across the wave
-    for (int64_t slot = slot_lo + int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; slot < slot_hi;
+    for (int64_t slot = slot_lo + int64_t(blockIdx.x) * 4 + wv; slot < slot_hi;
          slot += int64_t(gridDim.x) * 4) {
     const int64_t sg = dev::find_segment(s_slot0, n_strips, slot);
     const int64_t g = s_group[sg];
@@ -130,21 +141,31 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
 
     float c = kInf;          // c[i][j-1] (own value of the previous step)
     int len = 0;
+    for (int r0 = 0; r0 < N; r0 += kWave) {
+    const int nr = min(kWave, N - r0);
+    const int gi = r0 + i;   // this lane's row
+    c = kInf;
+    len = 0;
     float up_prev = kInf;    // c[i-1][j-1]
     int lup_prev = 0;
-    for (int t = 0; t < N + M - 1; ++t) {
+    for (int t = 0; t < nr + M - 1; ++t) {
         const int j = t - i;
         float up = __shfl_up(c, 1, kWave);  // c[i-1][j]: lane i-1 at step t-1
         int lup = __shfl_up(len, 1, kWave);
+        if (i == 0) {  // the row above the chunk (none above row 0)
+            const bool in = kLong && r0 > 0 && j >= 0 && j < M;
+            up = in ? rowc[in ? j : 0] : kInf;
+            lup = in ? rowl[in ? j : 0] : 0;
+        }
         float diag = up_prev, left = c;
         int ldiag = lup_prev, lleft = len;
-        if (i == 0) { up = kInf; diag = kInf; }
+        if (gi == 0) diag = kInf;
         if (j == 0) { left = kInf; diag = kInf; }
         up_prev = up;
         lup_prev = lup;
-        if (i < N && j >= 0 && j < M) {
-            const float dv = d[int64_t(i) * F + j];
-            if (i == 0 && j == 0) {
+        if (i < nr && j >= 0 && j < M) {
+            const float dv = d[int64_t(gi) * F + j];
+            if (gi == 0 && j == 0) {
                 c = dv;
                 len = 1;
             } else {
@@ -156,9 +177,14 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
                 c = dv + best;
                 len = lb + 1;
             }
+            if (kLong && i == nr - 1) {  // this chunk's last row, for the next chunk
+                rowc[j] = c;
+                rowl[j] = len;
+            }
         }
     }
-    if (i == N - 1) p32[slot] = norm == FABX_NORM_PATH ? c / float(len) : c;
+    }
+    if (i == (N - 1) % kWave) p32[slot] = norm == FABX_NORM_PATH ? c / float(len) : c;
     }
 }
 
@@ -179,11 +205,11 @@ void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const GramSeg
 }
 
 void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const GroupTables &g,
-               const ItemTables &it, int norm, float *p32) {
+               const ItemTables &it, int norm, bool has_long, float *p32) {
     if (st.n <= 0 || st.n_slots <= 0) return;
-    hipLaunchKernelGGL(k_dtw_plain, dim3(grid_for(st.n_slots, 4)), dim3(256), 0, s, dmat, st.group,
-                       st.slot0, st.row0, st.base, st.n, g.item0, g.n_items, g.frame0, g.n_frames,
-                       g.pair_base, it.len, it.dst, norm, p32);
+    hipLaunchKernelGGL(has_long ? k_dtw_plain<true> : k_dtw_plain<false>, dim3(grid_for(st.n_slots, 4)),
+                       dim3(256), 0, s, dmat, st.group, st.slot0, st.row0, st.base, st.n, g.item0, g.n_items,
+                       g.frame0, g.n_frames, g.pair_base, it.len, it.dst, norm, p32);
     FABX_HIP(hipGetLastError());
 }
 

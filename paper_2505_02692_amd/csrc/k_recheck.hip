@@ -22,7 +22,8 @@ namespace fabx {
 namespace kern {
 namespace {
 
-constexpr int kMaxL = FABX_MAX_ITEM_FRAMES;
+constexpr int kMaxL = 64;                    // items of at most this many frames: k_recheck_dtw
+constexpr int kLongMax = FABX_MAX_ITEM_FRAMES;  // longer ones (up to this): k_long_dtw
 constexpr double kPi = 3.14159265358979323846;
 
 template <typename T>
@@ -46,11 +47,70 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-// One 256-thread block per listed pair: the four waves share the N + M frame
-// norms and then the N x M frame distances (a wave per frame pair at a time,
-// its 64 lanes splitting the feature dimension, one butterfly sum each), held
-// in LDS; then one wave runs the DTW over anti-diagonals (lane = row i), with
-// the diagonal > left > up predecessor order on exact ties.
+// 1 / ||frame|| (the whole wave; every lane gets it).
+template <typename T>
+__device__ __forceinline__ double wave_inv_norm(const T *row, int dim, int lane) {
+    double s = 0.0;
+    for (int k = lane; k < dim; k += dev::kWave) {
+        const double v = ld(row, k);
+        s += v * v;
+    }
+    return 1.0 / sqrt(wave_sum_f64(s));
+}
+
+// Angular distance of frames u and v with inverse norms su and sv (the whole
+// wave, its lanes splitting the dimension; every lane gets it).
+template <typename T>
+__device__ __forceinline__ double wave_frame_distance(const T *u, const T *v, double su, double sv, int dim,
+                                                      int lane) {
+    double c = 0.0;
+    for (int k = lane; k < dim; k += dev::kWave) c += (ld(u, k) * su) * (ld(v, k) * sv);
+    c = wave_sum_f64(c);
+    double sm = 0.0, sp = 0.0;
+    if (!(fabs(c) < 1.0 - 0x1p-20)) {   // wave-uniform: c is the same in every lane
+        for (int k = lane; k < dim; k += dev::kWave) {
+            const double a = ld(u, k) * su, b = ld(v, k) * sv;
+            sm += (a - b) * (a - b);
+            sp += (a + b) * (a + b);
+        }
+        sm = wave_sum_f64(sm);
+        sp = wave_sum_f64(sp);
+    }
+    return angle_over_pi_units(c, sm, sp);
+}
+
+// The DTW update of cell (i, j) from its neighbours' costs and path lengths,
+// with the first row and column accumulating along themselves and the
+// diagonal > left > up order on exact ties.
+__device__ __forceinline__ void dtw_update(int i, int j, double d, double diag, int ldiag, double left,
+                                           int lleft, double up, int lup, double &c, int &len) {
+    if (i == 0 && j == 0) {
+        c = d;
+        len = 1;
+    } else if (i == 0) {
+        c = left + d;
+        len = lleft + 1;
+    } else if (j == 0) {
+        c = up + d;
+        len = lup + 1;
+    } else if (diag <= left && diag <= up) {
+        c = diag + d;
+        len = ldiag + 1;
+    } else if (left <= up) {
+        c = left + d;
+        len = lleft + 1;
+    } else {
+        c = up + d;
+        len = lup + 1;
+    }
+}
+
+// One 256-thread block per listed pair of items of at most kMaxL frames (the
+// others are left to k_long_dtw): the four waves share the N + M frame norms
+// and then the N x M frame distances (a wave per frame pair at a time, its 64
+// lanes splitting the feature dimension, one butterfly sum each), held in LDS;
+// then one wave runs the DTW over anti-diagonals (lane = row i), with the
+// diagonal > left > up predecessor order on exact ties.
 template <typename T>
 __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat, int dim,
                                                      const int64_t *__restrict__ g_item0,
@@ -74,41 +134,22 @@ __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat,
         const int64_t local = slot - g_pair_base[g];
         const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
         const int N = item_len[x], M = item_len[y];
+        if (N > kMaxL || M > kMaxL) continue;  // block-uniform
         const T *fx = feat + item_src[x] * int64_t(dim);
         const T *fy = feat + item_src[y] * int64_t(dim);
         auto frame = [&](int f) { return f < N ? fx + int64_t(f) * dim : fy + int64_t(f - N) * dim; };
         // norms of the N + M frames, a wave per frame
         for (int f = w; f < N + M; f += 4) {
-            const T *row = frame(f);
-            double s = 0.0;
-            for (int k = lane; k < dim; k += dev::kWave) {
-                const double v = ld(row, k);
-                s += v * v;
-            }
-            s = wave_sum_f64(s);
-            if (lane == 0) inrm[f] = 1.0 / sqrt(s);
+            const double r = wave_inv_norm(frame(f), dim, lane);
+            if (lane == 0) inrm[f] = r;
         }
         __syncthreads();
         // frame distances, a wave per (i, j)
         for (int cidx = w; cidx < N * M; cidx += 4) {
             const int i = cidx / M, j = cidx % M;
-            const T *u = fx + int64_t(i) * dim;
-            const T *v = fy + int64_t(j) * dim;
-            const double su = inrm[i], sv = inrm[N + j];
-            double c = 0.0;
-            for (int k = lane; k < dim; k += dev::kWave) c += (ld(u, k) * su) * (ld(v, k) * sv);
-            c = wave_sum_f64(c);
-            double sm = 0.0, sp = 0.0;
-            if (!(fabs(c) < 1.0 - 0x1p-20)) {   // wave-uniform: c is the same in every lane
-                for (int k = lane; k < dim; k += dev::kWave) {
-                    const double a = ld(u, k) * su, b = ld(v, k) * sv;
-                    sm += (a - b) * (a - b);
-                    sp += (a + b) * (a + b);
-                }
-                sm = wave_sum_f64(sm);
-                sp = wave_sum_f64(sp);
-            }
-            if (lane == 0) dm[cidx] = angle_over_pi_units(c, sm, sp);
+            const double d = wave_frame_distance(fx + int64_t(i) * dim, fy + int64_t(j) * dim, inrm[i],
+                                                 inrm[N + j], dim, lane);
+            if (lane == 0) dm[cidx] = d;
         }
         __syncthreads();
         if (w == 0) {
@@ -125,32 +166,124 @@ __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat,
                 const int ldiag = lup_prev, lleft = len;
                 up_prev = up;
                 lup_prev = lup;
-                if (i < N && j >= 0 && j < M) {
-                    const double d = dm[i * M + j];
-                    if (i == 0 && j == 0) {
-                        c = d;
-                        len = 1;
-                    } else if (i == 0) {
-                        c = left + d;
-                        len = lleft + 1;
-                    } else if (j == 0) {
-                        c = up + d;
-                        len = lup + 1;
-                    } else if (diag <= left && diag <= up) {
-                        c = diag + d;
-                        len = ldiag + 1;
-                    } else if (left <= up) {
-                        c = left + d;
-                        len = lleft + 1;
-                    } else {
-                        c = up + d;
-                        len = lup + 1;
-                    }
-                }
+                if (i < N && j >= 0 && j < M)
+                    dtw_update(i, j, dm[i * M + j], diag, ldiag, left, lleft, up, lup, c, len);
             }
             if (i == N - 1) p64[slot] = norm == FABX_NORM_PATH ? c / double(len) : c;
         }
         __syncthreads();
+    }
+}
+
+// One 256-thread block per listed pair in which an item has more than kMaxL
+// frames (pairs of shorter items are skipped): the same arithmetic as
+// k_recheck_dtw, tiled.  Rows go in chunks of 64 (lane = row), each chunk
+// sweeping all M columns along anti-diagonals; a chunk hands its last row's
+// costs and path lengths to the next one through LDS (`rowc`, `rowl`).  The
+// frame distances of a chunk are made 32 columns at a time by the four waves
+// into a ring of three 32-column tiles: at step s lane i reads column s - i,
+// so the steps of tile k (s in [32k, 32k + 32)) read tiles k - 2 .. k only,
+// and tile k + 1 may overwrite tile k - 2 once those steps are done.
+// The result of pair `slot` goes to p64, and also to p32 and flags (0: robust,
+// unmarked) when they are given (the first computation of such a pair).
+template <typename T>
+__global__ __launch_bounds__(256) void k_long_dtw(const T *__restrict__ feat, int dim,
+                                                  const int64_t *__restrict__ g_item0,
+                                                  const int64_t *__restrict__ g_n,
+                                                  const int64_t *__restrict__ g_pair_base,
+                                                  int64_t n_groups,
+                                                  const int64_t *__restrict__ item_src,
+                                                  const int32_t *__restrict__ item_len,
+                                                  const int64_t *__restrict__ list,
+                                                  const unsigned int *__restrict__ count,
+                                                  int64_t max_count, int norm,
+                                                  double *__restrict__ p64, float *__restrict__ p32,
+                                                  uint8_t *__restrict__ flags) {
+    constexpr int kTc = 32, kRing = 3, kRingCols = kRing * kTc;
+    __shared__ double dm[dev::kWave * kRingCols];  // [row of chunk][ring column]
+    __shared__ double rinv_r[dev::kWave], rinv_c[kTc];
+    __shared__ double rowc[kLongMax];              // previous chunk's last row: costs
+    __shared__ int rowl[kLongMax];                 // and path lengths
+    const int lane = threadIdx.x % dev::kWave, w = threadIdx.x / dev::kWave;
+    const int64_t total = count ? min(int64_t(*count), max_count) : max_count;
+    for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
+        const int64_t slot = list[e];
+        const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
+        const int64_t n = g_n[g];
+        const int64_t local = slot - g_pair_base[g];
+        const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
+        const int N = item_len[x], M = item_len[y];
+        if (N <= kMaxL && M <= kMaxL) continue;  // block-uniform: k_recheck_dtw's pairs
+        const T *fx = feat + item_src[x] * int64_t(dim);
+        const T *fy = feat + item_src[y] * int64_t(dim);
+        const int n_tiles = (M + kTc - 1) / kTc;
+        double c = 0.0;
+        int len = 0;
+        for (int r0 = 0; r0 < N; r0 += dev::kWave) {
+            const int nr = min(dev::kWave, N - r0);
+            __syncthreads();  // the previous chunk's steps are done with the norms and the ring
+            for (int f = w; f < nr; f += 4) {
+                const double r = wave_inv_norm(fx + int64_t(r0 + f) * dim, dim, lane);
+                if (lane == 0) rinv_r[f] = r;
+            }
+            // wave 0's sweep state: lane i holds row r0 + i at column s - i
+            const int i = lane;
+            double up_prev = 0.0;
+            int lup_prev = 0;
+            c = 0.0;
+            len = 0;
+            int s = 0;
+            const int steps = M + nr - 1;
+            for (int k = 0; k < n_tiles; ++k) {
+                const int c0 = k * kTc, nc = min(kTc, M - c0);
+                const int ring0 = (k % kRing) * kTc;
+                __syncthreads();  // tile k - 2's steps are done (and the row norms are in)
+                for (int f = w; f < nc; f += 4) {
+                    const double r = wave_inv_norm(fy + int64_t(c0 + f) * dim, dim, lane);
+                    if (lane == 0) rinv_c[f] = r;
+                }
+                __syncthreads();
+                for (int cidx = w; cidx < nr * nc; cidx += 4) {
+                    const int ii = cidx / nc, jj = cidx % nc;
+                    const double d = wave_frame_distance(fx + int64_t(r0 + ii) * dim, fy + int64_t(c0 + jj) * dim,
+                                                         rinv_r[ii], rinv_c[jj], dim, lane);
+                    if (lane == 0) dm[ii * kRingCols + ring0 + jj] = d;
+                }
+                __syncthreads();
+                if (w == 0) {
+                    const int s_end = k == n_tiles - 1 ? steps : c0 + kTc;
+                    for (; s < s_end; ++s) {
+                        const int j = s - i;
+                        double up = __shfl_up(c, 1, dev::kWave);   // lane i - 1's cost, step s - 1
+                        int lup = __shfl_up(len, 1, dev::kWave);
+                        if (i == 0) {  // the row above the chunk, read before this step's store
+                            const bool in = r0 > 0 && j >= 0 && j < M;
+                            up = in ? rowc[j] : 0.0;
+                            lup = in ? rowl[j] : 0;
+                        }
+                        const double diag = up_prev, left = c;
+                        const int ldiag = lup_prev, lleft = len;
+                        up_prev = up;
+                        lup_prev = lup;
+                        if (i < nr && j >= 0 && j < M) {
+                            const double d = dm[i * kRingCols + ((j / kTc) % kRing) * kTc + j % kTc];
+                            dtw_update(r0 + i, j, d, diag, ldiag, left, lleft, up, lup, c, len);
+                            if (i == nr - 1) {  // this chunk's last row, for the next chunk
+                                rowc[j] = c;
+                                rowl[j] = len;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // lane (N - 1) % 64 of wave 0 ended on cell (N - 1, M - 1)
+        if (w == 0 && lane == (N - 1) % dev::kWave) {
+            const double v = norm == FABX_NORM_PATH ? c / double(len) : c;
+            p64[slot] = v;
+            if (p32) p32[slot] = float(v);
+            if (flags) flags[slot] = 0;
+        }
     }
 }
 
@@ -217,12 +350,30 @@ __global__ __launch_bounds__(256) void k_recheck_pooled(const T *__restrict__ fe
 
 }  // namespace
 
+void long_dtw(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
+              const ItemTables &it, const int64_t *list, const unsigned int *count, int64_t max_count, int norm,
+              double *p64, float *p32, uint8_t *flags) {
+    if (max_count <= 0) return;
+    const unsigned blocks = unsigned(std::min<int64_t>(max_count, 4096));
+    if (dtype == FABX_DTYPE_F32)
+        hipLaunchKernelGGL(k_long_dtw<float>, dim3(blocks), dim3(256), 0, s, static_cast<const float *>(features),
+                           dim, g.item0, g.n_items, g.pair_base, g.n_groups, it.src, it.len, list, count,
+                           max_count, norm, p64, p32, flags);
+    else
+        hipLaunchKernelGGL(k_long_dtw<uint16_t>, dim3(blocks), dim3(256), 0, s,
+                           static_cast<const uint16_t *>(features), dim, g.item0, g.n_items, g.pair_base,
+                           g.n_groups, it.src, it.len, list, count, max_count, norm, p64, p32, flags);
+    FABX_HIP(hipGetLastError());
+}
+
 void recheck_fp64(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
                   const ItemTables &it, const int64_t *list, const unsigned int *count,
-                  int64_t max_count, int mode, int norm, double *p64) {
+                  int64_t max_count, int mode, int norm, bool has_long, double *p64) {
     if (max_count <= 0) return;
     if (mode == FABX_MODE_POOLED && dim > 2048) fail(FABX_EINVAL, "pooled recheck supports dim <= 2048");
     const unsigned blocks = unsigned(std::min<int64_t>(max_count, 4096));
+    if (mode == FABX_MODE_DTW && has_long)
+        long_dtw(s, features, dtype, dim, g, it, list, count, max_count, norm, p64, nullptr, nullptr);
     if (mode == FABX_MODE_DTW) {
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL(k_recheck_dtw<float>, dim3(blocks), dim3(256), 0, s,

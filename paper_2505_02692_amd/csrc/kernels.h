@@ -81,9 +81,10 @@ struct PlainStrips {
 };
 // One wave per ordered item pair of the strips' slots: anti-diagonal DTW over
 // the strip's F32 distance matrix (lane = row), exact diagonal > left > up
-// predecessor order.  norm: FABX_NORM_PATH / FABX_NORM_NONE.
+// predecessor order.  norm: FABX_NORM_PATH / FABX_NORM_NONE.  has_long: some
+// item has more than 64 frames (rows then go in chunks of 64).
 void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const GroupTables &g,
-               const ItemTables &it, int norm, float *p32);
+               const ItemTables &it, int norm, bool has_long, float *p32);
 
 // --- k_fused.hip (BF16 form)
 struct FusedPlan {
@@ -167,9 +168,18 @@ void recount(hipStream_t s, const CellDev *cells, const int32_t *rows, const uns
 // FP64 distance of each listed pair slot from the raw features (unit vectors
 // by division by the sequential-sum norm, cosine as a sequential sum, acos or
 // the half-chord atan2 form near |cos| = 1, DTW with diagonal > left > up).
+// has_long: the task has items of more than 64 frames (DTW mode); their pairs
+// go through the tiled kernel of long_dtw.
 void recheck_fp64(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
                   const ItemTables &it, const int64_t *list, const unsigned int *count,
-                  int64_t max_count, int mode, int norm, double *p64);
+                  int64_t max_count, int mode, int norm, bool has_long, double *p64);
+// The same FP64 DTW for the listed slots whose pair has an item of more than
+// 64 frames (up to FABX_MAX_ITEM_FRAMES); others are skipped.  count: device
+// count of listed slots, or null for max_count.  p32 and flags (may be null)
+// also receive the value and 0 (robust, unmarked).
+void long_dtw(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
+              const ItemTables &it, const int64_t *list, const unsigned int *count, int64_t max_count, int norm,
+              double *p64, float *p32, uint8_t *flags);
 
 }  // namespace kern
 }  // namespace fabx

@@ -274,10 +274,11 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     p.dtw_norm = o.dtw_norm;
     p.distance = o.distance;
     // the raw DTW cost (FABX_NORM_NONE) sums up to 2 L - 1 frame distances
-    // (L: the longest item), each with its own error: its default margin is
-    // that many times the per-distance one
+    // (L: the longest item the BF16 kernels take; pairs of longer items are
+    // computed in FP64), each with its own error: its default margin is that
+    // many times the per-distance one
     const double path_cells = p.mode == FABX_MODE_DTW && p.dtw_norm == FABX_NORM_NONE
-                                  ? double(2 * std::max(ds.max_len, 1) - 1) : 1.0;
+                                  ? double(2 * std::clamp(ds.max_len, 1, kFusedRowFrames) - 1) : 1.0;
     p.margin = o.margin < 0 ? kMarginK / std::sqrt(double(ds.dim)) * path_cells : o.margin;
     p.delta = o.delta < 0 ? kDeltaK / std::sqrt(double(ds.dim)) : o.delta;
     p.keep_pairs = o.keep_pairs != 0;
@@ -289,6 +290,8 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     p.fused = FusedConfig{o.fused_cols, o.fused_blocks_per_cu};  // cols 0: the tuning table
     if (p.mode == FABX_MODE_DTW && ds.max_len > FABX_MAX_ITEM_FRAMES)
         fail(FABX_EINVAL, "an item is longer than FABX_MAX_ITEM_FRAMES frames (DTW mode)");
+    if (p.mode == FABX_MODE_DTW && p.fused.cols >= kStreamMinCols && ds.max_len > kFusedRowFrames)
+        fail(FABX_EINVAL, "the streaming DTW kernel (fused_cols >= 512) takes items of at most 64 frames");
     if (ds.dim > 2048) fail(FABX_EINVAL, "feature dim above 2048 is not supported");
     return p;
 }
@@ -300,7 +303,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
     int64_t b = rows * dim_pad * (bf16 ? 2 : 4) + rows * 4;
     if (p.mode == FABX_MODE_DTW && !bf16) b += std::min(t.n_dmat, plain_dmat_cells()) * 4;
     b += t.n_pair_slots * 4;
-    if (bf16) b += t.n_pair_slots * (1 + 8 + 8);
+    if (bf16) b += t.n_pair_slots * (1 + 8 + 8) + int64_t(t.long_slots.size()) * 8;
     b += int64_t(t.cells.size()) * (8 + 32) + int64_t(t.units.size()) * 4 + t.sum_nx * 8 +
          int64_t(t.items.size()) * 24;
     return b + (1 << 20);
@@ -385,6 +388,7 @@ struct DevPtrs {
     const int32_t *cb = nullptr, *g_cb0 = nullptr, *rb_cstart = nullptr;
     const int64_t *rb_unit_prefix = nullptr;
     const int64_t *tiles = nullptr;             // pooled: Gram tile prefix per group
+    const int64_t *long_slots = nullptr;        // BF16 DTW: slots of pairs with an item over 64 frames
     std::array<const int64_t *, 8> strips{};    // plain DTW: group, slot0, row0, nrows, col0, ncols, base, tiles
     void *xn = nullptr;
     float *rinv = nullptr, *dmat = nullptr, *p32 = nullptr;
@@ -398,13 +402,18 @@ struct DevPtrs {
 
 // Byte offsets of the pooled tile prefix or of the plain form's strip columns.
 struct PlanLayout {
-    size_t tiles = 0;
+    size_t tiles = 0, long_slots = 0;
     std::array<size_t, 8> strips{};
-    bool has_tiles = false, has_strips = false;
+    bool has_tiles = false, has_strips = false, has_long = false;
 };
 
-PlanLayout add_plan(Packer &pk, const std::vector<int64_t> &tiles, const PlainPlan &strips) {
+PlanLayout add_plan(Packer &pk, const std::vector<int64_t> &tiles, const PlainPlan &strips,
+                    const std::vector<int64_t> &long_slots) {
     PlanLayout L;
+    if (!long_slots.empty()) {
+        L.long_slots = pk.add(long_slots);
+        L.has_long = true;
+    }
     if (!tiles.empty()) {
         L.tiles = pk.add(tiles);
         L.has_tiles = true;
@@ -420,6 +429,7 @@ PlanLayout add_plan(Packer &pk, const std::vector<int64_t> &tiles, const PlainPl
 
 void set_plan(DevPtrs &d, const char *base, const PlanLayout &L) {
     if (L.has_tiles) d.tiles = reinterpret_cast<const int64_t *>(base + L.tiles);
+    if (L.has_long) d.long_slots = reinterpret_cast<const int64_t *>(base + L.long_slots);
     if (L.has_strips)
         for (size_t k = 0; k < 8; ++k) d.strips[k] = reinterpret_cast<const int64_t *>(base + L.strips[k]);
 }
@@ -509,7 +519,7 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
             kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.dmat, euclid ? 1 : 0);
             const kern::PlainStrips ps{sp[0] + k0, sp[1] + k0, sp[2] + k0, sp[6] + k0, ns,
                                        strips.slot0[size_t(b.second)] - strips.slot0[k0]};
-            kern::dtw_plain(stream, d.dmat, ps, gt, it, p.dtw_norm, d.p32);
+            kern::dtw_plain(stream, d.dmat, ps, gt, it, p.dtw_norm, t.max_len > kFusedRowFrames, d.p32);
         }
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw && fcfg.cols >= kStreamMinCols) {
@@ -525,6 +535,9 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
                            cplan->rb_unit_prefix.back(), fcfg.cols, fcfg.blocks_per_cu, ds.ctx->n_cu};
         kern::fused_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt, it, fp, p.dtw_norm,
                          float(p.delta), d.p32, d.flags, nonrobust_n, unit_ctr);
+        // pairs with an item over 64 frames: FP64 from the raw features
+        kern::long_dtw(stream, ds.features, ds.dtype, dim, gt, it, d.long_slots, nullptr,
+                       int64_t(t.long_slots.size()), p.dtw_norm, d.p64, d.p32, d.flags);
         st.computed_dtw_cells = cplan->cells;
     } else if (!bf16) {
         const kern::GramSegments seg{gt.item0, gt.n_items, gt.item0, gt.n_items, gt.pair_base, d.tiles, G,
@@ -545,7 +558,7 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
     if (bf16) {
         kern::collect_marked(stream, d.flags, t.n_pair_slots, d.recheck_list, marked_n, t.n_pair_slots, recount_n);
         kern::recheck_fp64(stream, ds.features, ds.dtype, dim, gt, it, d.recheck_list, marked_n, t.n_pair_slots,
-                           p.mode, p.dtw_norm, d.p64);
+                           p.mode, p.dtw_norm, dtw && t.max_len > kFusedRowFrames, d.p64);
         kern::recount(stream, d.cells, d.recount_list, recount_n, t.sum_nx, gt, d.p32, d.p64, d.flags,
                       d.half_units);
     }
@@ -646,6 +659,8 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     ColPlan *cplan = nullptr;
     if (dtw && bf16) {
         fcfg = p.fused.cols > 0 ? p.fused : ds.ctx->tuner.lookup(tune_key(t, p));
+        if (fcfg.cols >= kStreamMinCols && t.max_len > kFusedRowFrames)
+            fail(FABX_EINVAL, "the streaming DTW kernel (fused_cols >= 512) takes items of at most 64 frames");
         cplan = &col_plan(t, fcfg.cols);
         res->fused = fcfg;
         st.fused_cols = fcfg.cols;
@@ -683,9 +698,11 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     DevBuf &plan_d = pend->plan_d;
     plan_d.pool = pool;
     DevPtrs d;
-    if (pooled || plain_dtw) {
+    static const std::vector<int64_t> no_slots;
+    const std::vector<int64_t> &long_slots = dtw && bf16 ? t.long_slots : no_slots;
+    if (pooled || plain_dtw || !long_slots.empty()) {
         Packer pp;
-        const PlanLayout pl = add_plan(pp, tiles, strips);
+        const PlanLayout pl = add_plan(pp, tiles, strips, long_slots);
         pp.upload(plan_d, ds.ctx->staging, ds.ctx->copy_stream, stream);
         set_plan(d, plan_d.as<char>(), pl);
     }
@@ -821,6 +838,8 @@ void score_in_scratch(TaskImpl &t, const ScoreParams &p, char *base, size_t cap,
     ColPlan *cplan = nullptr;
     if (dtw && bf16) {
         fcfg = p.fused.cols > 0 ? p.fused : ds.ctx->tuner.lookup(tune_key(t, p));
+        if (fcfg.cols >= kStreamMinCols && t.max_len > kFusedRowFrames)
+            fail(FABX_EINVAL, "the streaming DTW kernel (fused_cols >= 512) takes items of at most 64 frames");
         cplan = &col_plan(t, fcfg.cols);
         st.fused_cols = fcfg.cols;
         st.fused_blocks_per_cu = fcfg.blocks_per_cu;
@@ -833,7 +852,8 @@ void score_in_scratch(TaskImpl &t, const ScoreParams &p, char *base, size_t cap,
     auto layout = [&](const PlainPlan &strips, Packer &pk, TableLayout &tl, PlanLayout &pl,
                       std::array<std::vector<int64_t>, 5> &gcols) {
         tl = add_task_tables(t, cplan, pk, gcols);
-        pl = add_plan(pk, tiles, strips);
+        static const std::vector<int64_t> no_slots;  // the packer keeps pointers: no temporaries
+        pl = add_plan(pk, tiles, strips, dtw && bf16 ? t.long_slots : no_slots);
         const size_t tables = (pk.total + 255) & ~size_t(255);
         return tables + workspace_sizes(t, p, strips, stream_k).total_aligned();
     };

@@ -454,18 +454,24 @@ void walk_groups(const WalkCtx &w, int64_t s_begin, int64_t s_end, Sink &out) {
 }
 
 // Whole items of group gi packed, in task order, into blocks of at most
-// `limit` frames (at least one item per block: an item above the limit is only
-// legal in pooled mode, which does not use these blocks).  Writes [n][4] =
-// group, first item, n items, n frames to `out` if given; returns the count.
+// `limit` frames.  Items of more than kFusedRowFrames frames are left out (a
+// block ends before such an item and the next starts after it): their pairs
+// are computed by the FP64 long-item kernel.  Writes [n][4] = group, first
+// item, n items, n frames to `out` if given; returns the count.
 int32_t pack_blocks(const TaskImpl &t, int64_t gi, int limit, int32_t *out) {
     const Group &g = t.groups[size_t(gi)];
     int32_t nb = 0;
     int64_t k = g.item0;
     const int64_t end = g.item0 + g.n_items;
     while (k < end) {
+        if (t.item_len[size_t(k)] > kFusedRowFrames) {
+            ++k;
+            continue;
+        }
         const int32_t first = int32_t(k);
         int32_t frames = 0, cnt = 0;
-        while (k < end && (cnt == 0 || frames + t.item_len[size_t(k)] <= limit)) {
+        while (k < end && t.item_len[size_t(k)] <= kFusedRowFrames &&
+               (cnt == 0 || frames + t.item_len[size_t(k)] <= limit)) {
             frames += t.item_len[size_t(k)];
             ++cnt;
             ++k;
@@ -626,6 +632,22 @@ void plan_blocks(TaskImpl &t) {
             pack_blocks(t, gi, kFusedRowFrames, t.rb.data() + 4 * size_t(t.g_rb0[size_t(gi)]));
     });
     t.fused_cells = col_plan(t, Tuner::default_config().cols).cells;
+    // pair slots with an item of more than kFusedRowFrames frames, both
+    // orientations, (x, x) left out: the FP64 long-item kernel's list
+    t.long_slots.clear();
+    if (t.max_len > kFusedRowFrames) {
+        for (const Group &g : t.groups) {
+            const int64_t n = g.n_items;
+            for (int64_t a = 0; a < n; ++a) {
+                const bool la = t.item_len[size_t(g.item0 + a)] > kFusedRowFrames;
+                for (int64_t b = a + 1; b < n; ++b) {
+                    if (!la && t.item_len[size_t(g.item0 + b)] <= kFusedRowFrames) continue;
+                    t.long_slots.push_back(g.pair_base + a * n + b);
+                    t.long_slots.push_back(g.pair_base + b * n + a);
+                }
+            }
+        }
+    }
 }
 
 std::shared_ptr<TaskImpl> build_task(const std::shared_ptr<DatasetImpl> &ds, int32_t on,

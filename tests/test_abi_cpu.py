@@ -167,12 +167,22 @@ def test_score_opts_layout_and_defaults():
     assert (o2.fused_cols, o2.fused_blocks_per_cu) == (256, 2)
 
 
-def test_long_items_rejected_in_dtw_mode():
+def test_item_length_limits_in_dtw_mode():
+    """Items above FABX_MAX_ITEM_FRAMES are rejected in DTW mode; items of
+    65..FABX_MAX_ITEM_FRAMES frames pass the option checks except with the
+    streaming kernel (fused_cols >= 512), which takes at most 64 frames."""
     attrs = np.array([[0], [0], [1]], np.int32)
-    t = _host_task(attrs, 0, [], [], lengths=np.array([3, 65, 2]))
+    t = _host_task(attrs, 0, [], [], lengths=np.array([3, L.FABX_MAX_ITEM_FRAMES + 1, 2]))
     with pytest.raises(fx.FabxError) as e:
         t.score(mode="dtw")
-    assert e.value.code == L.FABX_EINVAL
+    assert e.value.code == L.FABX_EINVAL and "FABX_MAX_ITEM_FRAMES" in str(e.value)
+    t = _host_task(attrs, 0, [], [], lengths=np.array([3, 65, 2]))
+    with pytest.raises(fx.FabxError) as e:
+        t.score(mode="dtw", fused_cols=512)
+    assert e.value.code == L.FABX_EINVAL and "at most 64 frames" in str(e.value)
+    with pytest.raises(fx.FabxError) as e:   # past the option checks: no device here
+        t.score(mode="dtw")
+    assert e.value.code == L.FABX_EINVAL and "no device" in str(e.value)
 
 
 def test_null_handles():

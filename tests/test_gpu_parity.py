@@ -179,6 +179,59 @@ def test_single_frame_items_and_long_items():
     check(w1, precision="fp32")
 
 
+# Items of more than 64 frames (up to FABX_MAX_ITEM_FRAMES): in the BF16 form
+# every pair with such an item is computed in FP64 (tiled DTW, rows in chunks
+# of 64 handing their last row to the next chunk), so its FP32 copy is the
+# FP64 value rounded once; the plain FP32 form runs its DTW in row chunks.
+@pytest.mark.parametrize("precision,norm", [("bf16", "path"), ("bf16", "none"), ("fp32", "path"),
+                                            ("fp32", "none")])
+def test_long_items_match_oracle(precision, norm):
+    w = workloads.batched_c4(n_groups=10, size_lo=5, size_hi=16, len_lo=1, len_hi=200, dim=64,
+                             centroid_std=0.3, seed=31)
+    lens = np.diff(w.offsets)
+    assert (lens > 64).sum() >= 10 and (lens <= 64).sum() >= 10 and lens.max() > 128
+    tol = {("fp32", "path"): 2e-5, ("fp32", "none"): 2e-3}.get((precision, norm))
+    t, res, orc = check(w, precision=precision, norm=norm, pair_tol=tol)
+    xs, ys, want = all_oracle_pairs(orc)
+    f32, fl, _ = res.pairs(xs, ys)
+    long_pair = (lens[xs] > 64) | (lens[ys] > 64)
+    assert long_pair.sum() > 100
+    if precision == "bf16":
+        # FP64 values rounded once to FP32, and never flagged non-robust
+        err = np.abs(f32[long_pair].astype(np.float64) - want[long_pair])
+        assert err.max() <= 2.0 ** -23 * np.maximum(np.abs(want[long_pair]), 1.0).max()
+        assert not (fl[long_pair] & 1).any()
+
+
+def test_long_items_at_the_limit_and_beyond():
+    """An item of exactly FABX_MAX_ITEM_FRAMES frames (16 row chunks) scores like
+    the oracle; one frame more is EINVAL."""
+    _say("items of FABX_MAX_ITEM_FRAMES frames")
+    rng = np.random.default_rng(41)
+    lens = np.array([L.FABX_MAX_ITEM_FRAMES, 3, 70, 1, L.FABX_MAX_ITEM_FRAMES - 1, 20], np.int64)
+    dim = 16
+    cent = rng.standard_normal((2, dim))
+    label = np.array([0, 1, 0, 1, 0, 1], np.int32)
+    frames = [cent[l] + 0.8 * rng.standard_normal((n, dim)) for l, n in zip(label, lens)]
+    feats = torch.tensor(np.concatenate(frames).astype(np.float32))
+    off = np.zeros(len(lens) + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    attrs = np.stack([label, np.zeros(6, np.int32)], axis=1)
+    w = workloads.Workload("long-limit", feats, off, attrs, ["label", "ctx"], 0, [1], [])
+    for precision in ("bf16", "fp32"):
+        check(w, precision=precision, pair_tol=(2e-5 if precision == "fp32" else None), levels=False)
+    lens2 = lens.copy()
+    lens2[0] += 1
+    frames[0] = np.concatenate([frames[0], frames[0][:1]])
+    off2 = np.zeros(len(lens2) + 1, np.int64)
+    off2[1:] = np.cumsum(lens2)
+    w2 = workloads.Workload("too-long", torch.tensor(np.concatenate(frames).astype(np.float32)), off2, attrs,
+                            ["label", "ctx"], 0, [1], [])
+    with pytest.raises(fx.FabxError) as e:
+        gpu_score(w2)
+    assert e.value.code == L.FABX_EINVAL
+
+
 def test_exact_copies_tie_at_one_half():
     _say("exact copies")
     rng = np.random.default_rng(3)
@@ -1116,6 +1169,31 @@ def test_server_small_job_passes_a_waiting_large_one():
           f"p99 {st['p99_queue_ms']:.1f} ms, mean run {st['mean_run_ms']:.1f} ms", flush=True)
     assert st["p50_queue_ms"] < 0.25 * t_big
     assert st["p99_queue_ms"] > 0.25 * t_big   # the second large job did wait
+    srv.close()
+
+
+def test_server_device_memory_steady_over_waves():
+    """Finished jobs give their device tables and workspace back to the
+    context's pool: a second wave of the same jobs runs in the memory the first
+    one left (device free memory unchanged), and nothing stays counted as in
+    use once the outcomes are fetched."""
+    _say("server: device memory over two waves of jobs")
+    ws = [workloads.serving_job(40 + k, n_items=1500 + 300 * k, dim=(256, 512, 768)[k % 3], across=bool(k % 2),
+                                device="cuda") for k in range(8)]
+    dss = [fx.Dataset(ctx(), w.features, w.offsets, w.attrs) for w in ws]
+    srv = fx.Server(ctx(), hbm_budget_bytes=24 << 30, n_streams=1)   # one job at a time: same peak each wave
+    free = []
+    for wave in range(3):
+        ids = [srv.submit(ds, w.on, w.by, w.across) for w, ds in zip(ws, dss)]
+        for jid in ids:
+            srv.wait(jid)
+        torch.cuda.synchronize()
+        st = srv.stats
+        assert st["hbm_in_use"] == 0 and st["running"] == 0 and st["queued"] == 0
+        free.append(torch.cuda.mem_get_info()[0])
+        print(f"  wave {wave}: device free {free[-1] / 2**30:.3f} GiB, high water "
+              f"{st['hbm_high_water'] / 2**30:.3f} GiB", flush=True)
+    assert free[2] == free[1]
     srv.close()
 
 

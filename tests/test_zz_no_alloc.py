@@ -52,6 +52,22 @@ def test_noalloc_equals_score_on_two_calls(mode, precision, norm):
         assert 0 < st["workspace_bytes"] <= L.FABX_NOALLOC_SCRATCH_BYTES
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_noalloc_with_items_over_64_frames(precision):
+    """Pairs with an item of more than 64 frames take the FP64 kernel (BF16
+    form) or row chunks (FP32 form); their slot list lives in the scratch too."""
+    w = workloads.batched_c4(n_groups=10, size_lo=5, size_hi=16, len_lo=1, len_hi=200, dim=64,
+                             centroid_std=0.3, seed=31)
+    small = workloads.plain_c1(centroid_std=0.15, seed=2)
+    for wl in (w, small):
+        _say(f"noalloc long items {precision} {wl.name} n_items={wl.n_items}")
+        ds, t = _task(wl)
+        ref = t.score(precision=precision)
+        got, st = fx.fabx_score_noalloc(t.h, fx.make_opts(precision=precision), len(t))
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.half_units)
+
+
 def test_noalloc_rejects_a_task_beyond_the_scratch():
     _say("noalloc: task over the scratch limit")
     w = workloads.within_c2(n_items=30000, dim=768, centroid_std=0.1, seed=8)
