@@ -279,13 +279,17 @@ def serving_stream(fx, ctx, torch, workloads, n_jobs, seed=4, load=0.7, n_stream
             "late_arrivals": late, "results_equal_alone": bool(same)}
 
 
-def cpu_baseline(oracle, w, target_seconds=15.0, seed=0):
+def cpu_baseline(oracle, fx, w, target_seconds=15.0, seed=0):
     """The FP64 oracle on the host cores, on a bounded sample of whole BY groups
     of the same workload: groups in a seeded random order, taken while the
     estimated oracle time stays within `target_seconds` (groups whose estimate
-    alone exceeds half of it are passed over).  The oracle's time per unit of
-    cost (squared frame count of a group times dim) is measured first on the
-    smallest groups.  Only the sampled groups' items are handed to the oracle."""
+    alone exceeds half of it are passed over).  A group's oracle time has two
+    parts, its frame distances and DTW (squared frame count times dim) and its
+    triplet comparisons; a probe on the smallest groups gives the time per unit
+    of each, each charged with the whole probe time, and a group's estimate is
+    the larger of the two, so big groups are not underestimated.  The triplets
+    per group come from a host-only task of the library (no device work).  Only
+    the sampled groups' items are handed to the oracle."""
     by = list(w.by)
     keys = [tuple(r) for r in w.attrs[:, by].tolist()] if by else [()] * w.n_items
     lens = np.diff(w.offsets)
@@ -295,6 +299,12 @@ def cpu_baseline(oracle, w, target_seconds=15.0, seed=0):
         frames[k] = frames.get(k, 0) + int(lens[i])
     groups = sorted(members)
     cost = {g: float(frames[g]) ** 2 * w.dim for g in groups}
+    host = fx.Task(fx.Dataset(fx.Context(-1), None, w.offsets, w.attrs), w.on, w.by, w.across)
+    ckeys, (nt, _) = host.keys, host.sizes
+    trip = {g: 0.0 for g in groups}
+    for row, n in zip(ckeys[:, 2:2 + len(by)].tolist(), nt.tolist()):
+        trip[tuple(row)] += float(n)
+    del host
 
     def run(take):
         items = np.concatenate([np.asarray(members[g], np.int64) for g in take])
@@ -313,12 +323,14 @@ def cpu_baseline(oracle, w, target_seconds=15.0, seed=0):
         if dt >= 0.5 or n_probe >= len(by_cost):
             break
         n_probe *= 2
-    rate = dt / sum(cost[g] for g in probe)   # seconds per cost unit
+    rate_d = dt / sum(cost[g] for g in probe)                  # seconds per distance-cost unit
+    rate_t = dt / max(sum(trip[g] for g in probe), 1.0)        # seconds per triplet
+    est_of = {g: max(cost[g] * rate_d, trip[g] * rate_t) for g in groups}
     log(f"cpu baseline: probe of {len(probe)} small groups took {dt:.2f} s")
     order = [groups[k] for k in np.random.default_rng(seed).permutation(len(groups))]
     take, est = [], 0.0
     for g in order:
-        e = cost[g] * rate
+        e = est_of[g]
         if e > 0.5 * target_seconds:
             continue
         if est + e > target_seconds:
@@ -328,13 +340,13 @@ def cpu_baseline(oracle, w, target_seconds=15.0, seed=0):
     r, dt = run(take)
     n_trip = int(r.n_triplets.sum())
     model, ncpu = cpu_info()
-    whole_s = rate * sum(cost.values())
+    whole_s = sum(est_of.values())
     log(f"cpu baseline: {len(take)} groups took {dt:.1f} s (estimated {est:.1f} s)")
     return {"value": n_trip / dt, "unit": "triplets/s", "cores": oracle.num_threads(), "kind": "oracle",
             "cpu_model": model, "nproc": ncpu,
             "sample": f"{len(take)} of {len(groups)} BY groups in seeded random order ({len(r.cells)} cells, "
                       f"{n_trip} triplets) of the same workload, FP64 DTW + scoring, {dt:.1f} s; the whole "
-                      f"workload would take about {whole_s:.0f} s at the probe's rate"}
+                      f"workload would take about {whole_s:.0f} s by the probe's estimate"}
 
 
 def committed_traffic(kernel_file, profile_file, cols, blocks_per_cu):
@@ -554,7 +566,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cpu = cpu_baseline(oracle, w)
+        cpu = cpu_baseline(oracle, fx, w)
         log(f"cpu baseline: {cpu}")
     wl_cfg = {"workload": wl_desc, "cells": st0["n_cells"], "triplets": n_trip,
               "dtw_cells": st0["dtw_cells"], "dtw_cells_unordered": st0["dtw_cells_sym"],

@@ -107,6 +107,9 @@ constexpr int kFusedRowFrames = 64;
 constexpr int kSortedMaxB = 4096;      // largest |B| counted from sorted rows (sorted in LDS)
 constexpr int kFusedColFrames = 128;  // default: tile kernel, 128-frame column blocks (the other is 256)
 constexpr int kStreamMinCols = 512;   // cols at or above this select the stream kernel
+// Units of a group with at least kBandMinCols column blocks go in bands of
+// kBandRows row blocks (see ColPlan); smaller groups fit L2 as they are.
+constexpr int kBandRows = 16, kBandMinCols = 24;
 
 // Launch choices of the fused kernel: column block width (128 or 256 frames)
 // and grid (blocks_per_cu > 0: a persistent grid of that many blocks per CU;
@@ -214,7 +217,7 @@ struct TableLayout {
     size_t item_src = 0, item_len = 0, item_dst = 0, item_group = 0;
     std::array<size_t, 5> g{};  // item0, n_items (+ sentinel), frame0, n_frames, pair_base (+ total)
     size_t cells = 0, units = 0, rb = 0, g_rb0 = 0;
-    std::array<size_t, 4> plan{};  // cb, rb_unit_prefix, g_cb0, rb_cstart of `plan_cols`
+    std::array<size_t, 5> plan{};  // cb, unit_prefix, g_cb0, rb_cstart, band_rb of `plan_cols`
     int plan_cols = 0;             // 0: no column plan in the buffer
 };
 
@@ -252,7 +255,7 @@ struct ResultImpl;
 //    they make with the task's row blocks (below).
 //  cols 512 / 1024 / 2048 (stream kernel): each row block's column stream
 //    (the group's frames from the row block's first frame on) cut into
-//    segments of about `cols` frames; only rb_unit_prefix (segments per row
+//    segments of about `cols` frames; only unit_prefix (segments per row
 //    block) and cells are used.
 struct ColPlan {
     int cols = 0;
@@ -263,14 +266,23 @@ struct ColPlan {
     // symmetric, so the units wholly below its diagonal are not computed: the
     // kernel writes each pair (x, y) with x before y, or x = y, at both (x, y)
     // and (y, x).  Per row block: its first kept column block (counted in the
-    // group) and the prefix of kept units over all row blocks.
+    // group).
     hvec<int32_t> rb_cstart;             // [n_rb]
-    hvec<int64_t> rb_unit_prefix;        // [n_rb + 1]
+    // Order of the units (tile kernel): bands of up to kBandRows consecutive
+    // row blocks of one group (band b = row blocks [band_rb[b], band_rb[b+1])),
+    // each band's units by column block, then row block, from its first row
+    // block's first kept column block on, so that the units in flight share a
+    // few row and column blocks in L2.  A unit whose column block comes before
+    // its own row block's first kept one is skipped by the kernel.
+    // unit_prefix: units per band, prefix; stream kernel: segments per row
+    // block, prefix (band_rb empty).
+    hvec<int32_t> band_rb;               // [n_bands + 1]
+    hvec<int64_t> unit_prefix;           // [n_bands + 1], stream kernel [n_rb + 1]
     int64_t cells = 0;                   // frame pairs the kept units cover (stream kernel: lanes x
                                          // stream columns, 64 per column)
     DevBuf dev;                          // device copy of the above, made on first use
-    const int32_t *d_cb = nullptr, *d_g_cb0 = nullptr, *d_rb_cstart = nullptr;
-    const int64_t *d_rb_unit_prefix = nullptr;
+    const int32_t *d_cb = nullptr, *d_g_cb0 = nullptr, *d_rb_cstart = nullptr, *d_band_rb = nullptr;
+    const int64_t *d_unit_prefix = nullptr;
 };
 
 struct TaskImpl {

@@ -220,10 +220,11 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                                                   const int64_t *__restrict__ item_dst,
                                                   const int32_t *__restrict__ rb,
                                                   const int32_t *__restrict__ cb,
-                                                  const int64_t *__restrict__ rb_unit_prefix,
+                                                  const int64_t *__restrict__ unit_prefix,
+                                                  const int32_t *__restrict__ band_rb,
                                                   const int32_t *__restrict__ g_cb0,
                                                   const int32_t *__restrict__ rb_cstart,
-                                                  int64_t n_rb, int64_t n_units, int64_t grid_q,
+                                                  int64_t n_bands, int64_t n_units, int64_t grid_q,
                                                   float delta, float *__restrict__ p32,
                                                   uint8_t *__restrict__ flags,
                                                   unsigned int *__restrict__ nonrobust_n,
@@ -244,14 +245,15 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const int64_t xcd = blockIdx.x % 8, n_m = gridDim.x / 8;
     const bool take = n_m < grid_q;
     __shared__ int64_t taken_s;
-    // next unit index for this block: read by every thread after a barrier; the
-    // write happens after the unit's last barrier, when all threads have read
-    // the previous value
+    // next unit index for this block: written by thread 0, read by every
+    // thread between two barriers (a skipped unit has no barrier of its own)
     auto next = [&](int64_t j) -> int64_t {
         if (!take) return j + n_m;
         if (threadIdx.x == 0) taken_s = int64_t(atomicAdd(unit_ctr + xcd, 1u));
         __syncthreads();
-        return taken_s;
+        const int64_t v = taken_s;
+        __syncthreads();
+        return v;
     };
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -259,11 +261,16 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const int64_t unit = xcd * grid_q + j;
     if (unit >= n_units) break;  // uniform across the block; later units are larger
 
-    // the unit's row block, its group, and its column block (the row block's
-    // units are its group's column blocks from rb_cstart on)
-    const int64_t rbi = dev::find_segment_wave(rb_unit_prefix, n_rb, unit);
+    // the unit's band, row block, group and column block: within a band,
+    // column blocks from the band's first kept one on, row blocks fastest
+    const int64_t bi = dev::find_segment_wave(unit_prefix, n_bands, unit);
+    const int rb0 = band_rb[bi], band_rows = band_rb[bi + 1] - rb0;
+    const int64_t local = unit - unit_prefix[bi];
+    const int64_t rbi = rb0 + local % band_rows;
+    const int c_local = rb_cstart[rb0] + int(local / band_rows);
+    if (c_local < rb_cstart[rbi]) continue;  // uniform: wholly below the group's diagonal
     const int64_t g = rb[4 * rbi];
-    const int cbi = g_cb0[g] + rb_cstart[rbi] + int(unit - rb_unit_prefix[rbi]);
+    const int cbi = g_cb0[g] + c_local;
     const int r_item0 = rb[4 * rbi + 1], r_nitems = rb[4 * rbi + 2], r_frames = rb[4 * rbi + 3];
     const int c_item0 = cb[4 * cbi + 1], c_nitems = cb[4 * cbi + 2], c_frames = cb[4 * cbi + 3];
     const int64_t r_frame0 = item_dst[r_item0], c_frame0 = item_dst[c_item0];
@@ -555,13 +562,13 @@ void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_
     const dim3 grid(unsigned(8 * per_xcd)), block(256);
     if (norm == FABX_NORM_PATH)
         hipLaunchKernelGGL((k_fused<kC, true>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
-                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.rb_unit_prefix, plan.g_cb0,
-                           plan.rb_cstart, plan.n_rb, plan.n_units, q, delta, p32, flags, nonrobust_n,
+                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.band_rb,
+                           plan.g_cb0, plan.rb_cstart, plan.n_bands, plan.n_units, q, delta, p32, flags, nonrobust_n,
                            unit_ctr);
     else
         hipLaunchKernelGGL((k_fused<kC, false>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
-                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.rb_unit_prefix, plan.g_cb0,
-                           plan.rb_cstart, plan.n_rb, plan.n_units, q, delta, p32, flags, nonrobust_n,
+                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.band_rb,
+                           plan.g_cb0, plan.rb_cstart, plan.n_bands, plan.n_units, q, delta, p32, flags, nonrobust_n,
                            unit_ctr);
 }
 

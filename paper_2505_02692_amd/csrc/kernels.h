@@ -90,11 +90,14 @@ void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const Gr
 struct FusedPlan {
     const int32_t *rb;        // row blocks: [n_rb][4] = group, first item (task), n items, n frames
     const int32_t *cb;        // col blocks: same layout
-    const int64_t *rb_unit_prefix;  // per row block: prefix of its work units, n_rb + 1
+    const int64_t *unit_prefix; // per band: prefix of its work units, n_bands + 1
+    const int32_t *band_rb;     // band b = row blocks [band_rb[b], band_rb[b + 1]) of one group
     const int32_t *g_cb0;       // per group: first column block
-    const int32_t *rb_cstart;   // per row block: its first column block (counted in the group);
-                                // the units of a row block are its group's column blocks from there
-    int64_t n_rb;
+    const int32_t *rb_cstart;   // per row block: its first kept column block (counted in the group)
+    // A band's units: column block c (from its first row block's rb_cstart on)
+    // x its row blocks, row block fastest; a unit with c before its row block's
+    // rb_cstart is skipped.
+    int64_t n_bands;
     int64_t n_units;
     int cols;            // column block width the blocks were packed for: 128 or 256
     int blocks_per_cu;   // persistent grid of blocks_per_cu * n_cu blocks; 0: one block per unit

@@ -107,18 +107,19 @@ TableLayout add_task_tables(const TaskImpl &t, const ColPlan *plan, Packer &pk,
     L.rb = pk.add(t.rb);
     L.g_rb0 = pk.add(t.g_rb0);
     if (plan) {
-        L.plan = {pk.add(plan->cb), pk.add(plan->rb_unit_prefix), pk.add(plan->g_cb0),
-                  pk.add(plan->rb_cstart)};
+        L.plan = {pk.add(plan->cb), pk.add(plan->unit_prefix), pk.add(plan->g_cb0), pk.add(plan->rb_cstart),
+                  pk.add(plan->band_rb)};
         L.plan_cols = plan->cols;
     }
     return L;
 }
 
-void set_col_plan(ColPlan &cp, const DevBuf &buf, const std::array<size_t, 4> &o) {
+void set_col_plan(ColPlan &cp, const DevBuf &buf, const std::array<size_t, 5> &o) {
     cp.d_cb = Packer::at<int32_t>(buf, o[0]);
-    cp.d_rb_unit_prefix = Packer::at<int64_t>(buf, o[1]);
+    cp.d_unit_prefix = Packer::at<int64_t>(buf, o[1]);
     cp.d_g_cb0 = Packer::at<int32_t>(buf, o[2]);
     cp.d_rb_cstart = Packer::at<int32_t>(buf, o[3]);
+    cp.d_band_rb = Packer::at<int32_t>(buf, o[4]);
 }
 
 // Device pointers of the task tables in dv.blob (and of the column plan packed
@@ -386,7 +387,8 @@ struct DevPtrs {
     const CellDev *cells = nullptr;
     const int32_t *units = nullptr, *rb = nullptr, *item_group = nullptr;
     const int32_t *cb = nullptr, *g_cb0 = nullptr, *rb_cstart = nullptr;
-    const int64_t *rb_unit_prefix = nullptr;
+    const int32_t *band_rb = nullptr;
+    const int64_t *unit_prefix = nullptr;
     const int64_t *tiles = nullptr;             // pooled: Gram tile prefix per group
     const int64_t *long_slots = nullptr;        // BF16 DTW: slots of pairs with an item over 64 frames
     std::array<const int64_t *, 8> strips{};    // plain DTW: group, slot0, row0, nrows, col0, ncols, base, tiles
@@ -524,15 +526,16 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw && fcfg.cols >= kStreamMinCols) {
         kern::frame_info(stream, it, d.item_group, gt.item0, d.finfo);
-        const kern::StreamPlan sp{d.rb, d.rb_unit_prefix, int64_t(t.rb.size() / 4), cplan->rb_unit_prefix.back(),
+        const kern::StreamPlan sp{d.rb, d.unit_prefix, int64_t(t.rb.size() / 4), cplan->unit_prefix.back(),
                                   fcfg.cols, fcfg.blocks_per_cu, ds.ctx->n_cu};
         const uint32_t delta_q = uint32_t(std::ceil(p.delta * 65535.0));
         kern::stream_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, d.finfo, gt, it, sp,
                           p.dtw_norm, delta_q, d.p32, d.flags, nonrobust_n, unit_ctr);
         st.computed_dtw_cells = cplan->cells;
     } else if (dtw) {
-        kern::FusedPlan fp{d.rb, d.cb, d.rb_unit_prefix, d.g_cb0, d.rb_cstart, int64_t(t.rb.size() / 4),
-                           cplan->rb_unit_prefix.back(), fcfg.cols, fcfg.blocks_per_cu, ds.ctx->n_cu};
+        kern::FusedPlan fp{d.rb, d.cb, d.unit_prefix, d.band_rb, d.g_cb0, d.rb_cstart,
+                           int64_t(cplan->band_rb.size()) - 1, cplan->unit_prefix.back(), fcfg.cols,
+                           fcfg.blocks_per_cu, ds.ctx->n_cu};
         kern::fused_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt, it, fp, p.dtw_norm,
                          float(p.delta), d.p32, d.flags, nonrobust_n, unit_ctr);
         // pairs with an item over 64 frames: FP64 from the raw features
@@ -688,8 +691,8 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     }
     if (cplan && !cplan->d_cb) {  // another column width for an already uploaded task
         Packer pc;
-        const std::array<size_t, 4> o{pc.add(cplan->cb), pc.add(cplan->rb_unit_prefix), pc.add(cplan->g_cb0),
-                                      pc.add(cplan->rb_cstart)};
+        const std::array<size_t, 5> o{pc.add(cplan->cb), pc.add(cplan->unit_prefix), pc.add(cplan->g_cb0),
+                                      pc.add(cplan->rb_cstart), pc.add(cplan->band_rb)};
         cplan->dev.pool = pool;
         pc.upload(cplan->dev, ds.ctx->staging, ds.ctx->copy_stream, stream);
         set_col_plan(*cplan, cplan->dev, o);
@@ -733,7 +736,8 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
         d.cb = cplan->d_cb;
         d.g_cb0 = cplan->d_g_cb0;
         d.rb_cstart = cplan->d_rb_cstart;
-        d.rb_unit_prefix = cplan->d_rb_unit_prefix;
+        d.unit_prefix = cplan->d_unit_prefix;
+        d.band_rb = cplan->d_band_rb;
     }
     d.xn = ws.xn.ptr;
     d.rinv = ws.rinv.as<float>();
@@ -900,9 +904,10 @@ void score_in_scratch(TaskImpl &t, const ScoreParams &p, char *base, size_t cap,
     d.item_group = reinterpret_cast<const int32_t *>(at(tl.item_group));
     if (cplan) {
         d.cb = reinterpret_cast<const int32_t *>(at(tl.plan[0]));
-        d.rb_unit_prefix = reinterpret_cast<const int64_t *>(at(tl.plan[1]));
+        d.unit_prefix = reinterpret_cast<const int64_t *>(at(tl.plan[1]));
         d.g_cb0 = reinterpret_cast<const int32_t *>(at(tl.plan[2]));
         d.rb_cstart = reinterpret_cast<const int32_t *>(at(tl.plan[3]));
+        d.band_rb = reinterpret_cast<const int32_t *>(at(tl.plan[4]));
     }
     set_plan(d, base, pl);
     const WorkspaceSizes wz = workspace_sizes(t, p, strips, stream_k);
@@ -955,7 +960,8 @@ void release_device(TaskImpl &t) {
         cp->d_cb = nullptr;
         cp->d_g_cb0 = nullptr;
         cp->d_rb_cstart = nullptr;
-        cp->d_rb_unit_prefix = nullptr;
+        cp->d_unit_prefix = nullptr;
+        cp->d_band_rb = nullptr;
     }
     t.packed.reset();
 }

@@ -502,14 +502,12 @@ void cell_keys(const TaskImpl &t, int32_t *out) {
 // Kept work units of a column plan (see ColPlan): for each row block, the
 // first column block of its group that ends after the row block's first item
 // (a suffix of the group's column blocks; row blocks ascend, so one pointer
-// per group walks the column blocks), the prefix of kept units, and the frame
-// pairs they cover.
+// per group walks the column blocks), and the frame pairs they cover; then
+// the bands the units are ordered in, and the prefix of units over bands.
 void plan_units(const TaskImpl &t, ColPlan &cp) {
     const int64_t G = int64_t(t.groups.size());
     const size_t n_rb = t.rb.size() / 4;
     cp.rb_cstart.resize(n_rb);
-    cp.rb_unit_prefix.resize(n_rb + 1);
-    cp.rb_unit_prefix[0] = 0;
     const int64_t kGroups = group_chunk(G);
     const int n_gc = int((G + kGroups - 1) / kGroups);
     std::vector<int64_t> part_cells(static_cast<size_t>(std::max(n_gc, 1)), 0);
@@ -531,15 +529,30 @@ void plan_units(const TaskImpl &t, ColPlan &cp) {
                     ++k;
                 }
                 cp.rb_cstart[r0 + size_t(r)] = k;
-                cp.rb_unit_prefix[r0 + size_t(r) + 1] = nc - k;
                 cells += int64_t(rbe[3]) * suffix;
             }
         }
         part_cells[size_t(c)] = cells;
     });
-    for (size_t i = 0; i < n_rb; ++i) cp.rb_unit_prefix[i + 1] += cp.rb_unit_prefix[i];
     cp.cells = 0;
     for (int64_t v : part_cells) cp.cells += v;
+    // Bands: runs of kBandRows row blocks in groups of at least kBandMinCols
+    // column blocks, else one row block each.  A band's units are its rows x
+    // the column blocks from its first row block's first kept one (the least
+    // of the band's, as they ascend with the row block) to the group's last.
+    cp.band_rb.clear();
+    cp.unit_prefix.clear();
+    cp.unit_prefix.push_back(0);
+    for (int64_t gi = 0; gi < G; ++gi) {
+        const int32_t r0 = t.g_rb0[size_t(gi)], nr = t.g_nrb[size_t(gi)], nc = cp.g_ncb[size_t(gi)];
+        const int32_t rows_per_band = nc >= kBandMinCols ? kBandRows : 1;
+        for (int32_t r = 0; r < nr; r += rows_per_band) {
+            const int32_t rows = std::min(rows_per_band, nr - r);
+            cp.band_rb.push_back(r0 + r);
+            cp.unit_prefix.push_back(cp.unit_prefix.back() + int64_t(rows) * (nc - cp.rb_cstart[size_t(r0 + r)]));
+        }
+    }
+    cp.band_rb.push_back(int32_t(n_rb));
 }
 
 // Stream kernel: segments of about `cols` frames of each row block's column
@@ -549,8 +562,8 @@ void plan_stream(const TaskImpl &t, ColPlan &cp) {
     for (const Group &g : t.groups)
         if (g.n_items > 0xFFFFFF) fail(FABX_EINVAL, "a BY group holds more than 2^24 - 1 items");
     const size_t n_rb = t.rb.size() / 4;
-    cp.rb_unit_prefix.resize(n_rb + 1);
-    cp.rb_unit_prefix[0] = 0;
+    cp.unit_prefix.resize(n_rb + 1);
+    cp.unit_prefix[0] = 0;
     const int64_t kGroups = group_chunk(G);
     const int n_gc = int((G + kGroups - 1) / kGroups);
     std::vector<int64_t> part_cells(static_cast<size_t>(std::max(n_gc, 1)), 0);
@@ -562,13 +575,13 @@ void plan_stream(const TaskImpl &t, ColPlan &cp) {
             for (int32_t r = 0; r < t.g_nrb[size_t(gi)]; ++r) {
                 const int32_t *rbe = t.rb.data() + 4 * (r0 + size_t(r));
                 const int64_t S = g.frame0 + g.n_frames - t.item_dst[size_t(rbe[1])];
-                cp.rb_unit_prefix[r0 + size_t(r) + 1] = (S + cp.cols - 1) / cp.cols;
+                cp.unit_prefix[r0 + size_t(r) + 1] = (S + cp.cols - 1) / cp.cols;
                 cells += int64_t(kFusedRowFrames) * S;
             }
         }
         part_cells[size_t(c)] = cells;
     });
-    for (size_t i = 0; i < n_rb; ++i) cp.rb_unit_prefix[i + 1] += cp.rb_unit_prefix[i];
+    for (size_t i = 0; i < n_rb; ++i) cp.unit_prefix[i + 1] += cp.unit_prefix[i];
     cp.cells = 0;
     for (int64_t v : part_cells) cp.cells += v;
 }
