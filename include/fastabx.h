@@ -55,7 +55,7 @@ extern "C" {
 #define FABX_DTYPE_BF16 1
 
 #define FABX_DISTANCE_ANGULAR 0      /* theta(u, v) / pi, in [0, 1] */
-#define FABX_DISTANCE_EUCLIDEAN 1    /* |u - v| (FABX_PREC_FP32 only) */
+#define FABX_DISTANCE_EUCLIDEAN 1    /* |u - v| of the raw frames (or means) */
 
 #define FABX_MODE_DTW 0              /* align frames with DTW */
 #define FABX_MODE_POOLED 1           /* mean over time, one vector per item */
@@ -244,20 +244,27 @@ int fabx_task_cell_sizes(const fabx_task *task, int64_t *n_triplets, int32_t *ab
 /* ----------------------------------------------------------------- score */
 
 typedef struct fabx_score_opts {
-    int32_t distance;    /* FABX_DISTANCE_ANGULAR, or FABX_DISTANCE_EUCLIDEAN with
-                            FABX_PREC_FP32 (other precisions: FABX_EINVAL) */
+    int32_t distance;    /* FABX_DISTANCE_ANGULAR | FABX_DISTANCE_EUCLIDEAN.  The
+                            Euclidean BF16_RECHECK form takes the unit-vector cosine
+                            of the MFMA Gram tile and each frame's FP32 length:
+                            |u - v|^2 = (|u| - |v|)^2 + 2 |u| |v| (1 - cos); zero
+                            frames are legal there.  Not with the stream kernel
+                            (fused_cols >= 512: FABX_EINVAL). */
     int32_t mode;        /* FABX_MODE_DTW | FABX_MODE_POOLED */
     int32_t precision;   /* FABX_PREC_FP32 | FABX_PREC_BF16_RECHECK */
     int32_t dtw_norm;    /* FABX_NORM_PATH | FABX_NORM_NONE */
     double margin;       /* BF16_RECHECK: a comparison with |d(x,a) - d(x,b)| <= margin
                             is re-decided on FP64 distances; < 0 selects the default
-                            2e-2 / sqrt(dim), times 2 L - 1 (L: the dataset's longest
-                            item) for the raw DTW cost (FABX_NORM_NONE), a sum of up
-                            to 2 L - 1 frame distances */
+                            2e-2 / sqrt(dim), times 2 L - 1 (L: the longest item, at
+                            most 64) for the raw DTW cost (FABX_NORM_NONE), a sum of up
+                            to 2 L - 1 frame distances.  Euclidean: in units of the
+                            largest frame (or mean) length S, found on the device; the
+                            default is pi times the angular one (an angle error e
+                            moves a Euclidean frame distance by at most S e). */
     double delta;        /* BF16_RECHECK + PATH: cumulative-cost window within which
                             alternative DTW predecessors must agree on the path length,
                             else the pair is recomputed in FP64; < 0 selects the default
-                            4e-2 / sqrt(dim) */
+                            4e-2 / sqrt(dim) (Euclidean: pi times that, in units of S) */
     int32_t keep_pairs;  /* nonzero: keep the per-pair distances for fabx_result_pairs */
     int32_t fused_cols;  /* BF16 DTW launch choice: 128 or 256 = the tile kernel with
                             column blocks of that many frames; 512, 1024 or 2048 = the
@@ -351,8 +358,10 @@ typedef struct fabx_stats {
     double ms_recheck;          /* FP64 recheck + recount */
     double ms_host_setup;       /* host: work plans, table uploads, workspace (before the first kernel) */
     double ms_host_finish;      /* host: after the results reached the host, until fabx_score returns */
-    double margin;              /* near-tie margin used (BF16 form; 0 for FP32) */
-    double delta;               /* path-length window used (BF16 form, DTW; else 0) */
+    double margin;              /* near-tie margin used (BF16 form; 0 for FP32; Euclidean: in
+                                   units of the largest frame length) */
+    double delta;               /* path-length window used (BF16 form, DTW; else 0; the same
+                                   units as margin) */
     int32_t fused_cols;         /* fused kernel column block width used (BF16 DTW; else 0) */
     int32_t fused_blocks_per_cu;/* its grid: blocks per CU, 0 = one block per work unit */
     int64_t dtw_cells_sym;      /* sum over the unordered pairs {x, y} of which some cell needs

@@ -242,6 +242,7 @@ struct Workspace {
     DevBuf p64;         // F64 [n_pair_slots]
     DevBuf half_units;  // uint64 [n_cells], then the score's 64 counter bytes
     DevBuf finfo;       // uint32 [n_frames]: frame info of the stream kernel
+    DevBuf flen;        // F32 [rows]: frame (or mean) lengths (Euclidean BF16 form)
     DevBuf recheck_list, recount_list;
     size_t total() const;
     void release();

@@ -210,7 +210,12 @@ struct NormStage {
 // Row (within the 32 x 32 tile) of accumulator element i of this lane.
 __device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i / 4) + 4 * (lane / 32) + (i % 4); }
 
-template <int kC, bool kPath>
+// kEuclid: the Euclidean distance of the raw frames, from the same unit-vector
+// cosine and each frame's FP32 length (flen): |u - v|^2 = (|u| - |v|)^2 +
+// 2 |u| |v| (1 - cos).  A near-parallel element is stored with its sign bit
+// set (the DTW of a careful unit takes its magnitude and notes it), and delta
+// is in units of the largest frame length (*scale, FP32 bits).
+template <int kC, bool kPath, bool kEuclid>
 __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ xn,
                                                   const float *__restrict__ rinv, int dim_pad,
                                                   const int64_t *__restrict__ g_item0,
@@ -228,12 +233,16 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                                                   float delta, float *__restrict__ p32,
                                                   uint8_t *__restrict__ flags,
                                                   unsigned int *__restrict__ nonrobust_n,
-                                                  unsigned int *__restrict__ unit_ctr) {
+                                                  unsigned int *__restrict__ unit_ctr,
+                                                  const float *__restrict__ flen,
+                                                  const unsigned int *__restrict__ scale) {
     using T = Tile<kC>;
     constexpr int kDStride = T::kDStride, kFlagLen = T::kFlagLen;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kSmemBytes];
     __shared__ uint16_t colflag[4][kFlagLen];
     __shared__ __attribute__((aligned(16))) float norm_s[kRows + kC];  // row then column inverse norms
+    __shared__ __attribute__((aligned(16))) float len_s[kEuclid ? kRows + kC : 1];  // and lengths
+    if constexpr (kEuclid) delta *= __uint_as_float(*scale);
     __shared__ int near_s;  // the unit holds a near-parallel frame pair
     // XCD-aware order: the 8 XCDs take blocks round-robin, so XCD x works
     // through the contiguous unit range [x * grid_q, (x+1) * grid_q) (units of
@@ -277,8 +286,9 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
 
     if (threadIdx.x == 0) near_s = 0;  // read after the barriers of the Gram tile and the epilogue
     // 1. Gram tile
-    NormStage<kC> ns;
+    NormStage<kC> ns, ls;
     ns.load(rinv, r_frame0, r_frames, c_frame0, c_frames);
+    if constexpr (kEuclid) ls.load(flen, r_frame0, r_frames, c_frame0, c_frames);
     // column items before the row block's first item pair only with rows after
     // them, which other units write: their columns (the first c_skip of the
     // block) are not needed
@@ -287,7 +297,10 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     for (int k = 0; k < min(k_first, c_nitems); ++k) c_skip += item_len[c_item0 + k];
     f32x16 acc[2][T::kCT];
     gram_tile<kC>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, r_frame0, r_frames, c_frame0,
-                  c_frames, c_skip, acc, [&] { ns.store(norm_s); });
+                  c_frames, c_skip, acc, [&] {
+                      ns.store(norm_s);
+                      if constexpr (kEuclid) ls.store(len_s);
+                  });
 
     // 2. epilogue -> LDS distance tile (the staging buffers are dead now).  Only
     // the rows and column waves that hold frames are written; the DTW reads the
@@ -310,6 +323,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
         if (col0 >= c_frames || col0 + 32 <= c_skip) continue;
         const int col = col0 + lane % 32;
         const float rc = norm_s[kRows + col];
+        const float lc = kEuclid ? len_s[kRows + col] : 0.0f;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && r_frames <= 32) break;
@@ -319,8 +333,15 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             for (int i = 0; i < 16; ++i) {
                 const int r = 32 * h + acc_row(i, lane);
                 const float cs = fminf(fmaxf(acc[h][ct][i] * norm_s[r] * rc, -1.0f), 1.0f);
-                cmax = fmaxf(cmax, 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs));
-                dt[r * kDStride + col] = dev::acos_over_pi(cs);
+                const float ac = 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs);
+                cmax = fmaxf(cmax, ac);
+                if constexpr (kEuclid) {
+                    const float lr = len_s[r], dl = lr - lc;
+                    const float d = __builtin_sqrtf(fmaxf(fmaf(dl, dl, 2.0f * lr * lc * (1.0f - cs)), 0.0f));
+                    dt[r * kDStride + col] = ac > kNearCos ? -d : d;
+                } else {
+                    dt[r * kDStride + col] = dev::acos_over_pi(cs);
+                }
             }
         }
     }
@@ -432,12 +453,19 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             const uint32_t su = up <= thr ? Pup : 0u;
             P = pk_step(pk_max(pk_max(sd, sl), su));
         }
+        float dvc = dv;
         if constexpr (careful) {
             const uint32_t nup = top ? 0u : shr1u(0u, nz);
-            const uint32_t nq = (dv < kNearD || dv > 1.0f - kNearD) ? 1u : 0u;
+            uint32_t nq;
+            if constexpr (kEuclid) {
+                nq = __float_as_uint(dv) >> 31;  // marked by the epilogue
+                dvc = fabsf(dv);
+            } else {
+                nq = (dv < kNearD || dv > 1.0f - kNearD) ? 1u : 0u;
+            }
             nz = nq | nup | (first ? 0u : nz);
         }
-        c = dv + m;
+        c = dvc + m;
         up_prev = up;
         Pup_prev = Pup;
         // Pair (x, y) of the group, x the row item: kept when x comes before y
@@ -496,7 +524,9 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
 
 // Pooled mode: MFMA Gram tile of pooled unit vectors, angular distance straight
 // into the pair matrix (64 x 128 item tile per block).  |cos| above kNearCos
-// flags the pair non-robust, for the FP64 recheck.
+// flags the pair non-robust, for the FP64 recheck.  kEuclid: the Euclidean
+// distance of the means from the same cosine and their FP32 lengths (flen).
+template <bool kEuclid>
 __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__restrict__ xn,
                                                               const float *__restrict__ rinv,
                                                               int dim_pad,
@@ -506,11 +536,13 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
                                                               const int64_t *__restrict__ tile_prefix,
                                                               int64_t n_groups, int64_t n_tiles,
                                                               float *__restrict__ out,
-                                                              uint8_t *__restrict__ flags) {
+                                                              uint8_t *__restrict__ flags,
+                                                              const float *__restrict__ flen) {
     using T = Tile<128>;
     constexpr int kCols = T::kCols;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kStageBytes];
     __shared__ __attribute__((aligned(16))) float norm_s[kRows + kCols];
+    __shared__ __attribute__((aligned(16))) float len_s[kEuclid ? kRows + kCols : 1];
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t g = dev::find_segment_wave(tile_prefix, n_groups, tile);
     const int64_t n = nrows[g];
@@ -518,11 +550,15 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
     const int64_t local = tile - tile_prefix[g];
     const int64_t r0 = (local / ntc) * kRows, c0 = (local % ntc) * kCols;
     const int nr = int(min<int64_t>(kRows, n - r0)), nc = int(min<int64_t>(kCols, n - c0));
-    NormStage<128> ns;
+    NormStage<128> ns, ls;
     ns.load(rinv, row0[g] + r0, nr, row0[g] + c0, nc);
+    if constexpr (kEuclid) ls.load(flen, row0[g] + r0, nr, row0[g] + c0, nc);
     f32x16 acc[2][1];
     gram_tile<128>(reinterpret_cast<uint16_t *>(smem_raw), xn, dim_pad, row0[g] + r0, nr, row0[g] + c0, nc, 0,
-                   acc, [&] { ns.store(norm_s); });
+                   acc, [&] {
+                       ns.store(norm_s);
+                       if constexpr (kEuclid) ls.store(len_s);
+                   });
     const f32x16 &acc0 = acc[0][0], &acc1 = acc[1][0];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int col = 32 * w + lane % 32;
@@ -535,7 +571,12 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
         auto put = [&](int r, float a) {
             const float cs = fminf(fmaxf(a * norm_s[r] * rc, -1.0f), 1.0f);
             const int64_t at = (r0 + r) * n + c0 + col;
-            o[at] = dev::acos_over_pi(cs);
+            if constexpr (kEuclid) {
+                const float lr = len_s[r], lc = len_s[kRows + col], dl = lr - lc;
+                o[at] = __builtin_sqrtf(fmaxf(fmaf(dl, dl, 2.0f * lr * lc * (1.0f - cs)), 0.0f));
+            } else {
+                o[at] = dev::acos_over_pi(cs);
+            }
             if (fabsf(cs) > kNearCos) fo[at] = 1;
         };
 #pragma unroll
@@ -552,7 +593,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_angular_bf16(const uint16_t *__
 template <int kC>
 void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad, const GroupTables &g,
                   const ItemTables &it, const FusedPlan &plan, int norm, float delta, float *p32,
-                  uint8_t *flags, unsigned int *nonrobust_n, unsigned int *unit_ctr) {
+                  uint8_t *flags, unsigned int *nonrobust_n, unsigned int *unit_ctr, const float *flen,
+                  const unsigned int *scale) {
     // units are split into 8 contiguous ranges, one per XCD; blocks of XCD x take
     // the units of range x in turn
     const int64_t q = (plan.n_units + 7) / 8;
@@ -560,16 +602,16 @@ void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_
     if (plan.blocks_per_cu > 0)
         per_xcd = std::min<int64_t>(per_xcd, std::max<int64_t>(1, int64_t(plan.blocks_per_cu) * plan.n_cu / 8));
     const dim3 grid(unsigned(8 * per_xcd)), block(256);
-    if (norm == FABX_NORM_PATH)
-        hipLaunchKernelGGL((k_fused<kC, true>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
-                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.band_rb,
-                           plan.g_cb0, plan.rb_cstart, plan.n_bands, plan.n_units, q, delta, p32, flags, nonrobust_n,
-                           unit_ctr);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items, g.pair_base, it.len,
+                           it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.band_rb, plan.g_cb0, plan.rb_cstart,
+                           plan.n_bands, plan.n_units, q, delta, p32, flags, nonrobust_n, unit_ctr, flen, scale);
+    };
+    const bool path = norm == FABX_NORM_PATH;
+    if (flen)
+        path ? go(k_fused<kC, true, true>) : go(k_fused<kC, false, true>);
     else
-        hipLaunchKernelGGL((k_fused<kC, false>), grid, block, 0, s, xn, rinv, dim_pad, g.item0, g.n_items,
-                           g.pair_base, it.len, it.dst, plan.rb, plan.cb, plan.unit_prefix, plan.band_rb,
-                           plan.g_cb0, plan.rb_cstart, plan.n_bands, plan.n_units, q, delta, p32, flags, nonrobust_n,
-                           unit_ctr);
+        path ? go(k_fused<kC, true, false>) : go(k_fused<kC, false, false>);
 }
 
 }  // namespace
@@ -577,13 +619,15 @@ void launch_fused(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_
 void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                 const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,
                 float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n,
-                unsigned int *unit_ctr) {
+                unsigned int *unit_ctr, const float *flen, const unsigned int *scale) {
     if (plan.n_units <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
     if (plan.cols == 128)
-        launch_fused<128>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n, unit_ctr);
+        launch_fused<128>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n, unit_ctr,
+                          flen, scale);
     else if (plan.cols == 256)
-        launch_fused<256>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n, unit_ctr);
+        launch_fused<256>(s, xn, rinv, dim_pad, g, it, plan, norm, delta, p32, flags, nonrobust_n, unit_ctr,
+                          flen, scale);
     else
         fail(FABX_EINVAL, "fused kernel column block must be 128 or 256 frames");
     FABX_HIP(hipGetLastError());
@@ -592,11 +636,12 @@ void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pa
 void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                        const int64_t *row0, const int64_t *nrows, const int64_t *base,
                        const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out,
-                       uint8_t *flags) {
+                       uint8_t *flags, const float *flen) {
     if (n_tiles <= 0) return;
     if (dim_pad % kKc) fail(FABX_EINVAL, "padded dim must be a multiple of 64");
-    hipLaunchKernelGGL(k_gram_angular_bf16, dim3(grid_for(n_tiles, 1)), dim3(256), 0, s, xn, rinv,
-                       dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out, flags);
+    hipLaunchKernelGGL(flen ? k_gram_angular_bf16<true> : k_gram_angular_bf16<false>, dim3(grid_for(n_tiles, 1)),
+                       dim3(256), 0, s, xn, rinv, dim_pad, row0, nrows, base, tile_prefix, n_groups, n_tiles, out,
+                       flags, flen);
     FABX_HIP(hipGetLastError());
 }
 

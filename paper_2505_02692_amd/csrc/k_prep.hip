@@ -8,7 +8,10 @@
 //
 // out_form: kUnitF32 (FP32 unit rows), kUnitBF16 (BF16 unit rows + 1 / norm
 // of the rounded row), kRawF32 (FP32 rows as they are; no zero-norm check,
-// since a zero vector has a length).
+// since a zero vector has a length), kUnitBF16Len (the BF16 form of the
+// Euclidean distance: kUnitBF16 plus each row's FP32 length and the largest
+// length over all rows; a zero row is legal there and packs as zeros with
+// 1 / norm = 0).
 //
 // HBM-bound: one read of each feature row, one write of the packed row.
 // One 256-thread block per task item, each wave takes every 4th frame.
@@ -21,7 +24,7 @@ namespace {
 
 using dev::kWave;
 
-constexpr int kUnitF32 = 0, kUnitBF16 = 1, kRawF32 = 2;
+constexpr int kUnitF32 = 0, kUnitBF16 = 1, kRawF32 = 2, kUnitBF16Len = 3;
 
 template <typename Tin>
 __device__ __forceinline__ void load_row_chunk(const Tin *row, int k, int dim, float v[4]);
@@ -56,8 +59,8 @@ template <int kChunks>
 __device__ __forceinline__ void store_unit_row(float (&v)[kChunks][4], float ss, int lane, int dim_pad,
                                                int64_t out_row, void *out, int out_form,
                                                float *rinv) {
-    const float r = out_form == kRawF32 ? 1.0f : 1.0f / __builtin_sqrtf(ss);
-    if (out_form != kUnitBF16) {
+    const float r = out_form == kRawF32 ? 1.0f : ss > 0.0f ? 1.0f / __builtin_sqrtf(ss) : 0.0f;
+    if (out_form != kUnitBF16 && out_form != kUnitBF16Len) {
         float *o = static_cast<float *>(out) + out_row * dim_pad;
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
@@ -87,8 +90,21 @@ __device__ __forceinline__ void store_unit_row(float (&v)[kChunks][4], float ss,
             }
         }
         ss16 = dev::wave_sum(ss16);
-        if (lane == 0) rinv[out_row] = 1.0f / __builtin_sqrtf(ss16);
+        if (lane == 0) rinv[out_row] = ss16 > 0.0f ? 1.0f / __builtin_sqrtf(ss16) : 0.0f;
     }
+}
+
+// Largest row length of a block into *scale (FP32 bits; lengths are >= 0, so
+// their bit patterns order like the values): one atomic per block.
+__device__ __forceinline__ void block_max_to(float m, unsigned int *scale) {
+    __shared__ float wmax[4];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+    if (lane == 0) wmax[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(scale, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 // kChunks * 256 >= dim_pad: each lane keeps its 4 * kChunks elements in registers.
@@ -98,8 +114,10 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst,
                                                    void *out, int out_form, float *rinv, int *err,
-                                                   int64_t n_items, unsigned long long *err_item) {
+                                                   int64_t n_items, unsigned long long *err_item,
+                                                   float *len_out, unsigned int *scale) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    float lmax = 0.0f;  // kUnitBF16Len: the largest row length this thread saw
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int L = item_len[item];
     const int64_t s0 = item_src[item], d0 = item_dst[item];
@@ -125,7 +143,13 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
             }
         ss = dev::wave_sum(ss);
         su = dev::wave_sum(su);
-        if (out_form != kRawF32 && (!(ss > 0.0f) || !(su > 0.0f))) {
+        if (out_form == kUnitBF16Len) {
+            if (lane == 0) {
+                len_out[d0 + t] = __builtin_sqrtf(ss);
+                if (two) len_out[d0 + t + 4] = __builtin_sqrtf(su);
+            }
+            lmax = fmaxf(lmax, __builtin_sqrtf(fmaxf(ss, su)));
+        } else if (out_form != kRawF32 && (!(ss > 0.0f) || !(su > 0.0f))) {
             if (lane == 0) {
                 atomicExch(err, 1);
                 atomicMin(err_item, (unsigned long long)item);
@@ -137,6 +161,7 @@ __global__ __launch_bounds__(256) void k_normalize(const Tin *__restrict__ src, 
         if (two) store_unit_row<kChunks>(u, su, lane, dim_pad, d0 + t + 4, out, out_form, rinv);
     }
     }
+    if (out_form == kUnitBF16Len) block_max_to(lmax, scale);  // uniform over the block
 }
 
 template <typename Tin, int kChunks>
@@ -145,9 +170,11 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
                                                         const int32_t *__restrict__ item_len,
                                                         int64_t n_items, void *out, int out_form,
                                                         float *rinv, int *err,
-                                                        unsigned long long *err_item) {
+                                                        unsigned long long *err_item, float *len_out,
+                                                        unsigned int *scale) {
     // one wave per item
     const int lane = threadIdx.x % kWave;
+    float lmax = 0.0f;  // kUnitBF16Len: the largest mean length this thread saw
     for (int64_t item = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; item < n_items;
          item += int64_t(gridDim.x) * 4) {
     const int L = item_len[item];
@@ -177,7 +204,10 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
             ss = fmaf(v[c][e], v[c][e], ss);
         }
     ss = dev::wave_sum(ss);
-    if (out_form != kRawF32 && !(ss > 0.0f)) {
+    if (out_form == kUnitBF16Len) {
+        if (lane == 0) len_out[item] = __builtin_sqrtf(ss);
+        lmax = fmaxf(lmax, __builtin_sqrtf(ss));
+    } else if (out_form != kRawF32 && !(ss > 0.0f)) {
         if (lane == 0) {
             atomicExch(err, 1);
             atomicMin(err_item, (unsigned long long)item);
@@ -186,51 +216,52 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
     }
     store_unit_row<kChunks>(v, ss, lane, dim_pad, item, out, out_form, rinv);
     }
+    if (out_form == kUnitBF16Len) block_max_to(lmax, scale);  // uniform over the block
 }
 
 template <int kChunks>
 void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                  const ItemTables &it, void *out, int out_form, float *rinv, int *err,
-                 unsigned long long *err_item, bool pooled) {
+                 unsigned long long *err_item, float *len_out, unsigned int *scale, bool pooled) {
     if (pooled) {
         dim3 grid(grid_for(it.n_items, 4));
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL((k_pool_normalize<float, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
-                               it.n_items, out, out_form, rinv, err, err_item);
+                               it.n_items, out, out_form, rinv, err, err_item, len_out, scale);
         else
             hipLaunchKernelGGL((k_pool_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
-                               it.len, it.n_items, out, out_form, rinv, err, err_item);
+                               it.len, it.n_items, out, out_form, rinv, err, err_item, len_out, scale);
     } else {
         dim3 grid(grid_for(it.n_items, 1));
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL((k_normalize<float, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const float *>(features), dim, dim_pad, it.src, it.len,
-                               it.dst, out, out_form, rinv, err, it.n_items, err_item);
+                               it.dst, out, out_form, rinv, err, it.n_items, err_item, len_out, scale);
         else
             hipLaunchKernelGGL((k_normalize<uint16_t, kChunks>), grid, dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, dim_pad, it.src,
-                               it.len, it.dst, out, out_form, rinv, err, it.n_items, err_item);
+                               it.len, it.dst, out, out_form, rinv, err, it.n_items, err_item, len_out, scale);
     }
     FABX_HIP(hipGetLastError());
 }
 
 void dispatch(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
               const ItemTables &it, void *out, int out_form, float *rinv, int *err,
-              unsigned long long *err_item, bool pooled) {
+              unsigned long long *err_item, float *len_out, unsigned int *scale, bool pooled) {
     if (it.n_items <= 0) return;
     // chunks of 256 elements per wave pass
     const int chunks = (dim_pad + 255) / 256;
     switch (chunks) {
-        case 1: launch_norm<1>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 2: launch_norm<2>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 3: launch_norm<3>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 4: launch_norm<4>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 5: launch_norm<5>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 6: launch_norm<6>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 7: launch_norm<7>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
-        case 8: launch_norm<8>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, pooled); break;
+        case 1: launch_norm<1>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 2: launch_norm<2>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 3: launch_norm<3>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 4: launch_norm<4>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 5: launch_norm<5>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 6: launch_norm<6>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 7: launch_norm<7>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
+        case 8: launch_norm<8>(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, pooled); break;
         default: fail(FABX_EINVAL, "feature dim above 2048 is not supported");
     }
 }
@@ -239,14 +270,14 @@ void dispatch(hipStream_t s, const void *features, int dtype, int dim, int dim_p
 
 void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                const ItemTables &it, void *out, int out_form, float *rinv, int *err,
-               unsigned long long *err_item) {
-    dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, false);
+               unsigned long long *err_item, float *len_out, unsigned int *scale) {
+    dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, false);
 }
 
 void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                     const ItemTables &it, void *out, int out_form, float *rinv, int *err,
-                    unsigned long long *err_item) {
-    dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, true);
+                    unsigned long long *err_item, float *len_out, unsigned int *scale) {
+    dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, true);
 }
 
 }  // namespace kern

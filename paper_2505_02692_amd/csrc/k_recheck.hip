@@ -6,6 +6,8 @@
 //   angle        acos(cos) when |cos| < 1 - 2^-20, else the half-chord form
 //                2 atan2(||u - v||, ||u + v||), which stays accurate near 0 and pi
 //   distance     angle / pi; DTW with the diagonal > left > up predecessor order
+// or, for the Euclidean distance (euclid != 0), the square root of the sum of
+// squared differences of the raw frames (or means).
 // Contraction into FMA is disabled.
 //
 // Persistent grid: each 256-thread block takes listed pairs in turn.  The
@@ -79,6 +81,17 @@ __device__ __forceinline__ double wave_frame_distance(const T *u, const T *v, do
     return angle_over_pi_units(c, sm, sp);
 }
 
+// Euclidean distance of frames u and v (the whole wave; every lane gets it).
+template <typename T>
+__device__ __forceinline__ double wave_euclid_distance(const T *u, const T *v, int dim, int lane) {
+    double s = 0.0;
+    for (int k = lane; k < dim; k += dev::kWave) {
+        const double a = ld(u, k) - ld(v, k);
+        s += a * a;
+    }
+    return sqrt(wave_sum_f64(s));
+}
+
 // The DTW update of cell (i, j) from its neighbours' costs and path lengths,
 // with the first row and column accumulating along themselves and the
 // diagonal > left > up order on exact ties.
@@ -121,7 +134,7 @@ __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat,
                                                      const int32_t *__restrict__ item_len,
                                                      const int64_t *__restrict__ list,
                                                      const unsigned int *__restrict__ count,
-                                                     int64_t max_count, int norm,
+                                                     int64_t max_count, int norm, int euclid,
                                                      double *__restrict__ p64) {
     __shared__ double inrm[2 * kMaxL];     // 1 / ||frame|| of the N rows, then the M columns
     __shared__ double dm[kMaxL * kMaxL];   // frame distances, row-major [N][M]
@@ -138,17 +151,19 @@ __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat,
         const T *fx = feat + item_src[x] * int64_t(dim);
         const T *fy = feat + item_src[y] * int64_t(dim);
         auto frame = [&](int f) { return f < N ? fx + int64_t(f) * dim : fy + int64_t(f - N) * dim; };
-        // norms of the N + M frames, a wave per frame
-        for (int f = w; f < N + M; f += 4) {
-            const double r = wave_inv_norm(frame(f), dim, lane);
-            if (lane == 0) inrm[f] = r;
-        }
+        // norms of the N + M frames, a wave per frame (angular distance)
+        if (!euclid)
+            for (int f = w; f < N + M; f += 4) {
+                const double r = wave_inv_norm(frame(f), dim, lane);
+                if (lane == 0) inrm[f] = r;
+            }
         __syncthreads();
         // frame distances, a wave per (i, j)
         for (int cidx = w; cidx < N * M; cidx += 4) {
             const int i = cidx / M, j = cidx % M;
-            const double d = wave_frame_distance(fx + int64_t(i) * dim, fy + int64_t(j) * dim, inrm[i],
-                                                 inrm[N + j], dim, lane);
+            const T *u = fx + int64_t(i) * dim, *v = fy + int64_t(j) * dim;
+            const double d = euclid ? wave_euclid_distance(u, v, dim, lane)
+                                    : wave_frame_distance(u, v, inrm[i], inrm[N + j], dim, lane);
             if (lane == 0) dm[cidx] = d;
         }
         __syncthreads();
@@ -196,7 +211,7 @@ __global__ __launch_bounds__(256) void k_long_dtw(const T *__restrict__ feat, in
                                                   const int32_t *__restrict__ item_len,
                                                   const int64_t *__restrict__ list,
                                                   const unsigned int *__restrict__ count,
-                                                  int64_t max_count, int norm,
+                                                  int64_t max_count, int norm, int euclid,
                                                   double *__restrict__ p64, float *__restrict__ p32,
                                                   uint8_t *__restrict__ flags) {
     constexpr int kTc = 32, kRing = 3, kRingCols = kRing * kTc;
@@ -222,10 +237,11 @@ __global__ __launch_bounds__(256) void k_long_dtw(const T *__restrict__ feat, in
         for (int r0 = 0; r0 < N; r0 += dev::kWave) {
             const int nr = min(dev::kWave, N - r0);
             __syncthreads();  // the previous chunk's steps are done with the norms and the ring
-            for (int f = w; f < nr; f += 4) {
-                const double r = wave_inv_norm(fx + int64_t(r0 + f) * dim, dim, lane);
-                if (lane == 0) rinv_r[f] = r;
-            }
+            if (!euclid)
+                for (int f = w; f < nr; f += 4) {
+                    const double r = wave_inv_norm(fx + int64_t(r0 + f) * dim, dim, lane);
+                    if (lane == 0) rinv_r[f] = r;
+                }
             // wave 0's sweep state: lane i holds row r0 + i at column s - i
             const int i = lane;
             double up_prev = 0.0;
@@ -238,15 +254,17 @@ __global__ __launch_bounds__(256) void k_long_dtw(const T *__restrict__ feat, in
                 const int c0 = k * kTc, nc = min(kTc, M - c0);
                 const int ring0 = (k % kRing) * kTc;
                 __syncthreads();  // tile k - 2's steps are done (and the row norms are in)
-                for (int f = w; f < nc; f += 4) {
-                    const double r = wave_inv_norm(fy + int64_t(c0 + f) * dim, dim, lane);
-                    if (lane == 0) rinv_c[f] = r;
-                }
+                if (!euclid)
+                    for (int f = w; f < nc; f += 4) {
+                        const double r = wave_inv_norm(fy + int64_t(c0 + f) * dim, dim, lane);
+                        if (lane == 0) rinv_c[f] = r;
+                    }
                 __syncthreads();
                 for (int cidx = w; cidx < nr * nc; cidx += 4) {
                     const int ii = cidx / nc, jj = cidx % nc;
-                    const double d = wave_frame_distance(fx + int64_t(r0 + ii) * dim, fy + int64_t(c0 + jj) * dim,
-                                                         rinv_r[ii], rinv_c[jj], dim, lane);
+                    const T *u = fx + int64_t(r0 + ii) * dim, *v = fy + int64_t(c0 + jj) * dim;
+                    const double d = euclid ? wave_euclid_distance(u, v, dim, lane)
+                                            : wave_frame_distance(u, v, rinv_r[ii], rinv_c[jj], dim, lane);
                     if (lane == 0) dm[ii * kRingCols + ring0 + jj] = d;
                 }
                 __syncthreads();
@@ -300,7 +318,8 @@ __global__ __launch_bounds__(256) void k_recheck_pooled(const T *__restrict__ fe
                                                         const int32_t *__restrict__ item_len,
                                                         const int64_t *__restrict__ list,
                                                         const unsigned int *__restrict__ count,
-                                                        int64_t max_count, double *__restrict__ p64) {
+                                                        int64_t max_count, int euclid,
+                                                        double *__restrict__ p64) {
     __shared__ double mx[2048];
     __shared__ double my[2048];
     const int lane = threadIdx.x % dev::kWave;
@@ -322,7 +341,12 @@ __global__ __launch_bounds__(256) void k_recheck_pooled(const T *__restrict__ fe
             my[k] = sy / double(M);
         }
         __syncthreads();
-        if (threadIdx.x < dev::kWave) {
+        if (threadIdx.x < dev::kWave && euclid) {
+            double sd = 0.0;
+            for (int k = lane; k < dim; k += dev::kWave) sd += (mx[k] - my[k]) * (mx[k] - my[k]);
+            sd = wave_sum_f64(sd);
+            if (lane == 0) p64[slot] = sqrt(sd);
+        } else if (threadIdx.x < dev::kWave) {
             double sx = 0.0, sy = 0.0;
             for (int k = lane; k < dim; k += dev::kWave) {
                 sx += mx[k] * mx[k];
@@ -352,48 +376,48 @@ __global__ __launch_bounds__(256) void k_recheck_pooled(const T *__restrict__ fe
 
 void long_dtw(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
               const ItemTables &it, const int64_t *list, const unsigned int *count, int64_t max_count, int norm,
-              double *p64, float *p32, uint8_t *flags) {
+              int euclid, double *p64, float *p32, uint8_t *flags) {
     if (max_count <= 0) return;
     const unsigned blocks = unsigned(std::min<int64_t>(max_count, 4096));
     if (dtype == FABX_DTYPE_F32)
         hipLaunchKernelGGL(k_long_dtw<float>, dim3(blocks), dim3(256), 0, s, static_cast<const float *>(features),
                            dim, g.item0, g.n_items, g.pair_base, g.n_groups, it.src, it.len, list, count,
-                           max_count, norm, p64, p32, flags);
+                           max_count, norm, euclid, p64, p32, flags);
     else
         hipLaunchKernelGGL(k_long_dtw<uint16_t>, dim3(blocks), dim3(256), 0, s,
                            static_cast<const uint16_t *>(features), dim, g.item0, g.n_items, g.pair_base,
-                           g.n_groups, it.src, it.len, list, count, max_count, norm, p64, p32, flags);
+                           g.n_groups, it.src, it.len, list, count, max_count, norm, euclid, p64, p32, flags);
     FABX_HIP(hipGetLastError());
 }
 
 void recheck_fp64(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
                   const ItemTables &it, const int64_t *list, const unsigned int *count,
-                  int64_t max_count, int mode, int norm, bool has_long, double *p64) {
+                  int64_t max_count, int mode, int norm, bool has_long, int euclid, double *p64) {
     if (max_count <= 0) return;
     if (mode == FABX_MODE_POOLED && dim > 2048) fail(FABX_EINVAL, "pooled recheck supports dim <= 2048");
     const unsigned blocks = unsigned(std::min<int64_t>(max_count, 4096));
     if (mode == FABX_MODE_DTW && has_long)
-        long_dtw(s, features, dtype, dim, g, it, list, count, max_count, norm, p64, nullptr, nullptr);
+        long_dtw(s, features, dtype, dim, g, it, list, count, max_count, norm, euclid, p64, nullptr, nullptr);
     if (mode == FABX_MODE_DTW) {
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL(k_recheck_dtw<float>, dim3(blocks), dim3(256), 0, s,
                                static_cast<const float *>(features), dim, g.item0, g.n_items,
                                g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, norm,
-                               p64);
+                               euclid, p64);
         else
             hipLaunchKernelGGL(k_recheck_dtw<uint16_t>, dim3(blocks), dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, g.item0, g.n_items,
                                g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, norm,
-                               p64);
+                               euclid, p64);
     } else {
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL(k_recheck_pooled<float>, dim3(blocks), dim3(256), 0, s,
                                static_cast<const float *>(features), dim, g.item0, g.n_items,
-                               g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, p64);
+                               g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, euclid, p64);
         else
             hipLaunchKernelGGL(k_recheck_pooled<uint16_t>, dim3(blocks), dim3(256), 0, s,
                                static_cast<const uint16_t *>(features), dim, g.item0, g.n_items,
-                               g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, p64);
+                               g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, euclid, p64);
     }
     FABX_HIP(hipGetLastError());
 }

@@ -31,8 +31,10 @@ __global__ __launch_bounds__(256) void k_triplets(const CellDev *__restrict__ ce
                                                   uint8_t *flags, float margin,
                                                   int32_t *__restrict__ recount,
                                                   unsigned int *__restrict__ recount_n,
-                                                  int64_t recount_cap) {
+                                                  int64_t recount_cap,
+                                                  const unsigned int *__restrict__ scale) {
     const int lane = threadIdx.x % kWave;
+    if (scale) margin *= __uint_as_float(*scale);  // margin in units of the largest frame length
     // one wave per unit; the loop bound is uniform across the wave
     for (int64_t unit = int64_t(blockIdx.x) * 4 + threadIdx.x / kWave; unit < n_units;
          unit += int64_t(gridDim.x) * 4) {
@@ -148,7 +150,9 @@ __global__ __launch_bounds__(256) void k_triplets_sorted(const CellDev *__restri
                                                          uint8_t *flags, float margin,
                                                          int32_t *__restrict__ recount,
                                                          unsigned int *__restrict__ recount_n,
-                                                         int64_t recount_cap) {
+                                                         int64_t recount_cap,
+                                                         const unsigned int *__restrict__ scale) {
+    if (scale) margin *= __uint_as_float(*scale);  // margin in units of the largest frame length
     __shared__ float sv[kSortedMaxB];
     __shared__ uint16_t si[kSortedMaxB];
     __shared__ unsigned long long red[4];
@@ -334,20 +338,22 @@ __global__ __launch_bounds__(256) void k_recount(const CellDev *__restrict__ cel
 
 void triplets(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
               const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
-              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap) {
+              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap,
+              const unsigned int *scale) {
     if (n_units <= 0) return;
     hipLaunchKernelGGL(k_triplets, dim3(grid_for(n_units, 4)), dim3(256), 0, s, cells, units, n_units,
                        g.pair_base, g.n_items, p32, W, flags, margin, recount, recount_n,
-                       recount_cap);
+                       recount_cap, scale);
     FABX_HIP(hipGetLastError());
 }
 
 void triplets_sorted(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
                      const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
-                     float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap) {
+                     float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap,
+                     const unsigned int *scale) {
     if (n_units <= 0) return;
     hipLaunchKernelGGL(k_triplets_sorted, dim3(grid_for(n_units, 1)), dim3(256), 0, s, cells, units, n_units,
-                       g.pair_base, g.n_items, p32, W, flags, margin, recount, recount_n, recount_cap);
+                       g.pair_base, g.n_items, p32, W, flags, margin, recount, recount_n, recount_cap, scale);
     FABX_HIP(hipGetLastError());
 }
 

@@ -38,18 +38,21 @@ struct GroupTables {
 // --- k_prep.hip
 // Pack every frame of every task item into the packed buffer (row stride
 // dim_pad, zero padded).  out_form = 0: F32 unit rows; 1: BF16 unit rows plus
-// rinv[f] = 1 / ||bf16 row|| (F32); 2: F32 rows unscaled (Euclidean distance).
-// In forms 0 and 1 a zero-norm frame sets err[0] = 1 and lowers err_item
-// (unsigned long long) to its task item.
+// rinv[f] = 1 / ||bf16 row|| (F32); 2: F32 rows unscaled (Euclidean distance,
+// FP32 form); 3: form 1 plus len_out[f] = ||frame|| (F32) and *scale = the
+// largest length (F32 bits; *scale zero before the call), a zero frame packed
+// as zeros with rinv 0 (Euclidean distance, BF16 form).  In forms 0 and 1 a
+// zero-norm frame sets err[0] = 1 and lowers err_item (unsigned long long) to
+// its task item.  len_out and scale may be null outside form 3.
 void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                const ItemTables &it, void *out, int out_form, float *rinv, int *err,
-               unsigned long long *err_item);
+               unsigned long long *err_item, float *len_out, unsigned int *scale);
 
 // Time pooling: mean of each item's frames (F32 accumulation), then the same
 // packing; one packed row per task item.
 void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                     const ItemTables &it, void *out, int out_form, float *rinv, int *err,
-                    unsigned long long *err_item);
+                    unsigned long long *err_item, float *len_out, unsigned int *scale);
 
 // --- k_plain.hip (plain FP32 form)
 // Segments of Gram output: segment s holds the distances of packed rows
@@ -104,10 +107,12 @@ struct FusedPlan {
     int n_cu;
 };
 // unit_ctr: 8 counters, zero at launch (the XCDs' next units of a persistent grid)
+// flen (non-null: Euclidean distance): FP32 frame lengths; scale: the largest
+// (FP32 bits), delta being in units of it.
 void fused_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                 const GroupTables &g, const ItemTables &it, const FusedPlan &plan, int norm,
                 float delta, float *p32, uint8_t *flags, unsigned int *nonrobust_n,
-                unsigned int *unit_ctr);
+                unsigned int *unit_ctr, const float *flen, const unsigned int *scale);
 
 // --- k_stream.hip (BF16 form, DTW mode: the column-stream kernel)
 // Per task frame: bit 31 first frame of its item, bit 30 last frame, bits
@@ -130,27 +135,32 @@ void stream_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_p
                  const GroupTables &g, const ItemTables &it, const StreamPlan &plan, int norm, uint32_t delta_q,
                  float *p32, uint8_t *flags, unsigned int *nonrobust_n, unsigned int *unit_ctr);
 
-// Pooled mode, BF16 MFMA: theta/pi between pooled item vectors of each group;
-// flags[slot] = 1 (non-robust) for a nearly parallel or antiparallel pair
-// (flags zeroed before).
+// Pooled mode, BF16 MFMA: theta/pi between pooled item vectors of each group
+// (flen non-null: the Euclidean distance of the means, from the cosine and
+// their FP32 lengths); flags[slot] = 1 (non-robust) for a nearly parallel or
+// antiparallel pair (flags zeroed before).
 void gram_angular_bf16(hipStream_t s, const uint16_t *xn, const float *rinv, int dim_pad,
                        const int64_t *row0, const int64_t *nrows, const int64_t *base,
                        const int64_t *tile_prefix, int64_t n_groups, int64_t n_tiles, float *out,
-                       uint8_t *flags);
+                       uint8_t *flags, const float *flen);
 
 // --- k_triplets.hip
 // One wave per unit [cell, x_begin, x_end): W[cell] += sum over the unit's rows of
 // 2[d(x,a) < d(x,b)] + [d(x,a) == d(x,b)].  With flags != nullptr (BF16 form), a row
 // holding a comparison with |d(x,a) - d(x,b)| <= margin, or a non-robust pair, is
 // not counted: its pairs get flag bit 1 and (cell, x) is appended to recount.
+// scale (may be null): margin is in units of *scale (FP32 bits; the Euclidean
+// BF16 form's largest frame length).
 void triplets(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
               const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
-              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap);
+              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap,
+              const unsigned int *scale);
 // Large cells, one x per unit: the same counts and marks from the row's B
 // distances sorted in LDS (|B| <= kSortedMaxB).
 void triplets_sorted(hipStream_t s, const CellDev *cells, const int32_t *units, int64_t n_units,
               const GroupTables &g, const float *p32, unsigned long long *W, uint8_t *flags,
-              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap);
+              float margin, int32_t *recount, unsigned int *recount_n, int64_t recount_cap,
+              const unsigned int *scale);
 
 // Zeroes W [n_cells] and the 64 counter bytes after it (the u64 at byte 8 of
 // those, the error item, is set to all ones).
@@ -172,17 +182,17 @@ void recount(hipStream_t s, const CellDev *cells, const int32_t *rows, const uns
 // by division by the sequential-sum norm, cosine as a sequential sum, acos or
 // the half-chord atan2 form near |cos| = 1, DTW with diagonal > left > up).
 // has_long: the task has items of more than 64 frames (DTW mode); their pairs
-// go through the tiled kernel of long_dtw.
+// go through the tiled kernel of long_dtw.  euclid: the Euclidean distance.
 void recheck_fp64(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
                   const ItemTables &it, const int64_t *list, const unsigned int *count,
-                  int64_t max_count, int mode, int norm, bool has_long, double *p64);
+                  int64_t max_count, int mode, int norm, bool has_long, int euclid, double *p64);
 // The same FP64 DTW for the listed slots whose pair has an item of more than
 // 64 frames (up to FABX_MAX_ITEM_FRAMES); others are skipped.  count: device
 // count of listed slots, or null for max_count.  p32 and flags (may be null)
 // also receive the value and 0 (robust, unmarked).
 void long_dtw(hipStream_t s, const void *features, int dtype, int dim, const GroupTables &g,
               const ItemTables &it, const int64_t *list, const unsigned int *count, int64_t max_count, int norm,
-              double *p64, float *p32, uint8_t *flags);
+              int euclid, double *p64, float *p32, uint8_t *flags);
 
 }  // namespace kern
 }  // namespace fabx

@@ -24,6 +24,7 @@ namespace {
 // wide safety factor over the errors measured by the parity tests.
 constexpr double kMarginK = 2e-2;
 constexpr double kDeltaK = 4e-2;
+constexpr double kPi = 3.14159265358979323846;
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Collects host arrays (256-byte aligned pieces) into one layout.  copy_to
@@ -262,8 +263,6 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     if (opts) o = *opts;
     if (o.distance != FABX_DISTANCE_ANGULAR && o.distance != FABX_DISTANCE_EUCLIDEAN)
         fail(FABX_EINVAL, "bad distance");
-    if (o.distance == FABX_DISTANCE_EUCLIDEAN && o.precision != FABX_PREC_FP32)
-        fail(FABX_EINVAL, "the Euclidean distance is implemented in the FP32 form only");
     if (o.mode != FABX_MODE_DTW && o.mode != FABX_MODE_POOLED) fail(FABX_EINVAL, "bad mode");
     if (o.precision != FABX_PREC_FP32 && o.precision != FABX_PREC_BF16_RECHECK)
         fail(FABX_EINVAL, "bad precision");
@@ -280,8 +279,13 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     // many times the per-distance one
     const double path_cells = p.mode == FABX_MODE_DTW && p.dtw_norm == FABX_NORM_NONE
                                   ? double(2 * std::clamp(ds.max_len, 1, kFusedRowFrames) - 1) : 1.0;
-    p.margin = o.margin < 0 ? kMarginK / std::sqrt(double(ds.dim)) * path_cells : o.margin;
-    p.delta = o.delta < 0 ? kDeltaK / std::sqrt(double(ds.dim)) : o.delta;
+    // BF16 form of the Euclidean distance: margin and delta are in units of the
+    // largest frame (or mean) length S, and an angle error e moves a frame
+    // distance by at most S e, so the angular bounds are scaled by pi (the
+    // angular distance being the angle / pi)
+    const double unit = p.distance == FABX_DISTANCE_EUCLIDEAN ? kPi : 1.0;
+    p.margin = o.margin < 0 ? unit * kMarginK / std::sqrt(double(ds.dim)) * path_cells : o.margin;
+    p.delta = o.delta < 0 ? unit * kDeltaK / std::sqrt(double(ds.dim)) : o.delta;
     p.keep_pairs = o.keep_pairs != 0;
     if (o.fused_cols != 0 && o.fused_cols != 128 && o.fused_cols != 256 && o.fused_cols != 512 &&
         o.fused_cols != 1024 && o.fused_cols != 2048)
@@ -293,6 +297,8 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
         fail(FABX_EINVAL, "an item is longer than FABX_MAX_ITEM_FRAMES frames (DTW mode)");
     if (p.mode == FABX_MODE_DTW && p.fused.cols >= kStreamMinCols && ds.max_len > kFusedRowFrames)
         fail(FABX_EINVAL, "the streaming DTW kernel (fused_cols >= 512) takes items of at most 64 frames");
+    if (p.fused.cols >= kStreamMinCols && p.distance == FABX_DISTANCE_EUCLIDEAN)
+        fail(FABX_EINVAL, "the streaming DTW kernel (fused_cols >= 512) computes the angular distance only");
     if (ds.dim > 2048) fail(FABX_EINVAL, "feature dim above 2048 is not supported");
     return p;
 }
@@ -302,6 +308,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
     const int64_t dim_pad = round_up(t.ds->dim, 64);
     const int64_t rows = p.mode == FABX_MODE_DTW ? t.n_frames : int64_t(t.items.size());
     int64_t b = rows * dim_pad * (bf16 ? 2 : 4) + rows * 4;
+    if (bf16 && p.distance == FABX_DISTANCE_EUCLIDEAN) b += rows * 4;  // frame lengths
     if (p.mode == FABX_MODE_DTW && !bf16) b += std::min(t.n_dmat, plain_dmat_cells()) * 4;
     b += t.n_pair_slots * 4;
     if (bf16) b += t.n_pair_slots * (1 + 8 + 8) + int64_t(t.long_slots.size()) * 8;
@@ -312,7 +319,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
 
 size_t Workspace::total() const {
     const DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units,
-                           &recheck_list, &recount_list, &finfo};
+                           &recheck_list, &recount_list, &finfo, &flen};
     size_t s = 0;
     for (auto *b : all) s += b->bytes;
     return s;
@@ -320,7 +327,7 @@ size_t Workspace::total() const {
 
 void Workspace::release() {
     DevBuf *all[] = {&xn, &rinv, &dmat, &p32, &flags, &p64, &half_units,
-                     &recheck_list, &recount_list, &finfo};
+                     &recheck_list, &recount_list, &finfo, &flen};
     for (auto *b : all) b->release();
 }
 
@@ -400,6 +407,7 @@ struct DevPtrs {
     int32_t *recount_list = nullptr;
     unsigned long long *half_units = nullptr;   // [n_cells], then the score's 64 counter bytes
     uint32_t *finfo = nullptr;                  // stream kernel: frame info [n_frames]
+    float *flen = nullptr;                      // Euclidean BF16 form: frame (or mean) lengths
 };
 
 // Byte offsets of the pooled tile prefix or of the plain form's strip columns.
@@ -439,10 +447,10 @@ void set_plan(DevPtrs &d, const char *base, const PlanLayout &L) {
 // Workspace bytes of one score (0 for buffers the form does not use).
 struct WorkspaceSizes {
     size_t xn = 0, rinv = 0, dmat = 0, p32 = 0, flags = 0, p64 = 0, recheck_list = 0, recount_list = 0,
-           half_units = 0, finfo = 0;
+           half_units = 0, finfo = 0, flen = 0;
     size_t total_aligned() const {
         size_t s = 0;
-        for (size_t b : {xn, rinv, dmat, p32, flags, p64, recheck_list, recount_list, half_units, finfo})
+        for (size_t b : {xn, rinv, dmat, p32, flags, p64, recheck_list, recount_list, half_units, finfo, flen})
             s += (b + 255) & ~size_t(255);
         return s;
     }
@@ -467,6 +475,7 @@ WorkspaceSizes workspace_sizes(const TaskImpl &t, const ScoreParams &p, const Pl
     // per-cell counts, then 64 counter bytes: both come back with one copy
     w.half_units = t.cells.size() * 8 + 64;
     if (stream) w.finfo = size_t(t.n_frames) * 4;
+    if (bf16 && p.distance == FABX_DISTANCE_EUCLIDEAN) w.flen = size_t(rows) * 4;
     return w;
 }
 
@@ -494,6 +503,10 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
     unsigned int *marked_n = reinterpret_cast<unsigned int *>(counters + 20);
     unsigned int *nonrobust_n = reinterpret_cast<unsigned int *>(counters + 24);
     unsigned int *unit_ctr = reinterpret_cast<unsigned int *>(counters + 32);  // [8]
+    const bool euclid = p.distance == FABX_DISTANCE_EUCLIDEAN;
+    // Euclidean BF16 form: frame lengths and the largest one (FP32 bits)
+    float *flen = bf16 && euclid ? d.flen : nullptr;
+    unsigned int *scale = bf16 && euclid ? reinterpret_cast<unsigned int *>(counters + 28) : nullptr;
     auto mark = [&] {
         if (tm) tm->mark();
     };
@@ -501,13 +514,13 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
     kern::init_score(stream, d.half_units, n_cells);
     if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(d.flags, 0, size_t(t.n_pair_slots), stream));
     mark();  // 1
-    const bool euclid = p.distance == FABX_DISTANCE_EUCLIDEAN;  // FP32 form only
-    const int out_form = bf16 ? 1 : euclid ? 2 : 0;
+    const int out_form = bf16 ? (euclid ? 3 : 1) : euclid ? 2 : 0;
     if (dtw)
-        kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, d.xn, out_form, d.rinv, err, err_item);
+        kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, d.xn, out_form, d.rinv, err, err_item,
+                        flen, scale);
     else
         kern::pool_normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, d.xn, out_form, d.rinv, err,
-                             err_item);
+                             err_item, flen, scale);
     mark();  // 2
     const auto &sp = d.strips;
     if (plain_dtw) {
@@ -537,10 +550,10 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
                            int64_t(cplan->band_rb.size()) - 1, cplan->unit_prefix.back(), fcfg.cols,
                            fcfg.blocks_per_cu, ds.ctx->n_cu};
         kern::fused_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt, it, fp, p.dtw_norm,
-                         float(p.delta), d.p32, d.flags, nonrobust_n, unit_ctr);
+                         float(p.delta), d.p32, d.flags, nonrobust_n, unit_ctr, flen, scale);
         // pairs with an item over 64 frames: FP64 from the raw features
         kern::long_dtw(stream, ds.features, ds.dtype, dim, gt, it, d.long_slots, nullptr,
-                       int64_t(t.long_slots.size()), p.dtw_norm, d.p64, d.p32, d.flags);
+                       int64_t(t.long_slots.size()), p.dtw_norm, euclid ? 1 : 0, d.p64, d.p32, d.flags);
         st.computed_dtw_cells = cplan->cells;
     } else if (!bf16) {
         const kern::GramSegments seg{gt.item0, gt.n_items, gt.item0, gt.n_items, gt.pair_base, d.tiles, G,
@@ -548,20 +561,20 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
         kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.p32, euclid ? 1 : 0);
     } else {
         kern::gram_angular_bf16(stream, static_cast<const uint16_t *>(d.xn), d.rinv, dim_pad, gt.item0,
-                                gt.n_items, gt.pair_base, d.tiles, G, tiles.back(), d.p32, d.flags);
+                                gt.n_items, gt.pair_base, d.tiles, G, tiles.back(), d.p32, d.flags, flen);
     }
     mark();  // 3
     uint8_t *flags = bf16 ? d.flags : nullptr;
     int32_t *recount = bf16 ? d.recount_list : nullptr;
     kern::triplets(stream, d.cells, d.units, t.n_units_small, gt, d.p32, d.half_units, flags, float(p.margin),
-                   recount, recount_n, t.sum_nx);
+                   recount, recount_n, t.sum_nx, scale);
     kern::triplets_sorted(stream, d.cells, d.units + 3 * t.n_units_small, n_units - t.n_units_small, gt, d.p32,
-                          d.half_units, flags, float(p.margin), recount, recount_n, t.sum_nx);
+                          d.half_units, flags, float(p.margin), recount, recount_n, t.sum_nx, scale);
     mark();  // 4
     if (bf16) {
         kern::collect_marked(stream, d.flags, t.n_pair_slots, d.recheck_list, marked_n, t.n_pair_slots, recount_n);
         kern::recheck_fp64(stream, ds.features, ds.dtype, dim, gt, it, d.recheck_list, marked_n, t.n_pair_slots,
-                           p.mode, p.dtw_norm, dtw && t.max_len > kFusedRowFrames, d.p64);
+                           p.mode, p.dtw_norm, dtw && t.max_len > kFusedRowFrames, euclid ? 1 : 0, d.p64);
         kern::recount(stream, d.cells, d.recount_list, recount_n, t.sum_nx, gt, d.p32, d.p64, d.flags,
                       d.half_units);
     }
@@ -654,7 +667,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     Pool *pool = &ds.ctx->pool;
     if (!dv.blob.ptr) dv.blob.pool = pool;
     for (DevBuf *b : {&t.ws.xn, &t.ws.rinv, &t.ws.dmat, &t.ws.p32, &t.ws.flags, &t.ws.p64,
-                      &t.ws.half_units, &t.ws.recheck_list, &t.ws.recount_list, &t.ws.finfo})
+                      &t.ws.half_units, &t.ws.recheck_list, &t.ws.recount_list, &t.ws.finfo, &t.ws.flen})
         if (!b->ptr) b->pool = pool;
     // fused kernel: tile width and grid from the tuning table (or the caller),
     // and the task's column blocks for that width (uploaded on first use)
@@ -720,7 +733,8 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
                     std::make_pair(&ws.flags, wz.flags), std::make_pair(&ws.p64, wz.p64),
                     std::make_pair(&ws.recheck_list, wz.recheck_list),
                     std::make_pair(&ws.recount_list, wz.recount_list),
-                    std::make_pair(&ws.half_units, wz.half_units), std::make_pair(&ws.finfo, wz.finfo)})
+                    std::make_pair(&ws.half_units, wz.half_units), std::make_pair(&ws.finfo, wz.finfo),
+                    std::make_pair(&ws.flen, wz.flen)})
         if (bs.second) bs.first->ensure(bs.second);
     st.workspace_bytes = int64_t(ws.total());
     pend->host_bytes = size_t(n_cells) * 8 + 64;
@@ -749,6 +763,7 @@ std::shared_ptr<ResultImpl> launch_score(const std::shared_ptr<TaskImpl> &tp, co
     d.recount_list = ws.recount_list.as<int32_t>();
     d.half_units = ws.half_units.as<unsigned long long>();
     d.finfo = ws.finfo.as<uint32_t>();
+    d.flen = ws.flen.as<float>();
 
     pend->tm = std::make_unique<Timer>(stream, ds.ctx->events);
     tr.mark("workspace");
@@ -928,6 +943,7 @@ void score_in_scratch(TaskImpl &t, const ScoreParams &p, char *base, size_t cap,
     d.recount_list = reinterpret_cast<int32_t *>(take(wz.recount_list));
     d.half_units = reinterpret_cast<unsigned long long *>(take(wz.half_units));
     d.finfo = reinterpret_cast<uint32_t *>(take(wz.finfo));
+    d.flen = reinterpret_cast<float *>(take(wz.flen));
     st.workspace_bytes = int64_t(wz.total_aligned());
     std::vector<char> host(size_t(n_cells) * 8 + 64);
     try {

@@ -145,10 +145,14 @@ def test_bad_score_options():
     o.distance = 3
     with pytest.raises(fx.FabxError):
         fx.fabx_score(t.h, o)
-    # the Euclidean distance exists in the FP32 form only
+    # the streaming DTW kernel computes the angular distance only
+    with pytest.raises(fx.FabxError) as e:
+        fx.fabx_score(t.h, fx.make_opts(distance="euclidean", precision="bf16", fused_cols=1024))
+    assert e.value.code == L.FABX_EINVAL and "angular distance only" in str(e.value)
+    # the Euclidean BF16 form passes the option checks (no device here)
     with pytest.raises(fx.FabxError) as e:
         fx.fabx_score(t.h, fx.make_opts(distance="euclidean", precision="bf16"))
-    assert e.value.code == L.FABX_EINVAL and "Euclidean" in str(e.value)
+    assert e.value.code == L.FABX_EINVAL and "no device" in str(e.value)
     # a forced fused-kernel configuration must be one the kernel has
     for cols, bpc, msg in ((100, 0, "fused_cols"), (128, -1, "fused_blocks_per_cu"),
                            (256, 65, "fused_blocks_per_cu")):

@@ -682,6 +682,65 @@ def test_euclidean_fp32(mode, norm):
     assert mism <= max(2, len(orc.cells) // 1000)
 
 
+def _euclid_case(name):
+    if name == "c1-zero-frame":
+        w = workloads.plain_c1(centroid_std=0.15)
+        feats = w.features.clone()
+        feats[int(w.offsets[5])] = 0.0      # a zero frame has a length: it is scored
+        w.features = feats
+        return w
+    if name == "c2-shape-768":
+        return workloads.within_c2(n_items=3000, centroid_std=0.1, seed=41)
+    if name == "near-copies-1024":
+        # half the items with a copy under 1e-4 relative noise: near-parallel,
+        # near-equal-length frames, where the cosine form cancels
+        w = workloads.batched_c4(n_groups=8, size_lo=6, size_hi=20, len_lo=1, len_hi=12, dim=1024,
+                                 centroid_std=0.3, seed=42, dtype=torch.float32)
+        return _with_twins(w, 1e-4, seed=7)
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("mode,norm", [("dtw", "path"), ("dtw", "none"), ("pooled", "path")])
+@pytest.mark.parametrize("case", ["c1-zero-frame", "c2-shape-768", "near-copies-1024"])
+def test_euclidean_bf16_exact(case, mode, norm):
+    """The Euclidean distance in the BF16 + FP64-recheck form: the unit-vector
+    cosine from the MFMA Gram tile and each frame's FP32 length give
+    |u - v| = sqrt((|u| - |v|)^2 + 2 |u| |v| (1 - cos)); margin and DTW window
+    are the angular ones times pi times the largest length S.  Bar: every
+    cell's count equals the FP64 oracle's, every robust pair within
+    margin / 2, every FP64-rechecked pair within 1e-12 relative."""
+    w = _euclid_case(case)
+    _say(f"euclidean bf16 {case} {mode} {norm} n_items={w.n_items} dim={w.dim}")
+    t, res = gpu_score(w, mode=mode, precision="bf16", norm=norm, distance="euclidean", keep_pairs=True)
+    orc = oracle.score(w.features_f32_host(), w.offsets, w.attrs, w.on, w.by, w.across, mode, norm,
+                       distance="euclidean")
+    assert np.array_equal(t.keys, orc.keys.astype(np.int32))
+    assert np.array_equal(t.sizes[0], orc.n_triplets)
+    f = w.features_f32_host().astype(np.float64)
+    if mode == "dtw":
+        S = float(np.sqrt((f * f).sum(axis=1)).max())
+    else:
+        means = np.stack([f[w.offsets[i]:w.offsets[i + 1]].mean(axis=0) for i in range(w.n_items)])
+        S = float(np.sqrt((means * means).sum(axis=1)).max())
+    st = res.stats
+    margin = st["margin"] * S
+    xs, ys, want = all_oracle_pairs(orc)
+    f32, fl, f64 = res.pairs(xs, ys)
+    err = np.abs(f32.astype(np.float64) - want)
+    robust = (fl & 1) == 0
+    mism = int(np.count_nonzero(res.half_units != orc.half_units))
+    print(f"  S={S:.3f} margin={margin:.3g} max_robust_err={err[robust].max():.3g} "
+          f"nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']} recount={st['n_recount_rows']} "
+          f"mism={mism}/{len(orc.cells)} err={res.collapse():.6f} oracle_err={oracle.error_rate(orc):.6f}",
+          flush=True)
+    assert mism == 0
+    assert abs(res.collapse() - oracle.error_rate(orc)) <= 1e-12
+    assert err[robust].max() <= margin / 2
+    rechecked = (fl & 2) != 0
+    if rechecked.any():
+        assert (np.abs(f64[rechecked] - want[rechecked]) <= 1e-12 * np.maximum(want[rechecked], 1.0)).all()
+
+
 # ----------------------------------------------------- item-file front end --
 
 @pytest.mark.parametrize("libri_light", [False, True])
