@@ -315,38 +315,63 @@ def cpu_baseline(oracle, fx, w, target_seconds=15.0, seed=0):
         return r, time.perf_counter() - t0
 
     # the probe: the smallest groups, doubled until a run takes half a second
+    # (or until the next doubling is estimated, at the current rates, to take
+    # more than a few seconds: the larger groups come last)
     by_cost = sorted(groups, key=lambda g: cost[g])
     n_probe = 64
     while True:
         probe = by_cost[:n_probe]
         r, dt = run(probe)
+        rate_d = dt / sum(cost[g] for g in probe)                  # seconds per distance-cost unit
+        rate_t = dt / max(sum(trip[g] for g in probe), 1.0)        # seconds per triplet
         if dt >= 0.5 or n_probe >= len(by_cost):
             break
+        nxt = by_cost[:2 * n_probe]
+        if sum(max(cost[g] * rate_d, trip[g] * rate_t) for g in nxt) > 4.0:
+            break
         n_probe *= 2
-    rate_d = dt / sum(cost[g] for g in probe)                  # seconds per distance-cost unit
-    rate_t = dt / max(sum(trip[g] for g in probe), 1.0)        # seconds per triplet
     est_of = {g: max(cost[g] * rate_d, trip[g] * rate_t) for g in groups}
     log(f"cpu baseline: probe of {len(probe)} small groups took {dt:.2f} s")
     order = [groups[k] for k in np.random.default_rng(seed).permutation(len(groups))]
-    take, est = [], 0.0
-    for g in order:
-        e = est_of[g]
-        if e > 0.5 * target_seconds:
-            continue
-        if est + e > target_seconds:
-            break
-        take.append(g)
-        est += e
+
+    def select(scale):
+        take, est = [], 0.0
+        for g in order:
+            e = est_of[g] * scale
+            if e > 0.5 * target_seconds:
+                continue
+            if est + e > target_seconds:
+                break
+            take.append(g)
+            est += e
+        return take, est
+
+    take, est = select(1.0)
     r, dt = run(take)
+    log(f"cpu baseline: {len(take)} groups took {dt:.1f} s (estimated {est:.1f} s)")
+    # the estimates charge each part with the whole probe time, so they run
+    # high; when the sample took well under the target, scale them by what it
+    # took and draw the sample again (same order, so it grows)
+    scale = 1.0
+    for _ in range(3):
+        if est <= 0 or dt >= 0.4 * target_seconds:
+            break
+        scale *= max(dt / est, 0.05)
+        take2, est2 = select(scale)
+        if len(take2) <= len(take):
+            break
+        take, est = take2, est2
+        r, dt = run(take)
+        log(f"cpu baseline: rescaled by {scale:.4f}: {len(take)} groups took {dt:.1f} s "
+            f"(estimated {est:.1f} s)")
     n_trip = int(r.n_triplets.sum())
     model, ncpu = cpu_info()
-    whole_s = sum(est_of.values())
-    log(f"cpu baseline: {len(take)} groups took {dt:.1f} s (estimated {est:.1f} s)")
+    whole_s = sum(est_of.values()) * scale
     return {"value": n_trip / dt, "unit": "triplets/s", "cores": oracle.num_threads(), "kind": "oracle",
             "cpu_model": model, "nproc": ncpu,
             "sample": f"{len(take)} of {len(groups)} BY groups in seeded random order ({len(r.cells)} cells, "
                       f"{n_trip} triplets) of the same workload, FP64 DTW + scoring, {dt:.1f} s; the whole "
-                      f"workload would take about {whole_s:.0f} s by the probe's estimate"}
+                      f"workload would take about {whole_s:.0f} s by the rescaled estimate"}
 
 
 def committed_traffic(kernel_file, profile_file, cols, blocks_per_cu):

@@ -1083,7 +1083,7 @@ def test_batched_c4_full_size_sampled_groups():
     """The batched uneven workload at full size (5,000 BY groups of 2-2,000
     items, 1.05M items, lengths 1-60, dim 512 BF16), scored in one persistent
     launch as the bench runs it: every cell of 48 seeded groups of at most 200
-    items and 2 groups of 200-600 items equals the oracle's."""
+    items, 6 groups of 200-600 items and 2 of 600-1,200 equals the oracle's."""
     w = workloads.batched_c4(device="cuda")
     _say(f"batched-c4 full size n_items={w.n_items}")
     t, res = gpu_score(w)
@@ -1094,7 +1094,9 @@ def test_batched_c4_full_size_sampled_groups():
     rng = np.random.default_rng(11)
     small = ids[counts <= 200]
     mid = ids[(counts > 200) & (counts <= 600)]
-    chosen = list(rng.choice(small, 48, replace=False)) + list(rng.choice(mid, 2, replace=False))
+    large = ids[(counts > 600) & (counts <= 1200)]
+    chosen = (list(rng.choice(small, 48, replace=False)) + list(rng.choice(mid, 6, replace=False)) +
+              list(rng.choice(large, 2, replace=False)))
     n = _check_sampled_groups(w, t, res, chosen)
     print(f"  {n} cells equal the oracle's", flush=True)
 
