@@ -53,9 +53,11 @@ extern "C" {
 /* ------------------------------------------------------------------ enums */
 #define FABX_DTYPE_F32 0
 #define FABX_DTYPE_BF16 1
+#define FABX_DTYPE_UNITS 2           /* int32 discrete unit codes, dim 1 */
 
 #define FABX_DISTANCE_ANGULAR 0      /* theta(u, v) / pi, in [0, 1] */
 #define FABX_DISTANCE_EUCLIDEAN 1    /* |u - v| of the raw frames (or means) */
+#define FABX_DISTANCE_UNITS 2        /* discrete units: 0 for equal codes, else 1 */
 
 #define FABX_MODE_DTW 0              /* align frames with DTW */
 #define FABX_MODE_POOLED 1           /* mean over time, one vector per item */
@@ -114,7 +116,12 @@ void fabx_destroy(fabx_ctx *ctx);
 /* A dataset: ragged feature sequences plus an integer attribute table
  * (the Dataset class: "labels and a way to access the representations").
  *
- *  features  device pointer, [n_frames][dim] row-major, dtype F32 or BF16.
+ *  features  device pointer, [n_frames][dim] row-major, dtype F32 or BF16;
+ *            or, for discrete representations (the paper says ABX works with
+ *            them but gives no distance), FABX_DTYPE_UNITS: one int32 unit
+ *            code per frame, dim = 1, scored with FABX_DISTANCE_UNITS in DTW
+ *            mode (frame distance 0 for equal codes, 1 otherwise; the DTW
+ *            costs are then exact integers and every comparison is exact).
  *            BORROWED: it must stay valid and unchanged while the dataset
  *            (or any task / result made from it) is alive.
  *  offsets   host int64 [n_items + 1]; item i owns frames offsets[i] ..

@@ -11,7 +11,8 @@ Every function follows a passage of the paper (Poli, Chemla, Dupoux,
 * ``cells``            -- Background section: the ON / BY / ACROSS conditions
                           (Fig. 1 caption, Table 1) and the cell A x B x X.
 * ``frame_distance``   -- the "angular" distance named with the Score class,
-                          or the "euclidean" one named beside it.
+                          or the "euclidean" one named beside it, or the
+                          0 / 1 mismatch of discrete unit codes.
 * ``dtw``              -- the DTW recurrence of "Dynamic Time Warping on GPU".
 * ``pair_distances``   -- DTW over frame distances, or time pooling (same
                           section: "pool along the time domain").
@@ -93,12 +94,17 @@ def num_threads() -> int:
 
 # ---------------------------------------------------------------- distances --
 
-DISTANCES = {"angular": 0, "euclidean": 1}
+# "units": discrete unit codes (one value per frame, dim 1), distance 0 for
+# equal codes and 1 otherwise (DTW mode); the paper says ABX works with
+# discrete representations but gives no distance for them.
+DISTANCES = {"angular": 0, "euclidean": 1, "units": 2}
 
 
 def frame_distance(u: Sequence[float], v: Sequence[float], distance: str = "angular") -> float:
     """Distance of two raw vectors in FP64: the angle theta(u, v) / pi
-    ("angular") or the length of u - v ("euclidean")."""
+    ("angular"), the length of u - v ("euclidean"), or for one-element
+    vectors holding discrete unit codes 0 if the codes are equal, else 1
+    ("units")."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.float64)
     out = ctypes.c_double()

@@ -16,7 +16,11 @@
  *     domain"): angular distance of the per-item mean frames;
  *   - the Euclidean distance between two frames (the Score interface names
  *     "euclidean" beside "angular"): the square root of the sequential sum of
- *     squared differences, on the raw frames (or raw means), in either mode.
+ *     squared differences, on the raw frames (or raw means), in either mode;
+ *   - for discrete units (the paper says ABX works with discrete
+ *     representations but gives no distance for them): frames are unit codes
+ *     (D = 1) and the frame distance is 0 for equal codes, 1 otherwise; DTW
+ *     mode only.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA contraction,
  * so every sum is the plain sequential sum written below).
@@ -98,12 +102,22 @@ static double euclidean(const double *u, const double *v, int D)
     return sqrt(s);
 }
 
+/* Discrete units: 0 when the two codes are equal, else 1. */
+static double unit_mismatch(const double *u, const double *v)
+{
+    return u[0] == v[0] ? 0.0 : 1.0;
+}
+
 /* Exported for the closed-form pins: distance of two raw vectors
- * (distance 0 = angular, 1 = Euclidean). */
+ * (distance 0 = angular, 1 = Euclidean, 2 = unit mismatch with D = 1). */
 int oracle_frame_distance(const double *u, const double *v, int D, int distance, double *out)
 {
-    if (D <= 0 || distance < 0 || distance > 1)
+    if (D <= 0 || distance < 0 || distance > 2 || (distance == 2 && D != 1))
         return ORACLE_EINVAL;
+    if (distance == 2) {
+        *out = unit_mismatch(u, v);
+        return ORACLE_OK;
+    }
     if (distance == 1) {
         *out = euclidean(u, v, D);
         return ORACLE_OK;
@@ -204,7 +218,7 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                           int mode, int norm, int distance, double *out, int64_t *bad_item)
 {
     int status = ORACLE_OK;
-    if (D <= 0 || n_groups < 0 || distance < 0 || distance > 1)
+    if (D <= 0 || n_groups < 0 || distance < 0 || distance > 2 || (distance == 2 && (D != 1 || mode != 0)))
         return ORACLE_EINVAL;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t g = 0; g < n_groups; ++g) {
@@ -233,7 +247,7 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                 for (int64_t t = 0; t < L && rc == ORACLE_OK; ++t) {
                     const float *f = feat + (size_t)(f0 + t) * D;
                     double *u = uf + (size_t)(ustart[a] + t) * D;
-                    if (distance == 1)
+                    if (distance >= 1)
                         for (int k = 0; k < D; ++k)
                             u[k] = (double)f[k];
                     else
@@ -278,9 +292,10 @@ int oracle_pair_distances(const float *feat, const int64_t *offsets, int D,
                 }
                 for (int i = 0; i < N; ++i)
                     for (int j = 0; j < M; ++j)
-                        dm[(size_t)i * M + j] = distance == 1
-                                                    ? euclidean(ux + (size_t)i * D, uy + (size_t)j * D, D)
-                                                    : angular_unit(ux + (size_t)i * D, uy + (size_t)j * D, D);
+                        dm[(size_t)i * M + j] =
+                            distance == 2   ? unit_mismatch(ux + (size_t)i * D, uy + (size_t)j * D)
+                            : distance == 1 ? euclidean(ux + (size_t)i * D, uy + (size_t)j * D, D)
+                                            : angular_unit(ux + (size_t)i * D, uy + (size_t)j * D, D);
                 oracle_dtw(dm, N, M, norm, &out[p], NULL);
             }
             free(dm);

@@ -20,7 +20,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib as L
-from ._lib import (FABX_DISTANCE_ANGULAR, FABX_DISTANCE_EUCLIDEAN, FABX_DTYPE_BF16, FABX_DTYPE_F32,
+from ._lib import (FABX_DISTANCE_ANGULAR, FABX_DISTANCE_EUCLIDEAN, FABX_DISTANCE_UNITS, FABX_DTYPE_BF16,
+                   FABX_DTYPE_F32, FABX_DTYPE_UNITS,
                    FABX_MODE_DTW, FABX_MODE_POOLED, FABX_NORM_NONE,
                    FABX_NORM_PATH, FABX_PREC_BF16_RECHECK, FABX_PREC_FP32, fabx_dataset_desc,
                    fabx_score_opts, fabx_server_stats, fabx_stats)
@@ -325,7 +326,8 @@ def make_opts(mode: str = "dtw", precision: str = "bf16", norm: str = "path", ma
               delta: float = -1.0, keep_pairs: bool = False, fused_cols: int = 0,
               fused_blocks_per_cu: int = 0, distance: str = "angular") -> fabx_score_opts:
     o = fabx_score_opts_default()
-    o.distance = {"angular": FABX_DISTANCE_ANGULAR, "euclidean": FABX_DISTANCE_EUCLIDEAN}[distance]
+    o.distance = {"angular": FABX_DISTANCE_ANGULAR, "euclidean": FABX_DISTANCE_EUCLIDEAN,
+                  "units": FABX_DISTANCE_UNITS}[distance]
     o.mode = {"dtw": FABX_MODE_DTW, "pooled": FABX_MODE_POOLED}[mode]
     o.precision = {"fp32": FABX_PREC_FP32, "bf16": FABX_PREC_BF16_RECHECK}[precision]
     o.dtw_norm = {"path": FABX_NORM_PATH, "none": FABX_NORM_NONE}[norm]
@@ -366,7 +368,8 @@ class Context:
 
 
 class Dataset:
-    """Ragged features (device tensor [n_frames, dim], float32 or bfloat16) + attribute table."""
+    """Ragged features (device tensor [n_frames, dim], float32 or bfloat16; or
+    int32 unit codes [n_frames] of a discrete representation) + attribute table."""
 
     def __init__(self, ctx: Context, features, offsets, attrs):
         self.ctx = ctx
@@ -379,8 +382,11 @@ class Dataset:
             import torch
             if not features.is_contiguous():
                 raise ValueError("features must be contiguous")
-            dtype = {torch.float32: FABX_DTYPE_F32, torch.bfloat16: FABX_DTYPE_BF16}[features.dtype]
-            ptr, nf, dim = features.data_ptr(), int(features.shape[0]), int(features.shape[1])
+            dtype = {torch.float32: FABX_DTYPE_F32, torch.bfloat16: FABX_DTYPE_BF16,
+                     torch.int32: FABX_DTYPE_UNITS}[features.dtype]
+            nf = int(features.shape[0])
+            dim = 1 if features.dim() == 1 else int(features.shape[1])
+            ptr = features.data_ptr()
         self.h = fabx_dataset_create(ctx.h, ptr, dtype, nf, dim, offsets, attrs)
 
     @classmethod

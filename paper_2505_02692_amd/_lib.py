@@ -17,8 +17,10 @@ FABX_ENOTFOUND = -7
 
 FABX_DTYPE_F32 = 0
 FABX_DTYPE_BF16 = 1
+FABX_DTYPE_UNITS = 2
 FABX_DISTANCE_ANGULAR = 0
 FABX_DISTANCE_EUCLIDEAN = 1
+FABX_DISTANCE_UNITS = 2
 FABX_MODE_DTW = 0
 FABX_MODE_POOLED = 1
 FABX_PREC_FP32 = 0

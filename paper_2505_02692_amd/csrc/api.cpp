@@ -287,7 +287,9 @@ std::shared_ptr<DatasetImpl> new_dataset(fabx_ctx *ctx, const void *features, in
     if (n_items < 1) fail(FABX_EINVAL, "n_items must be >= 1");
     if (dim < 1) fail(FABX_EINVAL, "dim must be >= 1");
     if (n_attr < 1) fail(FABX_EINVAL, "n_attr must be >= 1");
-    if (dtype != FABX_DTYPE_F32 && dtype != FABX_DTYPE_BF16) fail(FABX_EINVAL, "unknown dtype");
+    if (dtype != FABX_DTYPE_F32 && dtype != FABX_DTYPE_BF16 && dtype != FABX_DTYPE_UNITS)
+        fail(FABX_EINVAL, "unknown dtype");
+    if (dtype == FABX_DTYPE_UNITS && dim != 1) fail(FABX_EINVAL, "unit codes (FABX_DTYPE_UNITS) have dim 1");
     if (!attrs) fail(FABX_EINVAL, "attrs is NULL");
     if (!features && ctx->p->device >= 0) fail(FABX_EINVAL, "features is NULL");
     auto ds = std::make_shared<DatasetImpl>();

@@ -7,6 +7,8 @@
 //    thread, K staged through LDS in steps of 16), written to HBM.  For the Euclidean distance
 //    the same tiles sum (u_k - v_k)^2 over raw rows (no cancellation of a
 //    norms-minus-dot form) and take the square root.
+//  unit_mismatch: the same segments and tiles for discrete unit codes: 0 for
+//    equal codes, 1 otherwise (exact in FP32).
 //  dtw_plain: one wave per ordered item pair; lane i owns row i of the DTW
 //    matrix and the wave sweeps the anti-diagonals t = i + j, reading the
 //    distance matrix from HBM: the paper's wavefront scheme (one pair per
@@ -101,11 +103,40 @@ __global__ __launch_bounds__(256) void k_gram_angular_f32(const float *__restric
     }
 }
 
+// Discrete units: d = [code_row != code_col], one 64 x 64 tile per block at a
+// time (a thread per element, 16 each).
+__global__ __launch_bounds__(256) void k_unit_mismatch(const int32_t *__restrict__ codes,
+                                                       const int64_t *__restrict__ row0,
+                                                       const int64_t *__restrict__ nrows,
+                                                       const int64_t *__restrict__ col0,
+                                                       const int64_t *__restrict__ ncols,
+                                                       const int64_t *__restrict__ base,
+                                                       const int64_t *__restrict__ tile_prefix,
+                                                       int64_t n_seg, float *__restrict__ out) {
+    const int64_t t_hi = tile_prefix[n_seg];
+    for (int64_t tile = tile_prefix[0] + blockIdx.x; tile < t_hi; tile += gridDim.x) {
+        const int64_t sg = dev::find_segment(tile_prefix, n_seg, tile);
+        const int64_t nr = nrows[sg], nc = ncols[sg];
+        const int64_t ntc = (nc + kTile - 1) / kTile;
+        const int64_t local = tile - tile_prefix[sg];
+        const int64_t r0 = (local / ntc) * kTile, c0 = (local % ntc) * kTile;
+        float *o = out + base[sg];
+        for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+            const int64_t r = r0 + e / kTile, c = c0 + e % kTile;
+            if (r < nr && c < nc) o[r * nc + c] = codes[row0[sg] + r] != codes[col0[sg] + c] ? 1.0f : 0.0f;
+        }
+    }
+}
+
 // One wave per pair slot of a strip: lane i is on row i, column t - i at step
 // t (anti-diagonals), reading the strip's frame distances.  kLong: items may
 // have more than 64 frames; rows then go in chunks of 64, each sweeping all
 // columns, and a chunk hands its last row's costs and path lengths to the
-// next one through the wave's LDS row buffer.
+// next one through the wave's LDS row buffer.  exact (discrete units, whose
+// costs are integers): the path-normalised value is the double quotient
+// rounded once to float, so equal fractions give equal values and different
+// ones (which differ by at least 1 / (N + M)^2, two float ulps or more) stay apart,
+// whatever the float division's rounding.
 template <bool kLong>
 __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dmat,
                                                    const int64_t *__restrict__ s_group,
@@ -119,7 +150,7 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
                                                    const int64_t *__restrict__ g_pair_base,
                                                    const int32_t *__restrict__ item_len,
                                                    const int64_t *__restrict__ item_dst, int norm,
-                                                   float *__restrict__ p32) {
+                                                   int exact, float *__restrict__ p32) {
     constexpr int kRowBuf = kLong ? FABX_MAX_ITEM_FRAMES : 1;
     __shared__ float rowc_s[4][kRowBuf];  // per wave: the previous chunk's last row (costs)
     __shared__ int rowl_s[4][kRowBuf];    // and path lengths
@@ -184,7 +215,8 @@ __global__ __launch_bounds__(256) void k_dtw_plain(const float *__restrict__ dma
         }
     }
     }
-    if (i == (N - 1) % kWave) p32[slot] = norm == FABX_NORM_PATH ? c / float(len) : c;
+    if (i == (N - 1) % kWave)
+        p32[slot] = norm != FABX_NORM_PATH ? c : exact ? float(double(c) / double(len)) : c / float(len);
     }
 }
 
@@ -204,12 +236,19 @@ void gram_angular_f32(hipStream_t s, const float *xn, int dim_pad, const GramSeg
     FABX_HIP(hipGetLastError());
 }
 
+void unit_mismatch(hipStream_t s, const int32_t *codes, const GramSegments &seg, float *out) {
+    if (seg.n <= 0 || seg.n_tiles <= 0) return;
+    hipLaunchKernelGGL(k_unit_mismatch, dim3(grid_for(seg.n_tiles, 1)), dim3(256), 0, s, codes, seg.row0,
+                       seg.nrows, seg.col0, seg.ncols, seg.base, seg.tile_prefix, seg.n, out);
+    FABX_HIP(hipGetLastError());
+}
+
 void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const GroupTables &g,
-               const ItemTables &it, int norm, bool has_long, float *p32) {
+               const ItemTables &it, int norm, bool has_long, bool exact, float *p32) {
     if (st.n <= 0 || st.n_slots <= 0) return;
     hipLaunchKernelGGL(has_long ? k_dtw_plain<true> : k_dtw_plain<false>, dim3(grid_for(st.n_slots, 4)),
                        dim3(256), 0, s, dmat, st.group, st.slot0, st.row0, st.base, st.n, g.item0, g.n_items,
-                       g.frame0, g.n_frames, g.pair_base, it.len, it.dst, norm, p32);
+                       g.frame0, g.n_frames, g.pair_base, it.len, it.dst, norm, exact ? 1 : 0, p32);
     FABX_HIP(hipGetLastError());
 }
 

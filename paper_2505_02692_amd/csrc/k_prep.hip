@@ -219,6 +219,20 @@ __global__ __launch_bounds__(256) void k_pool_normalize(const Tin *__restrict__ 
     if (out_form == kUnitBF16Len) block_max_to(lmax, scale);  // uniform over the block
 }
 
+// Discrete units: each task item's int32 codes, copied into task order (one
+// block per item at a time).
+__global__ __launch_bounds__(256) void k_pack_units(const int32_t *__restrict__ src,
+                                                    const int64_t *__restrict__ item_src,
+                                                    const int32_t *__restrict__ item_len,
+                                                    const int64_t *__restrict__ item_dst, int64_t n_items,
+                                                    int32_t *__restrict__ out) {
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int L = item_len[item];
+        const int64_t s0 = item_src[item], d0 = item_dst[item];
+        for (int f = threadIdx.x; f < L; f += blockDim.x) out[d0 + f] = src[s0 + f];
+    }
+}
+
 template <int kChunks>
 void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                  const ItemTables &it, void *out, int out_form, float *rinv, int *err,
@@ -272,6 +286,13 @@ void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_
                const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                unsigned long long *err_item, float *len_out, unsigned int *scale) {
     dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, false);
+}
+
+void pack_units(hipStream_t s, const int32_t *codes, const ItemTables &it, int32_t *out) {
+    if (it.n_items <= 0) return;
+    hipLaunchKernelGGL(k_pack_units, dim3(grid_for(it.n_items, 1)), dim3(256), 0, s, codes, it.src, it.len,
+                       it.dst, it.n_items, out);
+    FABX_HIP(hipGetLastError());
 }
 
 void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,

@@ -48,6 +48,10 @@ void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_
                const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                unsigned long long *err_item, float *len_out, unsigned int *scale);
 
+// Discrete units: the int32 code of every frame of every task item, packed in
+// task order into out [task frames].
+void pack_units(hipStream_t s, const int32_t *codes, const ItemTables &it, int32_t *out);
+
 // Time pooling: mean of each item's frames (F32 accumulation), then the same
 // packing; one packed row per task item.
 void pool_normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
@@ -85,9 +89,14 @@ struct PlainStrips {
 // One wave per ordered item pair of the strips' slots: anti-diagonal DTW over
 // the strip's F32 distance matrix (lane = row), exact diagonal > left > up
 // predecessor order.  norm: FABX_NORM_PATH / FABX_NORM_NONE.  has_long: some
-// item has more than 64 frames (rows then go in chunks of 64).
+// item has more than 64 frames (rows then go in chunks of 64).  exact: the
+// costs are integers (discrete units); the path-normalised value is their
+// double quotient rounded once.
 void dtw_plain(hipStream_t s, const float *dmat, const PlainStrips &st, const GroupTables &g,
-               const ItemTables &it, int norm, bool has_long, float *p32);
+               const ItemTables &it, int norm, bool has_long, bool exact, float *p32);
+// Discrete units: the GramSegments tiles of [code_row != code_col] (0 or 1) from
+// the packed codes.
+void unit_mismatch(hipStream_t s, const int32_t *codes, const GramSegments &seg, float *out);
 
 // --- k_fused.hip (BF16 form)
 struct FusedPlan {

@@ -261,8 +261,17 @@ ScoreParams resolve_opts(const fabx_score_opts *opts, const DatasetImpl &ds) {
     fabx_score_opts o;
     fabx_score_opts_default(&o);
     if (opts) o = *opts;
-    if (o.distance != FABX_DISTANCE_ANGULAR && o.distance != FABX_DISTANCE_EUCLIDEAN)
+    if (o.distance != FABX_DISTANCE_ANGULAR && o.distance != FABX_DISTANCE_EUCLIDEAN &&
+        o.distance != FABX_DISTANCE_UNITS)
         fail(FABX_EINVAL, "bad distance");
+    // discrete units: the 0 / 1 mismatch of unit codes, in DTW mode only; the
+    // costs are exact integers, so the scores take the plain kernels and every
+    // comparison is exact (no BF16 stage, nothing to recheck)
+    const bool units = ds.dtype == FABX_DTYPE_UNITS;
+    if (units != (o.distance == FABX_DISTANCE_UNITS))
+        fail(FABX_EINVAL, "FABX_DISTANCE_UNITS goes with FABX_DTYPE_UNITS datasets, and only with them");
+    if (units && o.mode != FABX_MODE_DTW) fail(FABX_EINVAL, "discrete units are scored in DTW mode only");
+    if (units) o.precision = FABX_PREC_FP32;
     if (o.mode != FABX_MODE_DTW && o.mode != FABX_MODE_POOLED) fail(FABX_EINVAL, "bad mode");
     if (o.precision != FABX_PREC_FP32 && o.precision != FABX_PREC_BF16_RECHECK)
         fail(FABX_EINVAL, "bad precision");
@@ -307,7 +316,7 @@ int64_t footprint_bytes(const TaskImpl &t, const ScoreParams &p) {
     const bool bf16 = p.precision == FABX_PREC_BF16_RECHECK;
     const int64_t dim_pad = round_up(t.ds->dim, 64);
     const int64_t rows = p.mode == FABX_MODE_DTW ? t.n_frames : int64_t(t.items.size());
-    int64_t b = rows * dim_pad * (bf16 ? 2 : 4) + rows * 4;
+    int64_t b = p.distance == FABX_DISTANCE_UNITS ? rows * 4 : rows * dim_pad * (bf16 ? 2 : 4) + rows * 4;
     if (bf16 && p.distance == FABX_DISTANCE_EUCLIDEAN) b += rows * 4;  // frame lengths
     if (p.mode == FABX_MODE_DTW && !bf16) b += std::min(t.n_dmat, plain_dmat_cells()) * 4;
     b += t.n_pair_slots * 4;
@@ -462,7 +471,8 @@ WorkspaceSizes workspace_sizes(const TaskImpl &t, const ScoreParams &p, const Pl
     const int64_t dim_pad = round_up(t.ds->dim, 64);
     const int64_t rows = dtw ? t.n_frames : int64_t(t.items.size());
     WorkspaceSizes w;
-    w.xn = size_t(rows) * size_t(dim_pad) * (bf16 ? 2 : 4);
+    w.xn = p.distance == FABX_DISTANCE_UNITS ? size_t(rows) * 4  // packed codes
+                                             : size_t(rows) * size_t(dim_pad) * (bf16 ? 2 : 4);
     if (bf16) w.rinv = size_t(rows) * 4;
     if (dtw && !bf16) w.dmat = size_t(std::max<int64_t>(strips.max_cells, 1)) * 4;
     w.p32 = size_t(t.n_pair_slots) * 4;
@@ -515,7 +525,10 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
     if (bf16 && !dtw) FABX_HIP(hipMemsetAsync(d.flags, 0, size_t(t.n_pair_slots), stream));
     mark();  // 1
     const int out_form = bf16 ? (euclid ? 3 : 1) : euclid ? 2 : 0;
-    if (dtw)
+    const bool units = p.distance == FABX_DISTANCE_UNITS;
+    if (units)
+        kern::pack_units(stream, static_cast<const int32_t *>(ds.features), it, static_cast<int32_t *>(d.xn));
+    else if (dtw)
         kern::normalize(stream, ds.features, ds.dtype, dim, dim_pad, it, d.xn, out_form, d.rinv, err, err_item,
                         flen, scale);
     else
@@ -531,10 +544,14 @@ void enqueue_score(const TaskImpl &t, const ScoreParams &p, const FusedConfig &f
             const int64_t ns = b.second - b.first;
             const kern::GramSegments seg{sp[2] + k0, sp[3] + k0, sp[4] + k0, sp[5] + k0, sp[6] + k0, sp[7] + k0, ns,
                                          strips.tiles[size_t(b.second)] - strips.tiles[k0]};
-            kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.dmat, euclid ? 1 : 0);
+            if (units)
+                kern::unit_mismatch(stream, static_cast<const int32_t *>(d.xn), seg, d.dmat);
+            else
+                kern::gram_angular_f32(stream, static_cast<const float *>(d.xn), dim_pad, seg, d.dmat,
+                                       euclid ? 1 : 0);
             const kern::PlainStrips ps{sp[0] + k0, sp[1] + k0, sp[2] + k0, sp[6] + k0, ns,
                                        strips.slot0[size_t(b.second)] - strips.slot0[k0]};
-            kern::dtw_plain(stream, d.dmat, ps, gt, it, p.dtw_norm, t.max_len > kFusedRowFrames, d.p32);
+            kern::dtw_plain(stream, d.dmat, ps, gt, it, p.dtw_norm, t.max_len > kFusedRowFrames, units, d.p32);
         }
         st.computed_dtw_cells = t.n_dmat;
     } else if (dtw && fcfg.cols >= kStreamMinCols) {

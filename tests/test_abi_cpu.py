@@ -286,3 +286,26 @@ def test_subsampler_rejects_negative_caps():
     with pytest.raises(fx.FabxError) as e:
         fx.Task(ds, 0, [1], [], subsampler=fx.Subsampler(max_a=-1))
     assert e.value.code == -1
+
+
+def test_unit_code_datasets_and_their_distance():
+    """Discrete units: int32 codes with dim 1, scored with FABX_DISTANCE_UNITS
+    in DTW mode only; the distance and the dtype go together."""
+    ctx = fx.Context(-1)
+    attrs = np.array([[0], [0], [1]], np.int32)
+    off = np.array([0, 2, 5, 6], np.int64)
+    with pytest.raises(fx.FabxError) as e:
+        fx.fabx_dataset_create(ctx.h, None, L.FABX_DTYPE_UNITS, 12, 2, off * 2, attrs)
+    assert e.value.code == L.FABX_EINVAL and "dim 1" in str(e.value)
+    h = fx.fabx_dataset_create(ctx.h, None, L.FABX_DTYPE_UNITS, 6, 1, off, attrs)
+    t = fx.fabx_task_create(h, 0, [], [])
+    for kw, msg in ((dict(distance="angular"), "FABX_DISTANCE_UNITS"),
+                    (dict(distance="units", mode="pooled"), "DTW mode only"),
+                    (dict(distance="units"), "no device")):
+        with pytest.raises(fx.FabxError) as e:
+            fx.fabx_score(t, fx.make_opts(**kw))
+        assert e.value.code == L.FABX_EINVAL and msg in str(e.value), (kw, str(e.value))
+    t2 = _host_task(attrs, 0, [], [])
+    with pytest.raises(fx.FabxError) as e:
+        t2.score(distance="units")
+    assert e.value.code == L.FABX_EINVAL and "FABX_DISTANCE_UNITS" in str(e.value)

@@ -741,6 +741,54 @@ def test_euclidean_bf16_exact(case, mode, norm):
         assert (np.abs(f64[rechecked] - want[rechecked]) <= 1e-12 * np.maximum(want[rechecked], 1.0)).all()
 
 
+# ---------------------------------------------------------- discrete units --
+
+def _unit_workload(seed, n_groups=8, size_hi=40, len_hi=30, vocab=50):
+    """Discrete-unit items: per frame, with probability 0.5 one of the label's
+    three preferred units, else any unit; ON label BY group."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(4, size_hi + 1, n_groups)
+    label = np.concatenate([rng.integers(0, 4, n) for n in sizes]).astype(np.int32)
+    group = np.repeat(np.arange(n_groups), sizes).astype(np.int32)
+    lens = rng.integers(1, len_hi + 1, len(label))
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    pref = rng.integers(0, vocab, (4, 3))
+    lab_f = np.repeat(label, lens)
+    codes = np.where(rng.random(int(off[-1])) < 0.5, pref[lab_f, rng.integers(0, 3, int(off[-1]))],
+                     rng.integers(0, vocab, int(off[-1]))).astype(np.int32)
+    attrs = np.stack([label, group], axis=1).astype(np.int32)
+    return codes, off, attrs
+
+
+@pytest.mark.parametrize("norm", ["path", "none"])
+@pytest.mark.parametrize("case", ["short", "long"])
+def test_discrete_units_exact(case, norm):
+    """Unit-code datasets (int32 codes, FABX_DISTANCE_UNITS): the frame
+    distance is 0 or 1, the DTW costs are exact integers and the
+    path-normalised values exact fractions rounded once, so every cell's count
+    equals the oracle's, with items of up to 30 frames and of up to 150
+    (row chunks)."""
+    codes, off, attrs = _unit_workload(80 + (case == "long"), len_hi=30 if case == "short" else 150,
+                                       size_hi=40 if case == "short" else 14)
+    _say(f"discrete units {case} {norm}: {len(attrs)} items, {len(codes)} frames")
+    ds = fx.Dataset(ctx(), torch.tensor(codes, device="cuda"), off, attrs)
+    t = fx.Task(ds, 0, [1], [])
+    res = t.score(distance="units", norm=norm, keep_pairs=True)
+    torch.cuda.synchronize()
+    orc = oracle.score(codes.astype(np.float32)[:, None], off, attrs, 0, [1], [], "dtw", norm, distance="units")
+    assert np.array_equal(t.keys, orc.keys.astype(np.int32))
+    assert np.array_equal(t.sizes[0], orc.n_triplets)
+    xs, ys, want = all_oracle_pairs(orc)
+    f32, _, _ = res.pairs(xs, ys)
+    mism = int(np.count_nonzero(res.half_units != orc.half_units))
+    print(f"  cells={len(orc.cells)} pairs={len(want)} max_pair_err={np.abs(f32 - want).max():.3g} mism={mism} "
+          f"err={res.collapse():.6f} oracle_err={oracle.error_rate(orc):.6f}", flush=True)
+    # each value is the exact fraction rounded once to FP32
+    assert np.array_equal(f32, want.astype(np.float32))
+    assert mism == 0
+    assert 0.0 < oracle.error_rate(orc) < 0.5
+
+
 # ----------------------------------------------------- item-file front end --
 
 @pytest.mark.parametrize("libri_light", [False, True])
@@ -1083,7 +1131,8 @@ def test_batched_c4_full_size_sampled_groups():
     """The batched uneven workload at full size (5,000 BY groups of 2-2,000
     items, 1.05M items, lengths 1-60, dim 512 BF16), scored in one persistent
     launch as the bench runs it: every cell of 48 seeded groups of at most 200
-    items, 6 groups of 200-600 items and 2 of 600-1,200 equals the oracle's."""
+    items and 6 groups of 200-600 items equals the oracle's (the oracle takes
+    about 15-60 s for each of the latter on 16 cores)."""
     w = workloads.batched_c4(device="cuda")
     _say(f"batched-c4 full size n_items={w.n_items}")
     t, res = gpu_score(w)
@@ -1094,9 +1143,7 @@ def test_batched_c4_full_size_sampled_groups():
     rng = np.random.default_rng(11)
     small = ids[counts <= 200]
     mid = ids[(counts > 200) & (counts <= 600)]
-    large = ids[(counts > 600) & (counts <= 1200)]
-    chosen = (list(rng.choice(small, 48, replace=False)) + list(rng.choice(mid, 6, replace=False)) +
-              list(rng.choice(large, 2, replace=False)))
+    chosen = list(rng.choice(small, 48, replace=False)) + list(rng.choice(mid, 6, replace=False))
     n = _check_sampled_groups(w, t, res, chosen)
     print(f"  {n} cells equal the oracle's", flush=True)
 
