@@ -351,14 +351,15 @@ def cpu_baseline(oracle, fx, w, target_seconds=15.0, seed=0):
     log(f"cpu baseline: {len(take)} groups took {dt:.1f} s (estimated {est:.1f} s)")
     # the estimates charge each part with the whole probe time, so they run
     # high; when the sample took well under the target, scale them by what it
-    # took and draw the sample again (same order, so it grows)
+    # took and draw the sample again (same order; groups passed over as too
+    # large may now fit)
     scale = 1.0
     for _ in range(3):
         if est <= 0 or dt >= 0.4 * target_seconds:
             break
         scale *= max(dt / est, 0.05)
         take2, est2 = select(scale)
-        if len(take2) <= len(take):
+        if take2 == take:
             break
         take, est = take2, est2
         r, dt = run(take)
@@ -490,6 +491,9 @@ def main():
                     help="let the second host thread's work use the shared host thread pool")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run 3 plain device copies of this many MiB (to scale HBM byte counters)")
+    ap.add_argument("--stream-probe-mib", type=int, default=0,
+                    help="also run the HBM streaming probe (the normalise kernel's access pattern, FP32 -> BF16, "
+                         "dim 768) over this many MiB of FP32 rows, three times, and log its bandwidth")
     args = ap.parse_args()
     c2_main = args.workload == "c2"
     if args.steps is None:
@@ -520,6 +524,23 @@ def main():
             dst.copy_(src)
         sync()
         log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB (read + write each)")
+        del src, dst
+    if args.stream_probe_mib > 0:
+        rows = (args.stream_probe_mib << 20) // (768 * 4)
+        src = torch.randn(rows, 768, device="cuda")
+        dst = torch.empty(rows, 768, device="cuda", dtype=torch.bfloat16)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        for k in range(3):
+            fx.fabx_probe_stream(src, dst)
+            ev[k + 1].record()
+        sync()
+        nbytes = rows * 768 * (4 + 2)
+        for k in range(3):
+            ms = ev[k].elapsed_time(ev[k + 1])
+            log(f"stream probe: {rows} rows x 768, {nbytes / 1e9:.2f} GB moved in {ms:.3f} ms = "
+                f"{nbytes / ms / 1e6:.0f} GB/s")
+        assert torch.equal(dst, src.to(torch.bfloat16))
         del src, dst
     gen_name, mode, wl_desc = WORKLOADS[args.workload]
     headline = args.workload == "c4"

@@ -442,6 +442,19 @@ typedef struct fabx_tune_report {
  * candidates disagree (a defect). */
 int fabx_autotune(fabx_task *task, const fabx_score_opts *opts, fabx_tune_report *report);
 
+/* HBM streaming probe, for measurement only: converts n_rows rows of dim FP32
+ * values (src, device, [n_rows][dim]) to BF16 rows of dim_pad = the multiple
+ * of 64 at or above dim (dst, device, [n_rows][dim_pad]; the padding columns
+ * are written as zeros) with the access widths and order of the normalise
+ * kernel but none of its arithmetic, on `hip_stream` (NULL: the null stream),
+ * asynchronously.  It moves 4 dim bytes in and 2 dim_pad bytes out per row,
+ * the normalise kernel's traffic for FP32 features, so the achievable
+ * bandwidth and the byte counters' scaling for that access pattern can be
+ * measured beside it.  Both buffers are caller-owned.  Errors: EINVAL (null
+ * pointer, n_rows < 0, dim not a positive multiple of 4 or above 2048),
+ * EHIP. */
+int fabx_probe_stream(const float *src, uint16_t *dst, int64_t n_rows, int32_t dim, void *hip_stream);
+
 /* -------------------------------------------------------------- collapse */
 
 /* ABX error rate 1 - D (Score.collapse).  n_levels = 0: D is the cell-size

@@ -339,6 +339,19 @@ def make_opts(mode: str = "dtw", precision: str = "bf16", norm: str = "path", ma
     return o
 
 
+def fabx_probe_stream(src, dst, stream=None) -> None:
+    """The HBM streaming probe (measurement only): src float32 [n_rows, dim] and
+    dst bfloat16 [n_rows, dim_pad] device tensors, on the given raw stream
+    (default: torch's current stream of src's device)."""
+    n_rows, dim = int(src.shape[0]), int(src.shape[1])
+    if dst.shape[0] != n_rows or dst.shape[1] != (dim + 63) // 64 * 64:
+        raise ValueError("dst must be [n_rows, dim rounded up to 64]")
+    if stream is None:
+        stream = _current_stream_ptr(src.device.index)
+    _check(lib().fabx_probe_stream(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n_rows, dim,
+                                   stream))
+
+
 def _current_stream_ptr(device: int):
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)

@@ -125,6 +125,7 @@ SIGNATURES = {
     "fabx_score_noalloc": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(_i64), _P(fabx_stats)]),
     "fabx_result_wait": (ctypes.c_int, [_vp]),
     "fabx_autotune": (ctypes.c_int, [_vp, _P(fabx_score_opts), _P(fabx_tune_report)]),
+    "fabx_probe_stream": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_int32, _vp]),
     "fabx_result_free": (None, [_vp]),
     "fabx_result_num_cells": (_i64, [_vp]),
     "fabx_result_key_width": (_i32, [_vp]),

@@ -7,6 +7,7 @@
 #include <new>
 
 #include "internal.h"
+#include "kernels.h"
 
 namespace fabx {
 
@@ -360,6 +361,13 @@ int fabx_slice_frames(const double *onset, const double *offset, int64_t n, doub
             start[k] = i0;
             len[k] = std::max<int64_t>(0, i1 - i0 + 1);
         }
+    });
+}
+
+int fabx_probe_stream(const float *src, uint16_t *dst, int64_t n_rows, int32_t dim, void *hip_stream) {
+    return guarded([&] {
+        if (!src || !dst || n_rows < 0 || dim <= 0) fail(FABX_EINVAL, "bad probe arguments");
+        fabx::kern::probe_stream(static_cast<hipStream_t>(hip_stream), src, dim, n_rows, dst);
     });
 }
 

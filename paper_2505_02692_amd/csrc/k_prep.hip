@@ -233,6 +233,49 @@ __global__ __launch_bounds__(256) void k_pack_units(const int32_t *__restrict__ 
     }
 }
 
+// HBM streaming probe with k_normalize's access widths and order: a block takes
+// 8 rows at a time, each wave two rows in flight, 16-byte FP32 loads per lane
+// and 8-byte BF16 stores, but no arithmetic beyond the conversion: it reads
+// 4 x dim and writes 2 x dim_pad bytes per row, the normalise kernel's
+// traffic for FP32 input, so the two can be compared and the byte counters
+// calibrated on this access pattern.
+template <int kChunks>
+__global__ __launch_bounds__(256) void k_probe_stream(const float *__restrict__ src, int dim, int dim_pad,
+                                                      int64_t n_rows, uint16_t *__restrict__ out) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int64_t r0 = int64_t(blockIdx.x) * 8; r0 < n_rows; r0 += int64_t(gridDim.x) * 8) {
+        const int64_t ra = r0 + wave, rb = r0 + wave + 4;
+        float v[kChunks][4], u[kChunks][4];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const int k = 4 * (lane + kWave * c);
+            load_row_chunk<float>(src + min(ra, n_rows - 1) * int64_t(dim), k, dim, v[c]);
+            load_row_chunk<float>(src + min(rb, n_rows - 1) * int64_t(dim), k, dim, u[c]);
+        }
+        auto put = [&](int64_t row, float (&w)[kChunks][4]) {
+            uint16_t *o = out + row * dim_pad;
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int k = 4 * (lane + kWave * c);
+                if (k < dim_pad) {
+                    uint2 q;
+                    q.x = uint32_t(dev::f32_to_bf16(w[c][0])) | (uint32_t(dev::f32_to_bf16(w[c][1])) << 16);
+                    q.y = uint32_t(dev::f32_to_bf16(w[c][2])) | (uint32_t(dev::f32_to_bf16(w[c][3])) << 16);
+                    *reinterpret_cast<uint2 *>(o + k) = q;
+                }
+            }
+        };
+        if (ra < n_rows) put(ra, v);
+        if (rb < n_rows) put(rb, u);
+    }
+}
+
+template <int kChunks>
+void launch_probe(hipStream_t s, const float *src, int dim, int dim_pad, int64_t n_rows, uint16_t *out) {
+    hipLaunchKernelGGL(k_probe_stream<kChunks>, dim3(grid_for((n_rows + 7) / 8, 1)), dim3(256), 0, s, src, dim,
+                       dim_pad, n_rows, out);
+}
+
 template <int kChunks>
 void launch_norm(hipStream_t s, const void *features, int dtype, int dim, int dim_pad,
                  const ItemTables &it, void *out, int out_form, float *rinv, int *err,
@@ -286,6 +329,23 @@ void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_
                const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                unsigned long long *err_item, float *len_out, unsigned int *scale) {
     dispatch(s, features, dtype, dim, dim_pad, it, out, out_form, rinv, err, err_item, len_out, scale, false);
+}
+
+void probe_stream(hipStream_t s, const float *src, int dim, int64_t n_rows, uint16_t *out) {
+    if (n_rows <= 0) return;
+    if (dim % 4 != 0 || dim > 2048) fail(FABX_EINVAL, "the streaming probe takes dim a multiple of 4, at most 2048");
+    const int dim_pad = int((dim + 63) / 64 * 64);
+    switch ((dim_pad + 255) / 256) {
+        case 1: launch_probe<1>(s, src, dim, dim_pad, n_rows, out); break;
+        case 2: launch_probe<2>(s, src, dim, dim_pad, n_rows, out); break;
+        case 3: launch_probe<3>(s, src, dim, dim_pad, n_rows, out); break;
+        case 4: launch_probe<4>(s, src, dim, dim_pad, n_rows, out); break;
+        case 5: launch_probe<5>(s, src, dim, dim_pad, n_rows, out); break;
+        case 6: launch_probe<6>(s, src, dim, dim_pad, n_rows, out); break;
+        case 7: launch_probe<7>(s, src, dim, dim_pad, n_rows, out); break;
+        default: launch_probe<8>(s, src, dim, dim_pad, n_rows, out); break;
+    }
+    FABX_HIP(hipGetLastError());
 }
 
 void pack_units(hipStream_t s, const int32_t *codes, const ItemTables &it, int32_t *out) {

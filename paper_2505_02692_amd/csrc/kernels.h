@@ -48,6 +48,10 @@ void normalize(hipStream_t s, const void *features, int dtype, int dim, int dim_
                const ItemTables &it, void *out, int out_form, float *rinv, int *err,
                unsigned long long *err_item, float *len_out, unsigned int *scale);
 
+// HBM streaming probe: rows [n_rows][dim] FP32 -> [n_rows][dim_pad] BF16 with
+// the normalise kernel's access widths (dim a multiple of 4, <= 2048).
+void probe_stream(hipStream_t s, const float *src, int dim, int64_t n_rows, uint16_t *out);
+
 // Discrete units: the int32 code of every frame of every task item, packed in
 // task order into out [task frames].
 void pack_units(hipStream_t s, const int32_t *codes, const ItemTables &it, int32_t *out);

@@ -33,17 +33,18 @@ def _task(w):
     return ds, fx.Task(ds, w.on, w.by, w.across)
 
 
-@pytest.mark.parametrize("mode,precision,norm", [("dtw", "bf16", "path"), ("dtw", "bf16", "none"),
-                                                 ("dtw", "fp32", "path"), ("pooled", "bf16", "path"),
-                                                 ("pooled", "fp32", "path")])
-def test_noalloc_equals_score_on_two_calls(mode, precision, norm):
+@pytest.mark.parametrize("mode,precision,norm,distance", [
+    ("dtw", "bf16", "path", "angular"), ("dtw", "bf16", "none", "angular"), ("dtw", "fp32", "path", "angular"),
+    ("pooled", "bf16", "path", "angular"), ("pooled", "fp32", "path", "angular"),
+    ("dtw", "bf16", "path", "euclidean"), ("pooled", "bf16", "path", "euclidean")])
+def test_noalloc_equals_score_on_two_calls(mode, precision, norm, distance):
     big = workloads.within_c2(n_items=3000, dim=256, centroid_std=0.1, seed=7)
     small = workloads.plain_c1(centroid_std=0.15, seed=2)
     for w in (big, small):
-        _say(f"noalloc {mode} {precision} {norm} {w.name} n_items={w.n_items}")
+        _say(f"noalloc {mode} {precision} {norm} {distance} {w.name} n_items={w.n_items}")
         ds, t = _task(w)
-        ref = t.score(mode=mode, precision=precision, norm=norm)
-        opts = fx.make_opts(mode=mode, precision=precision, norm=norm)
+        ref = t.score(mode=mode, precision=precision, norm=norm, distance=distance)
+        opts = fx.make_opts(mode=mode, precision=precision, norm=norm, distance=distance)
         got, st = fx.fabx_score_noalloc(t.h, opts, len(t))
         torch.cuda.synchronize()
         assert np.array_equal(got, ref.half_units)
@@ -64,6 +65,26 @@ def test_noalloc_with_items_over_64_frames(precision):
         ds, t = _task(wl)
         ref = t.score(precision=precision)
         got, st = fx.fabx_score_noalloc(t.h, fx.make_opts(precision=precision), len(t))
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.half_units)
+
+
+def test_noalloc_discrete_units():
+    """Unit-code datasets (the packed codes and the distance tiles of the plain
+    kernels) through the scratch array, on two calls in a row."""
+    rng = np.random.default_rng(5)
+    for n_items in (400, 90):
+        _say(f"noalloc discrete units n_items={n_items}")
+        lens = rng.integers(1, 40, n_items)
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        label = rng.integers(0, 3, n_items)
+        codes = np.where(rng.random(int(off[-1])) < 0.5, np.repeat(label, lens),
+                         rng.integers(0, 20, int(off[-1]))).astype(np.int32)
+        attrs = np.stack([label, rng.integers(0, 2, n_items)], axis=1).astype(np.int32)
+        ds = fx.Dataset(ctx(), torch.tensor(codes, device="cuda"), off, attrs)
+        t = fx.Task(ds, 0, [1], [])
+        ref = t.score(distance="units")
+        got, _ = fx.fabx_score_noalloc(t.h, fx.make_opts(distance="units"), len(t))
         torch.cuda.synchronize()
         assert np.array_equal(got, ref.half_units)
 
