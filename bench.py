@@ -573,6 +573,7 @@ def main():
     log(f"bf16 form, serial: {ms_step_serial:.2f} ms/step, stages {stages}")
     assert errs[-1] == serrs[-1]
     st0 = stats[-1]
+    log(f"task: {st0['n_items']} items in cells, {st0['n_frames']} frames packed")
     n_trip = st0["n_triplets"]
     value = n_trip / (ms_step / 1e3)
     t_build = []
@@ -616,7 +617,8 @@ def main():
         log(f"cpu baseline: {cpu}")
     wl_cfg = {"workload": wl_desc, "cells": st0["n_cells"], "triplets": n_trip,
               "dtw_cells": st0["dtw_cells"], "dtw_cells_unordered": st0["dtw_cells_sym"],
-              "items": w.n_items, "frames": w.n_frames, "dim": w.dim, "parallelism": "single GPU"}
+              "items": w.n_items, "frames": w.n_frames, "items_in_cells": st0["n_items"],
+              "frames_packed": st0["n_frames"], "dim": w.dim, "parallelism": "single GPU"}
     del ds, w
 
     # each further leg runs on a context of its own: a context keeps the device

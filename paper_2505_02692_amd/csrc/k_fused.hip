@@ -65,10 +65,11 @@ struct Tile {
     static constexpr int kCT = kWaveCols / 32;
     static constexpr int kDStride = kC + 2;  // LDS distance tile stride (floats)
     static constexpr int kStageBytes = (kRows + kC) * kLdsRow * 2;
-    // distance tile + a tail guard: the DTW loop reads up to 63 columns past a row's end
-    static constexpr int kTileBytes = (kRows * kDStride + kWave) * 4;
-    // column flags: a zero guard of one wave before the span and one wave + 2 after
-    static constexpr int kFlagLen = kWave + kC + kWave + 2;
+    // distance tile + a tail guard: the DTW loop reads up to 67 columns past a
+    // row's end (64 of drain, 3 of read-ahead)
+    static constexpr int kTileBytes = (kRows * kDStride + kWave + 4) * 4;
+    // column flags: a zero guard of one wave before the span and one wave + 4 after
+    static constexpr int kFlagLen = kWave + kC + kWave + 4;
     static constexpr int kSmemBytes = kStageBytes > kTileBytes ? kStageBytes : kTileBytes;
 };
 
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     using T = Tile<kC>;
     constexpr int kDStride = T::kDStride, kFlagLen = T::kFlagLen;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[T::kSmemBytes];
-    __shared__ uint16_t colflag[4][kFlagLen];
+    __shared__ uint32_t colflag[4][kFlagLen];
     __shared__ __attribute__((aligned(16))) float norm_s[kRows + kC];  // row then column inverse norms
     __shared__ __attribute__((aligned(16))) float len_s[kEuclid ? kRows + kC : 1];  // and lengths
     if constexpr (kEuclid) delta *= __uint_as_float(*scale);
@@ -315,7 +316,8 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     // and columns col0 + lane % 32 the element is a frame against itself when
     // acc_row(i, lane) - lane % 32 equals e = (column block start + col0) -
     // (row block start + 32h); two operations per element.
-    float cmax = 0.0f;
+    // (kept as bits: the values are >= 0, whose bit patterns order like them)
+    uint32_t cmax = 0;
     const int lane_term = 4 * (lane / 32) - lane % 32;
 #pragma unroll
     for (int ct = 0; ct < T::kCT; ++ct) {
@@ -331,21 +333,26 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             const int q = e > -32 && e < 32 ? int(e) - lane_term : 1 << 20;  // 1 << 20: no such element
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
+                // rows past the block's frames belong to no item (their DTW lanes
+                // are discarded): the elements from the first whose row in lanes
+                // 0-31 is one of them on are skipped (uniform over the wave; the
+                // rows grow with i)
+                if (32 * h + 8 * (i / 4) + (i % 4) >= r_frames) break;
                 const int r = 32 * h + acc_row(i, lane);
                 const float cs = fminf(fmaxf(acc[h][ct][i] * norm_s[r] * rc, -1.0f), 1.0f);
                 const float ac = 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs);
-                cmax = fmaxf(cmax, ac);
+                cmax = max(cmax, __float_as_uint(ac));
                 if constexpr (kEuclid) {
                     const float lr = len_s[r], dl = lr - lc;
                     const float d = __builtin_sqrtf(fmaxf(fmaf(dl, dl, 2.0f * lr * lc * (1.0f - cs)), 0.0f));
                     dt[r * kDStride + col] = ac > kNearCos ? -d : d;
                 } else {
-                    dt[r * kDStride + col] = dev::acos_over_pi(cs);
+                    dt[r * kDStride + col] = dev::acos_over_pi_clamped(cs);
                 }
             }
         }
     }
-    if (__ballot(cmax > kNearCos) != 0 && lane == 0) atomicOr(&near_s, 1);
+    if (__ballot(__uint_as_float(cmax) > kNearCos) != 0 && lane == 0) atomicOr(&near_s, 1);
 
     // 3. DTW.  Column items of this block split over the 4 waves by start frame.
     // Lane constants: the row item of lane `lane`.
@@ -382,7 +389,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             start += L;
         }
         // column c of this wave's span is entry kWave + c: bit 0 = first column
-        // of an item, bits 1..14 = the item's index in the column block, bit 15 =
+        // of an item, bits 1..14 = the item's index in the column block, bit 31 =
         // last column.  The guards read as 0 (no item start, no output).
         // Same-wave LDS stores land in issue order.
         for (int j = lane; j < kFlagLen; j += kWave) colflag[w][j] = 0;
@@ -392,7 +399,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                 const int L = item_len[c_item0 + k];
                 for (int j = lane; j < L; j += kWave)
                     colflag[w][kWave + start2 - s_begin + j] =
-                        uint16_t((j == 0 ? 1 : 0) | (k << 1) | (j == L - 1 ? 0x8000 : 0));
+                        uint32_t((j == 0 ? 1u : 0u) | (uint32_t(k) << 1) | (j == L - 1 ? 0x80000000u : 0u));
                 start2 += L;
             }
         }
@@ -407,25 +414,28 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const bool row_valid = x_task >= 0;
     const bool top = ir == 0;
     const bool last_row = row_valid && ir == nx - 1;
-    // The first row of an item has no row above.  The lane above it (the last
-    // row of another item, or a row past the block's frames) sends +inf
-    // instead of its cost: that lane may be on columns outside its span, where
-    // the tile holds values of no use (possibly stale LDS), so its cost must
-    // not be combined.  Lane 0 has no lane above: it reads 0 and adds +inf.
-    const bool send_inf = !row_valid || ir == nx - 1;
-    const float lane0_pen = lane == 0 ? kInf : 0.0f;
+    // The first row of an item has no row above: it adds +inf to whatever the
+    // lane above sends (the last row of another item, or a row past the
+    // block's frames; lane 0 reads 0).  That lane may be on columns outside its
+    // span, where the tile holds values of no use (possibly stale LDS), so the
+    // sum may be a quiet NaN; a first row's up neighbour only enters fminf
+    // (which returns the other operand for a NaN) and <= tests (false for a
+    // NaN, as for +inf below a finite threshold), and its own cost, the one
+    // it sends, is always finite on its columns.
+    const float top_pen = top ? kInf : 0.0f;
     const float diag_first = top ? 0.0f : kInf;       // virtual c[-1][-1] = 0 at an item start
     const uint32_t pd_first = top ? 0x0000FFFFu : 0u;  // its length interval: Lmin = Lmax = 0
     const int64_t px = row_valid ? int64_t(x_task) - gitem0 : 0;  // row item's position in the group
     // at step t the lane is on column t - ir of the wave's span: distance
-    // dcol[t], flags fcol[t], read a pair of steps ahead.  ir <= lane, so dcol[0]
-    // is inside the tile; the last read-ahead is at most max_n <= 64 columns past
-    // the span: row 63 then ends 2 floats short of the tile's tail guard, and the
-    // flags' zero guard covers it.
+    // dcol[t], flags fcol[t], read four steps ahead.  ir <= lane, so dcol[0] is
+    // inside the tile; the last read-ahead is at most max_n + 2 <= 66 columns
+    // past the span: row 63 then ends 3 floats short of the tile's tail guard,
+    // and the flags' zero guard covers it.
     const float *dcol = dt + lane * kDStride + s_begin - ir;
-    const uint16_t *fcol = &colflag[w][kWave - ir];
-    // a cell is output on the item's last row and last column: flags >= 0x8000
-    const uint32_t out_min = last_row ? 0x8000u : 0x10000u;
+    const uint32_t *fcol = &colflag[w][kWave - ir];
+    // a cell is output on the item's last row and last column: flags >=
+    // 0x80000000 (flags never reach 0xFFFFFFFF)
+    const uint32_t out_min = last_row ? 0x80000000u : 0xFFFFFFFFu;
 
     // Cells outside a lane's column range are computed too (on guard columns)
     // but never read: the first column of every item resets left and diagonal.
@@ -440,7 +450,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     constexpr bool careful = decltype(careful_tag)::value;
     auto step = [&](const uint32_t cf, const float dv) {
         const bool first = cf & 1;
-        up = shr1z(send_inf ? kInf : c) + lane0_pen;
+        up = shr1z(c) + top_pen;
         if (kPath) Pup = shr1u(Pup, P);
         const float diag = first ? diag_first : up_prev;
         const float left = first ? kInf : c;
@@ -498,20 +508,44 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             }
         }
     };
-    uint32_t cf0 = fcol[0], cf1 = fcol[1];
-    float dv0 = dcol[0], dv1 = dcol[1];
-    int t = 0;
-    for (; t + 1 < steps; t += 2) {
-        const uint32_t ca = cf0, cb2 = cf1;
-        const float da = dv0, db = dv1;
-        cf0 = fcol[t + 2];
-        cf1 = fcol[t + 3];
-        dv0 = dcol[t + 2];
-        dv1 = dcol[t + 3];
-        step(ca, da);
-        step(cb2, db);
+    // four steps at a time from one of two register buffers while the other
+    // takes the next four (read ahead up to step steps + 3); the buffers
+    // alternate, so no values are copied between them
+    auto load4 = [&](uint32_t (&f)[4], float (&d)[4], int t0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            f[k] = fcol[t0 + k];
+            d[k] = dcol[t0 + k];
+        }
+    };
+    auto run4 = [&](const uint32_t (&f)[4], const float (&d)[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) step(f[k], d[k]);
+    };
+    auto tail = [&](const uint32_t (&f)[4], const float (&d)[4], int n) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k < n) step(f[k], d[k]);
+    };
+    uint32_t fa[4], fb[4];
+    float da[4], db[4];
+    load4(fa, da, 0);
+    for (int t = 0;;) {
+        if (t + 4 > steps) {
+            tail(fa, da, steps - t);
+            break;
+        }
+        load4(fb, db, t + 4);
+        run4(fa, da);
+        t += 4;
+        if (t + 4 > steps) {
+            tail(fb, db, steps - t);
+            break;
+        }
+        load4(fa, da, t + 4);
+        run4(fb, db);
+        t += 4;
     }
-    if (t < steps) step(cf0, dv0);
     };
     if (near_s != 0)  // uniform: written before the barrier above
         run(std::true_type{});
