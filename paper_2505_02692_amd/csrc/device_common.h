@@ -101,14 +101,14 @@ __device__ __forceinline__ float acos_over_pi(float x) {
     return x < 0.0f ? 1.0f - r : r;
 }
 
-// acos_over_pi for x already in [-1, 1], with the reflection folded into the
-// last steps: r = acos(|x|) / pi as above lies in [0, 1/2], so h = r - 1/2 <= 0
-// and acos(x) / pi = 1/2 - copysign(h, x) (r for x >= 0, 1 - r below): one
-// fused multiply-add, a sign transfer and a subtraction replace the product,
-// the subtraction and the select (the result moves by at most one rounding of
-// a value below 1).
-__device__ __forceinline__ float acos_over_pi_clamped(float x) {
-    const float ax = fabsf(x);
+// acos_over_pi from ax = |x| (at most 1) and the sign of x, taken from s,
+// with the reflection folded into the last steps: r = acos(ax) / pi as above
+// lies in [0, 1/2], so h = r - 1/2 <= 0 and acos(x) / pi = 1/2 - copysign(h, s)
+// (r for x >= 0, 1 - r below).  One fused multiply-add, a sign transfer and a
+// subtraction replace the product, the subtraction and the select (the result
+// moves by at most one rounding of a value below 1).  ax arrives in a
+// register, so the multiply-adds take their coefficients as literals.
+__device__ __forceinline__ float acos_over_pi_abs(float ax, float s) {
     float p = -0.0012624911f * kInvPi;
     p = fmaf(p, ax, 0.0066700901f * kInvPi);
     p = fmaf(p, ax, -0.0170881256f * kInvPi);
@@ -118,7 +118,7 @@ __device__ __forceinline__ float acos_over_pi_clamped(float x) {
     p = fmaf(p, ax, -0.2145988016f * kInvPi);
     p = fmaf(p, ax, 1.5707963050f * kInvPi);
     const float h = fmaf(__builtin_amdgcn_sqrtf(1.0f - ax), p, -0.5f);
-    return 0.5f - copysignf(h, x);
+    return 0.5f - copysignf(h, s);
 }
 
 }  // namespace dev

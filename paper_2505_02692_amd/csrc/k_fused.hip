@@ -276,8 +276,18 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     const int64_t bi = dev::find_segment_wave(unit_prefix, n_bands, unit);
     const int rb0 = band_rb[bi], band_rows = band_rb[bi + 1] - rb0;
     const int64_t local = unit - unit_prefix[bi];
-    const int64_t rbi = rb0 + local % band_rows;
-    const int c_local = rb_cstart[rb0] + int(local / band_rows);
+    // 32-bit division whenever the offset fits (a band holds fewer than 2^32
+    // units unless a group has hundreds of millions of column blocks)
+    int64_t rbi;
+    int c_local;
+    if (local < (int64_t(1) << 32)) {
+        const uint32_t l32 = uint32_t(local), br = uint32_t(band_rows);
+        rbi = rb0 + int64_t(l32 % br);
+        c_local = rb_cstart[rb0] + int(l32 / br);
+    } else {
+        rbi = rb0 + local % band_rows;
+        c_local = rb_cstart[rb0] + int(local / band_rows);
+    }
     if (c_local < rb_cstart[rbi]) continue;  // uniform: wholly below the group's diagonal
     const int64_t g = rb[4 * rbi];
     const int cbi = g_cb0[g] + c_local;
@@ -331,23 +341,29 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             if (h == 1 && r_frames <= 32) break;
             const int64_t e = c_frame0 - r_frame0 + col0 - 32 * h;
             const int q = e > -32 && e < 32 ? int(e) - lane_term : 1 << 20;  // 1 << 20: no such element
+            // rows past the block's frames belong to no item (their DTW lanes are
+            // discarded): the groups of 8 rows (4 elements) from the first that
+            // starts past them on are skipped (uniform over the wave)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                // rows past the block's frames belong to no item (their DTW lanes
-                // are discarded): the elements from the first whose row in lanes
-                // 0-31 is one of them on are skipped (uniform over the wave; the
-                // rows grow with i)
-                if (32 * h + 8 * (i / 4) + (i % 4) >= r_frames) break;
-                const int r = 32 * h + acc_row(i, lane);
-                const float cs = fminf(fmaxf(acc[h][ct][i] * norm_s[r] * rc, -1.0f), 1.0f);
-                const float ac = 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs);
-                cmax = max(cmax, __float_as_uint(ac));
-                if constexpr (kEuclid) {
-                    const float lr = len_s[r], dl = lr - lc;
-                    const float d = __builtin_sqrtf(fmaxf(fmaf(dl, dl, 2.0f * lr * lc * (1.0f - cs)), 0.0f));
-                    dt[r * kDStride + col] = ac > kNearCos ? -d : d;
-                } else {
-                    dt[r * kDStride + col] = dev::acos_over_pi_clamped(cs);
+            for (int g4 = 0; g4 < 4; ++g4) {
+                if (32 * h + 8 * g4 >= r_frames) break;
+#pragma unroll
+                for (int i = 4 * g4; i < 4 * g4 + 4; ++i) {
+                    const int r = 32 * h + acc_row(i, lane);
+                    const float raw = acc[h][ct][i] * norm_s[r] * rc;
+                    if constexpr (kEuclid) {
+                        const float cs = fminf(fmaxf(raw, -1.0f), 1.0f);
+                        const float ac = 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs);
+                        cmax = max(cmax, __float_as_uint(ac));
+                        const float lr = len_s[r], dl = lr - lc;
+                        const float d =
+                            __builtin_sqrtf(fmaxf(fmaf(dl, dl, 2.0f * lr * lc * (1.0f - cs)), 0.0f));
+                        dt[r * kDStride + col] = ac > kNearCos ? -d : d;
+                    } else {
+                        const float ax = fminf(fabsf(raw), 1.0f);  // |cos|, clamped
+                        cmax = max(cmax, 8 * (i / 4) + (i % 4) == q ? 0u : __float_as_uint(ax));
+                        dt[r * kDStride + col] = dev::acos_over_pi_abs(ax, raw);
+                    }
                 }
             }
         }
@@ -376,12 +392,15 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     {
         const int skip = c_skip;
         const int kept = max(c_frames - skip, 1);
+        // item k belongs to wave floor(4 (start - skip) / kept), tested as
+        // w kept <= 4 (start - skip) < (w + 1) kept without a division
+        const int own_lo = w * kept, own_hi = own_lo + kept;
         int start = skip;
         bool seen = false;
         for (int k = k_first; k < c_nitems; ++k) {
             const int L = item_len[c_item0 + k];
-            const int owner = (4 * (start - skip)) / kept;
-            if (owner == w) {
+            const int a4 = 4 * (start - skip);
+            if (a4 >= own_lo && a4 < own_hi) {
                 if (!seen) { y_begin = k; s_begin = start; seen = true; }
                 y_end = k + 1;
                 s_end = start + L;
