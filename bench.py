@@ -55,7 +55,11 @@ WORKLOADS = {
            "lengths 5-25 (median 9), dim 768 fp32, DTW, path-normalised angular"),
     "c3": ("across_c3", "dtw", "across-speaker triphone task: 200k items, 40 labels, 100 speakers, BY prev/next "
            "ACROSS speaker, lengths 3-40, dim 1024 fp32, DTW, path-normalised angular"),
+    "c2-hard": ("within_c2", "dtw", "within-speaker triphone task (as c2) with label centroids of std 0.1, "
+                "so that many comparisons are near ties and go to the FP64 recheck"),
 }
+# generator arguments of the workloads above that differ from the generators' defaults
+WORKLOAD_KW = {"c2-hard": {"centroid_std": 0.1}}
 
 
 # extra score options (a forced fused-kernel configuration, --fused-config)
@@ -545,7 +549,7 @@ def main():
     gen_name, mode, wl_desc = WORKLOADS[args.workload]
     headline = args.workload == "c4"
     t_gen = time.perf_counter()
-    w = getattr(workloads, gen_name)(device="cuda")
+    w = getattr(workloads, gen_name)(device="cuda", **WORKLOAD_KW.get(args.workload, {}))
     ds = fx.Dataset(ctx, w.features, w.offsets, w.attrs)
     sync()
     log(f"workload {args.workload} ready in {time.perf_counter() - t_gen:.1f} s: {w.n_items} items, "

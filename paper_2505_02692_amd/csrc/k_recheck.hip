@@ -11,10 +11,13 @@
 // Contraction into FMA is disabled.
 //
 // Persistent grid: each 256-thread block takes listed pairs in turn.  The
-// sums run over the lanes of a wave and end in one butterfly; they differ
-// from the strictly sequential sums of the definition only in rounding
-// (about 1e-16 relative), and every pair goes through the same arithmetic, so
-// equal inputs (exact copies) still give equal distances.
+// frame norms and most frame products are sums over the lanes of a wave
+// ending in one butterfly; the frame products of k_recheck_dtw for pairs of
+// more than 256 frame pairs are sequential sums per frame pair.  Either
+// differs from the strictly sequential sums of the definition only in
+// rounding (about 1e-16 relative), and every pair of a kernel goes through
+// the same arithmetic (exact copies have equal lengths, so they meet in the
+// same kernel), so equal inputs still give equal distances.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -118,13 +121,35 @@ __device__ __forceinline__ void dtw_update(int i, int j, double d, double diag, 
     }
 }
 
+// LDS staging of k_recheck_dtw's frame products: room for 132 rows (N + M
+// frames and the tiles' overreach of up to 3 rows) of 32 features (+1 pad);
+// fewer rows take longer feature chunks
+constexpr int kRstage = (2 * kMaxL + 4) * 33;
+constexpr int kRper = 8;  // staging loads a thread has in flight at once
+
 // One 256-thread block per listed pair of items of at most kMaxL frames (the
-// others are left to k_long_dtw): the four waves share the N + M frame norms
-// and then the N x M frame distances (a wave per frame pair at a time, its 64
-// lanes splitting the feature dimension, one butterfly sum each), held in LDS;
-// then one wave runs the DTW over anti-diagonals (lane = row i), with the
-// diagonal > left > up predecessor order on exact ties.
-template <typename T>
+// others are left to k_long_dtw).  The four waves share the N + M frame norms
+// (a wave per frame, its lanes splitting the dimension).  The N x M frame
+// products are then a register-tiled FP64 product: the frames go through LDS
+// in chunks of features (as many as kRstage holds for N + M + 3 rows; each
+// thread issues kRper loads before their stores), as unit-vector
+// components (or raw values for the Euclidean distance), and a thread
+// accumulates T x T frame pairs, each a sequential sum over the features in
+// order, so every pair gets the same arithmetic whatever its tile: T = 2
+// (thread t on (2 (t / 16) + r, 2 (t % 16) + c)) when both items have at most
+// 32 frames, else T = 4.  Pairs of at most kSmallPairs frame pairs go to the
+// kTiled = false instantiation instead, whose small footprint keeps more
+// blocks per CU: there a wave takes a frame pair at a time, its lanes
+// splitting the features (one butterfly sum).  The class depends on N * M
+// only, so both orientations of a pair, and copies, share the arithmetic;
+// each instantiation skips the other's pairs.  A frame pair whose cosine is within 2^-20 of +-1 is
+// finished by a wave (lanes splitting the dimension) with the half-chord
+// sums.  The distances stay in LDS; one wave then runs the DTW over
+// anti-diagonals (lane = row i), with the diagonal > left > up predecessor
+// order on exact ties.
+constexpr int kSmallPairs = 256;  // pairs of at most this many frame pairs: a wave per frame pair
+
+template <typename T, bool kTiled>
 __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat, int dim,
                                                      const int64_t *__restrict__ g_item0,
                                                      const int64_t *__restrict__ g_n,
@@ -136,18 +161,22 @@ __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat,
                                                      const unsigned int *__restrict__ count,
                                                      int64_t max_count, int norm, int euclid,
                                                      double *__restrict__ p64) {
+    constexpr int kDm = kTiled ? kMaxL * kMaxL : kSmallPairs;  // room for N * M distances
     __shared__ double inrm[2 * kMaxL];     // 1 / ||frame|| of the N rows, then the M columns
-    __shared__ double dm[kMaxL * kMaxL];   // frame distances, row-major [N][M]
+    __shared__ double dm[kDm];             // frame distances, row-major [N][M]
+    __shared__ double st[kTiled ? kRstage : 1];  // a feature chunk of the N + M frames
+    __shared__ uint8_t near[kDm];                // cosine within 2^-20 of +-1
     const int lane = threadIdx.x % dev::kWave, w = threadIdx.x / dev::kWave;
+    const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;  // this thread's tile of frame pairs
     const int64_t total = min(int64_t(*count), max_count);
     for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
         const int64_t slot = list[e];
-        const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
+        const int64_t g = dev::find_segment_wave(g_pair_base, n_groups, slot);
         const int64_t n = g_n[g];
         const int64_t local = slot - g_pair_base[g];
         const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
         const int N = item_len[x], M = item_len[y];
-        if (N > kMaxL || M > kMaxL) continue;  // block-uniform
+        if (N > kMaxL || M > kMaxL || (N * M <= kSmallPairs) == kTiled) continue;  // block-uniform
         const T *fx = feat + item_src[x] * int64_t(dim);
         const T *fy = feat + item_src[y] * int64_t(dim);
         auto frame = [&](int f) { return f < N ? fx + int64_t(f) * dim : fy + int64_t(f - N) * dim; };
@@ -158,14 +187,110 @@ __global__ __launch_bounds__(256) void k_recheck_dtw(const T *__restrict__ feat,
                 if (lane == 0) inrm[f] = r;
             }
         __syncthreads();
-        // frame distances, a wave per (i, j)
-        for (int cidx = w; cidx < N * M; cidx += 4) {
-            const int i = cidx / M, j = cidx % M;
-            const T *u = fx + int64_t(i) * dim, *v = fy + int64_t(j) * dim;
-            const double d = euclid ? wave_euclid_distance(u, v, dim, lane)
-                                    : wave_frame_distance(u, v, inrm[i], inrm[N + j], dim, lane);
-            if (lane == 0) dm[cidx] = d;
+        // frame products.  Rows of st: 0..N-1 the x frames, N..N+M-1 the y
+        // frames; a tile reaching past them (i >= N or j >= M) reads at most 3
+        // rows further (inside st, whatever they hold) and its sums are dropped.
+        const int kc = min(dim, kRstage / (N + M + 3) - 1);  // features per chunk
+        const int pad = kc + 1;
+        auto products = [&](auto tile_tag) {
+            constexpr int kT = decltype(tile_tag)::value;
+            const int i0 = kT * ti, j0 = kT * tj;
+            const bool active = i0 < N && j0 < M;
+            double acc[kT][kT];
+#pragma unroll
+            for (int r = 0; r < kT; ++r)
+#pragma unroll
+                for (int c = 0; c < kT; ++c) acc[r][c] = 0.0;
+            for (int k0 = 0; k0 < dim; k0 += kc) {
+                const int kn = min(kc, dim - k0);
+                // kRper loads in flight per thread before their stores
+                const int nq = (N + M) * kc;
+                for (int q0 = 0; q0 < nq; q0 += 256 * kRper) {
+                    double v[kRper];
+#pragma unroll
+                    for (int u = 0; u < kRper; ++u) {
+                        const int q = q0 + threadIdx.x + 256 * u, f = q / kc, kk = q - f * kc;
+                        v[u] = q < nq && kk < kn ? ld(frame(f), k0 + kk) : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kRper; ++u) {
+                        const int q = q0 + threadIdx.x + 256 * u, f = q / kc, kk = q - f * kc;
+                        if (q < nq) st[f * pad + kk] = euclid ? v[u] : v[u] * inrm[f];
+                    }
+                }
+                __syncthreads();
+                if (active) {
+                    const double *sa = st + i0 * pad;
+                    const double *sb = st + (N + j0) * pad;
+                    for (int kk = 0; kk < kn; ++kk) {
+                        double a[kT], b[kT];
+#pragma unroll
+                        for (int r = 0; r < kT; ++r) a[r] = sa[r * pad + kk];
+#pragma unroll
+                        for (int c = 0; c < kT; ++c) b[c] = sb[c * pad + kk];
+#pragma unroll
+                        for (int r = 0; r < kT; ++r)
+#pragma unroll
+                            for (int c = 0; c < kT; ++c) {
+                                if (euclid) {
+                                    const double d = a[r] - b[c];
+                                    acc[r][c] = acc[r][c] + d * d;
+                                } else {
+                                    acc[r][c] = acc[r][c] + a[r] * b[c];
+                                }
+                            }
+                    }
+                }
+                __syncthreads();
+            }
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < kT; ++r)
+#pragma unroll
+                    for (int c = 0; c < kT; ++c) {
+                        const int i = i0 + r, j = j0 + c;
+                        if (i < N && j < M) {
+                            const double v = acc[r][c];
+                            if (euclid) {
+                                dm[i * M + j] = sqrt(v);
+                                near[i * M + j] = 0;
+                            } else {
+                                const bool nr = !(fabs(v) < 1.0 - 0x1p-20);
+                                dm[i * M + j] = nr ? 0.0 : acos(v) / kPi;
+                                near[i * M + j] = nr ? 1 : 0;
+                            }
+                        }
+                    }
+            }
+        };
+        if constexpr (!kTiled) {
+            // few frame pairs: a wave per pair, its lanes splitting the features
+            // (one butterfly sum), which keeps the lanes busy where tiles would not
+            for (int cidx = w; cidx < N * M; cidx += 4) {
+                const int i = cidx / M, j = cidx % M;
+                const T *u = fx + int64_t(i) * dim, *v = fy + int64_t(j) * dim;
+                const double d = euclid ? wave_euclid_distance(u, v, dim, lane)
+                                        : wave_frame_distance(u, v, inrm[i], inrm[N + j], dim, lane);
+                if (lane == 0) {
+                    dm[cidx] = d;
+                    near[cidx] = 0;
+                }
+            }
+        } else if (N <= 32 && M <= 32) {
+            products(std::integral_constant<int, 2>{});
+        } else {
+            products(std::integral_constant<int, 4>{});
         }
+        __syncthreads();
+        // near-parallel pairs: the half-chord form, a wave per pair
+        if (!euclid)
+            for (int cidx = w; cidx < N * M; cidx += 4) {
+                if (!near[cidx]) continue;  // wave-uniform
+                const int i = cidx / M, j = cidx % M;
+                const double d = wave_frame_distance(fx + int64_t(i) * dim, fy + int64_t(j) * dim, inrm[i],
+                                                     inrm[N + j], dim, lane);
+                if (lane == 0) dm[cidx] = d;
+            }
         __syncthreads();
         if (w == 0) {
             // lane i is on column t - i at step t: c[i-1][j] comes from lane i - 1
@@ -223,7 +348,7 @@ __global__ __launch_bounds__(256) void k_long_dtw(const T *__restrict__ feat, in
     const int64_t total = count ? min(int64_t(*count), max_count) : max_count;
     for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
         const int64_t slot = list[e];
-        const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
+        const int64_t g = dev::find_segment_wave(g_pair_base, n_groups, slot);
         const int64_t n = g_n[g];
         const int64_t local = slot - g_pair_base[g];
         const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
@@ -326,7 +451,7 @@ __global__ __launch_bounds__(256) void k_recheck_pooled(const T *__restrict__ fe
     const int64_t total = min(int64_t(*count), max_count);
     for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
         const int64_t slot = list[e];
-        const int64_t g = dev::find_segment(g_pair_base, n_groups, slot);
+        const int64_t g = dev::find_segment_wave(g_pair_base, n_groups, slot);
         const int64_t n = g_n[g];
         const int64_t local = slot - g_pair_base[g];
         const int64_t x = g_item0[g] + local / n, y = g_item0[g] + local % n;
@@ -399,16 +524,22 @@ void recheck_fp64(hipStream_t s, const void *features, int dtype, int dim, const
     if (mode == FABX_MODE_DTW && has_long)
         long_dtw(s, features, dtype, dim, g, it, list, count, max_count, norm, euclid, p64, nullptr, nullptr);
     if (mode == FABX_MODE_DTW) {
-        if (dtype == FABX_DTYPE_F32)
-            hipLaunchKernelGGL(k_recheck_dtw<float>, dim3(blocks), dim3(256), 0, s,
-                               static_cast<const float *>(features), dim, g.item0, g.n_items,
-                               g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, norm,
-                               euclid, p64);
-        else
-            hipLaunchKernelGGL(k_recheck_dtw<uint16_t>, dim3(blocks), dim3(256), 0, s,
-                               static_cast<const uint16_t *>(features), dim, g.item0, g.n_items,
-                               g.pair_base, g.n_groups, it.src, it.len, list, count, max_count, norm,
-                               euclid, p64);
+        // pairs of short items, then the others (each kernel skips the other's)
+        if (dtype == FABX_DTYPE_F32) {
+            hipLaunchKernelGGL((k_recheck_dtw<float, false>), dim3(blocks), dim3(256), 0, s,
+                               static_cast<const float *>(features), dim, g.item0, g.n_items, g.pair_base,
+                               g.n_groups, it.src, it.len, list, count, max_count, norm, euclid, p64);
+            hipLaunchKernelGGL((k_recheck_dtw<float, true>), dim3(blocks), dim3(256), 0, s,
+                               static_cast<const float *>(features), dim, g.item0, g.n_items, g.pair_base,
+                               g.n_groups, it.src, it.len, list, count, max_count, norm, euclid, p64);
+        } else {
+            hipLaunchKernelGGL((k_recheck_dtw<uint16_t, false>), dim3(blocks), dim3(256), 0, s,
+                               static_cast<const uint16_t *>(features), dim, g.item0, g.n_items, g.pair_base,
+                               g.n_groups, it.src, it.len, list, count, max_count, norm, euclid, p64);
+            hipLaunchKernelGGL((k_recheck_dtw<uint16_t, true>), dim3(blocks), dim3(256), 0, s,
+                               static_cast<const uint16_t *>(features), dim, g.item0, g.n_items, g.pair_base,
+                               g.n_groups, it.src, it.len, list, count, max_count, norm, euclid, p64);
+        }
     } else {
         if (dtype == FABX_DTYPE_F32)
             hipLaunchKernelGGL(k_recheck_pooled<float>, dim3(blocks), dim3(256), 0, s,
