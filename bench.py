@@ -379,20 +379,33 @@ def cpu_baseline(oracle, fx, w, target_seconds=15.0, seed=0):
                       f"workload would take about {whole_s:.0f} s by the rescaled estimate"}
 
 
-def committed_traffic(kernel_file, profile_file, cols, blocks_per_cu):
-    """HBM bytes per launch of the dominant kernel in the configuration that ran,
-    from the committed rocprofv3 byte-counter summary, used only while the kernel
-    source is the one that was measured (its SHA-256 prefix is recorded beside
-    the figure)."""
+FUSED_SOURCES = ("paper_2505_02692_amd/csrc/k_fused.hip", "paper_2505_02692_amd/csrc/device_common.h")
+
+
+def fused_source_hash():
+    """SHA-256 prefix of the fused kernel's sources (the kernel file and the
+    device helpers it includes), the key of its committed byte counts."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in FUSED_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(profile_file, cols, blocks_per_cu):
+    """HBM bytes per launch of the dominant kernel in the configuration that ran,
+    from the committed rocprofv3 byte-counter summary, used only while the kernel
+    sources are the ones that were measured (their SHA-256 prefix is recorded
+    beside the figure)."""
+    root = os.path.dirname(os.path.abspath(__file__))
     try:
-        src = open(os.path.join(root, kernel_file), "rb").read()
         lines = open(os.path.join(root, profile_file)).read().splitlines()
+        want = {"source_sha256": fused_source_hash(),
+                "kernel": f"k_fused<{cols},true>", "blocks_per_cu": str(blocks_per_cu)}
     except OSError:
         return None
-    want = {"source_sha256": hashlib.sha256(src).hexdigest()[:16],
-            "kernel": f"k_fused<{cols},true>", "blocks_per_cu": str(blocks_per_cu)}
     for line in lines:
         f = line.strip().strip("`").split()
         if not f or f[0] != "traffic":
@@ -424,8 +437,7 @@ def roofline(w, mode, st0, pstats, profile_file):
         return {"kernel": "k_triplets_sorted", "bound": "alu", "ms_per_launch": pk["ms_triplets"],
                 "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None}
     ach = dist_flops / (pk["ms_distance"] / 1e3) / 1e12
-    traffic = (committed_traffic("paper_2505_02692_amd/csrc/k_fused.hip", profile_file,
-                                 st0["fused_cols"], st0["fused_blocks_per_cu"])
+    traffic = (committed_traffic(profile_file, st0["fused_cols"], st0["fused_blocks_per_cu"])
                if (mode == "dtw" and profile_file) else None)
     return {"kernel": "k_fused" if mode == "dtw" else "k_gram_angular_bf16", "bound": "mfma",
             "achieved": ach, "peak": MFMA_BF16_PEAK_TFLOPS,
@@ -577,7 +589,9 @@ def main():
     log(f"bf16 form, serial: {ms_step_serial:.2f} ms/step, stages {stages}")
     assert errs[-1] == serrs[-1]
     st0 = stats[-1]
-    log(f"task: {st0['n_items']} items in cells, {st0['n_frames']} frames packed")
+    log(f"task: {st0['n_items']} items in cells, {st0['n_frames']} frames packed; fused kernel "
+        f"k_fused<{st0['fused_cols']},...> blocks_per_cu={st0['fused_blocks_per_cu']}, "
+        f"sources sha256 {fused_source_hash()}")
     n_trip = st0["n_triplets"]
     value = n_trip / (ms_step / 1e3)
     t_build = []

@@ -98,16 +98,23 @@ __device__ __forceinline__ uint32_t pk_step(uint32_t a) {
 template <int kN>
 struct Chunk {
     static constexpr int kPer = kN * (kKc / 8) / 256;
-    uint4 v[kPer];
-    // rows beyond nr read as zero
+    // one vector value, not an array, so it stays in registers
+    typedef uint32_t Vec __attribute__((ext_vector_type(4 * kPer)));
+    Vec v;
+    // rows beyond nr (>= 1) repeat row nr - 1: finite values whose products
+    // only reach accumulator rows or columns that are never used, or that are
+    // scaled by a zero inverse norm (no zero fill, no masked loads)
     __device__ __forceinline__ void load(const uint16_t *__restrict__ xn, int dim_pad, int64_t row0, int nr,
                                          int k0) {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int p = threadIdx.x + 256 * i;
-            const int r = p / (kKc / 8), q = p % (kKc / 8);
-            v[i] = make_uint4(0, 0, 0, 0);
-            if (r < nr) v[i] = *reinterpret_cast<const uint4 *>(xn + (row0 + r) * dim_pad + k0 + q * 8);
+            const int r = min(p / (kKc / 8), nr - 1), q = p % (kKc / 8);
+            const uint4 t = *reinterpret_cast<const uint4 *>(xn + (row0 + r) * dim_pad + k0 + q * 8);
+            v[4 * i] = t.x;
+            v[4 * i + 1] = t.y;
+            v[4 * i + 2] = t.z;
+            v[4 * i + 3] = t.w;
         }
     }
     __device__ __forceinline__ void store(uint16_t *lds) const {
@@ -115,7 +122,8 @@ struct Chunk {
         for (int i = 0; i < kPer; ++i) {
             const int p = threadIdx.x + 256 * i;
             const int r = p / (kKc / 8), q = p % (kKc / 8);
-            *reinterpret_cast<uint4 *>(lds + r * kLdsRow + q * 8) = v[i];
+            *reinterpret_cast<uint4 *>(lds + r * kLdsRow + q * 8) =
+                make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
         }
     }
 };
