@@ -78,8 +78,8 @@ struct Tile {
 __device__ __forceinline__ float shr1z(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
-__device__ __forceinline__ uint32_t shr1u(uint32_t old, uint32_t v) {
-    return uint32_t(__builtin_amdgcn_update_dpp(int(old), int(v), 0x138, 0xf, 0xf, false));
+__device__ __forceinline__ uint32_t shr1uz(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xf, 0xf, true));
 }
 
 __device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
@@ -415,8 +415,9 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
             }
             start += L;
         }
-        // column c of this wave's span is entry kWave + c: bit 0 = first column
-        // of an item, bits 1..14 = the item's index in the column block, bit 31 =
+        // column c of this wave's span is entry kWave + c: byte 0 = 1 at the
+        // first column of an item (tested with one byte-select compare), bits
+        // 8..21 = the item's index in the column block, bit 31 =
         // last column.  The guards read as 0 (no item start, no output).
         // Same-wave LDS stores land in issue order.
         for (int j = lane; j < kFlagLen; j += kWave) colflag[w][j] = 0;
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                 const int L = item_len[c_item0 + k];
                 for (int j = lane; j < L; j += kWave)
                     colflag[w][kWave + start2 - s_begin + j] =
-                        uint32_t((j == 0 ? 1u : 0u) | (uint32_t(k) << 1) | (j == L - 1 ? 0x80000000u : 0u));
+                        uint32_t((j == 0 ? 1u : 0u) | (uint32_t(k) << 8) | (j == L - 1 ? 0x80000000u : 0u));
                 start2 += L;
             }
         }
@@ -476,9 +477,10 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     auto run = [&](auto careful_tag) {
     constexpr bool careful = decltype(careful_tag)::value;
     auto step = [&](const uint32_t cf, const float dv) {
-        const bool first = cf & 1;
+        const bool first = uint8_t(cf) != 0;
         up = shr1z(c) + top_pen;
-        if (kPath) Pup = shr1u(Pup, P);
+        // (lane 0 reads 0: a first row, whose up interval is never taken)
+        if (kPath) Pup = shr1uz(P);
         const float diag = first ? diag_first : up_prev;
         const float left = first ? kInf : c;
         const float m = fminf(fminf(diag, left), up);
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
         }
         float dvc = dv;
         if constexpr (careful) {
-            const uint32_t nup = top ? 0u : shr1u(0u, nz);
+            const uint32_t nup = top ? 0u : shr1uz(nz);
             uint32_t nq;
             if constexpr (kEuclid) {
                 nq = __float_as_uint(dv) >> 31;  // marked by the epilogue
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
         // writer: the pairs with x after y are written by the unit holding
         // (y, x).
         if (cf >= out_min) {
-            const int64_t py = int64_t(c_item0) + ((cf >> 1) & 0x3FFF) - gitem0;
+            const int64_t py = int64_t(c_item0) + ((cf >> 8) & 0x3FFF) - gitem0;
             if (px <= py) {
                 const int64_t slot = pbase + px * gn + py, mirror = pbase + py * gn + px;
                 float v;
