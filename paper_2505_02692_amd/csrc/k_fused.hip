@@ -333,7 +333,10 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     // parallel by construction.  In the sub-tile of rows 32h + acc_row(i, lane)
     // and columns col0 + lane % 32 the element is a frame against itself when
     // acc_row(i, lane) - lane % 32 equals e = (column block start + col0) -
-    // (row block start + 32h); two operations per element.
+    // (row block start + 32h), which needs |e| < 32.  The Euclidean epilogue
+    // tests each element (it also marks near-parallel ones); the angular one
+    // takes the maximum over all elements and redoes it for the rare sub-tiles
+    // with |e| < 32 without those elements.
     // (kept as bits: the values are >= 0, whose bit patterns order like them)
     uint32_t cmax = 0;
     const int lane_term = 4 * (lane / 32) - lane % 32;
@@ -347,8 +350,12 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && r_frames <= 32) break;
+            uint32_t cmax_t = 0;  // this sub-tile's largest |cos| (bits)
+            // a sub-tile within 32 frames of the diagonal may hold frames against
+            // themselves (uniform over the wave; rare)
             const int64_t e = c_frame0 - r_frame0 + col0 - 32 * h;
-            const int q = e > -32 && e < 32 ? int(e) - lane_term : 1 << 20;  // 1 << 20: no such element
+            const bool on_diag = e > -32 && e < 32;
+            const int q = on_diag ? int(e) - lane_term : 1 << 20;  // 1 << 20: no such element
             // rows past the block's frames belong to no item (their DTW lanes are
             // discarded): the groups of 8 rows (4 elements) from the first that
             // starts past them on are skipped (uniform over the wave)
@@ -362,18 +369,34 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
                     if constexpr (kEuclid) {
                         const float cs = fminf(fmaxf(raw, -1.0f), 1.0f);
                         const float ac = 8 * (i / 4) + (i % 4) == q ? 0.0f : fabsf(cs);
-                        cmax = max(cmax, __float_as_uint(ac));
+                        cmax_t = max(cmax_t, __float_as_uint(ac));
                         const float lr = len_s[r], dl = lr - lc;
                         const float d =
                             __builtin_sqrtf(fmaxf(fmaf(dl, dl, 2.0f * lr * lc * (1.0f - cs)), 0.0f));
-                        dt[r * kDStride + col] = ac > kNearCos ? -d : d;
+                        dt[r * kDStride + col] = ac > kNearCos ? -d : d;  // the sign marks it
                     } else {
                         const float ax = fminf(fabsf(raw), 1.0f);  // |cos|, clamped
-                        cmax = max(cmax, 8 * (i / 4) + (i % 4) == q ? 0u : __float_as_uint(ax));
+                        cmax_t = max(cmax_t, __float_as_uint(ax));
                         dt[r * kDStride + col] = dev::acos_over_pi_abs(ax, raw);
                     }
                 }
             }
+            // angular: the loop above took every element; on the diagonal the
+            // sub-tile's largest |cos| is taken again without a frame against itself
+            if (!kEuclid && on_diag) {
+                cmax_t = 0;
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    if (32 * h + 8 * g4 >= r_frames) break;
+#pragma unroll
+                    for (int i = 4 * g4; i < 4 * g4 + 4; ++i) {
+                        const int r = 32 * h + acc_row(i, lane);
+                        const float ax = fminf(fabsf(acc[h][ct][i] * norm_s[r] * rc), 1.0f);
+                        cmax_t = max(cmax_t, 8 * (i / 4) + (i % 4) == q ? 0u : __float_as_uint(ax));
+                    }
+                }
+            }
+            cmax = max(cmax, cmax_t);
         }
     }
     if (__ballot(__uint_as_float(cmax) > kNearCos) != 0 && lane == 0) atomicOr(&near_s, 1);
