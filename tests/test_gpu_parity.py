@@ -697,11 +697,17 @@ def _euclid_case(name):
         w = workloads.batched_c4(n_groups=8, size_lo=6, size_hi=20, len_lo=1, len_hi=12, dim=1024,
                                  centroid_std=0.3, seed=42, dtype=torch.float32)
         return _with_twins(w, 1e-4, seed=7)
+    if name == "long-copies-1024":
+        # items of 17-64 frames and exact copies: the FP64 recheck takes these
+        # pairs (more than 256 frame pairs) in its register-tiled form
+        w = workloads.batched_c4(n_groups=6, size_lo=4, size_hi=8, len_lo=17, len_hi=64, dim=1024,
+                                 centroid_std=0.3, seed=43, dtype=torch.float32)
+        return _with_twins(w, 0.0, seed=8)
     raise ValueError(name)
 
 
 @pytest.mark.parametrize("mode,norm", [("dtw", "path"), ("dtw", "none"), ("pooled", "path")])
-@pytest.mark.parametrize("case", ["c1-zero-frame", "c2-shape-768", "near-copies-1024"])
+@pytest.mark.parametrize("case", ["c1-zero-frame", "c2-shape-768", "near-copies-1024", "long-copies-1024"])
 def test_euclidean_bf16_exact(case, mode, norm):
     """The Euclidean distance in the BF16 + FP64-recheck form: the unit-vector
     cosine from the MFMA Gram tile and each frame's FP32 length give
@@ -1370,6 +1376,21 @@ def test_near_parallel_frames_exact(dim, eps):
     print(f"  nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']}", flush=True)
     assert st["n_nonrobust_pairs"] > 0
     check(w, mode="pooled")
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_near_parallel_long_items_exact(eps):
+    """Items of 17-64 frames and their (near) copies at dim 1024: the FP64
+    recheck takes such pairs (more than 256 frame pairs) as register tiles of
+    2 x 2 or 4 x 4 frame pairs, and frame pairs whose cosine is within 2^-20
+    of +-1 go to its half-chord pass; every cell equals the oracle's."""
+    base = workloads.batched_c4(n_groups=6, size_lo=4, size_hi=8, len_lo=17, len_hi=64, dim=1024,
+                                centroid_std=0.1, seed=72, dtype=torch.float32)
+    w = _with_twins(base, eps, seed=9)
+    _, res, _ = check(w)
+    st = res.stats
+    print(f"  nonrobust={st['n_nonrobust_pairs']} recheck={st['n_recheck_pairs']}", flush=True)
+    assert st["n_recheck_pairs"] > 0
 
 
 # ---------------------------------------------------------------- subsampler --
