@@ -45,6 +45,10 @@ __device__ double angle_over_pi_units(double c, double sm, double sp) {
     return th / kPi;
 }
 
+// The per-lane loops over the features below are unrolled so that the loads
+// of several features are in flight at once; each lane still adds its terms
+// in feature order.
+
 // Sum of a double over the wave (butterfly; every lane gets the sum).
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
@@ -56,6 +60,7 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 template <typename T>
 __device__ __forceinline__ double wave_inv_norm(const T *row, int dim, int lane) {
     double s = 0.0;
+#pragma unroll 4
     for (int k = lane; k < dim; k += dev::kWave) {
         const double v = ld(row, k);
         s += v * v;
@@ -69,10 +74,12 @@ template <typename T>
 __device__ __forceinline__ double wave_frame_distance(const T *u, const T *v, double su, double sv, int dim,
                                                       int lane) {
     double c = 0.0;
+#pragma unroll 4
     for (int k = lane; k < dim; k += dev::kWave) c += (ld(u, k) * su) * (ld(v, k) * sv);
     c = wave_sum_f64(c);
     double sm = 0.0, sp = 0.0;
     if (!(fabs(c) < 1.0 - 0x1p-20)) {   // wave-uniform: c is the same in every lane
+#pragma unroll 4
         for (int k = lane; k < dim; k += dev::kWave) {
             const double a = ld(u, k) * su, b = ld(v, k) * sv;
             sm += (a - b) * (a - b);
@@ -88,6 +95,7 @@ __device__ __forceinline__ double wave_frame_distance(const T *u, const T *v, do
 template <typename T>
 __device__ __forceinline__ double wave_euclid_distance(const T *u, const T *v, int dim, int lane) {
     double s = 0.0;
+#pragma unroll 4
     for (int k = lane; k < dim; k += dev::kWave) {
         const double a = ld(u, k) - ld(v, k);
         s += a * a;
