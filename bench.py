@@ -504,7 +504,8 @@ def main():
     ap.add_argument("--depth", type=int, default=2,
                     help="scores kept enqueued on the device by the pipelined loop (side 'launch')")
     ap.add_argument("--side-pool", action="store_true",
-                    help="let the second host thread's work use the shared host thread pool")
+                    help="let the second host thread's work use the shared host thread pool (the default "
+                         "for tasks of a million cells or more)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run 3 plain device copies of this many MiB (to scale HBM byte counters)")
     ap.add_argument("--stream-probe-mib", type=int, default=0,
@@ -571,13 +572,18 @@ def main():
         cols, bpc = (int(v) for v in args.fused_config.split(","))
         SCORE_KW.update(fused_cols=cols, fused_blocks_per_cu=bpc)
     # untimed: warm-up steps, then pick the fused kernel's tiles / grid for this task shape
-    run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, args.side, not args.side_pool, args.depth)
+    _, wst, _ = run_pipelined(fx, ds, w, "bf16", args.warmup, sync, mode, args.side, not args.side_pool,
+                              args.depth)
     sync()
-    log("warmup done")
+    # the second thread's host work (score set-up, collapse) runs in place,
+    # single-threaded, so that it never takes the pool from the next build;
+    # a task of a million cells or more has a collapse that needs the pool
+    side_serial = not args.side_pool and (not wst or wst[-1]["n_cells"] < 1_000_000)
+    log(f"warmup done; second thread's host work {'in place' if side_serial else 'on the pool'}")
     tune = (fx.Task(ds, w.on, w.by, w.across).autotune(mode=mode)
             if not (args.no_autotune or args.fused_config) else None)
     log(f"autotune: {tune}")
-    dt, pstats, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, args.side, not args.side_pool,
+    dt, pstats, errs = run_pipelined(fx, ds, w, "bf16", args.steps, sync, mode, args.side, side_serial,
                                      args.depth)
     ms_step = dt / args.steps * 1e3
     log(f"bf16 form, pipelined: {ms_step:.2f} ms/step")
