@@ -275,15 +275,23 @@ __global__ __launch_bounds__(256, 4) void k_fused(const uint16_t *__restrict__ x
     };
     const int lane = threadIdx.x % kWave;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // the band of the block's previous unit and its unit range: a persistent
+    // block's next unit usually lies in it, which spares the band search
+    int64_t band_c = -1, band_lo = 0, band_hi = 0;
     for (int64_t j = take ? next(0) : int64_t(blockIdx.x / 8); j < grid_q; j = next(j)) {
     const int64_t unit = xcd * grid_q + j;
     if (unit >= n_units) break;  // uniform across the block; later units are larger
 
     // the unit's band, row block, group and column block: within a band,
     // column blocks from the band's first kept one on, row blocks fastest
-    const int64_t bi = dev::find_segment_wave(unit_prefix, n_bands, unit);
+    if (band_c < 0 || unit < band_lo || unit >= band_hi) {  // uniform
+        band_c = dev::find_segment_wave(unit_prefix, n_bands, unit);
+        band_lo = unit_prefix[band_c];
+        band_hi = unit_prefix[band_c + 1];
+    }
+    const int64_t bi = band_c;
     const int rb0 = band_rb[bi], band_rows = band_rb[bi + 1] - rb0;
-    const int64_t local = unit - unit_prefix[bi];
+    const int64_t local = unit - band_lo;
     // 32-bit division whenever the offset fits (a band holds fewer than 2^32
     // units unless a group has hundreds of millions of column blocks)
     int64_t rbi;
